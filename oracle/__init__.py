@@ -1,0 +1,242 @@
+"""FP64 CPU oracle of the exact t-SNE hot path (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg are the only users. The product package never imports this
+module, and this module imports nothing from the product package.
+
+Each function restates the part of the method it follows; the arithmetic
+itself lives in ``tsne_oracle.c`` (and ``mlp_oracle.c`` for the surrogate
+network), in double precision.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_d = ctypes.c_double
+
+DEFAULT_TOL = 1e-12
+DEFAULT_MAX_ITER = 200
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.LIB
+    if not os.path.exists(path):
+        _build.build()
+    lib = ctypes.CDLL(path)
+    sig = {
+        "orc_sqdist": (None, [_f64p, _i64, _i32, _f64p]),
+        "orc_calibrate_drow": (ctypes.c_int, [_f64p, _i64, _i64, _d, ctypes.c_int, _d,
+                                              ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                              ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+        "orc_calibrate": (None, [_f64p, _i64, _i32, _d, ctypes.c_void_p, _i64, ctypes.c_int, _d,
+                                 _f64p, _f64p, _f64p, _f64p, _i32p]),
+        "orc_joint_p": (None, [_f64p, _i64, _i32, _f64p, _f64p, _f64p, _f64p]),
+        "orc_p_entries": (None, [_f64p, _i64, _i32, _i64p, _i64p, _i64, _f64p, _f64p, _f64p,
+                                 _f64p, _f64p, _f64p, _f64p]),
+        "orc_p_entropy_term": (_d, [_f64p, _i64]),
+        "orc_z": (_d, [_f64p, _i64]),
+        "orc_gradient": (None, [_f64p, _i64, _f64p, _d, _f64p, ctypes.POINTER(_d)]),
+        "orc_repulsion_rows": (None, [_f64p, _i64, _i64p, _i64, _d, _f64p]),
+        "orc_cost": (None, [_f64p, _i64, _f64p, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+        "orc_step": (None, [_f64p, _i64, _f64p, _f64p, _f64p, _d, _d, _d, _d, ctypes.c_int,
+                            ctypes.c_void_p, ctypes.c_void_p]),
+        "orc_knn_overlap": (_d, [_f64p, _i64, _i32, _f64p, _i64p, _i64, ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# Input similarities and calibration (Eqs. 1-2)
+# --------------------------------------------------------------------------
+
+def sqdist(x) -> np.ndarray:
+    """Full matrix of squared Euclidean distances, direct-difference form."""
+    x = _f64(x)
+    n, d = x.shape
+    out = np.empty((n, n), dtype=np.float64)
+    _load().orc_sqdist(x, n, d, out)
+    return out
+
+
+@dataclass
+class RowStats:
+    beta: np.ndarray  # Gaussian precision per row (Eq. 1)
+    m: np.ndarray  # row minimum of d_ij, j != i (shift of the exponent)
+    S: np.ndarray  # sum_{j != i} exp(-beta (d_ij - m)) at the returned beta
+    H: np.ndarray  # entropy of p_{.|i} in nats at the returned beta
+    iters: np.ndarray  # evaluations used; negative if the row did not converge
+
+
+def calibrate(x, perplexity: float, rows=None, max_iter: int = DEFAULT_MAX_ITER,
+              tol: float = DEFAULT_TOL) -> RowStats:
+    """Per-row bisection on beta so that H(p_{.|i}) = ln(perplexity) (Eqs. 1-2).
+
+    ``rows`` limits the work to the listed rows (distances are recomputed per
+    row, nothing of size n^2 is stored); outputs follow the order of ``rows``.
+    """
+    x = _f64(x)
+    n, d = x.shape
+    if rows is None:
+        nr, rp = n, None
+    else:
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nr, rp = rows.shape[0], rows.ctypes.data_as(ctypes.c_void_p)
+    beta, m, S, H = (np.empty(nr) for _ in range(4))
+    iters = np.empty(nr, dtype=np.int32)
+    _load().orc_calibrate(x, n, d, float(perplexity), rp, nr, int(max_iter), float(tol),
+                          beta, m, S, H, iters)
+    return RowStats(beta, m, S, H, iters)
+
+
+def calibrate_drow(drow, i: int, perplexity: float, max_iter: int = DEFAULT_MAX_ITER,
+                   tol: float = DEFAULT_TOL):
+    """Calibrate one row from a given distance row (drow[i] is ignored)."""
+    drow = _f64(drow)
+    b, m, S, H = _d(), _d(), _d(), _d()
+    it = _load().orc_calibrate_drow(drow, drow.shape[0], int(i), float(perplexity),
+                                    int(max_iter), float(tol), ctypes.byref(b), ctypes.byref(m),
+                                    ctypes.byref(S), ctypes.byref(H))
+    return b.value, m.value, S.value, H.value, it
+
+
+# --------------------------------------------------------------------------
+# Joint P (Eq. 3)
+# --------------------------------------------------------------------------
+
+def joint_p(x, st: RowStats) -> np.ndarray:
+    """Full square P, p_ij = (p_{j|i} + p_{i|j}) / (2n), zero diagonal."""
+    x = _f64(x)
+    n, d = x.shape
+    out = np.empty((n, n), dtype=np.float64)
+    _load().orc_joint_p(x, n, d, _f64(st.beta), _f64(st.m), _f64(st.S), out)
+    return out
+
+
+def p_entries(x, ii, jj, st_i: RowStats, st_j: RowStats) -> np.ndarray:
+    """Entries p_{ii[k], jj[k]} from the statistics of their two rows."""
+    x = _f64(x)
+    n, d = x.shape
+    ii = np.ascontiguousarray(ii, dtype=np.int64)
+    jj = np.ascontiguousarray(jj, dtype=np.int64)
+    out = np.empty(ii.shape[0])
+    _load().orc_p_entries(x, n, d, ii, jj, ii.shape[0], _f64(st_i.beta), _f64(st_i.m),
+                          _f64(st_i.S), _f64(st_j.beta), _f64(st_j.m), _f64(st_j.S), out)
+    return out
+
+
+def p_entropy_term(P) -> float:
+    """sum_{p > 0} p ln p over i != j (the constant part of Eq. 5)."""
+    P = _f64(P)
+    return _load().orc_p_entropy_term(P, P.shape[0])
+
+
+# --------------------------------------------------------------------------
+# Output side: Z, gradient, cost, update (Eqs. 4-6, 9, 10)
+# --------------------------------------------------------------------------
+
+def z(y) -> float:
+    """Z = sum_{k != l} (1 + ||y_k - y_l||^2)^{-1} (denominator of Eq. 4)."""
+    y = _f64(y)
+    return _load().orc_z(y, y.shape[0])
+
+
+def gradient(P, y, alpha: float = 1.0):
+    """Eq. 6 with early exaggeration alpha on p_ij; returns (g, Z)."""
+    P, y = _f64(P), _f64(y)
+    g = np.empty_like(y)
+    zz = _d()
+    _load().orc_gradient(P, y.shape[0], y, float(alpha), g, ctypes.byref(zz))
+    return g, zz.value
+
+
+def repulsion_rows(y, rows, Z: float) -> np.ndarray:
+    """-4 sum_j w_ij^2 (y_i - y_j) / Z for the listed rows (Eq. 6 at alpha = 0)."""
+    y = _f64(y)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((rows.shape[0], 2))
+    _load().orc_repulsion_rows(y, y.shape[0], rows, rows.shape[0], float(Z), out)
+    return out
+
+
+def cost(P, y):
+    """(KL of Eq. 5, pseudo-normalised cost of Eq. 9) with the true P."""
+    P, y = _f64(P), _f64(y)
+    kl, cn = _d(), _d()
+    _load().orc_cost(P, y.shape[0], y, ctypes.byref(kl), ctypes.byref(cn))
+    return kl.value, cn.value
+
+
+@dataclass
+class StepParams:
+    alpha: float  # early exaggeration on p_ij
+    mu: float  # momentum
+    eta: float  # learning rate
+    min_gain: float = 0.01
+    recentre: bool = True
+
+
+def schedule(t: int, switch: int = 250, exaggeration: float = 12.0, eta: float = 200.0):
+    """Exaggeration 12 and momentum 0.5 before iteration ``switch``, then 1 and 0.8."""
+    early = t < switch
+    return StepParams(alpha=exaggeration if early else 1.0, mu=0.5 if early else 0.8, eta=eta)
+
+
+def step(P, y, u, gains, prm: StepParams, want_grad: bool = False):
+    """One update of (Y, U, G) in place (Eq. 10, descent reading, gains); returns (g, Z)."""
+    for a in (y, u, gains):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    n = y.shape[0]
+    g = np.empty_like(y) if want_grad else None
+    zz = _d()
+    _load().orc_step(_f64(P), n, y, u, gains, prm.alpha, prm.mu, prm.eta, prm.min_gain,
+                     int(prm.recentre),
+                     g.ctypes.data_as(ctypes.c_void_p) if g is not None else None,
+                     ctypes.cast(ctypes.pointer(zz), ctypes.c_void_p))
+    return g, zz.value
+
+
+def run(P, y0, iters: int, start: int = 0, state=None, sched=schedule):
+    """Run ``iters`` updates from Y0 (U = 0, G = 1) or from ``state`` = (Y, U, G)."""
+    if state is None:
+        y = _f64(y0).copy()
+        u = np.zeros_like(y)
+        gains = np.ones_like(y)
+    else:
+        y, u, gains = (np.array(a, dtype=np.float64) for a in state)
+    P = _f64(P)
+    for t in range(start, start + iters):
+        step(P, y, u, gains, sched(t))
+    return y, u, gains
+
+
+def knn_overlap(x, y, rows, k: int = 10) -> float:
+    """Mean |kNN_k in X  intersect  kNN_k in Y| / k over the query rows (ties: lower index)."""
+    x, y = _f64(x), _f64(y)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    return _load().orc_knn_overlap(x, x.shape[0], x.shape[1], y, rows, rows.shape[0], int(k))
