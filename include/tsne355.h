@@ -1,0 +1,146 @@
+/*
+ * tsne355 — exact t-SNE hot path on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libtsne355.so. The library computes the perplexity-calibrated
+ * input affinities P and runs the exact KL-gradient iteration of t-SNE as
+ * described in "bigMap: Big Data Mapping with parallelized t-SNE" (Garriga
+ * and Bartumeus, arXiv 1812.09869), section "ptSNE: parallelized t-SNE",
+ * Eqs. 1-6, 9 and 10. Output maps are 2-D.
+ *
+ * Conventions (all entry points):
+ *   - Array arguments are DEVICE pointers unless stated otherwise: dense,
+ *     row-major, FP32 unless stated otherwise. X is n x d, maps are n x 2.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL means the
+ *     default stream). Nothing is allocated: the caller owns all memory,
+ *     including the workspace `ws`, a device buffer of at least
+ *     tsne_workspace_bytes() bytes, 256-byte aligned.
+ *   - Arguments are validated on the host before any launch; a bad argument
+ *     returns an error code at once and launches nothing. Conditions found
+ *     on the device (non-finite values, a row whose bisection did not
+ *     converge, a workspace that does not hold affinities for this n) set a
+ *     flag word inside the workspace, returned by tsne_sync_status().
+ *   - Return values are tsne_status codes; tsne_last_error() gives a message
+ *     for the last failing call of the calling thread.
+ *   - Calls that share a workspace must be ordered on one stream; the
+ *     library keeps no other state.
+ */
+#ifndef TSNE355_H
+#define TSNE355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TSNE_API __attribute__((visibility("default")))
+#else
+#define TSNE_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSNE_OK = 0,
+  TSNE_E_ARG = 1,        /* null pointer, n < 2, d < 1, bad mode, bad range */
+  TSNE_E_PERPLEXITY = 2, /* perplexity not in (1, n - 1): Eq. 2 caps it at n - 1 */
+  TSNE_E_WORKSPACE = 3,  /* workspace too small or misaligned */
+  TSNE_E_DEVICE = 4,     /* a HIP runtime call failed */
+  TSNE_E_NONFINITE = 5,  /* device: non-finite input, Z, gradient or map */
+  TSNE_E_NOCONV = 6,     /* device: a row's bisection hit max_bisect */
+  TSNE_E_STATE = 7       /* device: workspace holds no affinities for this n */
+} tsne_status;
+
+/* Precision of the squared-distance contraction d = |x|^2 + |y|^2 - 2 x.y
+ * that feeds the affinities. All modes run on MFMA; the bisection and every
+ * reduction stay FP64/FP32 as documented below. */
+typedef enum {
+  TSNE_DIST_FP64 = 0,   /* FP64 MFMA on the centred input (default) */
+  TSNE_DIST_FP32 = 1,   /* FP32 MFMA */
+  TSNE_DIST_BF16 = 2,   /* BF16 operands, FP32 accumulate */
+  TSNE_DIST_BF16X3 = 3, /* BF16 hi/lo split, hi.hi + hi.lo + lo.hi, FP32 accumulate */
+  TSNE_DIST_FP16 = 4,   /* FP16 operands, FP32 accumulate */
+  TSNE_DIST_FP16X3 = 5  /* FP16 hi/lo split, three products, FP32 accumulate */
+} tsne_dist_mode;
+
+/* Options of the affinity stage. A NULL pointer selects the defaults
+ * {TSNE_DIST_FP64, 200, 1e-6}. */
+typedef struct {
+  int32_t dist_mode;  /* tsne_dist_mode */
+  int32_t max_bisect; /* bisection passes per row, >= 1 */
+  double tol_h;       /* stop when |H_i - ln(perplexity)| <= tol_h (nats), > 0 */
+} tsne_aff_opts;
+
+/* Parameters of one update (Eq. 10 and the paragraph after it). */
+typedef struct {
+  float exaggeration;  /* alpha: multiplies p_ij in the gradient (early exaggeration) */
+  float momentum;      /* mu */
+  float learning_rate; /* eta */
+  float min_gain;      /* floor of the adaptive gains */
+  int32_t recentre;    /* nonzero: subtract the mean of the map after the update */
+} tsne_step_params;
+
+/* Bytes of workspace for n points in d dimensions with the given distance
+ * mode; 0 if the arguments are out of range. Host-only, no device work. */
+TSNE_API size_t tsne_workspace_bytes(int64_t n, int32_t d, int32_t dist_mode);
+
+/*
+ * Input affinities (Eqs. 1-3). x: n x d FP32 (device). For every row i the
+ * precision beta_i of the Gaussian kernel is found by bisection so that the
+ * entropy of p_{.|i} equals ln(perplexity) (Eq. 2, in nats); then
+ * p_ij = (p_{j|i} + p_{i|j}) / (2n) is stored in the workspace (FP32, upper
+ * triangle, tile-packed). Self terms are zero. Errors: TSNE_E_ARG,
+ * TSNE_E_PERPLEXITY, TSNE_E_WORKSPACE, TSNE_E_DEVICE; device flags may set
+ * TSNE_E_NONFINITE (non-finite x) or TSNE_E_NOCONV.
+ */
+TSNE_API int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
+                    const tsne_aff_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One iteration of the exact gradient descent from state (y, u, g), each
+ * n x 2 FP32 on the device, updated in place:
+ *   grad_i = 4 sum_j (alpha p_ij - q_ij) w_ij (y_i - y_j),
+ *            w_ij = 1 / (1 + |y_i - y_j|^2), q_ij = w_ij / Z      (Eqs. 4, 6)
+ *   g <- (grad > 0) != (u > 0) ? g + 0.2 : 0.8 g;  g <- max(g, min_gain)
+ *   u <- momentum u - learning_rate g grad;  y <- y + u           (Eq. 10)
+ *   y <- y - mean(y) if recentre.
+ * grad_out (nullable, n x 2 FP32) receives the gradient; z_out (nullable,
+ * device double) receives Z. Requires a workspace filled by
+ * tsne_affinities for the same n. Z and all row sums are reduced in FP64 in
+ * a fixed order: repeated calls give bitwise identical results.
+ */
+TSNE_API int tsne_step(void *ws, int64_t n, float *y, float *u, float *g, const tsne_step_params *prm,
+              float *grad_out, double *z_out, void *stream);
+
+/* Gradient of Eq. 6 (with exaggeration alpha) at map y, without an update.
+ * grad_out: n x 2 FP32 (device, required); z_out nullable device double. */
+TSNE_API int tsne_gradient(void *ws, int64_t n, const float *y, float alpha, float *grad_out,
+                  double *z_out, void *stream);
+
+/* KL cost of Eq. 5 and the pseudo-normalised cost of Eq. 9 at map y, with
+ * the true P (no exaggeration). out: device double[2] = {KL, C_norm}. */
+TSNE_API int tsne_cost(void *ws, int64_t n, const float *y, double *out, void *stream);
+
+/* Synchronises the stream and returns the first device-side condition
+ * recorded in the workspace (TSNE_OK if none). Clears nothing. */
+TSNE_API int tsne_sync_status(void *ws, void *stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+TSNE_API const char *tsne_last_error(void);
+
+/* Test hooks. Row statistics of the calibration: beta (double), row minimum
+ * m of the squared distances (float), normaliser S = sum_j exp(-beta (d_ij -
+ * m)) (double), entropy H in nats (double), bisection passes (int32,
+ * negative if not converged). Any pointer may be NULL. */
+TSNE_API int tsne_export_rowstats(void *ws, int64_t n, double *beta, float *m, double *S, double *H,
+                         int32_t *evals, void *stream);
+
+/* Test hook: dense rows row0 .. row0 + nrows - 1 of P (nrows x n FP32). */
+TSNE_API int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *out,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSNE355_H */

@@ -1,0 +1,192 @@
+"""ctypes binding of libtsne355.so (argument marshalling only).
+
+Every function here takes torch CUDA tensors, checks shape/dtype/device,
+passes their device pointers and the current HIP stream to the C ABI of
+``include/tsne355.h`` and turns a non-zero status into ``TsneError``. No
+arithmetic of the method is done in Python; if the library is missing the
+call fails loudly instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsne355.so")
+
+TSNE_OK = 0
+STATUS = {
+    0: "TSNE_OK",
+    1: "TSNE_E_ARG",
+    2: "TSNE_E_PERPLEXITY",
+    3: "TSNE_E_WORKSPACE",
+    4: "TSNE_E_DEVICE",
+    5: "TSNE_E_NONFINITE",
+    6: "TSNE_E_NOCONV",
+    7: "TSNE_E_STATE",
+}
+DIST_MODES = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp16": 4, "fp16x3": 5}
+
+EXPORTED = [
+    "tsne_workspace_bytes",
+    "tsne_affinities",
+    "tsne_step",
+    "tsne_gradient",
+    "tsne_cost",
+    "tsne_sync_status",
+    "tsne_last_error",
+    "tsne_export_rowstats",
+    "tsne_export_p_rows",
+]
+
+
+class TsneError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class AffOpts(ctypes.Structure):
+    _fields_ = [("dist_mode", ctypes.c_int32), ("max_bisect", ctypes.c_int32),
+                ("tol_h", ctypes.c_double)]
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("exaggeration", ctypes.c_float), ("momentum", ctypes.c_float),
+                ("learning_rate", ctypes.c_float), ("min_gain", ctypes.c_float),
+                ("recentre", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_1812_09869_amd.build` "
+            "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    sigs = {
+        "tsne_workspace_bytes": (ctypes.c_size_t, [_i64, _i32, _i32]),
+        "tsne_affinities": (ctypes.c_int, [_vp, _i64, _i32, ctypes.c_double,
+                                           ctypes.POINTER(AffOpts), _vp, ctypes.c_size_t, _vp]),
+        "tsne_step": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, ctypes.POINTER(StepParams), _vp,
+                                     _vp, _vp]),
+        "tsne_gradient": (ctypes.c_int, [_vp, _i64, _vp, ctypes.c_float, _vp, _vp, _vp]),
+        "tsne_cost": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp]),
+        "tsne_sync_status": (ctypes.c_int, [_vp, _vp]),
+        "tsne_last_error": (ctypes.c_char_p, []),
+        "tsne_export_rowstats": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "tsne_export_p_rows": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != TSNE_OK:
+        raise TsneError(rc, load().tsne_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=torch.float32, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(n: int, d: int, dist_mode: str | int = "fp64") -> int:
+    mode = DIST_MODES[dist_mode] if isinstance(dist_mode, str) else int(dist_mode)
+    return int(load().tsne_workspace_bytes(n, d, mode))
+
+
+def new_workspace(n: int, d: int, dist_mode: str | int = "fp64", device="cuda") -> torch.Tensor:
+    nbytes = workspace_bytes(n, d, dist_mode)
+    if nbytes == 0:
+        raise TsneError(1, f"no workspace size for n={n}, d={d}, mode={dist_mode}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def affinities(x: torch.Tensor, perplexity: float, ws: torch.Tensor, dist_mode="fp64",
+               max_bisect: int = 200, tol_h: float = 1e-6):
+    n, d = x.shape
+    mode = DIST_MODES[dist_mode] if isinstance(dist_mode, str) else int(dist_mode)
+    opts = AffOpts(mode, max_bisect, tol_h)
+    _check(load().tsne_affinities(_ptr(x, name="x"), n, d, float(perplexity),
+                                  ctypes.byref(opts), _ptr(ws, torch.uint8, name="ws"),
+                                  ws.numel(), _stream()))
+
+
+def step(ws, n, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True,
+         grad_out=None, z_out=None):
+    prm = StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0)
+    sh = (n, 2)
+    _check(load().tsne_step(_ptr(ws, torch.uint8, name="ws"), n, _ptr(y, shape=sh, name="y"),
+                            _ptr(u, shape=sh, name="u"), _ptr(g, shape=sh, name="g"),
+                            ctypes.byref(prm), _ptr(grad_out, shape=sh, name="grad_out"),
+                            _ptr(z_out, torch.float64, name="z_out"), _stream()))
+
+
+def gradient(ws, n, y, alpha, grad_out, z_out=None):
+    sh = (n, 2)
+    _check(load().tsne_gradient(_ptr(ws, torch.uint8, name="ws"), n, _ptr(y, shape=sh, name="y"),
+                                float(alpha), _ptr(grad_out, shape=sh, name="grad_out"),
+                                _ptr(z_out, torch.float64, name="z_out"), _stream()))
+
+
+def cost(ws, n, y, out):
+    _check(load().tsne_cost(_ptr(ws, torch.uint8, name="ws"), n, _ptr(y, shape=(n, 2), name="y"),
+                            _ptr(out, torch.float64, shape=(2,), name="out"), _stream()))
+
+
+def sync_status(ws) -> int:
+    """Synchronise and return the device status code (0 = OK), without raising."""
+    return int(load().tsne_sync_status(_ptr(ws, torch.uint8, name="ws"), _stream()))
+
+
+def check_status(ws):
+    _check(sync_status(ws))
+
+
+def export_rowstats(ws, n):
+    dev = ws.device
+    beta = torch.empty(n, dtype=torch.float64, device=dev)
+    m = torch.empty(n, dtype=torch.float32, device=dev)
+    S = torch.empty(n, dtype=torch.float64, device=dev)
+    H = torch.empty(n, dtype=torch.float64, device=dev)
+    ev = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(load().tsne_export_rowstats(_ptr(ws, torch.uint8, name="ws"), n,
+                                       _ptr(beta, torch.float64), _ptr(m), _ptr(S, torch.float64),
+                                       _ptr(H, torch.float64), _ptr(ev, torch.int32), _stream()))
+    return beta, m, S, H, ev
+
+
+def export_p_rows(ws, n, row0, nrows):
+    out = torch.empty((nrows, n), dtype=torch.float32, device=ws.device)
+    _check(load().tsne_export_p_rows(_ptr(ws, torch.uint8, name="ws"), n, row0, nrows, _ptr(out),
+                                     _stream()))
+    return out

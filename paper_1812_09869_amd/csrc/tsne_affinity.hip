@@ -1,0 +1,556 @@
+// Input affinities P on the GPU (section "Similarities in the input space",
+// Eqs. 1-3 of the bigMap paper):
+//   1. centre X (distances are translation invariant) and form row norms;
+//   2. per block of T rows: squared distances to all points on MFMA
+//      (d_ij = |x_i|^2 + |x_j|^2 - 2 x_i.x_j), a per-row bisection on the
+//      Gaussian precision beta_i so that the entropy of p_{.|i} equals
+//      ln(perplexity), and a copy of the block's upper-triangle tiles into
+//      the P store;
+//   3. in place over the stored tiles: p_ij = (p_{j|i} + p_{i|j}) / (2n).
+#include <float.h>
+#include <math.h>
+
+#include "tsne_internal.h"
+
+namespace tsne {
+
+namespace {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr float kBig = 3.0e38f;  // stands for an excluded entry (self pair)
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline void flag_error(Hdr *h, uint32_t bit) { atomicOr(&h->err, bit); }
+
+// ----------------------------------------------------------------------------
+// Wave / block reductions (fixed order, hence deterministic)
+// ----------------------------------------------------------------------------
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline float wave_min_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ----------------------------------------------------------------------------
+// 0. Header
+// ----------------------------------------------------------------------------
+__global__ void k_init_hdr(Hdr *h, int64_t n, int32_t d, int32_t mode, double perplexity) {
+  if (threadIdx.x == 0) {
+    h->magic = kMagic;
+    h->n = n;
+    h->d = d;
+    h->ready = 0;
+    h->err = 0;
+    h->mode = mode;
+    h->perplexity = perplexity;
+    h->z = 0.0;
+    h->c_p = 0.0;
+    h->p_sum = 0.0;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 1. Column means (FP64) and centred, transposed X with FP64 row norms
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_colmean(const float *__restrict__ x, int64_t n, int32_t d,
+                                                 double *__restrict__ mean) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)x[i * d + k];
+  s = wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) mean[k] = (red[0] + red[1] + red[2] + red[3]) / (double)n;
+}
+
+__global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int64_t n, int32_t d,
+                                                int64_t npad, int32_t dpad,
+                                                const double *__restrict__ mean,
+                                                double *__restrict__ xcT,
+                                                double *__restrict__ norms, Hdr *h) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npad) return;
+  double nrm = 0.0;
+  bool bad = false;
+  for (int k = 0; k < dpad; ++k) {
+    double v = 0.0;
+    if (i < n && k < d) {
+      float xv = x[i * d + k];
+      bad |= !isfinite(xv);
+      v = (double)xv - mean[k];
+    }
+    xcT[(int64_t)k * npad + i] = v;
+    nrm += v * v;
+  }
+  norms[i] = nrm;
+  if (bad) flag_error(h, kErrNonFinite);
+}
+
+// ----------------------------------------------------------------------------
+// 2a. Distance block on FP64 MFMA: rows b*T .. b*T+T-1 against all columns.
+//
+// v_mfma_f64_16x16x4f64 computes a 16x16 block of A(16x4) B(4x16). Lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] and receives D[l/16 + 4r][l%16]
+// in accumulator element r (rows interleaved by 4, unlike the FP32/BF16
+// 16x16 variants, whose element r holds row 4(l/16) + r). X is stored transposed (k-major), so the 16
+// lanes that share a k read 16 consecutive doubles. A wave computes a
+// 64 x 64 block (4 x 4 MFMA tiles); a workgroup of 4 waves covers 64 rows x
+// 256 columns.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
+                                                  const double *__restrict__ norms, int64_t npad,
+                                                  int32_t dpad, int32_t b,
+                                                  float *__restrict__ dblock) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  const int row0_loc = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)b * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < dpad; k0 += 4) {
+    const double *xk = xcT + (int64_t)(k0 + lk) * npad;
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = xk[row0 + a * 16 + li];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[c] = xk[col0 + c * 16 + li];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + a * 16 + lk + 4 * r;
+      const double ni = norms[(int64_t)b * T + il];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t j = col0 + c * 16 + li;
+        double dd = ni + norms[j] - 2.0 * acc[a][c][r];
+        dblock[(int64_t)il * npad + j] = (float)fmax(dd, 0.0);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 2b. Per-row bisection on beta (Eqs. 1-2).
+//
+// One workgroup of 1024 threads per row. The row's distances, shifted by the
+// row minimum m, are held in registers (VPT per thread) when they fit, else
+// re-read from the block scratch on every pass. Each pass forms, with FP32
+// exponentials and FP32 per-thread partial sums combined in FP64,
+//   S = sum_j exp(-beta (d_j - m)),  T = sum_j (d_j - m) exp(-beta (d_j - m)),
+//   H = ln S + beta T / S,
+// where beta is the FP32-rounded precision actually applied. Bracket logic:
+// start at beta = 1 with [0, inf); a too-high entropy doubles beta until an
+// upper end exists, then each pass halves the bracket. Stops at
+// |H - ln u| <= tol_h, at a bracket narrower than FP32 resolution, or after
+// max_bisect passes (then the row is flagged as not converged).
+// ----------------------------------------------------------------------------
+constexpr int kCalThreads = 1024;
+
+struct CalOut {
+  double *beta, *S, *H;
+  float *m, *a, *r;
+  int32_t *evals;
+};
+
+template <int VPT>
+__global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restrict__ dblock,
+                                                           int64_t n, int64_t npad, int32_t b,
+                                                           double logu, int max_bisect,
+                                                           double tol_h, CalOut out, Hdr *h) {
+  __shared__ double sred[2][kCalThreads / 64];
+  __shared__ float smin[kCalThreads / 64];
+  __shared__ double sbeta;
+  __shared__ int sdone;
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int64_t i = (int64_t)b * T + blockIdx.x;
+  if (i >= n) return;
+  const float *row = dblock + (int64_t)blockIdx.x * npad;
+
+  // row minimum over j != i, j < n
+  float mn = INFINITY;
+  float v[VPT > 0 ? VPT : 1];
+  if constexpr (VPT > 0) {
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      int64_t j = (int64_t)q * kCalThreads + tid;
+      float dv = (j < n && j != i) ? row[j] : INFINITY;
+      v[q] = dv;
+      mn = fminf(mn, dv);
+    }
+  } else {
+    for (int64_t j = tid; j < n; j += kCalThreads)
+      if (j != i) mn = fminf(mn, row[j]);
+  }
+  mn = wave_min_f(mn);
+  if (ln == 0) smin[wv] = mn;
+  __syncthreads();
+  float m = smin[0];
+#pragma unroll
+  for (int q = 1; q < kCalThreads / 64; ++q) m = fminf(m, smin[q]);
+  if constexpr (VPT > 0) {
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) v[q] = (v[q] == INFINITY) ? kBig : v[q] - m;
+  }
+
+  double beta = 1.0, lo = 0.0, hi = INFINITY, S = 0.0, H = 0.0;
+  float a = 0.f;
+  int it = 0;
+  bool ok = false;
+  for (;;) {
+    ++it;
+    a = fmaxf((float)(beta * kLog2e), 1e-30f);
+    float s = 0.f, tt = 0.f;
+    if constexpr (VPT > 0) {
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) {
+        float e = __builtin_amdgcn_exp2f(-a * v[q]);
+        s += e;
+        tt = fmaf(v[q], e, tt);
+      }
+    } else {
+      for (int64_t j = tid; j < n; j += kCalThreads) {
+        float dm = (j == i) ? kBig : row[j] - m;
+        float e = __builtin_amdgcn_exp2f(-a * dm);
+        s += e;
+        tt = fmaf(dm, e, tt);
+      }
+    }
+    double ds = wave_sum_d((double)s), dt = wave_sum_d((double)tt);
+    if (ln == 0) {
+      sred[0][wv] = ds;
+      sred[1][wv] = dt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double SS = 0.0, TT = 0.0;
+      for (int q = 0; q < kCalThreads / 64; ++q) {
+        SS += sred[0][q];
+        TT += sred[1][q];
+      }
+      const double beff = (double)a * kLn2;
+      S = SS;
+      H = log(SS) + beff * TT / SS;
+      int done = 0;
+      if (fabs(H - logu) <= tol_h) {
+        done = 1;
+      } else if (isfinite(hi) && (hi - lo) <= hi * 0x1p-24) {
+        done = 1;
+      } else if (it >= max_bisect) {
+        done = 2;
+      } else if (H > logu) {
+        lo = beta;
+        beta = isinf(hi) ? 2.0 * beta : 0.5 * (beta + hi);
+      } else {
+        hi = beta;
+        beta = 0.5 * (lo + beta);
+      }
+      sbeta = beta;
+      sdone = done;
+      ok = (done == 1);
+    }
+    __syncthreads();
+    if (sdone) break;
+    beta = sbeta;
+  }
+  if (tid == 0) {
+    const double beff = (double)a * kLn2;
+    out.beta[i] = beff;
+    out.S[i] = S;
+    out.H[i] = H;
+    out.m[i] = m;
+    out.a[i] = a;
+    out.r[i] = (float)(1.0 / (2.0 * (double)n * S));
+    out.evals[i] = ok ? it : -it;
+    if (!ok) flag_error(h, kErrNoConv);
+    if (!isfinite(H) || !isfinite(S)) flag_error(h, kErrNonFinite);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 2c. Copy the block's tiles (b, J >= b) into the P store in consumer order.
+// The diagonal tile holds both orders of each pair; both take the distance
+// of the upper element so that the stored P is exactly symmetric.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock, int64_t npad,
+                                               int32_t nb, int32_t b, float4 *__restrict__ P) {
+  const int J = b + blockIdx.x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int tc = l & 15, tr = (l >> 4) + 4 * w;
+  float4 *dst = P + (size_t)tile_start(b, nb) * TT4 + (size_t)blockIdx.x * TT4;
+  const float *src = dblock + (int64_t)J * T;
+  if (J != b) {
+#pragma unroll 4
+    for (int s = 0; s < 64; ++s) {
+      const int k = s >> 2, mq = s & 3;
+      const float *rp = src + (int64_t)(tr + 16 * k) * npad + tc + 64 * mq;
+      dst[s * 256 + t] = make_float4(rp[0], rp[16], rp[32], rp[48]);
+    }
+  } else {
+    for (int s = 0; s < 64; ++s) {
+      const int k = s >> 2, mq = s & 3;
+      const int il = tr + 16 * k;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int jl = tc + 16 * (4 * mq + e);
+        const int lo = il < jl ? il : jl, hi = il < jl ? jl : il;
+        v[e] = src[(int64_t)lo * npad + hi];
+      }
+      dst[s * 256 + t] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 3. Symmetrise and normalise in place (Eq. 3):
+//    p_ij = exp2(-a_i (d - m_i)) r_i + exp2(-a_j (d - m_j)) r_j,  r = 1/(2 n S).
+// Also per tile: sum p and sum p ln p over ordered pairs (off-diagonal tiles
+// stand for both (i, j) and (j, i)).
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const float *__restrict__ a,
+                                              const float *__restrict__ m,
+                                              const float *__restrict__ r, int64_t n, int32_t nb,
+                                              double2 *__restrict__ ppart) {
+  __shared__ double red[2][4];
+  int I, J;
+  tile_coords(blockIdx.x, nb, I, J);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int tc = l & 15, tr = (l >> 4) + 4 * w;
+  const bool diag = (I == J);
+  float ar[16], mr[16], rr[16], ac[16], mc[16], rc[16];
+  uint32_t rvalid = 0, cvalid = 0;  // bit k: row tr+16k (column tc+16k) is a real point
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    int64_t i = (int64_t)I * T + tr + 16 * k;
+    bool ok = i < n;
+    rvalid |= ok ? (1u << k) : 0u;
+    ar[k] = ok ? a[i] : 0.f;
+    mr[k] = ok ? m[i] : 0.f;
+    rr[k] = ok ? r[i] : 0.f;
+    int64_t j = (int64_t)J * T + tc + 16 * k;
+    ok = j < n;
+    cvalid |= ok ? (1u << k) : 0u;
+    ac[k] = ok ? a[j] : 0.f;
+    mc[k] = ok ? m[j] : 0.f;
+    rc[k] = ok ? r[j] : 0.f;
+  }
+  float4 *tp = P + (size_t)blockIdx.x * TT4;
+  float psum = 0.f, plp = 0.f;
+#pragma unroll 2
+  for (int s = 0; s < 64; ++s) {
+    const int k = s >> 2, mq = s & 3;
+    float4 dv = tp[s * 256 + t];
+    float dd[4] = {dv.x, dv.y, dv.z, dv.w};
+    float pv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma clang fp contract(off)
+      const int mm = 4 * mq + e;
+      // no contraction into an FMA here (pragma above), so that the two
+      // orders of a pair in a diagonal tile give bitwise equal sums
+      float pi = __builtin_amdgcn_exp2f(-ar[k] * (dd[e] - mr[k])) * rr[k];
+      float pj = __builtin_amdgcn_exp2f(-ac[mm] * (dd[e] - mc[mm])) * rc[mm];
+      float p = pi + pj;
+      if (diag && tr == tc && k == mm) p = 0.f;
+      if (!((rvalid >> k) & (cvalid >> mm) & 1u)) p = 0.f;
+      pv[e] = p;
+      psum += p;
+      // denormal p (< FLT_MIN) contribute below 1e-36 and are skipped: the
+      // hardware log flushes them to zero
+      plp += (p >= FLT_MIN) ? p * __builtin_amdgcn_logf(p) : 0.f;
+    }
+    tp[s * 256 + t] = make_float4(pv[0], pv[1], pv[2], pv[3]);
+  }
+  double ds = wave_sum_d((double)psum), dl = wave_sum_d((double)plp);
+  if (l == 0) {
+    red[0][w] = ds;
+    red[1][w] = dl;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double mult = diag ? 1.0 : 2.0;
+    double S = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    double Lg = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    ppart[blockIdx.x] = make_double2(mult * S, mult * Lg * kLn2);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_pack_reduce(const double2 *__restrict__ ppart,
+                                                      int64_t nt, Hdr *h) {
+  __shared__ double red[2][16];
+  double s = 0.0, lg = 0.0;
+  for (int64_t q = threadIdx.x; q < nt; q += 1024) {
+    s += ppart[q].x;
+    lg += ppart[q].y;
+  }
+  s = wave_sum_d(s);
+  lg = wave_sum_d(lg);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s;
+    red[1][threadIdx.x >> 6] = lg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0, Lg = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      S += red[0][q];
+      Lg += red[1][q];
+    }
+    h->p_sum = S;
+    h->c_p = Lg;
+    if (!isfinite(S) || !isfinite(Lg)) atomicOr(&h->err, kErrNonFinite);
+    h->ready = 1;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Exports (test hooks)
+// ----------------------------------------------------------------------------
+__device__ inline bool state_ok(const Hdr *h, int64_t n) {
+  return h->magic == kMagic && h->n == n && h->ready == 1;
+}
+
+__global__ __launch_bounds__(256) void k_export_rows(const float4 *__restrict__ P, int64_t n,
+                                                     int32_t nb, int64_t row0, int64_t nrows,
+                                                     float *__restrict__ out, Hdr *h) {
+  if (!state_ok(h, n)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    return;
+  }
+  // one thread per output element (row rr, column j)
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nrows * n) return;
+  const int64_t rr = idx / n, j = idx % n;
+  int64_t i = row0 + rr, jj = j;
+  if (i / T > jj / T) {  // lower triangle: read the mirrored entry
+    int64_t tmp = i;
+    i = jj;
+    jj = tmp;
+  }
+  const int I = (int)(i / T), J = (int)(jj / T);
+  const int il = (int)(i % T), jl = (int)(jj % T);
+  const int tr = il & 15, k = il >> 4, tc = jl & 15, mmi = jl >> 4;
+  const int mq = mmi >> 2, e = mmi & 3;
+  const int th = (tr >> 2) * 64 + (tr & 3) * 16 + tc;
+  const int s = k * 4 + mq;
+  const float *tile = reinterpret_cast<const float *>(P + (size_t)tile_start(I, nb) * TT4 +
+                                                      (size_t)(J - I) * TT4);
+  out[idx] = tile[((size_t)s * 256 + th) * 4 + e];
+}
+
+__global__ void k_export_stats(int64_t n, const double *__restrict__ beta,
+                               const float *__restrict__ m, const double *__restrict__ S,
+                               const double *__restrict__ H, const int32_t *__restrict__ ev,
+                               double *ob, float *om, double *oS, double *oH, int32_t *oe,
+                               Hdr *h) {
+  if (!(h->magic == kMagic && h->n == n)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    return;
+  }
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (ob) ob[i] = beta[i];
+  if (om) om[i] = m[i];
+  if (oS) oS[i] = S[i];
+  if (oH) oH[i] = H[i];
+  if (oe) oe[i] = ev[i];
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Host-side sequencing
+// ----------------------------------------------------------------------------
+hipError_t launch_affinities(const Layout &L, const float *x, double perplexity, int max_bisect,
+                             double tol_h, void *ws, hipStream_t st) {
+  Hdr *h = at<Hdr>(ws, L.hdr);
+  hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(64), 0, st, h, L.n, L.d, L.mode, perplexity);
+  double *mean = at<double>(ws, L.xmean);
+  double *xcT = at<double>(ws, L.xcT);
+  double *norms = at<double>(ws, L.norms);
+  float *dblock = at<float>(ws, L.dblock);
+  float4 *P = at<float4>(ws, L.P);
+  hipLaunchKernelGGL(k_colmean, dim3(L.d), dim3(256), 0, st, x, L.n, L.d, mean);
+  hipLaunchKernelGGL(k_centre, dim3((unsigned)((L.npad + 255) / 256)), dim3(256), 0, st, x, L.n,
+                     L.d, L.npad, L.dpad, mean, xcT, norms, h);
+  CalOut co{at<double>(ws, L.beta), at<double>(ws, L.S), at<double>(ws, L.H),
+            at<float>(ws, L.m),     at<float>(ws, L.a),  at<float>(ws, L.r),
+            at<int32_t>(ws, L.evals)};
+  const double logu = log(perplexity);
+  const int64_t vpt_need = (L.n + kCalThreads - 1) / kCalThreads;
+  for (int b = 0; b < L.nb; ++b) {
+    hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / 256), T / 64), dim3(256), 0, st, xcT,
+                       norms, L.npad, L.dpad, b, dblock);
+    const int rows = (int)((L.n - (int64_t)b * T) < T ? (L.n - (int64_t)b * T) : T);
+    dim3 g(rows), blk(kCalThreads);
+    if (vpt_need <= 1)
+      hipLaunchKernelGGL(k_calibrate<1>, g, blk, 0, st, dblock, L.n, L.npad, b, logu, max_bisect,
+                         tol_h, co, h);
+    else if (vpt_need <= 2)
+      hipLaunchKernelGGL(k_calibrate<2>, g, blk, 0, st, dblock, L.n, L.npad, b, logu, max_bisect,
+                         tol_h, co, h);
+    else if (vpt_need <= 4)
+      hipLaunchKernelGGL(k_calibrate<4>, g, blk, 0, st, dblock, L.n, L.npad, b, logu, max_bisect,
+                         tol_h, co, h);
+    else if (vpt_need <= 8)
+      hipLaunchKernelGGL(k_calibrate<8>, g, blk, 0, st, dblock, L.n, L.npad, b, logu, max_bisect,
+                         tol_h, co, h);
+    else if (vpt_need <= 16)
+      hipLaunchKernelGGL(k_calibrate<16>, g, blk, 0, st, dblock, L.n, L.npad, b, logu,
+                         max_bisect, tol_h, co, h);
+    else if (vpt_need <= 32)
+      hipLaunchKernelGGL(k_calibrate<32>, g, blk, 0, st, dblock, L.n, L.npad, b, logu,
+                         max_bisect, tol_h, co, h);
+    else if (vpt_need <= 64)
+      hipLaunchKernelGGL(k_calibrate<64>, g, blk, 0, st, dblock, L.n, L.npad, b, logu,
+                         max_bisect, tol_h, co, h);
+    else
+      hipLaunchKernelGGL(k_calibrate<0>, g, blk, 0, st, dblock, L.n, L.npad, b, logu, max_bisect,
+                         tol_h, co, h);
+    hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
+  }
+  double2 *ppart = at<double2>(ws, L.ppart);
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)L.nt), dim3(256), 0, st, P, co.a, co.m, co.r, L.n,
+                     L.nb, ppart);
+  hipLaunchKernelGGL(k_pack_reduce, dim3(1), dim3(1024), 0, st, ppart, L.nt, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_p_rows(const Layout &L, void *ws, int64_t row0, int64_t nrows,
+                                float *out, hipStream_t st) {
+  const int64_t total = nrows * L.n;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     at<const float4>(ws, L.P), L.n, L.nb, row0, nrows, out, at<Hdr>(ws, L.hdr));
+  return hipGetLastError();
+}
+
+hipError_t launch_export_rowstats(const Layout &L, void *ws, double *beta, float *m, double *S,
+                                  double *H, int32_t *evals, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_stats, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, L.n,
+                     at<const double>(ws, L.beta), at<const float>(ws, L.m),
+                     at<const double>(ws, L.S), at<const double>(ws, L.H),
+                     at<const int32_t>(ws, L.evals), beta, m, S, H, evals, at<Hdr>(ws, L.hdr));
+  return hipGetLastError();
+}
+
+}  // namespace tsne

@@ -1,0 +1,193 @@
+// C ABI of libtsne355: argument validation, workspace layout and launch
+// sequencing. Device work lives in tsne_affinity.hip and tsne_iterate.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/tsne355.h"
+#include "tsne_internal.h"
+
+namespace tsne {
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+Layout make_layout(int64_t n, int32_t d, int32_t mode) {
+  Layout L;
+  L.n = n;
+  L.d = d;
+  L.mode = mode;
+  L.nb = (int32_t)((n + T - 1) / T);
+  L.npad = (int64_t)L.nb * T;
+  L.nt = (int64_t)L.nb * (L.nb + 1) / 2;
+  L.dpad = (d + 3) / 4 * 4;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  const size_t np = (size_t)L.npad;
+  L.hdr = take(256);
+  L.beta = take(np * 8);
+  L.S = take(np * 8);
+  L.H = take(np * 8);
+  L.m = take(np * 4);
+  L.a = take(np * 4);
+  L.r = take(np * 4);
+  L.evals = take(np * 4);
+  L.P = take((size_t)L.nt * T * T * 4);
+  L.part = take((size_t)L.nb * L.nb * T * 16);
+  L.zpart = take((size_t)L.nt * 8);
+  L.cpart = take((size_t)L.nt * 16);
+  L.ppart = take((size_t)L.nt * 16);
+  L.meanpart = take((size_t)L.nb * 16);
+  L.iter_end = o;
+  // affinity-stage scratch (only needed inside tsne_affinities)
+  L.xmean = take((size_t)L.dpad * 8);
+  L.xcT = take((size_t)L.dpad * np * 8);
+  L.norms = take(np * 8);
+  L.dblock = take((size_t)T * np * 4);
+  L.total = o;
+  return L;
+}
+
+}  // namespace tsne
+
+using tsne::Layout;
+
+static thread_local char g_err[512];
+
+static int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+static int ok() {
+  g_err[0] = '\0';
+  return TSNE_OK;
+}
+
+static int hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) return fail(TSNE_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+static bool valid_n(int64_t n) { return n >= 2 && n <= (int64_t)1 << 30; }
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+extern "C" {
+
+size_t tsne_workspace_bytes(int64_t n, int32_t d, int32_t dist_mode) {
+  if (!valid_n(n) || d < 1 || d > 65536 || dist_mode != TSNE_DIST_FP64) return 0;
+  return tsne::make_layout(n, d, dist_mode).total;
+}
+
+int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
+                    const tsne_aff_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  tsne_aff_opts o = {TSNE_DIST_FP64, 200, 1e-6};
+  if (opts) o = *opts;
+  if (!x || !ws) return fail(TSNE_E_ARG, "tsne_affinities: null pointer");
+  if (!valid_n(n)) return fail(TSNE_E_ARG, "tsne_affinities: n = %lld out of range", (long long)n);
+  if (d < 1 || d > 65536) return fail(TSNE_E_ARG, "tsne_affinities: d = %d out of range", d);
+  if (o.dist_mode != TSNE_DIST_FP64)
+    return fail(TSNE_E_ARG, "tsne_affinities: distance mode %d not available", o.dist_mode);
+  if (o.max_bisect < 1 || !(o.tol_h > 0.0))
+    return fail(TSNE_E_ARG, "tsne_affinities: max_bisect >= 1 and tol_h > 0 required");
+  if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))
+    return fail(TSNE_E_PERPLEXITY, "tsne_affinities: perplexity %g not in (1, n-1 = %lld)",
+                perplexity, (long long)(n - 1));
+  if (!aligned(ws, 256)) return fail(TSNE_E_WORKSPACE, "tsne_affinities: ws not 256-byte aligned");
+  const Layout L = tsne::make_layout(n, d, o.dist_mode);
+  if (ws_bytes < L.total)
+    return fail(TSNE_E_WORKSPACE, "tsne_affinities: workspace %zu bytes, need %zu", ws_bytes,
+                L.total);
+  return hip_check(tsne::launch_affinities(L, x, perplexity, o.max_bisect, o.tol_h, ws,
+                                           (hipStream_t)stream),
+                   "tsne_affinities");
+}
+
+static int check_iter_args(const char *fn, void *ws, int64_t n) {
+  if (!ws) return fail(TSNE_E_ARG, "%s: null workspace", fn);
+  if (!valid_n(n)) return fail(TSNE_E_ARG, "%s: n = %lld out of range", fn, (long long)n);
+  if (!aligned(ws, 256)) return fail(TSNE_E_WORKSPACE, "%s: ws not 256-byte aligned", fn);
+  return TSNE_OK;
+}
+
+int tsne_step(void *ws, int64_t n, float *y, float *u, float *g, const tsne_step_params *prm,
+              float *grad_out, double *z_out, void *stream) {
+  if (int rc = check_iter_args("tsne_step", ws, n)) return rc;
+  if (!y || !u || !g || !prm) return fail(TSNE_E_ARG, "tsne_step: null pointer");
+  if (!(prm->learning_rate >= 0.f) || !(prm->min_gain >= 0.f) || !isfinite(prm->momentum) ||
+      !isfinite(prm->exaggeration))
+    return fail(TSNE_E_ARG, "tsne_step: invalid parameters");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = tsne::launch_force(L, ws, y, st);
+  if (e == hipSuccess)
+    e = tsne::launch_update(L, ws, y, u, g, prm->exaggeration, prm->momentum, prm->learning_rate,
+                            prm->min_gain, prm->recentre, grad_out, z_out, st);
+  return hip_check(e, "tsne_step");
+}
+
+int tsne_gradient(void *ws, int64_t n, const float *y, float alpha, float *grad_out,
+                  double *z_out, void *stream) {
+  if (int rc = check_iter_args("tsne_gradient", ws, n)) return rc;
+  if (!y || !grad_out) return fail(TSNE_E_ARG, "tsne_gradient: null pointer");
+  if (!isfinite(alpha)) return fail(TSNE_E_ARG, "tsne_gradient: non-finite alpha");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = tsne::launch_force(L, ws, y, st);
+  if (e == hipSuccess) e = tsne::launch_gradient_only(L, ws, alpha, grad_out, z_out, st);
+  return hip_check(e, "tsne_gradient");
+}
+
+int tsne_cost(void *ws, int64_t n, const float *y, double *out, void *stream) {
+  if (int rc = check_iter_args("tsne_cost", ws, n)) return rc;
+  if (!y || !out) return fail(TSNE_E_ARG, "tsne_cost: null pointer");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  return hip_check(tsne::launch_cost(L, ws, y, out, (hipStream_t)stream), "tsne_cost");
+}
+
+int tsne_sync_status(void *ws, void *stream) {
+  if (!ws) return fail(TSNE_E_ARG, "tsne_sync_status: null workspace");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_check(e, "tsne_sync_status: synchronize");
+  tsne::Hdr h;
+  e = hipMemcpy(&h, ws, sizeof h, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_check(e, "tsne_sync_status: copy");
+  if (h.err & tsne::kErrState)
+    return fail(TSNE_E_STATE, "workspace holds no affinities for this n");
+  if (h.err & tsne::kErrNonFinite) return fail(TSNE_E_NONFINITE, "non-finite value on device");
+  if (h.err & tsne::kErrNoConv)
+    return fail(TSNE_E_NOCONV, "a row's bisection stopped at max_bisect");
+  return ok();
+}
+
+const char *tsne_last_error(void) { return g_err; }
+
+int tsne_export_rowstats(void *ws, int64_t n, double *beta, float *m, double *S, double *H,
+                         int32_t *evals, void *stream) {
+  if (int rc = check_iter_args("tsne_export_rowstats", ws, n)) return rc;
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  return hip_check(tsne::launch_export_rowstats(L, ws, beta, m, S, H, evals, (hipStream_t)stream),
+                   "tsne_export_rowstats");
+}
+
+int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *out,
+                       void *stream) {
+  if (int rc = check_iter_args("tsne_export_p_rows", ws, n)) return rc;
+  if (!out) return fail(TSNE_E_ARG, "tsne_export_p_rows: null pointer");
+  if (row0 < 0 || nrows < 0 || row0 + nrows > n)
+    return fail(TSNE_E_ARG, "tsne_export_p_rows: rows out of range");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  return hip_check(tsne::launch_export_p_rows(L, ws, row0, nrows, out, (hipStream_t)stream),
+                   "tsne_export_p_rows");
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal definitions shared by the HIP translation units of libtsne355:
+// workspace layout, tile geometry, device helpers and launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tsne {
+
+// ---------------------------------------------------------------------------
+// Tile geometry
+//
+// The n x n pair matrix is cut into T x T tiles; only tiles (I, J) with I <= J
+// are stored ("upper triangle"), enumerated row by row. Inside a tile the
+// 256 threads of a workgroup are laid out as a 16 x 16 grid (tr, tc): thread
+// t = 64 w + l (wave w, lane l) has tc = l % 16, tr = l / 16 + 4 w, and owns
+// rows tr + 16 k and columns tc + 16 m (k, m in 0..15). P is stored in the
+// order in which these threads consume it: float4 number s * 256 + t of a
+// tile holds the pairs (row tr + 16 (s / 4), column tc + 16 (4 (s % 4) + e)),
+// e = 0..3, so every wave-wide float4 load is one contiguous 1 KiB segment.
+// ---------------------------------------------------------------------------
+constexpr int T = 256;             // tile edge
+constexpr int TT4 = T * T / 4;     // float4 per tile
+constexpr int kThreads = 256;      // threads per tile workgroup
+constexpr uint64_t kMagic = 0x74534E4533353501ull;
+
+// Error bits of the device flag word.
+constexpr uint32_t kErrNonFinite = 1u;
+constexpr uint32_t kErrNoConv = 2u;
+constexpr uint32_t kErrState = 4u;
+
+// Header at the start of the workspace (device memory).
+struct Hdr {
+  uint64_t magic;
+  int64_t n;
+  int32_t d;
+  int32_t ready;
+  uint32_t err;
+  int32_t mode;
+  double perplexity;
+  double z;        // Z of the last force pass
+  double c_p;      // sum_{i != j} p_ij ln p_ij
+  double p_sum;    // sum_{i != j} p_ij
+  double pad[8];
+};
+static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
+
+struct Layout {
+  int64_t n = 0, npad = 0, nt = 0;
+  int32_t nb = 0, d = 0, dpad = 0, mode = 0;
+  // byte offsets from the workspace base
+  size_t hdr = 0, beta = 0, S = 0, H = 0, m = 0, a = 0, r = 0, evals = 0;
+  size_t P = 0, part = 0, zpart = 0, cpart = 0, ppart = 0, meanpart = 0;
+  size_t iter_end = 0;  // end of the part that tsne_step needs
+  size_t xmean = 0, xcT = 0, norms = 0, xlo = 0, dblock = 0;
+  size_t total = 0;
+};
+
+Layout make_layout(int64_t n, int32_t d, int32_t mode);
+
+// Upper-triangle tile enumeration: row I holds tiles (I, I..nb-1).
+__host__ __device__ inline int64_t tile_start(int64_t I, int64_t nb) {
+  return I * nb - I * (I - 1) / 2;
+}
+
+__device__ inline void tile_coords(int64_t t, int nb, int &I, int &J) {
+  double b = 2.0 * nb + 1.0;
+  int i = (int)((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+  if (i < 0) i = 0;
+  if (i > nb - 1) i = nb - 1;
+  while (i > 0 && tile_start(i, nb) > t) --i;
+  while (i < nb - 1 && tile_start(i + 1, nb) <= t) ++i;
+  I = i;
+  J = i + (int)(t - tile_start(i, nb));
+}
+
+template <typename P>
+inline P *at(void *ws, size_t off) {
+  return reinterpret_cast<P *>(reinterpret_cast<char *>(ws) + off);
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (all asynchronous on `stream`)
+// ---------------------------------------------------------------------------
+hipError_t launch_affinities(const Layout &L, const float *x, double perplexity, int max_bisect,
+                             double tol_h, void *ws, hipStream_t stream);
+hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t stream);
+hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
+                         float mu, float eta, float min_gain, int recentre, float *grad_out,
+                         double *z_out, hipStream_t stream);
+hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *grad_out,
+                                double *z_out, hipStream_t stream);
+hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out,
+                       hipStream_t stream);
+hipError_t launch_export_p_rows(const Layout &L, void *ws, int64_t row0, int64_t nrows,
+                                float *out, hipStream_t stream);
+hipError_t launch_export_rowstats(const Layout &L, void *ws, double *beta, float *m, double *S,
+                                  double *H, int32_t *evals, hipStream_t stream);
+
+}  // namespace tsne

@@ -1,0 +1,463 @@
+// Exact gradient iteration (Eqs. 4-6 and 10 of the bigMap paper) and the KL
+// cost (Eqs. 5 and 9).
+//
+// Force pass over the stored upper-triangle tiles. For every unordered pair
+// (i, j) of a tile, with d = y_i - y_j and w = 1 / (1 + |d|^2):
+//   Z   += 2 w                     (ordered pairs, denominator of Eq. 4)
+//   A_i += p w d,  A_j -= p w d     (attraction, Eq. 6 numerator with p)
+//   R_i += w^2 d,  R_j -= w^2 d     (repulsion, Eq. 6 with q = w / Z)
+// so that g_i = 4 (alpha A_i - R_i / Z) once Z is known. A diagonal tile
+// holds both orders of each pair and accumulates the row side only.
+//
+// Each tile writes its row-side partials into the slot (I, J) of block I and
+// its column-side partials into the slot (J, I) of block J; every slot is
+// written exactly once per pass and the update sums the slots of a row in a
+// fixed order in FP64, so results are bitwise reproducible.
+#include <math.h>
+
+#include "tsne_internal.h"
+
+namespace tsne {
+
+namespace {
+
+constexpr double kLn2 = 0.69314718055994530942;
+
+__device__ inline void flag_error(Hdr *h, uint32_t bit) { atomicOr(&h->err, bit); }
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the 16 lanes of a DPP row (rotations by 8, 4, 2, 1); every lane of
+// the row ends with the total.
+__device__ inline float row16_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, false));
+  return v;
+}
+
+// Header check shared by the iteration kernels: the workspace must hold
+// affinities for exactly this n.
+__device__ inline bool state_ok(Hdr *h, int64_t n) {
+  return h->magic == kMagic && h->n == n && h->ready == 1;
+}
+
+// ----------------------------------------------------------------------------
+// Force tile kernel
+// ----------------------------------------------------------------------------
+// Rows of the tile are visited one at a time (k); the P values of the next
+// row are loaded while the current one is processed.
+template <bool DIAG, bool EDGE>
+__device__ __forceinline__ void force_tile(const float4 *__restrict__ tp,
+                                           const float2 *__restrict__ yrow, const float2 yc[16],
+                                           uint32_t rvalid, uint32_t cvalid, int t, int tr, int tc,
+                                           float4 &myrow, float4 colacc[16], float &z) {
+  float4 cur[4], nxt[4];
+#pragma unroll
+  for (int mq = 0; mq < 4; ++mq) cur[mq] = tp[mq * 256 + t];
+  float2 yi = ((rvalid & 1u) ? yrow[0] : make_float2(0.f, 0.f));
+#pragma unroll 1
+  for (int k = 0; k < 16; ++k) {
+    float2 yn = make_float2(0.f, 0.f);
+    if (k < 15) {
+#pragma unroll
+      for (int mq = 0; mq < 4; ++mq) nxt[mq] = tp[((k + 1) * 4 + mq) * 256 + t];
+      if ((rvalid >> (k + 1)) & 1u) yn = yrow[16 * (k + 1)];
+    }
+    float ax = 0.f, ay = 0.f, rx = 0.f, ry = 0.f;
+#pragma unroll
+    for (int mq = 0; mq < 4; ++mq) {
+      const float4 pv = cur[mq];
+      const float pp[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = 4 * mq + e;
+        const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
+        const float q = fmaf(dx, dx, fmaf(dy, dy, 1.0f));
+        float w = __builtin_amdgcn_rcpf(q);
+        if (DIAG) {
+          if (tr == tc && k == m) w = 0.f;
+        }
+        if (EDGE) {
+          if (!((rvalid >> k) & (cvalid >> m) & 1u)) w = 0.f;
+        }
+        z += w;
+        const float pw = pp[e] * w, w2 = w * w;
+        ax = fmaf(pw, dx, ax);
+        ay = fmaf(pw, dy, ay);
+        rx = fmaf(w2, dx, rx);
+        ry = fmaf(w2, dy, ry);
+        if (!DIAG) {
+          colacc[m].x = fmaf(-pw, dx, colacc[m].x);
+          colacc[m].y = fmaf(-pw, dy, colacc[m].y);
+          colacc[m].z = fmaf(-w2, dx, colacc[m].z);
+          colacc[m].w = fmaf(-w2, dy, colacc[m].w);
+        }
+      }
+    }
+    ax = row16_sum(ax);
+    ay = row16_sum(ay);
+    rx = row16_sum(rx);
+    ry = row16_sum(ry);
+    if (tc == k) myrow = make_float4(ax, ay, rx, ry);
+#pragma unroll
+    for (int mq = 0; mq < 4; ++mq) cur[mq] = nxt[mq];
+    yi = yn;
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
+                                                  const float2 *__restrict__ Y, int64_t n,
+                                                  int32_t nb, float4 *__restrict__ part,
+                                                  double *__restrict__ zpart, Hdr *h) {
+  __shared__ float4 colbuf[16][T + 4];  // [row group tr][column], padded rows
+  __shared__ double zred[4];
+  if (!state_ok(h, n)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    return;
+  }
+  int I, J;
+  tile_coords(blockIdx.x, nb, I, J);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int tc = l & 15, tr = (l >> 4) + 4 * w;
+  float2 yc[16];
+  uint32_t rvalid = 0, cvalid = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = (int64_t)I * T + tr + 16 * k;
+    const int64_t j = (int64_t)J * T + tc + 16 * k;
+    const bool vi = i < n, vj = j < n;
+    rvalid |= vi ? (1u << k) : 0u;
+    cvalid |= vj ? (1u << k) : 0u;
+    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
+  }
+  const float2 *yrow = Y + (int64_t)I * T + tr;  // row tr + 16 k at yrow[16 k]
+  const bool edge = ((int64_t)(J + 1) * T > n);
+  const float4 *tp = P + (size_t)blockIdx.x * TT4;
+  float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 colacc[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) colacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+  float z = 0.f;
+  if (I == J) {
+    if (edge)
+      force_tile<true, true>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+    else
+      force_tile<true, false>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+  } else {
+    if (edge)
+      force_tile<false, true>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+    else
+      force_tile<false, false>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+  }
+  // row side: this thread holds row tr + 16 tc
+  part[((size_t)I * nb + J) * T + tr + 16 * tc] = myrow;
+  // column side: reduce over the 16 row groups through LDS
+  if (I != J) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) colbuf[tr][tc + 16 * m] = colacc[m];
+  }
+  double zd = wave_sum_d((double)z);
+  if (l == 0) zred[w] = zd;
+  __syncthreads();
+  if (I != J) {
+    float4 s = colbuf[0][t];
+#pragma unroll
+    for (int g = 1; g < 16; ++g) {
+      const float4 v = colbuf[g][t];
+      s.x += v.x;
+      s.y += v.y;
+      s.z += v.z;
+      s.w += v.w;
+    }
+    part[((size_t)J * nb + I) * T + t] = s;
+  }
+  if (t == 0) zpart[blockIdx.x] = (zred[0] + zred[1] + zred[2] + zred[3]) * (I == J ? 1.0 : 2.0);
+}
+
+// Z = sum of the tile partials in tile order (one workgroup).
+__global__ __launch_bounds__(1024) void k_zreduce(const double *__restrict__ zpart, int64_t nt,
+                                                  int64_t n, Hdr *h, double *z_out) {
+  __shared__ double red[16];
+  if (!state_ok(h, n)) return;
+  double s = 0.0;
+  for (int64_t q = threadIdx.x; q < nt; q += 1024) s += zpart[q];
+  s = wave_sum_d(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double Z = 0.0;
+    for (int q = 0; q < 16; ++q) Z += red[q];
+    h->z = Z;
+    if (z_out) *z_out = Z;
+    if (!isfinite(Z) || !(Z > 0.0)) flag_error(h, kErrNonFinite);
+  }
+}
+
+// Gradient of row i from its nb slots: g = 4 (alpha A - R / Z).
+__device__ inline float2 row_gradient(const float4 *__restrict__ part, int32_t nb, int b, int r,
+                                      double alpha, double Z) {
+  double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
+  const float4 *pp = part + (size_t)b * nb * T + r;
+  for (int s = 0; s < nb; ++s) {
+    const float4 v = pp[(size_t)s * T];
+    ax += v.x;
+    ay += v.y;
+    rx += v.z;
+    ry += v.w;
+  }
+  return make_float2((float)(4.0 * (alpha * ax - rx / Z)), (float)(4.0 * (alpha * ay - ry / Z)));
+}
+
+// Update (Eq. 10, descent): gains, momentum, position; per-block sums of the
+// new positions for the re-centring.
+__global__ __launch_bounds__(256) void k_update(const float4 *__restrict__ part, int64_t n,
+                                                int32_t nb, float2 *__restrict__ Y,
+                                                float2 *__restrict__ U, float2 *__restrict__ G,
+                                                float alpha, float mu, float eta, float min_gain,
+                                                float2 *__restrict__ grad_out,
+                                                double2 *__restrict__ meanpart, Hdr *h) {
+  __shared__ double red[2][4];
+  if (!state_ok(h, n)) return;
+  const int b = blockIdx.x, r = threadIdx.x;
+  const int64_t i = (int64_t)b * T + r;
+  double sx = 0.0, sy = 0.0;
+  bool bad = false;
+  if (i < n) {
+    const float2 g = row_gradient(part, nb, b, r, (double)alpha, h->z);
+    if (grad_out) grad_out[i] = g;
+    float2 u = U[i], gn = G[i], y = Y[i];
+    gn.x = ((g.x > 0.f) != (u.x > 0.f)) ? gn.x + 0.2f : gn.x * 0.8f;
+    gn.y = ((g.y > 0.f) != (u.y > 0.f)) ? gn.y + 0.2f : gn.y * 0.8f;
+    gn.x = fmaxf(gn.x, min_gain);
+    gn.y = fmaxf(gn.y, min_gain);
+    u.x = mu * u.x - eta * (gn.x * g.x);
+    u.y = mu * u.y - eta * (gn.y * g.y);
+    y.x += u.x;
+    y.y += u.y;
+    U[i] = u;
+    G[i] = gn;
+    Y[i] = y;
+    sx = y.x;
+    sy = y.y;
+    bad = !(isfinite(g.x) && isfinite(g.y) && isfinite(y.x) && isfinite(y.y));
+  }
+  if (bad) flag_error(h, kErrNonFinite);
+  sx = wave_sum_d(sx);
+  sy = wave_sum_d(sy);
+  if ((r & 63) == 0) {
+    red[0][r >> 6] = sx;
+    red[1][r >> 6] = sy;
+  }
+  __syncthreads();
+  if (r == 0)
+    meanpart[b] = make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                               red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+}
+
+__global__ __launch_bounds__(256) void k_recentre(const double2 *__restrict__ meanpart, int64_t n,
+                                                  int32_t nb, float2 *__restrict__ Y, Hdr *h) {
+  __shared__ float2 smean;
+  if (!state_ok(h, n)) return;
+  if (threadIdx.x == 0) {
+    double mx = 0.0, my = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      mx += meanpart[b].x;
+      my += meanpart[b].y;
+    }
+    smean = make_float2((float)(mx / (double)n), (float)(my / (double)n));
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    float2 y = Y[i];
+    y.x -= smean.x;
+    y.y -= smean.y;
+    Y[i] = y;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_grad_only(const float4 *__restrict__ part, int64_t n,
+                                                   int32_t nb, float alpha,
+                                                   float2 *__restrict__ grad_out, Hdr *h) {
+  if (!state_ok(h, n)) return;
+  const int b = blockIdx.x, r = threadIdx.x;
+  const int64_t i = (int64_t)b * T + r;
+  if (i < n) {
+    const float2 g = row_gradient(part, nb, b, r, (double)alpha, h->z);
+    grad_out[i] = g;
+    if (!(isfinite(g.x) && isfinite(g.y))) flag_error(h, kErrNonFinite);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Cost: per tile sum p log2(1 + |d|^2) and Z, then
+//   KL = C_P + ln2 sum p log2(1 + |d|^2) + (sum p) ln Z,
+//   C_norm = (ln2 sum p log2(1 + |d|^2) + (sum p) ln Z) / (ln n + ln(n - 1)).
+// ----------------------------------------------------------------------------
+template <bool DIAG, bool EDGE>
+__device__ __forceinline__ void cost_tile(const float4 *__restrict__ tp,
+                                          const float2 *__restrict__ yrow, const float2 yc[16],
+                                          uint32_t rvalid, uint32_t cvalid, int t, int tr, int tc,
+                                          float &plq, float &z) {
+#pragma unroll 1
+  for (int k = 0; k < 16; ++k) {
+    const float2 yi = ((rvalid >> k) & 1u) ? yrow[16 * k] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int mq = 0; mq < 4; ++mq) {
+      const float4 pv = tp[(k * 4 + mq) * 256 + t];
+      const float pp[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = 4 * mq + e;
+        const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
+        const float q = fmaf(dx, dx, fmaf(dy, dy, 1.0f));
+        float w = __builtin_amdgcn_rcpf(q);
+        bool keep = true;
+        if (DIAG) keep = !(tr == tc && k == m);
+        if (EDGE) keep = keep && ((rvalid >> k) & (cvalid >> m) & 1u);
+        if (!keep) w = 0.f;
+        z += w;
+        plq = fmaf(pp[e], __builtin_amdgcn_logf(q), plq);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
+                                                 const float2 *__restrict__ Y, int64_t n,
+                                                 int32_t nb, double2 *__restrict__ cpart,
+                                                 Hdr *h) {
+  __shared__ double red[2][4];
+  if (!state_ok(h, n)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    return;
+  }
+  int I, J;
+  tile_coords(blockIdx.x, nb, I, J);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int tc = l & 15, tr = (l >> 4) + 4 * w;
+  float2 yc[16];
+  uint32_t rvalid = 0, cvalid = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = (int64_t)I * T + tr + 16 * k;
+    const int64_t j = (int64_t)J * T + tc + 16 * k;
+    const bool vi = i < n, vj = j < n;
+    rvalid |= vi ? (1u << k) : 0u;
+    cvalid |= vj ? (1u << k) : 0u;
+    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
+  }
+  const float2 *yrow = Y + (int64_t)I * T + tr;
+  const bool edge = ((int64_t)(J + 1) * T > n);
+  const float4 *tp = P + (size_t)blockIdx.x * TT4;
+  float plq = 0.f, z = 0.f;
+  if (I == J) {
+    if (edge)
+      cost_tile<true, true>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, plq, z);
+    else
+      cost_tile<true, false>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, plq, z);
+  } else {
+    if (edge)
+      cost_tile<false, true>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, plq, z);
+    else
+      cost_tile<false, false>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, plq, z);
+  }
+  double a = wave_sum_d((double)plq), c = wave_sum_d((double)z);
+  if (l == 0) {
+    red[0][w] = a;
+    red[1][w] = c;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const double mult = (I == J) ? 1.0 : 2.0;
+    cpart[blockIdx.x] = make_double2(mult * (red[0][0] + red[0][1] + red[0][2] + red[0][3]),
+                                     mult * (red[1][0] + red[1][1] + red[1][2] + red[1][3]));
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_cost_reduce(const double2 *__restrict__ cpart,
+                                                      int64_t nt, int64_t n, Hdr *h,
+                                                      double *out) {
+  __shared__ double red[2][16];
+  if (!state_ok(h, n)) return;
+  double a = 0.0, c = 0.0;
+  for (int64_t q = threadIdx.x; q < nt; q += 1024) {
+    a += cpart[q].x;
+    c += cpart[q].y;
+  }
+  a = wave_sum_d(a);
+  c = wave_sum_d(c);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double A = 0.0, Z = 0.0;
+    for (int q = 0; q < 16; ++q) {
+      A += red[0][q];
+      Z += red[1][q];
+    }
+    const double cross = kLn2 * A + h->p_sum * log(Z);  // H(P, Q)
+    out[0] = h->c_p + cross;
+    out[1] = cross / (log((double)n) + log((double)n - 1.0));
+    if (!isfinite(out[0])) flag_error(h, kErrNonFinite);
+  }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Host-side sequencing
+// ----------------------------------------------------------------------------
+hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t st) {
+  Hdr *h = at<Hdr>(ws, L.hdr);
+  hipLaunchKernelGGL(k_force, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
+                     reinterpret_cast<const float2 *>(y), L.n, L.nb, at<float4>(ws, L.part),
+                     at<double>(ws, L.zpart), h);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
+                         float mu, float eta, float min_gain, int recentre, float *grad_out,
+                         double *z_out, hipStream_t st) {
+  Hdr *h = at<Hdr>(ws, L.hdr);
+  hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
+                     L.n, h, z_out);
+  double2 *mp = at<double2>(ws, L.meanpart);
+  hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(256), 0, st, at<const float4>(ws, L.part), L.n,
+                     L.nb, reinterpret_cast<float2 *>(y), reinterpret_cast<float2 *>(u),
+                     reinterpret_cast<float2 *>(g), alpha, mu, eta, min_gain,
+                     reinterpret_cast<float2 *>(grad_out), mp, h);
+  if (recentre)
+    hipLaunchKernelGGL(k_recentre, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, mp, L.n,
+                       L.nb, reinterpret_cast<float2 *>(y), h);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *grad_out,
+                                double *z_out, hipStream_t st) {
+  Hdr *h = at<Hdr>(ws, L.hdr);
+  hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
+                     L.n, h, z_out);
+  hipLaunchKernelGGL(k_grad_only, dim3(L.nb), dim3(256), 0, st, at<const float4>(ws, L.part),
+                     L.n, L.nb, alpha, reinterpret_cast<float2 *>(grad_out), h);
+  return hipGetLastError();
+}
+
+hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, hipStream_t st) {
+  Hdr *h = at<Hdr>(ws, L.hdr);
+  double2 *cp = at<double2>(ws, L.cpart);
+  hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
+                     reinterpret_cast<const float2 *>(y), L.n, L.nb, cp, h);
+  hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
+  return hipGetLastError();
+}
+
+}  // namespace tsne

@@ -1,0 +1,86 @@
+"""Exact t-SNE driver over the C ABI (state handling and schedule only).
+
+``ExactTSNE`` owns a workspace, fills it with the affinities of X and runs
+the exact gradient iteration on the GPU. Every computation is a call into
+libtsne355; this module only allocates tensors and chooses per-iteration
+parameters.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+
+@dataclass
+class Schedule:
+    """Early exaggeration and momentum switch at ``switch``; constant learning rate.
+
+    Defaults: exaggeration 12 and momentum 0.5 before iteration 250, then 1
+    and 0.8; learning rate 200; gains floored at 0.01.
+    """
+
+    switch: int = 250
+    exaggeration: float = 12.0
+    mom_early: float = 0.5
+    mom_late: float = 0.8
+    learning_rate: float = 200.0
+    min_gain: float = 0.01
+
+    def __call__(self, t: int):
+        early = t < self.switch
+        return (self.exaggeration if early else 1.0, self.mom_early if early else self.mom_late,
+                self.learning_rate)
+
+
+class ExactTSNE:
+    def __init__(self, x: torch.Tensor, perplexity: float, dist_mode="fp64", max_bisect: int = 200,
+                 tol_h: float = 1e-6, ws: torch.Tensor | None = None):
+        if x.dim() != 2:
+            raise ValueError("x must be n x d")
+        self.n, self.d = x.shape
+        self.perplexity = float(perplexity)
+        self.ws = ws if ws is not None else _lib.new_workspace(self.n, self.d, dist_mode,
+                                                               device=x.device)
+        _lib.affinities(x, perplexity, self.ws, dist_mode, max_bisect, tol_h)
+        self._z = torch.zeros(1, dtype=torch.float64, device=x.device)
+        self._cost = torch.zeros(2, dtype=torch.float64, device=x.device)
+
+    def init_state(self, y0: torch.Tensor):
+        y = y0.detach().to(dtype=torch.float32).contiguous().clone()
+        return y, torch.zeros_like(y), torch.ones_like(y)
+
+    def step(self, t: int, state, sched: Schedule, grad_out=None, z_out=None):
+        y, u, g = state
+        alpha, mu, eta = sched(t)
+        _lib.step(self.ws, self.n, y, u, g, alpha, mu, eta, sched.min_gain, True, grad_out, z_out)
+
+    def run(self, state, iters: int, start: int = 0, sched: Schedule | None = None):
+        sched = sched or Schedule()
+        for t in range(start, start + iters):
+            self.step(t, state, sched)
+        return state
+
+    def gradient(self, y: torch.Tensor, alpha: float = 1.0):
+        g = torch.empty_like(y)
+        _lib.gradient(self.ws, self.n, y, alpha, g, self._z)
+        return g, self._z
+
+    def cost(self, y: torch.Tensor):
+        """Device tensor [KL, C_norm]."""
+        _lib.cost(self.ws, self.n, y, self._cost)
+        return self._cost
+
+    def status(self) -> int:
+        return _lib.sync_status(self.ws)
+
+    def check(self):
+        _lib.check_status(self.ws)
+
+    def rowstats(self):
+        return _lib.export_rowstats(self.ws, self.n)
+
+    def p_rows(self, row0: int, nrows: int):
+        return _lib.export_p_rows(self.ws, self.n, row0, nrows)

@@ -1,0 +1,208 @@
+"""GPU parity of the HIP path against the FP64 oracle at sizes the oracle runs in seconds.
+
+Gates (per step, from the same inputs):
+  * P:  ||P_gpu - P_ref||_F / ||P_ref||_F <= 1e-5 and
+        max |P_gpu - P_ref| / max P_ref <= 1e-5 (FP32 storage underflows the
+        far tail, so entry-wise relative error is not a meaningful gate there);
+  * beta_i relative error <= 1e-4 and |H_i - ln u| <= 1e-5 for every row;
+  * gradient: ||g_gpu - g_ref||_2 / ||g_ref||_2 <= 1e-4, Z relative <= 1e-6;
+  * cost: KL relative <= 1e-5, C_norm absolute <= 1e-6.
+Sizes cover one tile, several tiles, and ragged tails (n not a multiple of 256).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1812_09869_amd import _lib, synth
+from paper_1812_09869_amd.tsne import ExactTSNE, Schedule
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (n, d, perplexity, generator)
+    (3, 2, 1.5, "gauss"),
+    (17, 1, 5.0, "gauss"),
+    (255, 3, 10.0, "gauss"),
+    (257, 10, 30.0, "small"),
+    (600, 50, 30.0, "aniso"),
+    (1000, 128, 50.0, "gauss"),
+    (2000, 10, 30.0, "small"),
+]
+
+
+def _data(n, d, gen, seed):
+    if gen == "small":
+        x, lab = synth.plain_small(n, seed=seed)
+    elif gen == "aniso":
+        x, lab = synth.gmm_aniso(n, sample_seed=seed)
+    else:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        x = (rng.standard_normal((n, d)) * 2.0).astype(np.float32)
+        lab = rng.integers(0, 4, n)
+    return x, lab
+
+
+def _p_errors(pg, pr):
+    diff = pg - pr
+    return (np.linalg.norm(diff) / np.linalg.norm(pr), np.abs(diff).max() / np.abs(pr).max())
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"n{c[0]}_d{c[1]}")
+def case(request):
+    n, d, perp, gen = request.param
+    print(f"\n[case] n={n} d={d} perplexity={perp} gen={gen}", flush=True)
+    x, lab = _data(n, d, gen, seed=100 + n)
+    st = oracle.calibrate(x, perp)
+    P = oracle.joint_p(x, st)
+    xt = torch.from_numpy(x).cuda()
+    model = ExactTSNE(xt, perp)
+    return dict(n=n, d=d, perp=perp, x=x, lab=lab, st=st, P=P, model=model)
+
+
+def test_affinity_parity(case):
+    n, model, st, P = case["n"], case["model"], case["st"], case["P"]
+    assert model.status() == 0
+    beta, m, S, H, ev = (t.cpu().numpy() for t in model.rowstats())
+    assert np.all(ev > 0)
+    # beta is only as well determined as H allows (dH/dbeta = -beta Var(d)); the
+    # gate that matters is on P, beta is checked loosely
+    rel_beta = np.abs(beta - st.beta) / st.beta
+    assert rel_beta.max() <= 1e-4, rel_beta.max()
+    assert np.abs(H - math.log(case["perp"])).max() <= 1e-5
+    pg = model.p_rows(0, n).cpu().numpy().astype(np.float64)
+    assert np.array_equal(pg, pg.T)
+    assert np.all(np.diag(pg) == 0)
+    fro, mx = _p_errors(pg, P)
+    print(f"  P rel-Frobenius {fro:.2e} max-rel {mx:.2e} beta max-rel {rel_beta.max():.2e}")
+    assert fro <= 1e-5 and mx <= 1e-5
+
+
+@pytest.mark.parametrize("alpha", [1.0, 12.0])
+def test_gradient_parity(case, alpha):
+    n, model, P, lab = case["n"], case["model"], case["P"], case["lab"]
+    y = synth.clustered_state(lab, seed=7 + n)
+    g_ref, z_ref = oracle.gradient(P, y.astype(np.float64), alpha)
+    g, z = model.gradient(torch.from_numpy(y).cuda(), alpha)
+    g = g.cpu().numpy().astype(np.float64)
+    zg = float(z.cpu()[0])
+    assert model.status() == 0
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"  grad rel-L2 {rel:.2e}  Z rel {abs(zg - z_ref) / z_ref:.2e}")
+    assert rel <= 1e-4
+    assert abs(zg - z_ref) <= 1e-6 * z_ref
+
+
+def test_cost_parity(case):
+    n, model, P, lab = case["n"], case["model"], case["P"], case["lab"]
+    for y in (synth.embedding_init(n, seed=3), synth.clustered_state(lab, seed=9)):
+        kl_ref, cn_ref = oracle.cost(P, y.astype(np.float64))
+        out = model.cost(torch.from_numpy(y).cuda()).cpu().numpy()
+        print(f"  KL gpu {out[0]:.8f} ref {kl_ref:.8f}; Cnorm gpu {out[1]:.8f} ref {cn_ref:.8f}")
+        assert abs(out[0] - kl_ref) <= 1e-5 * max(abs(kl_ref), 1e-3)
+        assert abs(out[1] - cn_ref) <= 1e-6
+
+
+def test_step_parity(case):
+    """A few updates from Y0 (U = 0, G = 1) with the early-exaggeration parameters."""
+    n, model, P = case["n"], case["model"], case["P"]
+    y0 = synth.embedding_init(n, seed=11)
+    state = model.init_state(torch.from_numpy(y0).cuda())
+    yr, ur, gr = oracle.run(P, y0.astype(np.float64), 3)
+    model.run(state, 3)
+    y = state[0].cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(y - yr) / np.linalg.norm(yr)
+    print(f"  Y after 3 steps rel {rel:.2e}")
+    assert rel <= 1e-4
+    assert model.status() == 0
+
+
+def test_determinism(case):
+    n, model, lab = case["n"], case["model"], case["lab"]
+    y = torch.from_numpy(synth.clustered_state(lab, seed=5)).cuda()
+    a = model.gradient(y, 1.0)[0].clone()
+    b = model.gradient(y, 1.0)[0].clone()
+    assert torch.equal(a, b)
+
+
+def test_plain_small_full_run():
+    """The 2,000-point workload, 500 iterations, final KL against the oracle.
+
+    The stored oracle results include eight FP64 runs whose initial maps differ
+    by one FP32 ulp in one coordinate; their spread is the chaos floor of the
+    final KL. The GPU run must land within 1.5x that band around the oracle's
+    run from the unperturbed map (and the KL at iteration 1 and 10, before the
+    trajectories separate, within 1e-4).
+    """
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "plain_small_oracle.json")))
+    x, _ = synth.plain_small()
+    y0 = synth.embedding_init(x.shape[0], synth.SEEDS["init_small"])
+    model = ExactTSNE(torch.from_numpy(x).cuda(), 30.0)
+    state = model.init_state(torch.from_numpy(y0).cuda())
+    sched = Schedule()
+    kls = {}
+    t = 0
+    for t_end in (1, 10, 250, 500):
+        model.run(state, t_end - t, start=t, sched=sched)
+        t = t_end
+        kls[t_end] = float(model.cost(state[0]).cpu()[0])
+    assert model.status() == 0
+    ref = {int(k): v["kl"] for k, v in gold["checkpoints"].items()}
+    print("  KL gpu", kls, "\n  KL ref", ref)
+    for t_end in (1, 10):
+        assert abs(kls[t_end] - ref[t_end]) <= 1e-4 * ref[t_end]
+    ens = np.array(gold["final_kl_ulp_ensemble"])
+    band = 1.5 * np.abs(ens - ref[500]).max()
+    print(f"  final KL rel diff {abs(kls[500] - ref[500]) / ref[500]:.2e}; chaos band "
+          f"{band / ref[500]:.2e}")
+    assert abs(kls[500] - ref[500]) <= max(band, 1e-3 * ref[500])
+
+
+def test_argument_errors():
+    x = torch.zeros((10, 3), device="cuda")
+    ws = _lib.new_workspace(10, 3)
+    with pytest.raises(_lib.TsneError) as e:
+        _lib.affinities(x, 9.0, ws)  # perplexity must be < n - 1
+    assert e.value.code == 2
+    with pytest.raises(_lib.TsneError) as e:
+        _lib.affinities(x, 1.0, ws)
+    assert e.value.code == 2
+    with pytest.raises(_lib.TsneError) as e:
+        _lib.affinities(x, 3.0, ws[:100])
+    assert e.value.code == 3
+    with pytest.raises(_lib.TsneError) as e:
+        _lib.affinities(x, 3.0, ws, max_bisect=0)
+    assert e.value.code == 1
+    assert _lib.workspace_bytes(1, 3) == 0
+    y = torch.zeros((11, 2), device="cuda")
+    with pytest.raises(ValueError):
+        _lib.step(ws, 10, y, y, y, 1.0, 0.5, 200.0)
+
+
+def test_device_conditions():
+    """Non-finite input, an unreachable perplexity and a mismatched n are reported."""
+    rng = np.random.Generator(np.random.PCG64(1))
+    x = rng.standard_normal((40, 3)).astype(np.float32)
+    x[5, 1] = np.nan
+    ws = _lib.new_workspace(40, 3)
+    _lib.affinities(torch.from_numpy(x).cuda(), 5.0, ws)
+    assert _lib.sync_status(ws) == 5
+    # every point equidistant from every other: H = ln(n - 1) for any beta
+    xe = np.eye(12, dtype=np.float32)
+    ws = _lib.new_workspace(12, 12)
+    _lib.affinities(torch.from_numpy(xe).cuda(), 4.0, ws, max_bisect=40)
+    assert _lib.sync_status(ws) == 6
+    # a step for another n than the workspace holds
+    ws = _lib.new_workspace(40, 3)
+    _lib.affinities(torch.from_numpy(np.nan_to_num(x)).cuda(), 5.0, ws)
+    assert _lib.sync_status(ws) == 0
+    y = torch.zeros((39, 2), device="cuda")
+    u = torch.zeros_like(y)
+    g = torch.ones_like(y)
+    _lib.step(ws, 39, y, u, g, 1.0, 0.5, 200.0)
+    assert _lib.sync_status(ws) == 7
