@@ -112,6 +112,18 @@ TSNE_API int tsne_affinities(const float *x, int64_t n, int32_t d, double perple
 TSNE_API int tsne_step(void *ws, int64_t n, float *y, float *u, float *g, const tsne_step_params *prm,
               float *grad_out, double *z_out, void *stream);
 
+/* The two halves of tsne_step, for callers that time or schedule them
+ * separately. tsne_forces runs the pair pass over the stored tiles at map y
+ * (Student-t kernel, Z, attractive and repulsive row sums; Eqs. 4 and 6) and
+ * keeps the partial sums in the workspace; tsne_update reduces them, forms
+ * the gradient with exaggeration prm->exaggeration and applies the update
+ * of tsne_step to (y, u, g). tsne_update must follow tsne_forces for the same
+ * y on the same stream. */
+TSNE_API int tsne_forces(void *ws, int64_t n, const float *y, void *stream);
+TSNE_API int tsne_update(void *ws, int64_t n, float *y, float *u, float *g,
+                         const tsne_step_params *prm, float *grad_out, double *z_out,
+                         void *stream);
+
 /* Gradient of Eq. 6 (with exaggeration alpha) at map y, without an update.
  * grad_out: n x 2 FP32 (device, required); z_out nullable device double. */
 TSNE_API int tsne_gradient(void *ws, int64_t n, const float *y, float alpha, float *grad_out,

@@ -33,6 +33,8 @@ EXPORTED = [
     "tsne_workspace_bytes",
     "tsne_affinities",
     "tsne_step",
+    "tsne_forces",
+    "tsne_update",
     "tsne_gradient",
     "tsne_cost",
     "tsne_sync_status",
@@ -81,6 +83,9 @@ def load(path: str = LIB_PATH):
                                            ctypes.POINTER(AffOpts), _vp, ctypes.c_size_t, _vp]),
         "tsne_step": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, ctypes.POINTER(StepParams), _vp,
                                      _vp, _vp]),
+        "tsne_forces": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
+        "tsne_update": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, ctypes.POINTER(StepParams), _vp,
+                                       _vp, _vp]),
         "tsne_gradient": (ctypes.c_int, [_vp, _i64, _vp, ctypes.c_float, _vp, _vp, _vp]),
         "tsne_cost": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp]),
         "tsne_sync_status": (ctypes.c_int, [_vp, _vp]),
@@ -149,6 +154,21 @@ def step(ws, n, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01, r
                             _ptr(u, shape=sh, name="u"), _ptr(g, shape=sh, name="g"),
                             ctypes.byref(prm), _ptr(grad_out, shape=sh, name="grad_out"),
                             _ptr(z_out, torch.float64, name="z_out"), _stream()))
+
+
+def forces(ws, n, y):
+    _check(load().tsne_forces(_ptr(ws, torch.uint8, name="ws"), n, _ptr(y, shape=(n, 2), name="y"),
+                              _stream()))
+
+
+def update(ws, n, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True,
+           grad_out=None, z_out=None):
+    prm = StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0)
+    sh = (n, 2)
+    _check(load().tsne_update(_ptr(ws, torch.uint8, name="ws"), n, _ptr(y, shape=sh, name="y"),
+                              _ptr(u, shape=sh, name="u"), _ptr(g, shape=sh, name="g"),
+                              ctypes.byref(prm), _ptr(grad_out, shape=sh, name="grad_out"),
+                              _ptr(z_out, torch.float64, name="z_out"), _stream()))
 
 
 def gradient(ws, n, y, alpha, grad_out, z_out=None):

@@ -134,6 +134,27 @@ int tsne_step(void *ws, int64_t n, float *y, float *u, float *g, const tsne_step
   return hip_check(e, "tsne_step");
 }
 
+int tsne_forces(void *ws, int64_t n, const float *y, void *stream) {
+  if (int rc = check_iter_args("tsne_forces", ws, n)) return rc;
+  if (!y) return fail(TSNE_E_ARG, "tsne_forces: null pointer");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  return hip_check(tsne::launch_force(L, ws, y, (hipStream_t)stream), "tsne_forces");
+}
+
+int tsne_update(void *ws, int64_t n, float *y, float *u, float *g, const tsne_step_params *prm,
+                float *grad_out, double *z_out, void *stream) {
+  if (int rc = check_iter_args("tsne_update", ws, n)) return rc;
+  if (!y || !u || !g || !prm) return fail(TSNE_E_ARG, "tsne_update: null pointer");
+  if (!(prm->learning_rate >= 0.f) || !(prm->min_gain >= 0.f) || !isfinite(prm->momentum) ||
+      !isfinite(prm->exaggeration))
+    return fail(TSNE_E_ARG, "tsne_update: invalid parameters");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  return hip_check(tsne::launch_update(L, ws, y, u, g, prm->exaggeration, prm->momentum,
+                                       prm->learning_rate, prm->min_gain, prm->recentre,
+                                       grad_out, z_out, (hipStream_t)stream),
+                   "tsne_update");
+}
+
 int tsne_gradient(void *ws, int64_t n, const float *y, float alpha, float *grad_out,
                   double *z_out, void *stream) {
   if (int rc = check_iter_args("tsne_gradient", ws, n)) return rc;
