@@ -147,6 +147,10 @@ TSNE_API const char *tsne_last_error(void);
 TSNE_API int tsne_export_rowstats(void *ws, int64_t n, double *beta, float *m, double *S, double *H,
                          int32_t *evals, void *stream);
 
+/* Test hook: out (device double[4]) = {sum_{i != j} p_ij, sum_{i != j} p_ij ln p_ij,
+ * Z of the last force pass, perplexity}. */
+TSNE_API int tsne_export_scalars(void *ws, int64_t n, double *out, void *stream);
+
 /* Test hook: dense rows row0 .. row0 + nrows - 1 of P (nrows x n FP32). */
 TSNE_API int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *out,
                        void *stream);

@@ -40,6 +40,7 @@ EXPORTED = [
     "tsne_sync_status",
     "tsne_last_error",
     "tsne_export_rowstats",
+    "tsne_export_scalars",
     "tsne_export_p_rows",
 ]
 
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
         "tsne_sync_status": (ctypes.c_int, [_vp, _vp]),
         "tsne_last_error": (ctypes.c_char_p, []),
         "tsne_export_rowstats": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "tsne_export_scalars": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
         "tsne_export_p_rows": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),
     }
     for name, (res, args) in sigs.items():
@@ -203,6 +205,14 @@ def export_rowstats(ws, n):
                                        _ptr(beta, torch.float64), _ptr(m), _ptr(S, torch.float64),
                                        _ptr(H, torch.float64), _ptr(ev, torch.int32), _stream()))
     return beta, m, S, H, ev
+
+
+def export_scalars(ws, n):
+    """(sum P, sum p ln p, Z of the last force pass, perplexity) as Python floats."""
+    out = torch.empty(4, dtype=torch.float64, device=ws.device)
+    _check(load().tsne_export_scalars(_ptr(ws, torch.uint8, name="ws"), n,
+                                      _ptr(out, torch.float64), _stream()))
+    return tuple(float(v) for v in out.cpu())
 
 
 def export_p_rows(ws, n, row0, nrows):

@@ -475,6 +475,15 @@ __global__ void k_export_stats(int64_t n, const double *__restrict__ beta,
   if (oe) oe[i] = ev[i];
 }
 
+__global__ void k_export_scalars(int64_t n, const Hdr *h, double *out) {
+  if (threadIdx.x != 0) return;
+  const bool ok = h->magic == kMagic && h->n == n;
+  out[0] = ok ? h->p_sum : NAN;
+  out[1] = ok ? h->c_p : NAN;
+  out[2] = ok ? h->z : NAN;
+  out[3] = ok ? h->perplexity : NAN;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -550,6 +559,12 @@ hipError_t launch_export_rowstats(const Layout &L, void *ws, double *beta, float
                      at<const double>(ws, L.beta), at<const float>(ws, L.m),
                      at<const double>(ws, L.S), at<const double>(ws, L.H),
                      at<const int32_t>(ws, L.evals), beta, m, S, H, evals, at<Hdr>(ws, L.hdr));
+  return hipGetLastError();
+}
+
+hipError_t launch_export_scalars(const Layout &L, void *ws, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_scalars, dim3(1), dim3(64), 0, st, L.n, at<const Hdr>(ws, L.hdr),
+                     out);
   return hipGetLastError();
 }
 

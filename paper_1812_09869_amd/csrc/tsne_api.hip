@@ -200,6 +200,14 @@ int tsne_export_rowstats(void *ws, int64_t n, double *beta, float *m, double *S,
                    "tsne_export_rowstats");
 }
 
+int tsne_export_scalars(void *ws, int64_t n, double *out, void *stream) {
+  if (int rc = check_iter_args("tsne_export_scalars", ws, n)) return rc;
+  if (!out) return fail(TSNE_E_ARG, "tsne_export_scalars: null pointer");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  return hip_check(tsne::launch_export_scalars(L, ws, out, (hipStream_t)stream),
+                   "tsne_export_scalars");
+}
+
 int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *out,
                        void *stream) {
   if (int rc = check_iter_args("tsne_export_p_rows", ws, n)) return rc;

@@ -95,6 +95,7 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out,
                        hipStream_t stream);
 hipError_t launch_export_p_rows(const Layout &L, void *ws, int64_t row0, int64_t nrows,
                                 float *out, hipStream_t stream);
+hipError_t launch_export_scalars(const Layout &L, void *ws, double *out, hipStream_t stream);
 hipError_t launch_export_rowstats(const Layout &L, void *ws, double *beta, float *m, double *S,
                                   double *H, int32_t *evals, hipStream_t stream);
 
