@@ -53,6 +53,7 @@ __global__ void k_init_hdr(Hdr *h, int64_t n, int32_t d, int32_t mode, double pe
     h->z = 0.0;
     h->c_p = 0.0;
     h->p_sum = 0.0;
+    h->xmax = 0.f;
   }
 }
 
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int
   if (i >= npad) return;
   double nrm = 0.0;
   bool bad = false;
+  float amax = 0.f;
   for (int k = 0; k < dpad; ++k) {
     double v = 0.0;
     if (i < n && k < d) {
@@ -89,9 +91,16 @@ __global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int
     }
     xcT[(int64_t)k * npad + i] = v;
     nrm += v * v;
+    amax = fmaxf(amax, fabsf((float)v));
   }
   norms[i] = nrm;
   if (bad) flag_error(h, kErrNonFinite);
+  // max |centred x| over the wave, then one atomic per wave (non-negative
+  // floats order like their bit patterns)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if ((threadIdx.x & 63) == 0 && isfinite(amax))
+    atomicMax(reinterpret_cast<unsigned int *>(&h->xmax), __float_as_uint(amax));
 }
 
 // ----------------------------------------------------------------------------
@@ -143,6 +152,180 @@ __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT
         const int64_t j = col0 + c * 16 + li;
         double dd = ni + norms[j] - 2.0 * acc[a][c][r];
         dblock[(int64_t)il * npad + j] = (float)fmax(dd, 0.0);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 2a'. Reduced-precision distance contraction (the precision path).
+//
+// FP32 mode: the FP64-centred X rounded to FP32, v_mfma_f32_16x16x4f32, norms
+// of the rounded points, d = (n_i + n_j) - 2 x.y in FP32.
+// BF16 / FP16 modes: operands rounded to 16 bits, v_mfma_f32_16x16x32_{bf16,f16}
+// with FP32 accumulation. The single-product modes take the norms of the
+// rounded operands, so that d is the exact squared distance of two slightly
+// moved points (never negative, no cancellation blow-up of the dot-product
+// error). The x3 modes split x = hi + lo (lo = x - hi rounded again) and form
+// hi.hi + hi.lo + lo.hi as one contraction of length 3K over A' = [hi|hi|lo],
+// B' = [hi|lo|hi]; their norms are FP32 norms of the unsplit FP32 values.
+// FP16 operands are scaled by a power of two so that max |x| maps to <= 256
+// (exact, undone after the contraction).
+// 16x16x32 layout: lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and the
+// matching B column slice, and receives D[4(l/16) + r][l%16] in element r.
+// ----------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+__device__ inline float fp16_scale(const Hdr *h) {
+  // 2^(8 - ceil(log2 xmax)); 1 if xmax is 0
+  const float xm = h->xmax;
+  if (!(xm > 0.f)) return 1.f;
+  int e;
+  frexpf(xm, &e);  // xm = f 2^e, f in [0.5, 1)
+  return ldexpf(1.f, 8 - e);
+}
+
+__global__ __launch_bounds__(256) void k_prep_f32(const double *__restrict__ xcT, int64_t npad,
+                                                  int32_t dpad, float *__restrict__ xfT,
+                                                  float *__restrict__ norms32) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npad) return;
+  double nrm = 0.0;
+  for (int k = 0; k < dpad; ++k) {
+    const float v = (float)xcT[(int64_t)k * npad + i];
+    xfT[(int64_t)k * npad + i] = v;
+    nrm += (double)v * (double)v;
+  }
+  norms32[i] = (float)nrm;
+}
+
+template <typename H, bool SPLIT, bool SCALE>
+__global__ __launch_bounds__(256) void k_prep_lp(const double *__restrict__ xcT, int64_t npad,
+                                                 int32_t d, int32_t k32, H *__restrict__ xa,
+                                                 H *__restrict__ xb, float *__restrict__ norms32,
+                                                 const Hdr *h) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npad) return;
+  const float s = SCALE ? fp16_scale(h) : 1.f;
+  const int kk = SPLIT ? 3 * k32 : k32;
+  H *ra = xa + i * kk;
+  H *rb = xb + i * kk;
+  double nrm = 0.0;
+  for (int k = 0; k < k32; ++k) {
+    const float v = (k < d) ? (float)xcT[(int64_t)k * npad + i] : 0.f;
+    const H hi = (H)(v * s);
+    if (SPLIT) {
+      const H lo = (H)(v * s - (float)hi);
+      ra[k] = hi;
+      ra[k32 + k] = hi;
+      ra[2 * k32 + k] = lo;
+      rb[k] = hi;
+      rb[k32 + k] = lo;
+      rb[2 * k32 + k] = hi;
+      nrm += (double)v * (double)v;
+    } else {
+      ra[k] = hi;
+      const double hv = (double)(float)hi / (double)s;
+      nrm += hv * hv;
+    }
+  }
+  norms32[i] = (float)nrm;
+}
+
+__global__ __launch_bounds__(256) void k_dist_f32(const float *__restrict__ xfT,
+                                                  const float *__restrict__ norms, int64_t npad,
+                                                  int32_t dpad, int32_t b,
+                                                  float *__restrict__ dblock) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  const int row0_loc = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)b * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < dpad; k0 += 4) {
+    const float *xk = xfT + (int64_t)(k0 + lk) * npad;
+    float av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = xk[row0 + a * 16 + li];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[c] = xk[col0 + c * 16 + li];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[c], acc[a][c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + a * 16 + 4 * lk + r;
+      const float ni = norms[(int64_t)b * T + il];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t j = col0 + c * 16 + li;
+        const float dd = (ni + norms[j]) - 2.f * acc[a][c][r];
+        dblock[(int64_t)il * npad + j] = fmaxf(dd, 0.f);
+      }
+    }
+  }
+}
+
+template <typename H, typename V8, bool SCALE>
+__global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa, const H *__restrict__ xb,
+                                                 const float *__restrict__ norms, int64_t npad,
+                                                 int32_t kk, int32_t b, float *__restrict__ dblock,
+                                                 const Hdr *h) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  const int row0_loc = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)b * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  float inv_s2 = 1.f;
+  if (SCALE) {
+    const float s = fp16_scale(h);
+    inv_s2 = 1.f / (s * s);
+  }
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < kk; k0 += 32) {
+    V8 av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      av[a] = *reinterpret_cast<const V8 *>(xa + (row0 + a * 16 + li) * kk + k0 + 8 * lk);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      bv[c] = *reinterpret_cast<const V8 *>(xb + (col0 + c * 16 + li) * kk + k0 + 8 * lk);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if constexpr (sizeof(H) == 2 && __is_same(H, __bf16))
+          acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[c], acc[a][c], 0, 0, 0);
+        else
+          acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + a * 16 + 4 * lk + r;
+      const float ni = norms[(int64_t)b * T + il];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t j = col0 + c * 16 + li;
+        const float dd = (ni + norms[j]) - 2.f * (acc[a][c][r] * inv_s2);
+        dblock[(int64_t)il * npad + j] = fmaxf(dd, 0.f);
       }
     }
   }
@@ -506,9 +689,57 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
             at<int32_t>(ws, L.evals)};
   const double logu = log(perplexity);
   const int64_t vpt_need = (L.n + kCalThreads - 1) / kCalThreads;
+  const unsigned pgrid = (unsigned)((L.npad + 255) / 256);
+  const int32_t k32 = (L.d + 31) / 32 * 32;
+  float *norms32 = at<float>(ws, L.norms32);
+  float *xfT = at<float>(ws, L.xfT);
+  __bf16 *xa_b = at<__bf16>(ws, L.xa), *xb_b = at<__bf16>(ws, L.xb);
+  _Float16 *xa_h = at<_Float16>(ws, L.xa), *xb_h = at<_Float16>(ws, L.xb);
+  switch (L.mode) {
+    case TSNE_DIST_FP32:
+      hipLaunchKernelGGL(k_prep_f32, dim3(pgrid), dim3(256), 0, st, xcT, L.npad, L.dpad, xfT,
+                         norms32);
+      break;
+    case TSNE_DIST_BF16:
+      hipLaunchKernelGGL((k_prep_lp<__bf16, false, false>), dim3(pgrid), dim3(256), 0, st, xcT,
+                         L.npad, L.d, k32, xa_b, xb_b, norms32, h);
+      break;
+    case TSNE_DIST_BF16X3:
+      hipLaunchKernelGGL((k_prep_lp<__bf16, true, false>), dim3(pgrid), dim3(256), 0, st, xcT,
+                         L.npad, L.d, k32, xa_b, xb_b, norms32, h);
+      break;
+    case TSNE_DIST_FP16:
+      hipLaunchKernelGGL((k_prep_lp<_Float16, false, true>), dim3(pgrid), dim3(256), 0, st, xcT,
+                         L.npad, L.d, k32, xa_h, xb_h, norms32, h);
+      break;
+    case TSNE_DIST_FP16X3:
+      hipLaunchKernelGGL((k_prep_lp<_Float16, true, true>), dim3(pgrid), dim3(256), 0, st, xcT,
+                         L.npad, L.d, k32, xa_h, xb_h, norms32, h);
+      break;
+    default:
+      break;
+  }
+  const dim3 dgrid((unsigned)(L.npad / 256), T / 64);
   for (int b = 0; b < L.nb; ++b) {
-    hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / 256), T / 64), dim3(256), 0, st, xcT,
-                       norms, L.npad, L.dpad, b, dblock);
+    switch (L.mode) {
+      case TSNE_DIST_FP32:
+        hipLaunchKernelGGL(k_dist_f32, dgrid, dim3(256), 0, st, xfT, norms32, L.npad, L.dpad, b,
+                           dblock);
+        break;
+      case TSNE_DIST_BF16:
+      case TSNE_DIST_BF16X3:
+        hipLaunchKernelGGL((k_dist_lp<__bf16, v8bf, false>), dgrid, dim3(256), 0, st, xa_b, xb_b,
+                           norms32, L.npad, L.kk, b, dblock, h);
+        break;
+      case TSNE_DIST_FP16:
+      case TSNE_DIST_FP16X3:
+        hipLaunchKernelGGL((k_dist_lp<_Float16, v8h, true>), dgrid, dim3(256), 0, st, xa_h, xb_h,
+                           norms32, L.npad, L.kk, b, dblock, h);
+        break;
+      default:
+        hipLaunchKernelGGL(k_dist_f64, dgrid, dim3(256), 0, st, xcT, norms, L.npad, L.dpad, b,
+                           dblock);
+    }
     const int rows = (int)((L.n - (int64_t)b * T) < T ? (L.n - (int64_t)b * T) : T);
     dim3 g(rows), blk(kCalThreads);
     if (vpt_need <= 1)

@@ -48,6 +48,17 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.xcT = take((size_t)L.dpad * np * 8);
   L.norms = take(np * 8);
   L.dblock = take((size_t)T * np * 4);
+  if (mode == TSNE_DIST_FP32) {
+    L.xfT = take((size_t)L.dpad * np * 4);
+    L.norms32 = take(np * 4);
+  } else if (mode != TSNE_DIST_FP64) {
+    const int32_t k32 = (d + 31) / 32 * 32;
+    const bool split = (mode == TSNE_DIST_BF16X3 || mode == TSNE_DIST_FP16X3);
+    L.kk = split ? 3 * k32 : k32;
+    L.xa = take(np * (size_t)L.kk * 2);
+    L.xb = split ? take(np * (size_t)L.kk * 2) : L.xa;
+    L.norms32 = take(np * 4);
+  }
   L.total = o;
   return L;
 }
@@ -83,7 +94,9 @@ static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 extern "C" {
 
 size_t tsne_workspace_bytes(int64_t n, int32_t d, int32_t dist_mode) {
-  if (!valid_n(n) || d < 1 || d > 65536 || dist_mode != TSNE_DIST_FP64) return 0;
+  if (!valid_n(n) || d < 1 || d > 65536 || dist_mode < TSNE_DIST_FP64 ||
+      dist_mode > TSNE_DIST_FP16X3)
+    return 0;
   return tsne::make_layout(n, d, dist_mode).total;
 }
 
@@ -94,8 +107,8 @@ int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
   if (!x || !ws) return fail(TSNE_E_ARG, "tsne_affinities: null pointer");
   if (!valid_n(n)) return fail(TSNE_E_ARG, "tsne_affinities: n = %lld out of range", (long long)n);
   if (d < 1 || d > 65536) return fail(TSNE_E_ARG, "tsne_affinities: d = %d out of range", d);
-  if (o.dist_mode != TSNE_DIST_FP64)
-    return fail(TSNE_E_ARG, "tsne_affinities: distance mode %d not available", o.dist_mode);
+  if (o.dist_mode < TSNE_DIST_FP64 || o.dist_mode > TSNE_DIST_FP16X3)
+    return fail(TSNE_E_ARG, "tsne_affinities: unknown distance mode %d", o.dist_mode);
   if (o.max_bisect < 1 || !(o.tol_h > 0.0))
     return fail(TSNE_E_ARG, "tsne_affinities: max_bisect >= 1 and tol_h > 0 required");
   if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))

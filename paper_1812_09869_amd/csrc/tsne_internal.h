@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/tsne355.h"
+
 namespace tsne {
 
 // ---------------------------------------------------------------------------
@@ -42,7 +44,9 @@ struct Hdr {
   double z;        // Z of the last force pass
   double c_p;      // sum_{i != j} p_ij ln p_ij
   double p_sum;    // sum_{i != j} p_ij
-  double pad[8];
+  float xmax;      // max |centred x| (operand scaling of the FP16 modes)
+  float pad0;
+  double pad[7];
 };
 static_assert(sizeof(Hdr) <= 256, "header must fit its slot");
 
@@ -53,7 +57,9 @@ struct Layout {
   size_t hdr = 0, beta = 0, S = 0, H = 0, m = 0, a = 0, r = 0, evals = 0;
   size_t P = 0, part = 0, zpart = 0, cpart = 0, ppart = 0, meanpart = 0;
   size_t iter_end = 0;  // end of the part that tsne_step needs
-  size_t xmean = 0, xcT = 0, norms = 0, xlo = 0, dblock = 0;
+  int32_t kk = 0;  // K of the reduced-precision contraction (d rounded up, x3 for split modes)
+  size_t xmean = 0, xcT = 0, norms = 0, dblock = 0;
+  size_t xfT = 0, norms32 = 0, xa = 0, xb = 0;  // reduced-precision operands
   size_t total = 0;
 };
 
