@@ -84,6 +84,147 @@ def measured_traffic(n):
     return rec["traffic_bytes_per_launch"]
 
 
+MODES = ["fp64", "fp32", "fp16x3", "bf16x3", "fp16", "bf16"]
+
+
+def precision_leg(x, lab, n, d, perp, iters, steady_ms):
+    """Affinity time and per-step error of every distance mode at the benchmark size.
+
+    Errors are taken against the FP64 mode (which the parity tests hold to the
+    FP64 oracle at ~1e-6): P on 32 sampled rows (relative Frobenius), the
+    gradient (alpha = 1) and the KL at a fixed clustered map. A mode meets the
+    per-step gates if P <= 1e-5 and gradient <= 1e-4.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1812_09869_amd import _lib, synth
+
+    ws = _lib.new_workspace(n, d, max(MODES, key=lambda m: _lib.workspace_bytes(n, d, m)))
+    rng = np.random.Generator(np.random.PCG64(12))
+    rows = np.sort(rng.choice(n, 32, replace=False))
+    y = torch.from_numpy(synth.clustered_state(lab, seed=31, spread=30.0)).cuda()
+    gbuf = torch.empty_like(y)
+    cost = torch.zeros(2, dtype=torch.float64, device="cuda")
+    res, ref = {}, None
+    for mode in MODES:
+        times = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _lib.affinities(x, perp, ws, dist_mode=mode)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        if _lib.sync_status(ws) != 0:
+            res[mode] = {"status": _lib.sync_status(ws)}
+            continue
+        prow = torch.cat([_lib.export_p_rows(ws, n, int(r), 1) for r in rows]).double().cpu()
+        _lib.gradient(ws, n, y, 1.0, gbuf)
+        g = gbuf.double().cpu()
+        _lib.cost(ws, n, y, cost)
+        kl = float(cost[0].cpu())
+        if ref is None:
+            ref = (prow, g, kl)
+        pe = float(torch.linalg.norm(prow - ref[0]) / torch.linalg.norm(ref[0]))
+        ge = float(torch.linalg.norm(g - ref[1]) / torch.linalg.norm(ref[1]))
+        ke = abs(kl - ref[2]) / ref[2]
+        aff = min(times)
+        res[mode] = {
+            "affinity_ms": aff,
+            "p_rel_vs_fp64": pe,
+            "grad_rel_vs_fp64": ge,
+            "kl_rel_vs_fp64": ke,
+            "end_to_end_iters_per_s": iters / ((aff + iters * steady_ms) * 1e-3),
+            "meets_step_gates": bool(pe <= 1e-5 and ge <= 1e-4),
+        }
+        log(f"[bench] mode {mode:7s} affinities {aff:7.2f} ms  P {pe:.2e}  grad {ge:.2e}  "
+            f"KL {ke:.2e}")
+    del ws
+    return res
+
+
+def precision_report(n=262144, d=128, perp=50.0):
+    """Errors of every distance mode against the FP64 oracle on the 10-D subspace
+    mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
+    computes sampled rows: beta of 64 rows, and P at the 30 nearest and 30 random
+    columns of 24 rows), plus gradient and KL at a fixed clustered map against
+    the FP64 mode. Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1812_09869_amd import _lib, synth
+
+    x_np, lab = synth.subspace(n, d=d)
+    x = torch.from_numpy(x_np).cuda()
+    rng = np.random.Generator(np.random.PCG64(5))
+    brow = np.sort(rng.choice(n, 64, replace=False))
+    prow = np.sort(rng.choice(n, 24, replace=False))
+    t0 = time.perf_counter()
+    st_b = oracle.calibrate(x_np, perp, rows=brow)
+    ii, jj = [], []
+    xd = x_np.astype(np.float64)
+    for i in prow:
+        dist = ((xd - xd[i]) ** 2).sum(axis=1)
+        dist[i] = np.inf
+        cols = np.unique(np.concatenate([np.argsort(dist)[:30], rng.choice(n, 30, replace=False)]))
+        cols = cols[cols != i]
+        ii.extend([int(i)] * cols.size)
+        jj.extend(cols.tolist())
+    ii, jj = np.array(ii), np.array(jj)
+    need = np.unique(np.concatenate([ii, jj]))
+    st = oracle.calibrate(x_np, perp, rows=need)
+    pos = {r: k for k, r in enumerate(need)}
+
+    def pick(idx):
+        k = np.array([pos[r] for r in idx])
+        return oracle.RowStats(st.beta[k], st.m[k], st.S[k], st.H[k], st.iters[k])
+
+    p_ref = oracle.p_entries(x_np, ii, jj, pick(ii), pick(jj))
+    log(f"[precision] oracle references in {time.perf_counter() - t0:.1f} s")
+    ws = _lib.new_workspace(n, d, max(MODES, key=lambda m: _lib.workspace_bytes(n, d, m)))
+    y = torch.from_numpy(synth.clustered_state(lab, seed=41, spread=60.0)).cuda()
+    gbuf = torch.empty_like(y)
+    cost = torch.zeros(2, dtype=torch.float64, device="cuda")
+    out, ref = {}, None
+    for mode in MODES:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _lib.affinities(x, perp, ws, dist_mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        status = _lib.sync_status(ws)
+        beta = _lib.export_rowstats(ws, n)[0].cpu().numpy()
+        p_gpu = np.empty_like(p_ref)
+        for i in prow:
+            row = _lib.export_p_rows(ws, n, int(i), 1).cpu().numpy()[0].astype(np.float64)
+            sel = ii == i
+            p_gpu[sel] = row[jj[sel]]
+        _lib.gradient(ws, n, y, 1.0, gbuf)
+        g = gbuf.double().cpu()
+        _lib.cost(ws, n, y, cost)
+        kl = float(cost[0].cpu())
+        if ref is None:
+            ref = (g, kl)
+        big = p_ref >= 1e-3 * p_ref.max()
+        out[mode] = {
+            "status": status,
+            "affinity_ms": e0.elapsed_time(e1),
+            "beta_maxrel_vs_oracle": float((np.abs(beta[brow] - st_b.beta) / st_b.beta).max()),
+            "p_maxrel_large_vs_oracle": float((np.abs(p_gpu - p_ref)[big] / p_ref[big]).max()),
+            "p_maxabs_over_max_vs_oracle": float(np.abs(p_gpu - p_ref).max() / p_ref.max()),
+            "p_rel_l2_sampled_vs_oracle": float(np.linalg.norm(p_gpu - p_ref) /
+                                                np.linalg.norm(p_ref)),
+            "grad_rel_vs_fp64": float(torch.linalg.norm(g - ref[0]) / torch.linalg.norm(ref[0])),
+            "kl_rel_vs_fp64": abs(kl - ref[1]) / ref[1],
+            "kl": kl,
+        }
+        log(f"[precision] {mode}: {out[mode]}")
+    print(json.dumps({"workload": f"10-D subspace mixture, N={n}, D={d}, perplexity {perp:g}",
+                      "modes": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,7 +233,14 @@ def main():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--iters", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the per-distance-mode affinity timing and error leg")
+    ap.add_argument("--precision-report", action="store_true",
+                    help="only run the per-mode error report at N=262,144, D=128")
     args = ap.parse_args()
+    if args.precision_report:
+        precision_report()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -106,7 +254,7 @@ def main():
 
     _lib.load()
     n, d, perp = args.n, 50, 50.0
-    x_np, _ = synth.gmm_aniso(n)
+    x_np, lab_np = synth.gmm_aniso(n)
     y0_np = synth.embedding_init(n, seed=synth.SEEDS["init_aniso"])
     dev = torch.device("cuda:0")
     x = torch.from_numpy(x_np).to(dev)
@@ -219,6 +367,10 @@ def main():
         "final_kl": kl,
         "final_cnorm": cnorm,
     }
+    if not args.no_precision:
+        del ws
+        torch.cuda.empty_cache()
+        out["dist_modes"] = precision_leg(x, lab_np, n, d, perp, args.iters, steady_ms)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(x_np, perp, n, args.iters)
