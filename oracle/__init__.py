@@ -58,6 +58,13 @@ def _load():
         "orc_step": (None, [_f64p, _i64, _f64p, _f64p, _f64p, _d, _d, _d, _d, ctypes.c_int,
                             ctypes.c_void_p, ctypes.c_void_p]),
         "orc_knn_overlap": (_d, [_f64p, _i64, _i32, _f64p, _i64p, _i64, ctypes.c_int]),
+        "orc_mlp_param_count": (_i64, [ctypes.c_int, ctypes.c_int]),
+        "orc_bf16_round": (None, [_f64p, _i64, _f64p]),
+        "orc_mlp_forward": (None, [_f64p, ctypes.c_int, ctypes.c_int, _f64p, _f64p, _f64p, _i64,
+                                   ctypes.c_int, _f64p]),
+        "orc_mlp_gradient": (_d, [_f64p, ctypes.c_int, ctypes.c_int, _f64p, _f64p, _f64p, _f64p,
+                                  _i64, ctypes.c_int, _f64p]),
+        "orc_adam": (None, [_f64p, _f64p, _f64p, _f64p, _i64, _d, _d, _d, _d, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -240,3 +247,46 @@ def knn_overlap(x, y, rows, k: int = 10) -> float:
     x, y = _f64(x), _f64(y)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     return _load().orc_knn_overlap(x, x.shape[0], x.shape[1], y, rows, rows.shape[0], int(k))
+
+
+# --------------------------------------------------------------------------
+# Surrogate network (not in the paper): 50 -> 256 -> 256 -> 2, ReLU, MSE
+# --------------------------------------------------------------------------
+
+def bf16_round(a) -> np.ndarray:
+    """Round to bfloat16 (nearest even, through float), returned as float64."""
+    a = _f64(a)
+    out = np.empty_like(a)
+    _load().orc_bf16_round(a.ravel(), a.size, out.ravel())
+    return out
+
+
+def mlp_param_count(d_in: int = 50, hidden: int = 256) -> int:
+    return int(_load().orc_mlp_param_count(d_in, hidden))
+
+
+def mlp_forward(params, x, mean, invstd, hidden: int = 256, emulate: bool = False):
+    """out = W3 relu(W2 relu(W1 (x - mean) invstd + b1) + b2) + b3, rows of x."""
+    x = _f64(x)
+    B, d_in = x.shape
+    out = np.empty((B, 2))
+    _load().orc_mlp_forward(_f64(params), d_in, hidden, _f64(mean), _f64(invstd), x, B,
+                            int(emulate), out)
+    return out
+
+
+def mlp_gradient(params, x, y, mean, invstd, hidden: int = 256, emulate: bool = False):
+    """(loss, packed gradient) of L = (1/2B) sum |out - y|^2."""
+    x = _f64(x)
+    B, d_in = x.shape
+    g = np.empty(mlp_param_count(d_in, hidden))
+    loss = _load().orc_mlp_gradient(_f64(params), d_in, hidden, _f64(mean), _f64(invstd), x,
+                                    _f64(y), B, int(emulate), g)
+    return loss, g
+
+
+def adam(p, g, m, v, lr, beta1, beta2, eps, t):
+    """One Adam step (t is 1-based), in place on p, m, v (float64 arrays)."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _load().orc_adam(p, _f64(g), m, v, p.shape[0], lr, beta1, beta2, eps, int(t))
