@@ -155,6 +155,49 @@ TSNE_API int tsne_export_scalars(void *ws, int64_t n, double *out, void *stream)
 TSNE_API int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *out,
                        void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate (not in the paper): an MLP d_in -> H -> H -> 2 with ReLU
+ * that maps input points to their embedding, trained on (x, y) pairs that
+ * the exact path produced. Exact t-SNE (tsne_step) stays the fallback: a
+ * short refinement seeded from the network's output.
+ *
+ * Parameters are one packed FP32 device array: W1 [H][d_in], b1 [H],
+ * W2 [H][H], b2 [H], W3 [2][H], b3 [2] (row-major, out x in). Inputs are
+ * standardised as (x - mean) * invstd (mean, invstd: device float[d_in]).
+ * The two wide layers run as BF16 MFMA contractions with FP32 accumulation
+ * (operands rounded to nearest even), the output layer in FP32.
+ * Limits: 1 <= d_in <= 64, H in {64, 128, 192, 256}.
+ * ---------------------------------------------------------------------- */
+
+/* Number of packed parameters (79,362 for d_in = 50, H = 256). */
+TSNE_API int64_t tsne_mlp_param_count(int32_t d_in, int32_t hidden);
+
+/* Workspace bytes for batches of up to `batch` rows; train != 0 adds the
+ * buffers of the backward pass. 0 if the arguments are out of range. */
+TSNE_API size_t tsne_mlp_workspace_bytes(int32_t d_in, int32_t hidden, int64_t batch,
+                                         int32_t train);
+
+/* out (n x 2 FP32) = network(x) for the n rows of x (n x d_in FP32). Rows are
+ * processed in chunks of the batch size the workspace was sized for. */
+TSNE_API int tsne_mlp_forward(const float *params, int32_t d_in, int32_t hidden,
+                              const float *mean, const float *invstd, const float *x, int64_t n,
+                              float *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Gradient of L = (1 / (2B)) sum_b |net(x_b) - y_b|^2 over a batch of B rows,
+ * rows idx[0..B) of x and y (idx: device int32, or NULL for rows 0..B-1).
+ * grad: packed FP32 like params (fully overwritten); loss: device double. */
+TSNE_API int tsne_mlp_gradient(const float *params, int32_t d_in, int32_t hidden,
+                               const float *mean, const float *invstd, const float *x,
+                               const float *y, const int32_t *idx, int64_t batch, float *grad,
+                               double *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step t (1-based) on count packed FP32 parameters, in place on
+ * params, m and v: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+TSNE_API int tsne_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count,
+                           float lr, float beta1, float beta2, float eps, int32_t t,
+                           void *stream);
+
 #ifdef __cplusplus
 }
 #endif

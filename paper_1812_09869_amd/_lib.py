@@ -42,6 +42,11 @@ EXPORTED = [
     "tsne_export_rowstats",
     "tsne_export_scalars",
     "tsne_export_p_rows",
+    "tsne_mlp_param_count",
+    "tsne_mlp_workspace_bytes",
+    "tsne_mlp_forward",
+    "tsne_mlp_gradient",
+    "tsne_mlp_adam",
 ]
 
 
@@ -94,6 +99,14 @@ def load(path: str = LIB_PATH):
         "tsne_export_rowstats": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
         "tsne_export_scalars": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
         "tsne_export_p_rows": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),
+        "tsne_mlp_param_count": (ctypes.c_int64, [_i32, _i32]),
+        "tsne_mlp_workspace_bytes": (ctypes.c_size_t, [_i32, _i32, _i64, _i32]),
+        "tsne_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp,
+                                            ctypes.c_size_t, _vp]),
+        "tsne_mlp_gradient": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
+                                             _vp, _vp, ctypes.c_size_t, _vp]),
+        "tsne_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, _i32, _vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -220,3 +233,39 @@ def export_p_rows(ws, n, row0, nrows):
     _check(load().tsne_export_p_rows(_ptr(ws, torch.uint8, name="ws"), n, row0, nrows, _ptr(out),
                                      _stream()))
     return out
+
+
+# --------------------------------------------------------------------------
+# Surrogate network
+# --------------------------------------------------------------------------
+
+def mlp_param_count(d_in: int, hidden: int) -> int:
+    return int(load().tsne_mlp_param_count(d_in, hidden))
+
+
+def mlp_new_workspace(d_in: int, hidden: int, batch: int, train: bool, device="cuda"):
+    nbytes = int(load().tsne_mlp_workspace_bytes(d_in, hidden, batch, 1 if train else 0))
+    if nbytes == 0:
+        raise TsneError(1, f"no surrogate workspace for d_in={d_in}, hidden={hidden}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def mlp_forward(params, d_in, hidden, mean, invstd, x, out, ws):
+    n = x.shape[0]
+    _check(load().tsne_mlp_forward(_ptr(params, name="params"), d_in, hidden, _ptr(mean),
+                                   _ptr(invstd), _ptr(x, shape=(n, d_in), name="x"), n,
+                                   _ptr(out, shape=(n, 2), name="out"),
+                                   _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()))
+
+
+def mlp_gradient(params, d_in, hidden, mean, invstd, x, y, idx, batch, grad, loss, ws):
+    _check(load().tsne_mlp_gradient(_ptr(params, name="params"), d_in, hidden, _ptr(mean),
+                                    _ptr(invstd), _ptr(x, name="x"), _ptr(y, name="y"),
+                                    _ptr(idx, torch.int32, name="idx"), batch,
+                                    _ptr(grad, name="grad"), _ptr(loss, torch.float64, name="loss"),
+                                    _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()))
+
+
+def mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, t):
+    _check(load().tsne_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), lr,
+                                beta1, beta2, eps, int(t), _stream()))

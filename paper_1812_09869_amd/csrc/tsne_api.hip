@@ -7,6 +7,7 @@
 
 #include "../../include/tsne355.h"
 #include "tsne_internal.h"
+#include "tsne_mlp.h"
 
 namespace tsne {
 
@@ -230,6 +231,86 @@ int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *
   const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
   return hip_check(tsne::launch_export_p_rows(L, ws, row0, nrows, out, (hipStream_t)stream),
                    "tsne_export_p_rows");
+}
+
+static bool mlp_dims_ok(int32_t d_in, int32_t hidden) {
+  return d_in >= 1 && d_in <= 64 && hidden >= 64 && hidden <= 256 && hidden % 64 == 0;
+}
+
+int64_t tsne_mlp_param_count(int32_t d_in, int32_t hidden) {
+  if (!mlp_dims_ok(d_in, hidden)) return 0;
+  return (int64_t)hidden * d_in + hidden + (int64_t)hidden * hidden + hidden + 2 * hidden + 2;
+}
+
+size_t tsne_mlp_workspace_bytes(int32_t d_in, int32_t hidden, int64_t batch, int32_t train) {
+  if (!mlp_dims_ok(d_in, hidden) || batch < 1 || batch > ((int64_t)1 << 28)) return 0;
+  return tsne::make_mlp_layout(d_in, hidden, (batch + 63) / 64 * 64, train != 0).total;
+}
+
+// Largest batch (multiple of 64) whose layout fits in ws_bytes, or 0.
+static int64_t mlp_capacity(int32_t d_in, int32_t hidden, size_t ws_bytes, bool train) {
+  if (tsne::make_mlp_layout(d_in, hidden, 64, train).total > ws_bytes) return 0;
+  int64_t lo = 64, hi = 128;
+  while (hi <= ((int64_t)1 << 28) && tsne::make_mlp_layout(d_in, hidden, hi, train).total <= ws_bytes)
+    hi *= 2;
+  while (hi - lo > 64) {
+    int64_t mid = (lo + hi) / 2 / 64 * 64;
+    if (mid <= lo) break;
+    if (tsne::make_mlp_layout(d_in, hidden, mid, train).total <= ws_bytes)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+int tsne_mlp_forward(const float *params, int32_t d_in, int32_t hidden, const float *mean,
+                     const float *invstd, const float *x, int64_t n, float *out, void *ws,
+                     size_t ws_bytes, void *stream) {
+  if (!params || !mean || !invstd || !x || !out || !ws)
+    return fail(TSNE_E_ARG, "tsne_mlp_forward: null pointer");
+  if (!mlp_dims_ok(d_in, hidden) || n < 1)
+    return fail(TSNE_E_ARG, "tsne_mlp_forward: unsupported d_in %d / hidden %d / n %lld", d_in,
+                hidden, (long long)n);
+  if (!aligned(ws, 256)) return fail(TSNE_E_WORKSPACE, "tsne_mlp_forward: ws not 256-byte aligned");
+  const int64_t cap = mlp_capacity(d_in, hidden, ws_bytes, false);
+  if (cap == 0) return fail(TSNE_E_WORKSPACE, "tsne_mlp_forward: workspace too small");
+  const tsne::MlpLayout L = tsne::make_mlp_layout(d_in, hidden, cap, false);
+  return hip_check(tsne::launch_mlp_forward(L, params, mean, invstd, x, n, out, ws,
+                                            (hipStream_t)stream),
+                   "tsne_mlp_forward");
+}
+
+int tsne_mlp_gradient(const float *params, int32_t d_in, int32_t hidden, const float *mean,
+                      const float *invstd, const float *x, const float *y, const int32_t *idx,
+                      int64_t batch, float *grad, double *loss, void *ws, size_t ws_bytes,
+                      void *stream) {
+  if (!params || !mean || !invstd || !x || !y || !grad || !loss || !ws)
+    return fail(TSNE_E_ARG, "tsne_mlp_gradient: null pointer");
+  if (!mlp_dims_ok(d_in, hidden) || batch < 1)
+    return fail(TSNE_E_ARG, "tsne_mlp_gradient: unsupported d_in %d / hidden %d / batch %lld",
+                d_in, hidden, (long long)batch);
+  if (!aligned(ws, 256))
+    return fail(TSNE_E_WORKSPACE, "tsne_mlp_gradient: ws not 256-byte aligned");
+  const int64_t bpad = (batch + 63) / 64 * 64;
+  const tsne::MlpLayout L = tsne::make_mlp_layout(d_in, hidden, bpad, true);
+  if (L.total > ws_bytes)
+    return fail(TSNE_E_WORKSPACE, "tsne_mlp_gradient: workspace %zu bytes, need %zu", ws_bytes,
+                L.total);
+  return hip_check(tsne::launch_mlp_gradient(L, params, mean, invstd, x, y, idx, batch, grad, loss,
+                                             ws, (hipStream_t)stream),
+                   "tsne_mlp_gradient");
+}
+
+int tsne_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count, float lr,
+                  float beta1, float beta2, float eps, int32_t t, void *stream) {
+  if (!params || !grad || !m || !v) return fail(TSNE_E_ARG, "tsne_mlp_adam: null pointer");
+  if (count < 1 || t < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(TSNE_E_ARG, "tsne_mlp_adam: invalid arguments");
+  return hip_check(tsne::launch_adam(params, grad, m, v, count, lr, beta1, beta2, eps, t,
+                                     (hipStream_t)stream),
+                   "tsne_mlp_adam");
 }
 
 }  // extern "C"

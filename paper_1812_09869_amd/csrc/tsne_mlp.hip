@@ -1,0 +1,416 @@
+// Surrogate network on the GPU: 50 -> 256 -> 256 -> 2 (d_in -> H -> H -> 2),
+// ReLU, trained by mean squared error to map input points to their t-SNE
+// embedding, with BF16 MFMA contractions (FP32 accumulation) for the two wide
+// layers and FP32 VALU for the 2-wide output layer.
+//
+// Packed FP32 parameters: W1 [H][d_in], b1 [H], W2 [H][H], b2 [H], W3 [2][H],
+// b3 [2]. Inputs are standardised ((x - mean) * invstd) and rounded to BF16;
+// W1 and W2 are rounded to BF16 copies before each pass; hidden activations
+// are kept in FP32 and rounded to BF16 where they feed a contraction.
+#include <math.h>
+
+#include "tsne_internal.h"
+#include "tsne_mlp.h"
+
+namespace tsne {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kK1 = 64;  // d_in rounded up to the MFMA K step (d_in <= 64)
+
+// ----------------------------------------------------------------------------
+// Generic C[M][N] = sum_k A[m][k] B[n][k] on v_mfma_f32_16x16x32_bf16 with a
+// fused epilogue. One wave computes a 64 x 64 block (4 x 4 MFMA tiles); lane l
+// supplies rows l%16 of A and B with k-slice 8(l/16) .. 8(l/16)+7 and receives
+// D[4(l/16) + r][l%16] in element r. M, N multiples of 64, K of 32.
+// ----------------------------------------------------------------------------
+struct Epi {
+  const float *bias;   // per column n, or null
+  int relu;            // max(v, 0)
+  const float *mask;   // keep v only where mask[m * ldm + n] > 0, or null
+  int ldm;
+  float *outF;         // FP32 result [m * ldf + n] for n < nvalid, or null
+  int ldf, nvalid;
+  __bf16 *outB;        // BF16 result [m * ldb + n], or null
+  int ldb;
+  __bf16 *outBT;       // BF16 transposed result [n * ldt + m], or null
+  int ldt;
+};
+
+__global__ __launch_bounds__(64) void k_gemm_bf16(const __bf16 *__restrict__ A, int lda,
+                                                  const __bf16 *__restrict__ Bm, int ldbm, int K,
+                                                  Epi e) {
+  const int64_t m0 = (int64_t)blockIdx.x * 64;
+  const int n0 = blockIdx.y * 64;
+  const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    v8bf av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      av[a] = *reinterpret_cast<const v8bf *>(A + (m0 + a * 16 + li) * lda + k0 + 8 * lk);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      bv[c] = *reinterpret_cast<const v8bf *>(Bm + (int64_t)(n0 + c * 16 + li) * ldbm + k0 +
+                                              8 * lk);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[c], acc[a][c], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + a * 16 + 4 * lk + r;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int n = n0 + c * 16 + li;
+        float v = acc[a][c][r];
+        if (e.bias) v += e.bias[n];
+        if (e.relu) v = fmaxf(v, 0.f);
+        if (e.mask && !(e.mask[m * e.ldm + n] > 0.f)) v = 0.f;
+        if (e.outF && n < e.nvalid) e.outF[m * e.ldf + n] = v;
+        if (e.outB) e.outB[m * e.ldb + n] = (__bf16)v;
+        if (e.outBT) e.outBT[(int64_t)n * e.ldt + m] = (__bf16)v;
+      }
+    }
+  }
+}
+
+// BF16 copies of W1 (zero-padded to [H][kK1]), W2 and W2 transposed.
+__global__ void k_mlp_cast(const float *__restrict__ p, int d_in, int H, __bf16 *__restrict__ w1b,
+                           __bf16 *__restrict__ w2b, __bf16 *__restrict__ w2tb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const float *w1 = p, *w2 = p + (int64_t)H * d_in + H;
+  if (i < (int64_t)H * kK1) {
+    const int j = (int)(i / kK1), k = (int)(i % kK1);
+    w1b[i] = (__bf16)(k < d_in ? w1[(int64_t)j * d_in + k] : 0.f);
+  }
+  if (i < (int64_t)H * H) {
+    const int j = (int)(i / H), k = (int)(i % H);
+    const __bf16 v = (__bf16)w2[i];
+    w2b[i] = v;
+    w2tb[(int64_t)k * H + j] = v;
+  }
+}
+
+// Standardised BF16 inputs for a batch (rows idx[b] of x, or rows row0 + b).
+__global__ void k_mlp_gather(const float *__restrict__ x, int d_in, const float *__restrict__ mean,
+                             const float *__restrict__ invstd, const int32_t *__restrict__ idx,
+                             int64_t row0, int64_t B, int64_t Bpad, const float *__restrict__ y,
+                             __bf16 *__restrict__ xb, __bf16 *__restrict__ xbt,
+                             float *__restrict__ yb) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= Bpad) return;
+  const bool ok = b < B;
+  const int64_t r = ok ? (idx ? (int64_t)idx[b] : row0 + b) : 0;
+  for (int k = 0; k < kK1; ++k) {
+    float v = 0.f;
+    if (ok && k < d_in) v = (x[r * d_in + k] - mean[k]) * invstd[k];
+    const __bf16 hv = (__bf16)v;
+    xb[b * kK1 + k] = hv;
+    if (xbt) xbt[(int64_t)k * Bpad + b] = hv;
+  }
+  if (yb) {
+    yb[2 * b] = ok ? y[2 * r] : 0.f;
+    yb[2 * b + 1] = ok ? y[2 * r + 1] : 0.f;
+  }
+}
+
+// Output layer out = W3 h2 + b3 (FP32), one thread per row. With targets:
+// dout = (out - y) / B_total, per-row loss 0.5 |out - y|^2 summed per block,
+// and dh2 = (W3^T dout) masked by h2 > 0 (FP32, BF16 and BF16 transposed).
+__global__ __launch_bounds__(256) void k_mlp_head(
+    const float *__restrict__ h2, int H, const float *__restrict__ w3, const float *__restrict__ b3,
+    int64_t B, int64_t Bpad, const float *__restrict__ yb, double inv_batch, float *__restrict__ out,
+    int64_t out_row0, float *__restrict__ dout, float *__restrict__ dh2, __bf16 *__restrict__ dh2b,
+    __bf16 *__restrict__ dh2t, double *__restrict__ loss_part) {
+  __shared__ float sw[2 * 256];
+  __shared__ double red[4];
+  for (int k = threadIdx.x; k < 2 * H; k += 256) sw[k] = w3[k];
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double lsum = 0.0;
+  if (b < Bpad) {
+    const float *hr = h2 + b * H;
+    float o0 = 0.f, o1 = 0.f;
+    for (int k = 0; k < H; ++k) {
+      const float h = hr[k];
+      o0 = fmaf(sw[k], h, o0);
+      o1 = fmaf(sw[H + k], h, o1);
+    }
+    o0 += b3[0];
+    o1 += b3[1];
+    if (b < B && out) {
+      out[2 * (out_row0 + b)] = o0;
+      out[2 * (out_row0 + b) + 1] = o1;
+    }
+    if (yb) {
+      float d0 = 0.f, d1 = 0.f;
+      if (b < B) {
+        const float e0 = o0 - yb[2 * b], e1 = o1 - yb[2 * b + 1];
+        lsum = 0.5 * ((double)e0 * e0 + (double)e1 * e1);
+        d0 = (float)(e0 * inv_batch);
+        d1 = (float)(e1 * inv_batch);
+      }
+      dout[2 * b] = d0;
+      dout[2 * b + 1] = d1;
+      for (int k = 0; k < H; ++k) {
+        float g = fmaf(d0, sw[k], d1 * sw[H + k]);
+        if (!(hr[k] > 0.f)) g = 0.f;
+        dh2[b * H + k] = g;
+        dh2b[b * H + k] = (__bf16)g;
+        dh2t[(int64_t)k * Bpad + b] = (__bf16)g;
+      }
+    }
+  }
+  if (loss_part) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+// Column sums over the batch: out[n] = sum_b D[b][n] (one thread per column).
+__global__ void k_colsum(const float *__restrict__ D, int64_t B, int N, float *__restrict__ out) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int64_t b = 0; b < B; ++b) s += D[b * N + n];
+  out[n] = s;
+}
+
+// dW3[c][k] = sum_b dout[b][c] h2[b][k]; db3[c] = sum_b dout[b][c].
+__global__ void k_head_wgrad(const float *__restrict__ dout, const float *__restrict__ h2, int64_t B,
+                             int H, float *__restrict__ gw3, float *__restrict__ gb3) {
+  const int k = threadIdx.x;
+  if (k < H) {
+    float s0 = 0.f, s1 = 0.f;
+    for (int64_t b = 0; b < B; ++b) {
+      const float h = h2[b * H + k];
+      s0 = fmaf(dout[2 * b], h, s0);
+      s1 = fmaf(dout[2 * b + 1], h, s1);
+    }
+    gw3[k] = s0;
+    gw3[H + k] = s1;
+  }
+  if (k < 2) {
+    float s = 0.f;
+    for (int64_t b = 0; b < B; ++b) s += dout[2 * b + k];
+    gb3[k] = s;
+  }
+}
+
+__global__ void k_loss_reduce(const double *__restrict__ part, int nparts, double inv_batch,
+                              double *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < nparts; ++q) s += part[q];
+    *out = s * inv_batch;
+  }
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t count, float lr, float beta1, float beta2,
+                       float eps, float inv_c1, float inv_c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = beta1 * m[i] + (1.f - beta1) * gi;
+  const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * inv_c1) / (sqrtf(vi * inv_c2) + eps);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Workspace layout for a batch of up to Bpad rows (Bpad multiple of 64)
+// ----------------------------------------------------------------------------
+MlpLayout make_mlp_layout(int d_in, int H, int64_t Bpad, bool train) {
+  MlpLayout L;
+  L.d_in = d_in;
+  L.H = H;
+  L.Bpad = Bpad;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = (o + bytes + 255) / 256 * 256;
+    return at;
+  };
+  const size_t B = (size_t)Bpad, Hs = (size_t)H;
+  L.w1b = take(Hs * kK1 * 2);
+  L.w2b = take(Hs * Hs * 2);
+  L.w2tb = take(Hs * Hs * 2);
+  L.xb = take(B * kK1 * 2);
+  L.h1b = take(B * Hs * 2);
+  L.h2 = take(B * Hs * 4);
+  L.loss_part = take((B / 256 + 1) * 8);
+  if (train) {
+    L.xbt = take(B * kK1 * 2);
+    L.yb = take(B * 2 * 4);
+    L.h1 = take(B * Hs * 4);
+    L.h1t = take(B * Hs * 2);
+    L.dout = take(B * 2 * 4);
+    L.dh2 = take(B * Hs * 4);
+    L.dh2b = take(B * Hs * 2);
+    L.dh2t = take(B * Hs * 2);
+    L.dh1 = take(B * Hs * 4);
+    L.dh1t = take(B * Hs * 2);
+    L.gw1 = take(Hs * kK1 * 4);
+  }
+  L.total = o;
+  return L;
+}
+
+static Epi epi() {
+  Epi e{};
+  e.nvalid = 1 << 30;
+  return e;
+}
+
+// Forward pass of rows [row0, row0 + B) (or idx[0..B)) of x into out.
+static void forward_chunk(const MlpLayout &L, const float *params, const float *mean,
+                          const float *invstd, const float *x, const int32_t *idx, int64_t row0,
+                          int64_t B, float *out, void *ws, hipStream_t st) {
+  const int H = L.H;
+  const int64_t Bpad = (B + 63) / 64 * 64;
+  const float *b1 = params + (int64_t)H * L.d_in, *b2 = b1 + H + (int64_t)H * H;
+  const float *w3 = b2 + H, *b3 = w3 + 2 * H;
+  __bf16 *xb = at<__bf16>(ws, L.xb), *h1b = at<__bf16>(ws, L.h1b);
+  float *h2 = at<float>(ws, L.h2);
+  hipLaunchKernelGGL(k_mlp_gather, dim3((unsigned)((Bpad + 255) / 256)), dim3(256), 0, st, x,
+                     L.d_in, mean, invstd, idx, row0, B, Bpad, nullptr, xb, nullptr, nullptr);
+  Epi e1 = epi();
+  e1.bias = b1;
+  e1.relu = 1;
+  e1.outB = h1b;
+  e1.ldb = H;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, xb, kK1,
+                     at<const __bf16>(ws, L.w1b), kK1, kK1, e1);
+  Epi e2 = epi();
+  e2.bias = b2;
+  e2.relu = 1;
+  e2.outF = h2;
+  e2.ldf = H;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, h1b, H,
+                     at<const __bf16>(ws, L.w2b), H, H, e2);
+  hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)((Bpad + 255) / 256)), dim3(256), 0, st, h2, H,
+                     w3, b3, B, Bpad, nullptr, 0.0, out, row0 * (idx ? 0 : 1), nullptr, nullptr,
+                     nullptr, nullptr, nullptr);
+}
+
+hipError_t launch_mlp_cast(const MlpLayout &L, const float *params, void *ws, hipStream_t st) {
+  const int64_t cnt = (int64_t)L.H * (L.H > kK1 ? L.H : kK1);
+  hipLaunchKernelGGL(k_mlp_cast, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, params,
+                     L.d_in, L.H, at<__bf16>(ws, L.w1b), at<__bf16>(ws, L.w2b),
+                     at<__bf16>(ws, L.w2tb));
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpLayout &L, const float *params, const float *mean,
+                              const float *invstd, const float *x, int64_t n, float *out, void *ws,
+                              hipStream_t st) {
+  hipError_t e = launch_mlp_cast(L, params, ws, st);
+  for (int64_t r = 0; r < n && e == hipSuccess; r += L.Bpad) {
+    const int64_t B = (n - r) < L.Bpad ? (n - r) : L.Bpad;
+    forward_chunk(L, params, mean, invstd, x, nullptr, r, B, out, ws, st);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const float *mean,
+                               const float *invstd, const float *x, const float *y,
+                               const int32_t *idx, int64_t B, float *grad, double *loss,
+                               void *ws, hipStream_t st) {
+  const int H = L.H, d_in = L.d_in;
+  const int64_t Bpad = (B + 63) / 64 * 64;
+  const float *b1 = params + (int64_t)H * d_in, *b2 = b1 + H + (int64_t)H * H;
+  const float *w3 = b2 + H, *b3 = w3 + 2 * H;
+  float *g_w1 = grad, *g_b1 = g_w1 + (int64_t)H * d_in, *g_w2 = g_b1 + H,
+        *g_b2 = g_w2 + (int64_t)H * H, *g_w3 = g_b2 + H, *g_b3 = g_w3 + 2 * H;
+  __bf16 *xb = at<__bf16>(ws, L.xb), *xbt = at<__bf16>(ws, L.xbt), *h1b = at<__bf16>(ws, L.h1b),
+         *h1t = at<__bf16>(ws, L.h1t), *dh2b = at<__bf16>(ws, L.dh2b),
+         *dh2t = at<__bf16>(ws, L.dh2t), *dh1t = at<__bf16>(ws, L.dh1t);
+  float *yb = at<float>(ws, L.yb), *h1 = at<float>(ws, L.h1), *h2 = at<float>(ws, L.h2),
+        *dout = at<float>(ws, L.dout), *dh2 = at<float>(ws, L.dh2), *dh1 = at<float>(ws, L.dh1);
+  double *lp = at<double>(ws, L.loss_part);
+  hipError_t err = launch_mlp_cast(L, params, ws, st);
+  if (err != hipSuccess) return err;
+  const dim3 g256((unsigned)((Bpad + 255) / 256));
+  hipLaunchKernelGGL(k_mlp_gather, g256, dim3(256), 0, st, x, d_in, mean, invstd, idx, 0, B, Bpad,
+                     y, xb, xbt, yb);
+  // forward
+  Epi e1 = epi();
+  e1.bias = b1;
+  e1.relu = 1;
+  e1.outF = h1;
+  e1.ldf = H;
+  e1.outB = h1b;
+  e1.ldb = H;
+  e1.outBT = h1t;
+  e1.ldt = (int)Bpad;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, xb, kK1,
+                     at<const __bf16>(ws, L.w1b), kK1, kK1, e1);
+  Epi e2 = epi();
+  e2.bias = b2;
+  e2.relu = 1;
+  e2.outF = h2;
+  e2.ldf = H;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, h1b, H,
+                     at<const __bf16>(ws, L.w2b), H, H, e2);
+  hipLaunchKernelGGL(k_mlp_head, g256, dim3(256), 0, st, h2, H, w3, b3, B, Bpad, yb,
+                     1.0 / (double)B, nullptr, (int64_t)0, dout, dh2, dh2b, dh2t, lp);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, st, lp, (int)g256.x, 1.0 / (double)B,
+                     loss);
+  // output layer gradients
+  hipLaunchKernelGGL(k_head_wgrad, dim3(1), dim3(256), 0, st, dout, h2, Bpad, H, g_w3, g_b3);
+  // second layer: dW2 = dh2^T h1, db2 = colsum(dh2), dh1 = (dh2 W2) masked by h1 > 0
+  Epi ew2 = epi();
+  ew2.outF = g_w2;
+  ew2.ldf = H;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(H / 64, H / 64), dim3(64), 0, st, dh2t, (int)Bpad, h1t,
+                     (int)Bpad, (int)Bpad, ew2);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, dh2, Bpad, H, g_b2);
+  Epi ed1 = epi();
+  ed1.mask = h1;
+  ed1.ldm = H;
+  ed1.outF = dh1;
+  ed1.ldf = H;
+  ed1.outBT = dh1t;
+  ed1.ldt = (int)Bpad;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, dh2b, H,
+                     at<const __bf16>(ws, L.w2tb), H, H, ed1);
+  // first layer: dW1 = dh1^T xh (columns beyond d_in dropped), db1 = colsum(dh1)
+  Epi ew1 = epi();
+  ew1.outF = g_w1;
+  ew1.ldf = d_in;
+  ew1.nvalid = d_in;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3(H / 64, kK1 / 64), dim3(64), 0, st, dh1t, (int)Bpad, xbt,
+                     (int)Bpad, (int)Bpad, ew1);
+  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, dh1, Bpad, H, g_b1);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
+                       float beta1, float beta2, float eps, int32_t t, hipStream_t st) {
+  const double c1 = 1.0 - pow((double)beta1, t), c2 = 1.0 - pow((double)beta2, t);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, g, m, v,
+                     count, lr, beta1, beta2, eps, (float)(1.0 / c1), (float)(1.0 / c2));
+  return hipGetLastError();
+}
+
+}  // namespace tsne

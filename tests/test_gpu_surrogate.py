@@ -1,0 +1,132 @@
+"""Surrogate network on the GPU against the FP64 oracle, and its gain over exact t-SNE alone.
+
+Kernel parity compares with the oracle run with the same BF16 operand
+rounding (so the remaining difference is FP32 accumulation order), and reports
+the distance to the plain FP64 network as well. The quality of the learned
+map itself is parity unpinned (the surrogate is not in the paper); the gain
+test shows what it buys: at an equal budget of 100 exact iterations,
+refining the surrogate's map reaches a lower KL than exact t-SNE from a random
+start.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1812_09869_amd import _lib, synth
+from paper_1812_09869_amd.surrogate import Surrogate
+from paper_1812_09869_amd.tsne import ExactTSNE, Schedule
+
+pytestmark = pytest.mark.gpu
+
+D, H = 50, 256
+
+
+def _setup(B, seed=3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = oracle.mlp_param_count(D, H)
+    p = (rng.standard_normal(n) * 0.08).astype(np.float32)
+    x, _ = synth.gmm_aniso(B, sample_seed=seed)
+    y = rng.standard_normal((B, 2)).astype(np.float32)
+    mean = x.mean(axis=0).astype(np.float32)
+    invstd = (1.0 / x.std(axis=0)).astype(np.float32)
+    return p, x, y, mean, invstd
+
+
+def _blocks(v):
+    o, out = 0, {}
+    for name, size in (("W1", H * D), ("b1", H), ("W2", H * H), ("b2", H), ("W3", 2 * H),
+                       ("b3", 2)):
+        out[name] = v[o:o + size]
+        o += size
+    return out
+
+
+def _t(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+@pytest.mark.parametrize("B", [300, 1024])
+def test_gradient_parity(B):
+    p, x, y, mean, invstd = _setup(B)
+    loss_e, g_e = oracle.mlp_gradient(p, x, y, mean, invstd, H, emulate=True)
+    loss_f, g_f = oracle.mlp_gradient(p, x, y, mean, invstd, H, emulate=False)
+    ws = _lib.mlp_new_workspace(D, H, B, True)
+    grad = torch.empty(p.size, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    _lib.mlp_gradient(_t(p), D, H, _t(mean), _t(invstd), _t(x), _t(y), None, B, grad, loss, ws)
+    g = grad.cpu().numpy().astype(np.float64)
+    lg = float(loss.cpu()[0])
+    print(f"\n  B={B} loss gpu {lg:.8f} oracle(bf16) {loss_e:.8f} oracle(fp64) {loss_f:.8f}")
+    assert abs(lg - loss_e) <= 1e-5 * loss_e
+    for name, ge in _blocks(g_e).items():
+        gg, gf = _blocks(g)[name], _blocks(g_f)[name]
+        rel_e = np.linalg.norm(gg - ge) / np.linalg.norm(ge)
+        rel_f = np.linalg.norm(gg - gf) / np.linalg.norm(gf)
+        print(f"  {name}: rel-L2 vs bf16-emulating oracle {rel_e:.2e}, vs fp64 oracle {rel_f:.2e}")
+        assert rel_e <= 1e-4
+        assert rel_f <= 5e-2
+
+
+def test_forward_parity_chunked():
+    """n = 1000 rows through a workspace sized for 256: three full chunks and a ragged one."""
+    n = 1000
+    p, x, _, mean, invstd = _setup(n, seed=5)
+    ref = oracle.mlp_forward(p, x, mean, invstd, H, emulate=True)
+    ws = _lib.mlp_new_workspace(D, H, 256, False)
+    out = torch.empty((n, 2), device="cuda")
+    _lib.mlp_forward(_t(p), D, H, _t(mean), _t(invstd), _t(x), out, ws)
+    rel = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
+    print(f"\n  forward rel-L2 vs bf16-emulating oracle {rel:.2e}")
+    assert rel <= 1e-4
+
+
+def test_adam_parity():
+    rng = np.random.Generator(np.random.PCG64(8))
+    cnt = 5000
+    p = rng.standard_normal(cnt).astype(np.float32)
+    m = np.zeros(cnt)
+    v = np.zeros(cnt)
+    pr = p.astype(np.float64)
+    pt, mt, vt = _t(p), torch.zeros(cnt, device="cuda"), torch.zeros(cnt, device="cuda")
+    for t in range(1, 4):
+        g = rng.standard_normal(cnt).astype(np.float32)
+        oracle.adam(pr, g.astype(np.float64), m, v, 1e-3, 0.9, 0.999, 1e-8, t)
+        _lib.mlp_adam(pt, _t(g), mt, vt, 1e-3, 0.9, 0.999, 1e-8, t)
+    rel = np.abs(pt.cpu().numpy() - pr).max() / np.abs(pr).max()
+    print(f"\n  Adam after 3 steps: max abs diff / max |p| {rel:.2e}")
+    assert rel <= 1e-6
+
+
+def test_training_gain():
+    """Scaled-down surrogate experiment (N = 8,192 in D = 50)."""
+    n = 8192
+    x, lab = synth.gmm_aniso(n, sample_seed=71)
+    model = ExactTSNE(_t(x), 50.0)
+    state = model.init_state(_t(synth.embedding_init(n, seed=72)))
+    model.run(state, 500)
+    y = state[0].clone()
+    net = Surrogate(D, H, seed=synth.SEEDS["surrogate_init"])
+    losses = net.fit(_t(x), y, epochs=30, batch=512)
+    print(f"\n  training loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.5 * losses[0]
+    # new points from the same mixture
+    xn, _ = synth.gmm_aniso(n, sample_seed=73)
+    xnt = _t(xn)
+    ynet = net.predict(xnt)
+    new = ExactTSNE(xnt, 50.0)
+    kl_net = float(new.cost(ynet).cpu()[0])
+    refine = Schedule(switch=0, exaggeration=1.0, mom_late=0.8)
+    st = new.init_state(ynet)
+    new.run(st, 100, sched=refine)
+    kl_ref = float(new.cost(st[0]).cpu()[0])
+    st0 = new.init_state(_t(synth.embedding_init(n, seed=74)))
+    new.run(st0, 100)
+    kl_rand = float(new.cost(st0[0]).cpu()[0])
+    rows = np.arange(0, n, 16)
+    ov_net = oracle.knn_overlap(xn, ynet.cpu().numpy(), rows, 10)
+    ov_ref = oracle.knn_overlap(xn, st[0].cpu().numpy(), rows, 10)
+    print(f"  KL: surrogate {kl_net:.4f}, refined (100 it) {kl_ref:.4f}, random start (100 it) "
+          f"{kl_rand:.4f}; 10-NN overlap surrogate {ov_net:.3f}, refined {ov_ref:.3f}")
+    assert new.status() == 0
+    assert kl_ref < kl_rand
