@@ -144,6 +144,81 @@ def precision_leg(x, lab, n, d, perp, iters, steady_ms):
     return res
 
 
+def surrogate_leg(x_train, y_train, perp, n_new=1 << 20, n_eval=65536, epochs=100, batch=1024):
+    """Train the surrogate on the exact embedding, time inference on n_new new
+    points of the same mixture, and judge it on the first n_eval of them: KL and
+    10-NN overlap of (1) its map, (2) that map after 100 exact refinement
+    iterations (exaggeration 1, momentum 0.8, learning rate 200), (3) exact
+    t-SNE from a random start (1,000 iterations, standard schedule)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1812_09869_amd import synth
+    from paper_1812_09869_amd.surrogate import Surrogate
+    from paper_1812_09869_amd.tsne import ExactTSNE, Schedule
+
+    net = Surrogate(x_train.shape[1], 256, seed=synth.SEEDS["surrogate_init"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.fit(x_train, y_train, epochs=epochs, batch=batch)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[surrogate] trained {epochs} epochs in {t_train:.2f} s, loss {losses[0]:.4f} -> "
+        f"{losses[-1]:.4f}")
+    xn_np, _ = synth.gmm_aniso(n_new, sample_seed=synth.SEEDS["surrogate_new"])
+    xn = torch.from_numpy(xn_np).cuda()
+    out = torch.empty((n_new, 2), device="cuda")
+    net.predict(xn, out)  # warm-up
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        net.predict(xn, out)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    inf_ms = float(np.median(times))
+    log(f"[surrogate] inference on {n_new} points: {inf_ms:.3f} ms "
+        f"({n_new / inf_ms * 1e3:.3e} points/s)")
+    xe = xn[:n_eval].contiguous()
+    ye = out[:n_eval].clone()
+    model = ExactTSNE(xe, perp)
+    kl_net = float(model.cost(ye).cpu()[0])
+    refine = Schedule(switch=0, exaggeration=1.0, mom_late=0.8)
+    st = model.init_state(ye)
+    model.run(st, 100, sched=refine)
+    kl_ref = float(model.cost(st[0]).cpu()[0])
+    st0 = model.init_state(torch.from_numpy(synth.embedding_init(n_eval, seed=5002)).cuda())
+    kl_rand, t = {}, 0
+    for t_end in list(range(50, 1001, 50)):
+        model.run(st0, t_end - t, start=t)
+        t = t_end
+        kl_rand[t_end] = float(model.cost(st0[0]).cpu()[0])
+    rows = np.arange(0, n_eval, n_eval // 1024)
+    xe_np = xn_np[:n_eval]
+    ov = {k: oracle.knn_overlap(xe_np, v.cpu().numpy(), rows, 10)
+          for k, v in (("surrogate", ye), ("refined_100", st[0]), ("exact_1000", st0[0]))}
+    reach = next((t for t, v in sorted(kl_rand.items()) if v <= kl_ref), None)
+    res = {
+        "points_per_s": n_new / inf_ms * 1e3,
+        "inference_ms_1m_points": inf_ms,
+        "train_s": t_train,
+        "train_loss_first_last": [losses[0], losses[-1]],
+        "kl_surrogate": kl_net,
+        "kl_refined_100": kl_ref,
+        "kl_random_start_100": kl_rand[100],
+        "kl_exact_1000": kl_rand[1000],
+        "knn10_overlap": ov,
+        "gain_at_100_iterations": kl_rand[100] - kl_ref,
+        "random_start_iterations_to_reach_refined_kl": reach,
+        "fallback_refinement_needed": bool(kl_net > 1.05 * kl_rand[1000]),
+        "eval": f"first {n_eval} of {n_new} new points; 10-NN overlap on {rows.size} query rows",
+    }
+    log(f"[surrogate] {res}")
+    return res
+
+
 def precision_report(n=262144, d=128, perp=50.0):
     """Errors of every distance mode against the FP64 oracle on the 10-D subspace
     mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
@@ -235,6 +310,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the per-distance-mode affinity timing and error leg")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate training / inference / evaluation leg")
     ap.add_argument("--precision-report", action="store_true",
                     help="only run the per-mode error report at N=262,144, D=128")
     args = ap.parse_args()
@@ -367,6 +444,9 @@ def main():
         "final_kl": kl,
         "final_cnorm": cnorm,
     }
+    if not args.no_surrogate:
+        y_exact = y.clone()
+        out["surrogate"] = surrogate_leg(x, y_exact, perp)
     if not args.no_precision:
         del ws
         torch.cuda.empty_cache()
