@@ -156,6 +156,33 @@ TSNE_API int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows
                        void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batched iteration: many independent problems advanced together, one
+ * launch per phase for all of them (the GPU counterpart of the paper's
+ * independent partial t-SNEs, section "Parallelized implementation").
+ * Each problem has its own workspace, filled by tsne_affinities, and its own
+ * state (y, u, g: n x 2 FP32 device arrays). Every problem's result is
+ * bitwise identical to calling tsne_step on it alone.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  void *ws;    /* workspace holding the problem's affinities */
+  int64_t n;   /* number of points */
+  float *y, *u, *g;
+} tsne_batch_problem;
+
+/* Bytes of the batch workspace (device) for `count` problems; 0 if count < 1. */
+TSNE_API size_t tsne_batch_workspace_bytes(int32_t count);
+
+/* Writes the device table of the problems (host array) into batch_ws and
+ * synchronises the stream. The same array must be passed to tsne_batch_step;
+ * a mismatch is detected on the device and the step does nothing. */
+TSNE_API int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *batch_ws,
+                             size_t batch_ws_bytes, void *stream);
+
+/* One iteration (as tsne_step) of every problem, with the same parameters. */
+TSNE_API int tsne_batch_step(const tsne_batch_problem *problems, int32_t count,
+                             const void *batch_ws, const tsne_step_params *prm, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned surrogate (not in the paper): an MLP d_in -> H -> H -> 2 with ReLU
  * that maps input points to their embedding, trained on (x, y) pairs that
  * the exact path produced. Exact t-SNE (tsne_step) stays the fallback: a

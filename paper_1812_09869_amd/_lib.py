@@ -42,6 +42,9 @@ EXPORTED = [
     "tsne_export_rowstats",
     "tsne_export_scalars",
     "tsne_export_p_rows",
+    "tsne_batch_workspace_bytes",
+    "tsne_batch_plan",
+    "tsne_batch_step",
     "tsne_mlp_param_count",
     "tsne_mlp_workspace_bytes",
     "tsne_mlp_forward",
@@ -59,6 +62,11 @@ class TsneError(RuntimeError):
 class AffOpts(ctypes.Structure):
     _fields_ = [("dist_mode", ctypes.c_int32), ("max_bisect", ctypes.c_int32),
                 ("tol_h", ctypes.c_double)]
+
+
+class BatchProblem(ctypes.Structure):
+    _fields_ = [("ws", ctypes.c_void_p), ("n", ctypes.c_int64), ("y", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("g", ctypes.c_void_p)]
 
 
 class StepParams(ctypes.Structure):
@@ -99,6 +107,11 @@ def load(path: str = LIB_PATH):
         "tsne_export_rowstats": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
         "tsne_export_scalars": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
         "tsne_export_p_rows": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),
+        "tsne_batch_workspace_bytes": (ctypes.c_size_t, [_i32]),
+        "tsne_batch_plan": (ctypes.c_int, [ctypes.POINTER(BatchProblem), _i32, _vp,
+                                           ctypes.c_size_t, _vp]),
+        "tsne_batch_step": (ctypes.c_int, [ctypes.POINTER(BatchProblem), _i32, _vp,
+                                           ctypes.POINTER(StepParams), _vp]),
         "tsne_mlp_param_count": (ctypes.c_int64, [_i32, _i32]),
         "tsne_mlp_workspace_bytes": (ctypes.c_size_t, [_i32, _i32, _i64, _i32]),
         "tsne_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp,
@@ -269,3 +282,32 @@ def mlp_gradient(params, d_in, hidden, mean, invstd, x, y, idx, batch, grad, los
 def mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, t):
     _check(load().tsne_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), lr,
                                 beta1, beta2, eps, int(t), _stream()))
+
+
+# --------------------------------------------------------------------------
+# Batched iteration
+# --------------------------------------------------------------------------
+
+def batch_problems(entries):
+    """ctypes array of (ws, n, y, u, g) tuples of torch tensors."""
+    arr = (BatchProblem * len(entries))()
+    for k, (ws, n, y, u, g) in enumerate(entries):
+        sh = (n, 2)
+        arr[k] = BatchProblem(_ptr(ws, torch.uint8, name="ws").value, n,
+                              _ptr(y, shape=sh, name="y").value, _ptr(u, shape=sh, name="u").value,
+                              _ptr(g, shape=sh, name="g").value)
+    return arr
+
+
+def batch_plan(arr, device="cuda"):
+    count = len(arr)
+    nbytes = int(load().tsne_batch_workspace_bytes(count))
+    bws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    _check(load().tsne_batch_plan(arr, count, _ptr(bws, torch.uint8), nbytes, _stream()))
+    return bws
+
+
+def batch_step(arr, bws, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True):
+    prm = StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0)
+    _check(load().tsne_batch_step(arr, len(arr), _ptr(bws, torch.uint8), ctypes.byref(prm),
+                                  _stream()))

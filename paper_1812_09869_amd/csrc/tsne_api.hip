@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "../../include/tsne355.h"
@@ -231,6 +232,92 @@ int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *
   const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
   return hip_check(tsne::launch_export_p_rows(L, ws, row0, nrows, out, (hipStream_t)stream),
                    "tsne_export_p_rows");
+}
+
+size_t tsne_batch_workspace_bytes(int32_t count) {
+  if (count < 1 || count > (1 << 20)) return 0;
+  return tsne::kBatchHdrBytes + (size_t)count * sizeof(tsne::BatchEntry);
+}
+
+static int batch_totals(const char *fn, const tsne_batch_problem *pr, int32_t count,
+                        int64_t &tiles, int64_t &blocks) {
+  if (!pr || count < 1) return fail(TSNE_E_ARG, "%s: no problems", fn);
+  tiles = 0;
+  blocks = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    if (!pr[p].ws || !pr[p].y || !pr[p].u || !pr[p].g)
+      return fail(TSNE_E_ARG, "%s: null pointer in problem %d", fn, p);
+    if (!valid_n(pr[p].n)) return fail(TSNE_E_ARG, "%s: problem %d: bad n", fn, p);
+    if (!aligned(pr[p].ws, 256))
+      return fail(TSNE_E_WORKSPACE, "%s: problem %d: ws not 256-byte aligned", fn, p);
+    const tsne::Layout L = tsne::make_layout(pr[p].n, 1, TSNE_DIST_FP64);
+    tiles += L.nt;
+    blocks += L.nb;
+  }
+  if (tiles >= ((int64_t)1 << 31) || blocks >= ((int64_t)1 << 31))
+    return fail(TSNE_E_ARG, "%s: batch too large for one launch", fn);
+  return TSNE_OK;
+}
+
+int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *batch_ws,
+                    size_t batch_ws_bytes, void *stream) {
+  int64_t tiles, blocks;
+  if (int rc = batch_totals("tsne_batch_plan", problems, count, tiles, blocks)) return rc;
+  if (!batch_ws || !aligned(batch_ws, 256))
+    return fail(TSNE_E_WORKSPACE, "tsne_batch_plan: batch_ws null or misaligned");
+  const size_t need = tsne_batch_workspace_bytes(count);
+  if (batch_ws_bytes < need)
+    return fail(TSNE_E_WORKSPACE, "tsne_batch_plan: batch workspace %zu bytes, need %zu",
+                batch_ws_bytes, need);
+  char *host = (char *)calloc(1, need);
+  if (!host) return fail(TSNE_E_DEVICE, "tsne_batch_plan: host allocation failed");
+  tsne::BatchHdr *bh = reinterpret_cast<tsne::BatchHdr *>(host);
+  bh->magic = tsne::kBatchMagic;
+  bh->count = count;
+  bh->total_tiles = tiles;
+  bh->total_blocks = blocks;
+  tsne::BatchEntry *tab = reinterpret_cast<tsne::BatchEntry *>(host + tsne::kBatchHdrBytes);
+  int64_t t0 = 0;
+  int32_t b0 = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    const tsne::Layout L = tsne::make_layout(problems[p].n, 1, TSNE_DIST_FP64);
+    void *ws = problems[p].ws;
+    tsne::BatchEntry &e = tab[p];
+    e.P = tsne::at<const float4>(ws, L.P);
+    e.Y = reinterpret_cast<float2 *>(problems[p].y);
+    e.U = reinterpret_cast<float2 *>(problems[p].u);
+    e.G = reinterpret_cast<float2 *>(problems[p].g);
+    e.part = tsne::at<float4>(ws, L.part);
+    e.zpart = tsne::at<double>(ws, L.zpart);
+    e.meanpart = tsne::at<double2>(ws, L.meanpart);
+    e.h = tsne::at<tsne::Hdr>(ws, L.hdr);
+    e.n = L.n;
+    e.nt = L.nt;
+    e.nb = L.nb;
+    e.tile0 = t0;
+    e.blk0 = b0;
+    t0 += L.nt;
+    b0 += L.nb;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(batch_ws, host, need, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  free(host);
+  return hip_check(e, "tsne_batch_plan");
+}
+
+int tsne_batch_step(const tsne_batch_problem *problems, int32_t count, const void *batch_ws,
+                    const tsne_step_params *prm, void *stream) {
+  int64_t tiles, blocks;
+  if (int rc = batch_totals("tsne_batch_step", problems, count, tiles, blocks)) return rc;
+  if (!batch_ws || !prm) return fail(TSNE_E_ARG, "tsne_batch_step: null pointer");
+  if (!(prm->learning_rate >= 0.f) || !(prm->min_gain >= 0.f) || !isfinite(prm->momentum) ||
+      !isfinite(prm->exaggeration))
+    return fail(TSNE_E_ARG, "tsne_batch_step: invalid parameters");
+  return hip_check(tsne::launch_batch_step(batch_ws, count, tiles, blocks, prm->exaggeration,
+                                           prm->momentum, prm->learning_rate, prm->min_gain,
+                                           prm->recentre, (hipStream_t)stream),
+                   "tsne_batch_step");
 }
 
 static bool mlp_dims_ok(int32_t d_in, int32_t hidden) {

@@ -81,6 +81,28 @@ __device__ inline void tile_coords(int64_t t, int nb, int &I, int &J) {
   J = i + (int)(t - tile_start(i, nb));
 }
 
+// One problem of a batched iteration (device table entry).
+struct BatchEntry {
+  const float4 *P;
+  float2 *Y, *U, *G;
+  float4 *part;
+  double *zpart;
+  double2 *meanpart;
+  Hdr *h;
+  int64_t n, nt, tile0;  // tile0: first global tile index of this problem
+  int32_t nb, blk0;      // blk0: first global row-block index of this problem
+};
+
+// Header of a batch workspace, followed by `count` BatchEntry records.
+constexpr uint64_t kBatchMagic = 0x7453424154434801ull;
+struct BatchHdr {
+  uint64_t magic;
+  int32_t count;
+  int32_t pad;
+  int64_t total_tiles, total_blocks;
+};
+constexpr size_t kBatchHdrBytes = 256;
+
 template <typename P>
 inline P *at(void *ws, size_t off) {
   return reinterpret_cast<P *>(reinterpret_cast<char *>(ws) + off);
@@ -99,6 +121,9 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
                                 double *z_out, hipStream_t stream);
 hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out,
                        hipStream_t stream);
+hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tiles,
+                             int64_t total_blocks, float alpha, float mu, float eta,
+                             float min_gain, int recentre, hipStream_t stream);
 hipError_t launch_export_p_rows(const Layout &L, void *ws, int64_t row0, int64_t nrows,
                                 float *out, hipStream_t stream);
 hipError_t launch_export_scalars(const Layout &L, void *ws, double *out, hipStream_t stream);

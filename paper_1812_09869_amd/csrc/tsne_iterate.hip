@@ -111,18 +111,24 @@ __device__ __forceinline__ void force_tile(const float4 *__restrict__ tp,
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
-                                                  const float2 *__restrict__ Y, int64_t n,
-                                                  int32_t nb, float4 *__restrict__ part,
-                                                  double *__restrict__ zpart, Hdr *h) {
-  __shared__ float4 colbuf[16][T + 4];  // [row group tr][column], padded rows
-  __shared__ double zred[4];
+// One workgroup's share of the force pass: tile number `tile` of a problem.
+struct ForceSmem {
+  float4 colbuf[16][T + 4];  // [row group tr][column], padded rows
+  double zred[4];
+};
+
+__device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
+                                         const float2 *__restrict__ Y, int64_t n, int32_t nb,
+                                         float4 *__restrict__ part, double *__restrict__ zpart,
+                                         Hdr *h, int64_t tile, ForceSmem &sm) {
+  auto &colbuf = sm.colbuf;
+  auto &zred = sm.zred;
   if (!state_ok(h, n)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
   int I, J;
-  tile_coords(blockIdx.x, nb, I, J);
+  tile_coords(tile, nb, I, J);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
   float2 yc[16];
@@ -138,7 +144,7 @@ __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
   }
   const float2 *yrow = Y + (int64_t)I * T + tr;  // row tr + 16 k at yrow[16 k]
   const bool edge = ((int64_t)(J + 1) * T > n);
-  const float4 *tp = P + (size_t)blockIdx.x * TT4;
+  const float4 *tp = P + (size_t)tile * TT4;
   float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
   float4 colacc[16];
 #pragma unroll
@@ -177,13 +183,20 @@ __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
     }
     part[((size_t)J * nb + I) * T + t] = s;
   }
-  if (t == 0) zpart[blockIdx.x] = (zred[0] + zred[1] + zred[2] + zred[3]) * (I == J ? 1.0 : 2.0);
+  if (t == 0) zpart[tile] = (zred[0] + zred[1] + zred[2] + zred[3]) * (I == J ? 1.0 : 2.0);
 }
 
-// Z = sum of the tile partials in tile order (one workgroup).
-__global__ __launch_bounds__(1024) void k_zreduce(const double *__restrict__ zpart, int64_t nt,
-                                                  int64_t n, Hdr *h, double *z_out) {
-  __shared__ double red[16];
+__global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
+                                                  const float2 *__restrict__ Y, int64_t n,
+                                                  int32_t nb, float4 *__restrict__ part,
+                                                  double *__restrict__ zpart, Hdr *h) {
+  __shared__ ForceSmem sm;
+  force_wg(P, Y, n, nb, part, zpart, h, blockIdx.x, sm);
+}
+
+// Z = sum of the tile partials in tile order (one workgroup of 1024 threads).
+__device__ __forceinline__ void zreduce_wg(const double *__restrict__ zpart, int64_t nt, int64_t n,
+                                           Hdr *h, double *z_out, double (&red)[16]) {
   if (!state_ok(h, n)) return;
   double s = 0.0;
   for (int64_t q = threadIdx.x; q < nt; q += 1024) s += zpart[q];
@@ -197,6 +210,12 @@ __global__ __launch_bounds__(1024) void k_zreduce(const double *__restrict__ zpa
     if (z_out) *z_out = Z;
     if (!isfinite(Z) || !(Z > 0.0)) flag_error(h, kErrNonFinite);
   }
+}
+
+__global__ __launch_bounds__(1024) void k_zreduce(const double *__restrict__ zpart, int64_t nt,
+                                                  int64_t n, Hdr *h, double *z_out) {
+  __shared__ double red[16];
+  zreduce_wg(zpart, nt, n, h, z_out, red);
 }
 
 // Gradient of row i from its nb slots: g = 4 (alpha A - R / Z).
@@ -216,15 +235,14 @@ __device__ inline float2 row_gradient(const float4 *__restrict__ part, int32_t n
 
 // Update (Eq. 10, descent): gains, momentum, position; per-block sums of the
 // new positions for the re-centring.
-__global__ __launch_bounds__(256) void k_update(const float4 *__restrict__ part, int64_t n,
-                                                int32_t nb, float2 *__restrict__ Y,
-                                                float2 *__restrict__ U, float2 *__restrict__ G,
-                                                float alpha, float mu, float eta, float min_gain,
-                                                float2 *__restrict__ grad_out,
-                                                double2 *__restrict__ meanpart, Hdr *h) {
-  __shared__ double red[2][4];
+__device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64_t n, int32_t nb,
+                                          float2 *__restrict__ Y, float2 *__restrict__ U,
+                                          float2 *__restrict__ G, float alpha, float mu, float eta,
+                                          float min_gain, float2 *__restrict__ grad_out,
+                                          double2 *__restrict__ meanpart, Hdr *h, int b,
+                                          double (&red)[2][4]) {
   if (!state_ok(h, n)) return;
-  const int b = blockIdx.x, r = threadIdx.x;
+  const int r = threadIdx.x;
   const int64_t i = (int64_t)b * T + r;
   double sx = 0.0, sy = 0.0;
   bool bad = false;
@@ -260,9 +278,21 @@ __global__ __launch_bounds__(256) void k_update(const float4 *__restrict__ part,
                                red[1][0] + red[1][1] + red[1][2] + red[1][3]);
 }
 
-__global__ __launch_bounds__(256) void k_recentre(const double2 *__restrict__ meanpart, int64_t n,
-                                                  int32_t nb, float2 *__restrict__ Y, Hdr *h) {
-  __shared__ float2 smean;
+__global__ __launch_bounds__(256) void k_update(const float4 *__restrict__ part, int64_t n,
+                                                int32_t nb, float2 *__restrict__ Y,
+                                                float2 *__restrict__ U, float2 *__restrict__ G,
+                                                float alpha, float mu, float eta, float min_gain,
+                                                float2 *__restrict__ grad_out,
+                                                double2 *__restrict__ meanpart, Hdr *h) {
+  __shared__ double red[2][4];
+  update_wg(part, n, nb, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h, blockIdx.x,
+            red);
+}
+
+// Subtract the mean of the map from the rows of block `blk`.
+__device__ __forceinline__ void recentre_wg(const double2 *__restrict__ meanpart, int64_t n,
+                                            int32_t nb, float2 *__restrict__ Y, Hdr *h, int blk,
+                                            float2 &smean) {
   if (!state_ok(h, n)) return;
   if (threadIdx.x == 0) {
     double mx = 0.0, my = 0.0;
@@ -273,13 +303,100 @@ __global__ __launch_bounds__(256) void k_recentre(const double2 *__restrict__ me
     smean = make_float2((float)(mx / (double)n), (float)(my / (double)n));
   }
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blk * 256 + threadIdx.x;
   if (i < n) {
     float2 y = Y[i];
     y.x -= smean.x;
     y.y -= smean.y;
     Y[i] = y;
   }
+}
+
+__global__ __launch_bounds__(256) void k_recentre(const double2 *__restrict__ meanpart, int64_t n,
+                                                  int32_t nb, float2 *__restrict__ Y, Hdr *h) {
+  __shared__ float2 smean;
+  recentre_wg(meanpart, n, nb, Y, h, blockIdx.x, smean);
+}
+
+// ----------------------------------------------------------------------------
+// Batched iteration: many independent problems (each with its own workspace
+// and map) in one launch per phase. A device table lists the problems in
+// order with prefix sums of their tile and row-block counts; workgroup w
+// finds its problem by binary search and runs the single-problem code on it,
+// so every problem's result is bitwise the same as a separate launch.
+// ----------------------------------------------------------------------------
+__device__ inline int find_entry(const BatchEntry *tab, int count, int64_t key, bool by_tile) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t start = by_tile ? tab[mid].tile0 : tab[mid].blk0;
+    if (start <= key)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// The launch must match the plan held in the batch workspace.
+__device__ inline bool batch_ok(const BatchHdr *bh, int count, int64_t tiles, int64_t blocks) {
+  return bh->magic == kBatchMagic && bh->count == count && bh->total_tiles == tiles &&
+         bh->total_blocks == blocks;
+}
+
+__device__ inline const BatchEntry *batch_table(const BatchHdr *bh) {
+  return reinterpret_cast<const BatchEntry *>(reinterpret_cast<const char *>(bh) +
+                                              kBatchHdrBytes);
+}
+
+__global__ __launch_bounds__(256, 2) void k_force_batched(const BatchHdr *__restrict__ bh,
+                                                          int count, int64_t tiles,
+                                                          int64_t blocks) {
+  __shared__ ForceSmem sm;
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry *tab = batch_table(bh);
+  const int p = find_entry(tab, count, blockIdx.x, true);
+  const BatchEntry &e = tab[p];
+  const int64_t tile = (int64_t)blockIdx.x - e.tile0;
+  if (tile < 0 || tile >= e.nt) return;
+  force_wg(e.P, e.Y, e.n, e.nb, e.part, e.zpart, e.h, tile, sm);
+}
+
+__global__ __launch_bounds__(1024) void k_zreduce_batched(const BatchHdr *__restrict__ bh,
+                                                          int count, int64_t tiles,
+                                                          int64_t blocks) {
+  __shared__ double red[16];
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry &e = batch_table(bh)[blockIdx.x];
+  zreduce_wg(e.zpart, e.nt, e.n, e.h, nullptr, red);
+}
+
+__global__ __launch_bounds__(256) void k_update_batched(const BatchHdr *__restrict__ bh,
+                                                        int count, int64_t tiles, int64_t blocks,
+                                                        float alpha, float mu, float eta,
+                                                        float min_gain) {
+  __shared__ double red[2][4];
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry *tab = batch_table(bh);
+  const int p = find_entry(tab, count, blockIdx.x, false);
+  const BatchEntry &e = tab[p];
+  const int64_t b = (int64_t)blockIdx.x - e.blk0;
+  if (b < 0 || b >= e.nb) return;
+  update_wg(e.part, e.n, e.nb, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
+            (int)b, red);
+}
+
+__global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__restrict__ bh,
+                                                          int count, int64_t tiles,
+                                                          int64_t blocks) {
+  __shared__ float2 smean;
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry *tab = batch_table(bh);
+  const int p = find_entry(tab, count, blockIdx.x, false);
+  const BatchEntry &e = tab[p];
+  const int64_t b = (int64_t)blockIdx.x - e.blk0;
+  if (b < 0 || b >= e.nb) return;
+  recentre_wg(e.meanpart, e.n, e.nb, e.Y, e.h, (int)b, smean);
 }
 
 __global__ __launch_bounds__(256) void k_grad_only(const float4 *__restrict__ part, int64_t n,
@@ -457,6 +574,22 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, h
   hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
                      reinterpret_cast<const float2 *>(y), L.n, L.nb, cp, h);
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tiles,
+                             int64_t total_blocks, float alpha, float mu, float eta,
+                             float min_gain, int recentre, hipStream_t st) {
+  const BatchHdr *bh = reinterpret_cast<const BatchHdr *>(batch_ws);
+  hipLaunchKernelGGL(k_force_batched, dim3((unsigned)total_tiles), dim3(256), 0, st, bh, count,
+                     total_tiles, total_blocks);
+  hipLaunchKernelGGL(k_zreduce_batched, dim3(count), dim3(1024), 0, st, bh, count, total_tiles,
+                     total_blocks);
+  hipLaunchKernelGGL(k_update_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh, count,
+                     total_tiles, total_blocks, alpha, mu, eta, min_gain);
+  if (recentre)
+    hipLaunchKernelGGL(k_recentre_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh,
+                       count, total_tiles, total_blocks);
   return hipGetLastError();
 }
 

@@ -84,3 +84,34 @@ class ExactTSNE:
 
     def p_rows(self, row0: int, nrows: int):
         return _lib.export_p_rows(self.ws, self.n, row0, nrows)
+
+
+class BatchedTSNE:
+    """Independent exact t-SNE problems advanced together (one launch per phase).
+
+    ``problems`` is a list of (x, perplexity); each gets its own workspace and
+    affinities. ``run`` advances all of them with the same schedule.
+    """
+
+    def __init__(self, problems, dist_mode="fp64"):
+        self.models = [ExactTSNE(x, perp, dist_mode=dist_mode) for x, perp in problems]
+        self.states = None
+        self._arr = None
+        self._bws = None
+
+    def init_states(self, y0s):
+        self.states = [m.init_state(y0) for m, y0 in zip(self.models, y0s)]
+        self._arr = _lib.batch_problems([(m.ws, m.n, *st) for m, st in zip(self.models,
+                                                                            self.states)])
+        self._bws = _lib.batch_plan(self._arr, device=self.models[0].ws.device)
+        return self.states
+
+    def step(self, t: int, sched: Schedule):
+        alpha, mu, eta = sched(t)
+        _lib.batch_step(self._arr, self._bws, alpha, mu, eta, sched.min_gain, True)
+
+    def run(self, iters: int, start: int = 0, sched: Schedule | None = None):
+        sched = sched or Schedule()
+        for t in range(start, start + iters):
+            self.step(t, sched)
+        return self.states

@@ -1,0 +1,91 @@
+"""Batched iteration: many problems per launch.
+
+* Every problem's state after batched steps is bitwise equal to running
+  tsne_step on it alone (same kernels, same reduction order), so the batched
+  path inherits the single-problem parity with the oracle.
+* On the four smallest problems of the 64-problem workload: the gradient at
+  oracle states of iterations 0, 249 and 499 (oracle FP64 trajectories cast to
+  FP32) matches the oracle to 1e-4, and the batched 500-iteration run ends
+  within 2% of the oracle's final KL (the chaos floor measured on the
+  2,000-point workload is about 1%).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1812_09869_amd import _lib, synth
+from paper_1812_09869_amd.tsne import BatchedTSNE, ExactTSNE, Schedule
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_batched_bitwise_equals_single():
+    sizes = [(300, 5), (257, 3), (1000, 10), (40, 2), (2048, 7)]
+    rng = np.random.Generator(np.random.PCG64(9))
+    probs = [((rng.standard_normal((n, d)) * 3).astype(np.float32), 8.0) for n, d in sizes]
+    y0s = [synth.embedding_init(n, seed=20 + k) for k, (n, _) in enumerate(sizes)]
+    batched = BatchedTSNE([(_t(x), p) for x, p in probs])
+    batched.init_states([_t(y) for y in y0s])
+    sched = Schedule(switch=2)
+    batched.run(4, sched=sched)
+    for k, ((x, p), y0) in enumerate(zip(probs, y0s)):
+        single = ExactTSNE(_t(x), p)
+        st = single.init_state(_t(y0))
+        single.run(st, 4, sched=sched)
+        for a, b in zip(batched.states[k], st):
+            assert torch.equal(a, b), k
+        assert batched.models[k].status() == 0
+
+
+def test_batched_matches_oracle_on_smallest_problems():
+    ns = []
+    for p in range(64):
+        x, lab, perp = synth.batch_problem(p)
+        ns.append((x.shape[0], p))
+    chosen = [p for _, p in sorted(ns)[:4]]
+    data = [synth.batch_problem(p) for p in chosen]
+    y0s = [synth.embedding_init(x.shape[0], seed=4100 + p) for (x, _, _), p in zip(data, chosen)]
+    batched = BatchedTSNE([(_t(x), perp) for x, _, perp in data])
+    batched.init_states([_t(y) for y in y0s])
+    batched.run(500)
+    for k, ((x, lab, perp), p) in enumerate(zip(data, chosen)):
+        st = oracle.calibrate(x, perp)
+        P = oracle.joint_p(x, st)
+        model = batched.models[k]
+        state = None
+        t = 0
+        for t_check in (0, 249, 499):
+            y, u, g = oracle.run(P, y0s[k], t_check - t, start=t, state=state)
+            state = (y, u, g)
+            t = t_check
+            alpha = oracle.schedule(t_check).alpha
+            y32 = y.astype(np.float32)
+            g_ref, _ = oracle.gradient(P, y32.astype(np.float64), alpha)
+            g_gpu, _ = model.gradient(_t(y32), alpha)
+            rel = np.linalg.norm(g_gpu.cpu().numpy() - g_ref) / np.linalg.norm(g_ref)
+            print(f"\n  problem {p} (n={x.shape[0]}, d={x.shape[1]}) t={t_check}: grad rel {rel:.2e}")
+            assert rel <= 1e-4
+        y_end, _, _ = oracle.run(P, y0s[k], 1, start=499, state=state)
+        kl_ref = oracle.cost(P, y_end)[0]
+        kl_gpu = float(model.cost(batched.states[k][0]).cpu()[0])
+        print(f"  final KL gpu {kl_gpu:.5f} oracle {kl_ref:.5f} rel {abs(kl_gpu - kl_ref) / kl_ref:.2e}")
+        assert abs(kl_gpu - kl_ref) <= 0.02 * kl_ref
+        assert model.status() == 0
+
+
+def test_batch_mismatch_is_ignored_on_device():
+    """A step with a problem list other than the planned one changes nothing."""
+    rng = np.random.Generator(np.random.PCG64(2))
+    xs = [(rng.standard_normal((n, 3))).astype(np.float32) for n in (100, 200)]
+    b = BatchedTSNE([(_t(x), 5.0) for x in xs])
+    b.init_states([_t(synth.embedding_init(x.shape[0], seed=1)) for x in xs])
+    y_before = b.states[0][0].clone()
+    arr1 = _lib.batch_problems([(b.models[0].ws, 100, *b.states[0])])
+    _lib.batch_step(arr1, b._bws, 1.0, 0.5, 200.0)
+    torch.cuda.synchronize()
+    assert torch.equal(b.states[0][0], y_before)
