@@ -219,6 +219,48 @@ def surrogate_leg(x_train, y_train, perp, n_new=1 << 20, n_eval=65536, epochs=10
     return res
 
 
+def batched_leg(sweeps=500):
+    """The 64-problem workload (N ~ U{1000..20000}, D in {10, 50}, perplexity 30):
+    affinities of every problem, then `sweeps` batched iterations (one launch
+    per phase for all problems), timed with HIP events."""
+    import torch
+
+    from paper_1812_09869_amd import synth
+    from paper_1812_09869_amd.tsne import BatchedTSNE
+
+    data = [synth.batch_problem(p) for p in range(64)]
+    xs = [torch.from_numpy(x).cuda() for x, _, _ in data]
+    y0s = [torch.from_numpy(synth.embedding_init(x.shape[0], seed=4100 + p)).cuda()
+           for p, (x, _, _) in enumerate(data)]
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record()
+    batch = BatchedTSNE([(x, perp) for x, (_, _, perp) in zip(xs, data)])
+    e[1].record()
+    batch.init_states(y0s)
+    batch.run(sweeps)
+    e[2].record()
+    torch.cuda.synchronize()
+    status = max(m.status() for m in batch.models)
+    pairs = sum(m.n * (m.n - 1) / 2.0 for m in batch.models)
+    sweep_ms = e[1].elapsed_time(e[2]) / sweeps
+    res = {
+        "problems": len(batch.models),
+        "points": int(sum(m.n for m in batch.models)),
+        "affinities_ms": e[0].elapsed_time(e[1]),
+        "sweeps": sweeps,
+        "sweep_ms": sweep_ms,
+        "total_s": e[0].elapsed_time(e[2]) * 1e-3,
+        "problem_iterations_per_s": len(batch.models) * 1e3 / sweep_ms,
+        "pair_interactions_per_s": pairs * 1e3 / sweep_ms,
+        "p_bytes_per_sweep": 4.0 * pairs,
+        "achieved_gb_s": 4.0 * pairs / (sweep_ms * 1e-3) / 1e9,
+        "status": status,
+    }
+    log(f"[batched] {res}")
+    return res
+
+
 def precision_report(n=262144, d=128, perp=50.0):
     """Errors of every distance mode against the FP64 oracle on the 10-D subspace
     mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
@@ -310,6 +352,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the per-distance-mode affinity timing and error leg")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-problem batched leg")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate training / inference / evaluation leg")
     ap.add_argument("--precision-report", action="store_true",
@@ -447,8 +491,13 @@ def main():
     if not args.no_surrogate:
         y_exact = y.clone()
         out["surrogate"] = surrogate_leg(x, y_exact, perp)
-    if not args.no_precision:
+    if not args.no_precision or not args.no_batched:
         del ws
+        torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_leg()
+        torch.cuda.empty_cache()
+    if not args.no_precision:
         torch.cuda.empty_cache()
         out["dist_modes"] = precision_leg(x, lab_np, n, d, perp, args.iters, steady_ms)
     if not args.no_cpu_baseline:
