@@ -47,82 +47,140 @@ __device__ inline bool state_ok(Hdr *h, int64_t n) {
   return h->magic == kMagic && h->n == n && h->ready == 1;
 }
 
-// ----------------------------------------------------------------------------
-// Force tile kernel
-// ----------------------------------------------------------------------------
-// Rows of the tile are visited one at a time (k); the P values of the next
-// row are loaded while the current one is processed.
+// One row (k) of a thread's 16 x 16 block against its 16 columns.
 template <bool DIAG, bool EDGE>
-__device__ __forceinline__ void force_tile(const float4 *__restrict__ tp,
-                                           const float2 *__restrict__ yrow, const float2 yc[16],
-                                           uint32_t rvalid, uint32_t cvalid, int t, int tr, int tc,
-                                           float4 &myrow, float4 colacc[16], float &z) {
-  float4 cur[4], nxt[4];
+__device__ __forceinline__ float4 force_row(const float4 (&pv4)[4], float2 yi, const float2 yc[16],
+                                            uint32_t rvalid, uint32_t cvalid, int k, int tr, int tc,
+                                            float4 colacc[16], float &z) {
+  float ax = 0.f, ay = 0.f, rx = 0.f, ry = 0.f;
 #pragma unroll
-  for (int mq = 0; mq < 4; ++mq) cur[mq] = tp[mq * 256 + t];
-  float2 yi = ((rvalid & 1u) ? yrow[0] : make_float2(0.f, 0.f));
-#pragma unroll 1
-  for (int k = 0; k < 16; ++k) {
-    float2 yn = make_float2(0.f, 0.f);
-    if (k < 15) {
+  for (int mq = 0; mq < 4; ++mq) {
+    const float pp[4] = {pv4[mq].x, pv4[mq].y, pv4[mq].z, pv4[mq].w};
 #pragma unroll
-      for (int mq = 0; mq < 4; ++mq) nxt[mq] = tp[((k + 1) * 4 + mq) * 256 + t];
-      if ((rvalid >> (k + 1)) & 1u) yn = yrow[16 * (k + 1)];
-    }
-    float ax = 0.f, ay = 0.f, rx = 0.f, ry = 0.f;
-#pragma unroll
-    for (int mq = 0; mq < 4; ++mq) {
-      const float4 pv = cur[mq];
-      const float pp[4] = {pv.x, pv.y, pv.z, pv.w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int m = 4 * mq + e;
-        const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
-        const float q = fmaf(dx, dx, fmaf(dy, dy, 1.0f));
-        float w = __builtin_amdgcn_rcpf(q);
-        if (DIAG) {
-          if (tr == tc && k == m) w = 0.f;
-        }
-        if (EDGE) {
-          if (!((rvalid >> k) & (cvalid >> m) & 1u)) w = 0.f;
-        }
-        z += w;
-        const float pw = pp[e] * w, w2 = w * w;
-        ax = fmaf(pw, dx, ax);
-        ay = fmaf(pw, dy, ay);
-        rx = fmaf(w2, dx, rx);
-        ry = fmaf(w2, dy, ry);
-        if (!DIAG) {
-          colacc[m].x = fmaf(-pw, dx, colacc[m].x);
-          colacc[m].y = fmaf(-pw, dy, colacc[m].y);
-          colacc[m].z = fmaf(-w2, dx, colacc[m].z);
-          colacc[m].w = fmaf(-w2, dy, colacc[m].w);
-        }
+    for (int e = 0; e < 4; ++e) {
+      const int m = 4 * mq + e;
+      const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
+      const float q = fmaf(dx, dx, fmaf(dy, dy, 1.0f));
+      float w = __builtin_amdgcn_rcpf(q);
+      if (DIAG) {
+        if (tr == tc && k == m) w = 0.f;
+      }
+      if (EDGE) {
+        if (!((rvalid >> k) & (cvalid >> m) & 1u)) w = 0.f;
+      }
+      z += w;
+      const float pw = pp[e] * w, w2 = w * w;
+      ax = fmaf(pw, dx, ax);
+      ay = fmaf(pw, dy, ay);
+      rx = fmaf(w2, dx, rx);
+      ry = fmaf(w2, dy, ry);
+      if (!DIAG) {
+        colacc[m].x = fmaf(-pw, dx, colacc[m].x);
+        colacc[m].y = fmaf(-pw, dy, colacc[m].y);
+        colacc[m].z = fmaf(-w2, dx, colacc[m].z);
+        colacc[m].w = fmaf(-w2, dy, colacc[m].w);
       }
     }
-    ax = row16_sum(ax);
-    ay = row16_sum(ay);
-    rx = row16_sum(rx);
-    ry = row16_sum(ry);
-    if (tc == k) myrow = make_float4(ax, ay, rx, ry);
+  }
+  return make_float4(ax, ay, rx, ry);
+}
+
+// ---------------------------------------------------------------------------
+// P streaming through LDS. Each wave owns a ring of kStages row slots in LDS;
+// a slot holds the four float4 per lane that one row (k) of the thread's
+// 16 x 16 block needs. Rows are fetched kStages - 1 ahead with
+// global_load_lds_dwordx4 (global memory straight into LDS, no registers in
+// flight) and the wave waits on its own vector-memory counter for the row it
+// is about to use. The ring is read with ds_read_b128 inside an asm block
+// that also waits for the read, so the compiler neither reorders it nor adds
+// a blanket wait on all outstanding loads in front of it.
+// ---------------------------------------------------------------------------
+constexpr int kStages = 4;
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt immediate that waits until at most n vector-memory operations are
+// outstanding (expcnt and lgkmcnt left unconstrained).
+constexpr int vmcnt_imm(int n) { return (n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8); }
+
+__device__ __forceinline__ void fetch_row(const float4 *__restrict__ tp, int k, int t,
+                                          float4 *ring_slot /* this wave's slot base */) {
 #pragma unroll
-    for (int mq = 0; mq < 4; ++mq) cur[mq] = nxt[mq];
-    yi = yn;
+  for (int mq = 0; mq < 4; ++mq)
+    __builtin_amdgcn_global_load_lds((const void *)(tp + (k * 4 + mq) * 256 + t),
+                                     (lds_void_t *)(ring_slot + mq * 64), 16, 0, 0);
+}
+
+// The four float4 of this lane in one ring slot (LDS byte address of the
+// lane's first float4; the others follow at 1 KiB strides) and the position
+// of the row (LDS byte address of a float2).
+__device__ __forceinline__ void read_row(uint32_t p_addr, uint32_t y_addr, float4 (&v)[4],
+                                         float2 &yi) {
+  asm volatile(
+      "ds_read_b128 %0, %5\n\t"
+      "ds_read_b128 %1, %5 offset:1024\n\t"
+      "ds_read_b128 %2, %5 offset:2048\n\t"
+      "ds_read_b128 %3, %5 offset:3072\n\t"
+      "ds_read_b64 %4, %6\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=v"(v[0]), "=v"(v[1]), "=v"(v[2]), "=v"(v[3]), "=v"(yi)
+      : "v"(p_addr), "v"(y_addr)
+      : "memory");
+}
+
+// ---------------------------------------------------------------------------
+// Force pass: one workgroup per tile. Each wave streams its share of the
+// tile's P through its LDS ring (rows fetched kStages - 1 ahead) and keeps the
+// 16 column positions of its threads in registers.
+//   row side    16-lane DPP sums, one row per thread, written to slot (I, J);
+//   column side the 16 row groups' partial sums meet in LDS (the buffer
+//               overlays the ring, which is idle by then), written to slot
+//               (J, I);
+//   Z           FP32 per thread, FP64 across the workgroup, one value per tile.
+// ---------------------------------------------------------------------------
+
+struct ForceSmem {
+  union {
+    float4 colbuf[16][T + 4];        // [row group tr][column], padded rows
+    float4 ring[4][kStages][4][64];  // [wave][slot][float4 of the row][lane]
+  };
+  float2 yrow[T];                    // positions of the tile's rows
+  double zred[4];
+};
+
+template <bool DIAG, bool EDGE>
+__device__ __forceinline__ void tile_rows(const float4 *__restrict__ tp, float4 *wring,
+                                          uint32_t lane_addr, uint32_t yrow_addr,
+                                          const float2 yc[16], uint32_t rvalid, uint32_t cvalid,
+                                          int t, int tr, int tc, float4 &myrow, float4 colacc[16],
+                                          float &z) {
+#pragma unroll
+  for (int r = 0; r < kStages - 1; ++r) fetch_row(tp, r, t, wring + r * 256);
+#pragma unroll 1
+  for (int k = 0; k < 16; ++k) {
+    if (k + kStages - 1 < 16) {
+      fetch_row(tp, k + kStages - 1, t, wring + ((k + kStages - 1) % kStages) * 256);
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(4 * (kStages - 1)));
+    } else {
+      __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    }
+    float4 pv[4];
+    float2 yi;
+    read_row(lane_addr + (uint32_t)(k % kStages) * 4096u, yrow_addr + (uint32_t)(16 * k) * 8u, pv,
+             yi);
+    float4 r = force_row<DIAG, EDGE>(pv, yi, yc, rvalid, cvalid, k, tr, tc, colacc, z);
+    r.x = row16_sum(r.x);
+    r.y = row16_sum(r.y);
+    r.z = row16_sum(r.z);
+    r.w = row16_sum(r.w);
+    if (tc == k) myrow = r;
   }
 }
 
 // One workgroup's share of the force pass: tile number `tile` of a problem.
-struct ForceSmem {
-  float4 colbuf[16][T + 4];  // [row group tr][column], padded rows
-  double zred[4];
-};
-
 __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
                                          const float2 *__restrict__ Y, int64_t n, int32_t nb,
                                          float4 *__restrict__ part, double *__restrict__ zpart,
                                          Hdr *h, int64_t tile, ForceSmem &sm) {
-  auto &colbuf = sm.colbuf;
-  auto &zred = sm.zred;
   if (!state_ok(h, n)) {
     if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
@@ -142,7 +200,14 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
     cvalid |= vj ? (1u << k) : 0u;
     yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
   }
-  const float2 *yrow = Y + (int64_t)I * T + tr;  // row tr + 16 k at yrow[16 k]
+  {
+    const int64_t i = (int64_t)I * T + t;
+    sm.yrow[t] = i < n ? Y[i] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float4 *wring = &sm.ring[w][0][0][0];
+  const uint32_t lane_addr = (uint32_t)(size_t)((lds_void_t *)wring) + (uint32_t)l * 16u;
+  const uint32_t yrow_addr = (uint32_t)(size_t)((lds_void_t *)(sm.yrow + tr));
   const bool edge = ((int64_t)(J + 1) * T > n);
   const float4 *tp = P + (size_t)tile * TT4;
   float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -152,38 +217,45 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
   float z = 0.f;
   if (I == J) {
     if (edge)
-      force_tile<true, true>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+      tile_rows<true, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc, myrow,
+                            colacc, z);
     else
-      force_tile<true, false>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+      tile_rows<true, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
+                             myrow, colacc, z);
   } else {
     if (edge)
-      force_tile<false, true>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+      tile_rows<false, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
+                             myrow, colacc, z);
     else
-      force_tile<false, false>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, myrow, colacc, z);
+      tile_rows<false, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
+                              myrow, colacc, z);
   }
   // row side: this thread holds row tr + 16 tc
   part[((size_t)I * nb + J) * T + tr + 16 * tc] = myrow;
-  // column side: reduce over the 16 row groups through LDS
-  if (I != J) {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) colbuf[tr][tc + 16 * m] = colacc[m];
-  }
-  double zd = wave_sum_d((double)z);
-  if (l == 0) zred[w] = zd;
+  // column side: reduce over the 16 row groups through LDS (colbuf overlays
+  // the P ring, so every wave must be done with its ring first)
   __syncthreads();
   if (I != J) {
-    float4 s = colbuf[0][t];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) sm.colbuf[tr][tc + 16 * m] = colacc[m];
+  }
+  const double zd = wave_sum_d((double)z);
+  if (l == 0) sm.zred[w] = zd;
+  __syncthreads();
+  if (I != J) {
+    float4 s4 = sm.colbuf[0][t];
 #pragma unroll
     for (int g = 1; g < 16; ++g) {
-      const float4 v = colbuf[g][t];
-      s.x += v.x;
-      s.y += v.y;
-      s.z += v.z;
-      s.w += v.w;
+      const float4 v = sm.colbuf[g][t];
+      s4.x += v.x;
+      s4.y += v.y;
+      s4.z += v.z;
+      s4.w += v.w;
     }
-    part[((size_t)J * nb + I) * T + t] = s;
+    part[((size_t)J * nb + I) * T + t] = s4;
   }
-  if (t == 0) zpart[tile] = (zred[0] + zred[1] + zred[2] + zred[3]) * (I == J ? 1.0 : 2.0);
+  if (t == 0)
+    zpart[tile] = (sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (I == J ? 1.0 : 2.0);
 }
 
 __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
