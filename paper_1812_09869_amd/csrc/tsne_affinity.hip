@@ -512,7 +512,8 @@ __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock,
 __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const float *__restrict__ a,
                                               const float *__restrict__ m,
                                               const float *__restrict__ r, int64_t n, int32_t nb,
-                                              double2 *__restrict__ ppart) {
+                                              double2 *__restrict__ ppart,
+                                              uint8_t *__restrict__ nzflag) {
   __shared__ double red[2][4];
   int I, J;
   tile_coords(blockIdx.x, nb, I, J);
@@ -538,6 +539,7 @@ __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const floa
   }
   float4 *tp = P + (size_t)blockIdx.x * TT4;
   float psum = 0.f, plp = 0.f;
+  bool any = false;
 #pragma unroll 2
   for (int s = 0; s < 64; ++s) {
     const int k = s >> 2, mq = s & 3;
@@ -555,6 +557,11 @@ __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const floa
       float p = pi + pj;
       if (diag && tr == tc && k == mm) p = 0.f;
       if (!((rvalid >> k) & (cvalid >> mm) & 1u)) p = 0.f;
+      // values below the normal FP32 range are stored as 0 (they change no
+      // sum by more than 1e-38); a tile whose entries are all 0 is skipped
+      // by the attractive part of the force pass
+      if (p < FLT_MIN) p = 0.f;
+      any |= p > 0.f;
       pv[e] = p;
       psum += p;
       // denormal p (< FLT_MIN) contribute below 1e-36 and are skipped: the
@@ -568,8 +575,9 @@ __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const floa
     red[0][w] = ds;
     red[1][w] = dl;
   }
-  __syncthreads();
+  const int tile_any = __syncthreads_or(any ? 1 : 0);
   if (t == 0) {
+    nzflag[blockIdx.x] = tile_any ? 1 : 0;
     double mult = diag ? 1.0 : 2.0;
     double S = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     double Lg = red[1][0] + red[1][1] + red[1][2] + red[1][3];
@@ -770,7 +778,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
   }
   double2 *ppart = at<double2>(ws, L.ppart);
   hipLaunchKernelGGL(k_pack, dim3((unsigned)L.nt), dim3(256), 0, st, P, co.a, co.m, co.r, L.n,
-                     L.nb, ppart);
+                     L.nb, ppart, at<uint8_t>(ws, L.nz));
   hipLaunchKernelGGL(k_pack_reduce, dim3(1), dim3(1024), 0, st, ppart, L.nt, h);
   return hipGetLastError();
 }

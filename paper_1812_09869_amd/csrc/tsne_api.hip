@@ -44,6 +44,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.cpart = take((size_t)L.nt * 16);
   L.ppart = take((size_t)L.nt * 16);
   L.meanpart = take((size_t)L.nb * 16);
+  L.nz = take((size_t)L.nt);
   L.iter_end = o;
   // affinity-stage scratch (only needed inside tsne_affinities)
   L.xmean = take((size_t)L.dpad * 8);
@@ -290,6 +291,7 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.part = tsne::at<float4>(ws, L.part);
     e.zpart = tsne::at<double>(ws, L.zpart);
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
+    e.nz = tsne::at<const uint8_t>(ws, L.nz);
     e.h = tsne::at<tsne::Hdr>(ws, L.hdr);
     e.n = L.n;
     e.nt = L.nt;

@@ -56,6 +56,7 @@ struct Layout {
   // byte offsets from the workspace base
   size_t hdr = 0, beta = 0, S = 0, H = 0, m = 0, a = 0, r = 0, evals = 0;
   size_t P = 0, part = 0, zpart = 0, cpart = 0, ppart = 0, meanpart = 0;
+  size_t nz = 0;  // per tile: 1 if any stored p_ij of the tile is nonzero
   size_t iter_end = 0;  // end of the part that tsne_step needs
   int32_t kk = 0;  // K of the reduced-precision contraction (d rounded up, x3 for split modes)
   size_t xmean = 0, xcT = 0, norms = 0, dblock = 0;
@@ -88,6 +89,7 @@ struct BatchEntry {
   float4 *part;
   double *zpart;
   double2 *meanpart;
+  const uint8_t *nz;
   Hdr *h;
   int64_t n, nt, tile0;  // tile0: first global tile index of this problem
   int32_t nb, blk0;      // blk0: first global row-block index of this problem

@@ -176,11 +176,48 @@ __device__ __forceinline__ void tile_rows(const float4 *__restrict__ tp, float4 
   }
 }
 
+// A tile whose stored P is all zero: only the repulsive sums and Z, no P
+// traffic. Row positions come from LDS (no ring is in use here).
+template <bool DIAG, bool EDGE>
+__device__ __forceinline__ void tile_rows_zero(const float2 *yrow, const float2 yc[16],
+                                               uint32_t rvalid, uint32_t cvalid, int tr, int tc,
+                                               float4 &myrow, float4 colacc[16], float &z) {
+#pragma unroll 1
+  for (int k = 0; k < 16; ++k) {
+    const float2 yi = yrow[tr + 16 * k];
+    float rx = 0.f, ry = 0.f;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
+      const float q = fmaf(dx, dx, fmaf(dy, dy, 1.0f));
+      float w = __builtin_amdgcn_rcpf(q);
+      if (DIAG) {
+        if (tr == tc && k == m) w = 0.f;
+      }
+      if (EDGE) {
+        if (!((rvalid >> k) & (cvalid >> m) & 1u)) w = 0.f;
+      }
+      z += w;
+      const float w2 = w * w;
+      rx = fmaf(w2, dx, rx);
+      ry = fmaf(w2, dy, ry);
+      if (!DIAG) {
+        colacc[m].z = fmaf(-w2, dx, colacc[m].z);
+        colacc[m].w = fmaf(-w2, dy, colacc[m].w);
+      }
+    }
+    rx = row16_sum(rx);
+    ry = row16_sum(ry);
+    if (tc == k) myrow = make_float4(0.f, 0.f, rx, ry);
+  }
+}
+
 // One workgroup's share of the force pass: tile number `tile` of a problem.
 __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
                                          const float2 *__restrict__ Y, int64_t n, int32_t nb,
                                          float4 *__restrict__ part, double *__restrict__ zpart,
-                                         Hdr *h, int64_t tile, ForceSmem &sm) {
+                                         const uint8_t *__restrict__ nz, Hdr *h, int64_t tile,
+                                         ForceSmem &sm) {
   if (!state_ok(h, n)) {
     if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
@@ -215,7 +252,19 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 #pragma unroll
   for (int m = 0; m < 16; ++m) colacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
   float z = 0.f;
-  if (I == J) {
+  if (!nz[tile]) {
+    if (I == J) {
+      if (edge)
+        tile_rows_zero<true, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+      else
+        tile_rows_zero<true, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+    } else {
+      if (edge)
+        tile_rows_zero<false, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+      else
+        tile_rows_zero<false, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+    }
+  } else if (I == J) {
     if (edge)
       tile_rows<true, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc, myrow,
                             colacc, z);
@@ -261,9 +310,10 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
                                                   const float2 *__restrict__ Y, int64_t n,
                                                   int32_t nb, float4 *__restrict__ part,
-                                                  double *__restrict__ zpart, Hdr *h) {
+                                                  double *__restrict__ zpart,
+                                                  const uint8_t *__restrict__ nz, Hdr *h) {
   __shared__ ForceSmem sm;
-  force_wg(P, Y, n, nb, part, zpart, h, blockIdx.x, sm);
+  force_wg(P, Y, n, nb, part, zpart, nz, h, blockIdx.x, sm);
 }
 
 // Z = sum of the tile partials in tile order (one workgroup of 1024 threads).
@@ -431,7 +481,7 @@ __global__ __launch_bounds__(256, 2) void k_force_batched(const BatchHdr *__rest
   const BatchEntry &e = tab[p];
   const int64_t tile = (int64_t)blockIdx.x - e.tile0;
   if (tile < 0 || tile >= e.nt) return;
-  force_wg(e.P, e.Y, e.n, e.nb, e.part, e.zpart, e.h, tile, sm);
+  force_wg(e.P, e.Y, e.n, e.nb, e.part, e.zpart, e.nz, e.h, tile, sm);
 }
 
 __global__ __launch_bounds__(1024) void k_zreduce_batched(const BatchHdr *__restrict__ bh,
@@ -521,7 +571,7 @@ __device__ __forceinline__ void cost_tile(const float4 *__restrict__ tp,
 __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
                                                  const float2 *__restrict__ Y, int64_t n,
                                                  int32_t nb, double2 *__restrict__ cpart,
-                                                 Hdr *h) {
+                                                 const uint8_t *__restrict__ nz, Hdr *h) {
   __shared__ double red[2][4];
   if (!state_ok(h, n)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
@@ -546,7 +596,21 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
   const bool edge = ((int64_t)(J + 1) * T > n);
   const float4 *tp = P + (size_t)blockIdx.x * TT4;
   float plq = 0.f, z = 0.f;
-  if (I == J) {
+  if (!nz[blockIdx.x]) {
+    // no p_ij in this tile: only Z
+#pragma unroll 1
+    for (int k = 0; k < 16; ++k) {
+      const float2 yi = ((rvalid >> k) & 1u) ? yrow[16 * k] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
+        float w = __builtin_amdgcn_rcpf(fmaf(dx, dx, fmaf(dy, dy, 1.0f)));
+        bool keep = (I != J) || !(tr == tc && k == m);
+        keep = keep && ((rvalid >> k) & (cvalid >> m) & 1u);
+        z += keep ? w : 0.f;
+      }
+    }
+  } else if (I == J) {
     if (edge)
       cost_tile<true, true>(tp, yrow, yc, rvalid, cvalid, t, tr, tc, plq, z);
     else
@@ -609,7 +673,7 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_force, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
                      reinterpret_cast<const float2 *>(y), L.n, L.nb, at<float4>(ws, L.part),
-                     at<double>(ws, L.zpart), h);
+                     at<double>(ws, L.zpart), at<const uint8_t>(ws, L.nz), h);
   return hipGetLastError();
 }
 
@@ -644,7 +708,8 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, h
   Hdr *h = at<Hdr>(ws, L.hdr);
   double2 *cp = at<double2>(ws, L.cpart);
   hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
-                     reinterpret_cast<const float2 *>(y), L.n, L.nb, cp, h);
+                     reinterpret_cast<const float2 *>(y), L.n, L.nb, cp, at<const uint8_t>(ws, L.nz),
+                     h);
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
   return hipGetLastError();
 }

@@ -206,3 +206,35 @@ def test_device_conditions():
     g = torch.ones_like(y)
     _lib.step(ws, 39, y, u, g, 1.0, 0.5, 200.0)
     assert _lib.sync_status(ws) == 7
+
+
+def test_zero_tiles_sorted_input():
+    """Clustered input in cluster order: inter-cluster tiles hold only zeros and take the
+    repulsion-only path; gradient, Z and KL still match the oracle."""
+    n = 4000
+    x, lab = synth.plain_small(n, seed=606)
+    order = np.argsort(lab, kind="stable")
+    x, lab = np.ascontiguousarray(x[order]), lab[order]
+    st = oracle.calibrate(x, 30.0)
+    P = oracle.joint_p(x, st)
+    model = ExactTSNE(torch.from_numpy(x).cuda(), 30.0)
+    assert model.status() == 0
+    pg = model.p_rows(0, n).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(pg - P) / np.linalg.norm(P) <= 1e-5
+    nb = (n + 255) // 256
+    blocks = np.add.reduceat(np.add.reduceat(pg > 0, np.arange(0, n, 256), axis=0),
+                             np.arange(0, n, 256), axis=1)
+    zero_frac = np.mean(blocks[np.triu_indices(nb)] == 0)
+    print(f"\n  zero tiles {zero_frac:.2f}")
+    assert zero_frac > 0.3
+    for alpha in (1.0, 12.0):
+        y = synth.clustered_state(lab, seed=61)
+        g_ref, z_ref = oracle.gradient(P, y.astype(np.float64), alpha)
+        g, z = model.gradient(torch.from_numpy(y).cuda(), alpha)
+        rel = np.linalg.norm(g.cpu().numpy() - g_ref) / np.linalg.norm(g_ref)
+        print(f"  alpha {alpha}: grad rel {rel:.2e}")
+        assert rel <= 1e-4 and abs(float(z.cpu()[0]) - z_ref) <= 1e-6 * z_ref
+    y = synth.clustered_state(lab, seed=62)
+    kl_ref, _ = oracle.cost(P, y.astype(np.float64))
+    kl = float(model.cost(torch.from_numpy(y).cuda()).cpu()[0])
+    assert abs(kl - kl_ref) <= 1e-5 * kl_ref
