@@ -64,11 +64,23 @@ typedef enum {
 } tsne_dist_mode;
 
 /* Options of the affinity stage. A NULL pointer selects the defaults
- * {TSNE_DIST_FP64, 200, 1e-6}. */
+ * {TSNE_DIST_FP64, 200, 1e-6, 1}.
+ *
+ * reorder != 0: after P is formed, the points are renumbered internally so
+ * that points close in the input space are contiguous (a bisection tree
+ * that splits every segment of the order along its leading principal
+ * direction, with leaves of one 256-row tile), and P is rebuilt in that
+ * order. Tiles of P that then hold only zeros (flushed sub-normal values
+ * included) are skipped by the attractive part of every force pass and cost
+ * evaluation. Results are those of the same computation in another
+ * summation order; inputs and outputs of every call stay in the caller's
+ * order. Skipped when d > 2048 or n <= 256. */
 typedef struct {
   int32_t dist_mode;  /* tsne_dist_mode */
   int32_t max_bisect; /* bisection passes per row, >= 1 */
   double tol_h;       /* stop when |H_i - ln(perplexity)| <= tol_h (nats), > 0 */
+  int32_t reorder;    /* 1: group points by affinity components (default); 0: keep order */
+  int32_t reserved;   /* must be 0 */
 } tsne_aff_opts;
 
 /* Parameters of one update (Eq. 10 and the paragraph after it). */
@@ -89,7 +101,8 @@ TSNE_API size_t tsne_workspace_bytes(int64_t n, int32_t d, int32_t dist_mode);
  * precision beta_i of the Gaussian kernel is found by bisection so that the
  * entropy of p_{.|i} equals ln(perplexity) (Eq. 2, in nats); then
  * p_ij = (p_{j|i} + p_{i|j}) / (2n) is stored in the workspace (FP32, upper
- * triangle, tile-packed). Self terms are zero. Errors: TSNE_E_ARG,
+ * triangle, tile-packed; entries below the normal FP32 range are stored as
+ * 0). Self terms are zero. Errors: TSNE_E_ARG,
  * TSNE_E_PERPLEXITY, TSNE_E_WORKSPACE, TSNE_E_DEVICE; device flags may set
  * TSNE_E_NONFINITE (non-finite x) or TSNE_E_NOCONV.
  */
@@ -154,6 +167,14 @@ TSNE_API int tsne_export_scalars(void *ws, int64_t n, double *out, void *stream)
 /* Test hook: dense rows row0 .. row0 + nrows - 1 of P (nrows x n FP32). */
 TSNE_API int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *out,
                        void *stream);
+
+/* Test hook: the internal order and the zero-tile flags (device buffers,
+ * either may be NULL). perm (int32[n]): perm[r] is the caller's index of the
+ * point at internal position r (the identity when reordering is off).
+ * flags (uint8[nb (nb + 1) / 2], nb = ceil(n / 256)): one byte per tile of
+ * the upper triangle of P in row-major tile order, 0 when every entry of the
+ * tile is zero. */
+TSNE_API int tsne_export_order(void *ws, int64_t n, int32_t *perm, uint8_t *flags, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched iteration: many independent problems advanced together, one

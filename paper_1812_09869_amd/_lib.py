@@ -42,6 +42,7 @@ EXPORTED = [
     "tsne_export_rowstats",
     "tsne_export_scalars",
     "tsne_export_p_rows",
+    "tsne_export_order",
     "tsne_batch_workspace_bytes",
     "tsne_batch_plan",
     "tsne_batch_step",
@@ -61,7 +62,8 @@ class TsneError(RuntimeError):
 
 class AffOpts(ctypes.Structure):
     _fields_ = [("dist_mode", ctypes.c_int32), ("max_bisect", ctypes.c_int32),
-                ("tol_h", ctypes.c_double)]
+                ("tol_h", ctypes.c_double), ("reorder", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class BatchProblem(ctypes.Structure):
@@ -107,6 +109,7 @@ def load(path: str = LIB_PATH):
         "tsne_export_rowstats": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
         "tsne_export_scalars": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
         "tsne_export_p_rows": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),
+        "tsne_export_order": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp]),
         "tsne_batch_workspace_bytes": (ctypes.c_size_t, [_i32]),
         "tsne_batch_plan": (ctypes.c_int, [ctypes.POINTER(BatchProblem), _i32, _vp,
                                            ctypes.c_size_t, _vp]),
@@ -165,10 +168,10 @@ def new_workspace(n: int, d: int, dist_mode: str | int = "fp64", device="cuda") 
 
 
 def affinities(x: torch.Tensor, perplexity: float, ws: torch.Tensor, dist_mode="fp64",
-               max_bisect: int = 200, tol_h: float = 1e-6):
+               max_bisect: int = 200, tol_h: float = 1e-6, reorder: bool = True):
     n, d = x.shape
     mode = DIST_MODES[dist_mode] if isinstance(dist_mode, str) else int(dist_mode)
-    opts = AffOpts(mode, max_bisect, tol_h)
+    opts = AffOpts(mode, max_bisect, tol_h, 1 if reorder else 0, 0)
     _check(load().tsne_affinities(_ptr(x, name="x"), n, d, float(perplexity),
                                   ctypes.byref(opts), _ptr(ws, torch.uint8, name="ws"),
                                   ws.numel(), _stream()))
@@ -246,6 +249,16 @@ def export_p_rows(ws, n, row0, nrows):
     _check(load().tsne_export_p_rows(_ptr(ws, torch.uint8, name="ws"), n, row0, nrows, _ptr(out),
                                      _stream()))
     return out
+
+
+def export_order(ws, n):
+    """(perm, tile_flags): internal position -> caller index, and one byte per upper tile."""
+    nb = (n + 255) // 256
+    perm = torch.empty(n, dtype=torch.int32, device=ws.device)
+    flags = torch.empty(nb * (nb + 1) // 2, dtype=torch.uint8, device=ws.device)
+    _check(load().tsne_export_order(_ptr(ws, torch.uint8, name="ws"), n, _ptr(perm, torch.int32),
+                                    _ptr(flags, torch.uint8), _stream()))
+    return perm, flags
 
 
 # --------------------------------------------------------------------------

@@ -614,6 +614,203 @@ __global__ __launch_bounds__(1024) void k_pack_reduce(const double2 *__restrict_
 }
 
 // ----------------------------------------------------------------------------
+// 4. Locality reordering (not part of the method: it only changes the order
+// in which P is stored and summed).
+//
+// Points whose affinities are nonzero lie close in the input space, so an
+// order in which nearby points are contiguous concentrates the nonzero p_ij in
+// few tiles and leaves the rest all-zero (skipped by the attractive part of
+// every force pass). The order is a principal-direction bisection tree with
+// tile-aligned leaves: at level l the internal positions split into 2^l
+// segments [floor(s nb / 2^l) T, floor((s + 1) nb / 2^l) T); each segment is
+// sorted by the projection of its centred points on their leading principal
+// direction (a few power iterations from a fixed start), so that its two
+// halves at the next level are the two sides of that direction. Every step is
+// deterministic (fixed reduction orders, a fixed sorting network).
+// ----------------------------------------------------------------------------
+constexpr int kTreeThreads = 1024;
+constexpr int kTreeMaxD = 2048;
+constexpr int kTreePowerIters = 4;
+
+__global__ void k_reorder_init(int64_t n, int64_t npad, int32_t *__restrict__ perm,
+                               int32_t *__restrict__ inv) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npad) return;
+  perm[i] = (int32_t)i;
+  inv[i] = (int32_t)i;
+}
+
+// Sum of acc[0..7] over the workgroup (kTreeThreads threads) into out[0..7]
+// (LDS), in a fixed order.
+__device__ inline void tree_block_sum8(double (&acc)[8], double (*red)[8], double *out) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = wave_sum_d(acc[q]);
+  if (l == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[w][q] = acc[q];
+  }
+  __syncthreads();
+  if (t < 8) {
+    double s = 0.0;
+    for (int g = 0; g < kTreeThreads / 64; ++g) s += red[g][t];
+    out[t] = s;
+  }
+  __syncthreads();
+}
+
+__device__ inline uint32_t orderable_f32(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// One level of the tree: segment blockIdx.x of 2^level. Writes the sort keys
+// (segment << 32 | projection) and the caller indices of its positions.
+__global__ __launch_bounds__(kTreeThreads) void k_tree_level(
+    const double *__restrict__ xcT, int64_t npad, int32_t d, int64_t n, int32_t nb, int level,
+    const int32_t *__restrict__ perm, double *__restrict__ wbuf, uint64_t *__restrict__ keys,
+    int32_t *__restrict__ vals) {
+  __shared__ double mean[kTreeMaxD], v[kTreeMaxD];
+  __shared__ double red[kTreeThreads / 64][8];
+  __shared__ double out8[8];
+  __shared__ double nrm;
+  const int t = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  const int64_t lo = ((s * nb) >> level) * T;
+  int64_t hi = (((s + 1) * nb) >> level) * T;
+  if (hi > n) hi = n;
+  if (lo >= hi) return;
+  const uint64_t seg = (uint64_t)s << 32;
+  if (hi - lo <= T) {  // a leaf: keep its order
+    for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
+      keys[r] = seg | (uint64_t)(r - lo);
+      vals[r] = perm[r];
+    }
+    return;
+  }
+  const double inv_cnt = 1.0 / (double)(hi - lo);
+  // segment mean, 8 coordinates at a time
+  for (int k0 = 0; k0 < d; k0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
+      const int64_t i = perm[r];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < d) acc[q] += xcT[(int64_t)(k0 + q) * npad + i];
+    }
+    tree_block_sum8(acc, red, out8);
+    if (t < 8 && k0 + t < d) mean[k0 + t] = out8[t] * inv_cnt;
+  }
+  // fixed start vector
+  for (int k = t; k < d; k += kTreeThreads) {
+    const uint32_t hsh = (uint32_t)(k + 1) * 2654435761u;
+    v[k] = 0.5 + (double)(hsh >> 8) * (1.0 / 16777216.0);
+  }
+  __syncthreads();
+  for (int it = 0; it <= kTreePowerIters; ++it) {
+    // w_r = (x_r - mean) . v for this thread's rows (each thread reads back
+    // only what it wrote)
+    for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
+      const int64_t i = perm[r];
+      double wsum = 0.0;
+      for (int k = 0; k < d; ++k) wsum += (xcT[(int64_t)k * npad + i] - mean[k]) * v[k];
+      wbuf[r] = wsum;
+    }
+    if (it == kTreePowerIters) break;
+    // v' = sum_r (x_r - mean) w_r, then normalise
+    __syncthreads();
+    double ss = 0.0;
+    for (int k0 = 0; k0 < d; k0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+      for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
+        const int64_t i = perm[r];
+        const double wr = wbuf[r];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q < d) acc[q] += (xcT[(int64_t)(k0 + q) * npad + i] - mean[k0 + q]) * wr;
+      }
+      tree_block_sum8(acc, red, out8);
+      if (t < 8 && k0 + t < d) v[k0 + t] = out8[t];
+      if (t == 0)
+        for (int q = 0; q < 8 && k0 + q < d; ++q) ss += out8[q] * out8[q];
+    }
+    if (t == 0) nrm = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+    __syncthreads();
+    if (nrm == 0.0) {  // all points of the segment coincide: keep the order
+      for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
+        keys[r] = seg | (uint64_t)(r - lo);
+        vals[r] = perm[r];
+      }
+      return;
+    }
+    for (int k = t; k < d; k += kTreeThreads) v[k] *= nrm;
+    __syncthreads();
+  }
+  for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
+    keys[r] = seg | (uint64_t)orderable_f32((float)wbuf[r]);
+    vals[r] = perm[r];
+  }
+}
+
+// Keys of positions beyond n sort last.
+__global__ void k_tree_pad(int64_t n, int64_t npow2, uint64_t *__restrict__ keys,
+                           int32_t *__restrict__ vals) {
+  const int64_t r = n + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= npow2) return;
+  keys[r] = ~0ull;
+  vals[r] = (int32_t)(r < INT32_MAX ? r : INT32_MAX);
+}
+
+// One compare-exchange stage of a bitonic sort (ascending) of (key, value)
+// pairs over npow2 entries.
+__global__ void k_bitonic(uint64_t *__restrict__ keys, int32_t *__restrict__ vals, int64_t npow2,
+                          int64_t j, int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npow2) return;
+  const int64_t l = i ^ j;
+  if (l <= i) return;
+  const uint64_t a = keys[i], b = keys[l];
+  const bool up = (i & k) == 0;
+  if ((a > b) == up) {
+    keys[i] = b;
+    keys[l] = a;
+    const int32_t va = vals[i];
+    vals[i] = vals[l];
+    vals[l] = va;
+  }
+}
+
+__global__ void k_tree_apply(const int32_t *__restrict__ vals, int64_t n,
+                             int32_t *__restrict__ perm) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r < n) perm[r] = vals[r];
+}
+
+__global__ void k_inverse(const int32_t *__restrict__ perm, int64_t npad,
+                          int32_t *__restrict__ inv) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r < npad) inv[perm[r]] = (int32_t)r;
+}
+
+// Centred X and its norms in the internal order (padding rows stay zero).
+__global__ __launch_bounds__(256) void k_permute_x(const double *__restrict__ xcT,
+                                                   const double *__restrict__ norms,
+                                                   const int32_t *__restrict__ perm, int64_t n,
+                                                   int64_t npad, int32_t dpad,
+                                                   double *__restrict__ xcT2,
+                                                   double *__restrict__ norms2) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= npad) return;
+  const int64_t i = r < n ? perm[r] : -1;
+  for (int k = 0; k < dpad; ++k) xcT2[(int64_t)k * npad + r] = i >= 0 ? xcT[(int64_t)k * npad + i] : 0.0;
+  norms2[r] = i >= 0 ? norms[i] : 0.0;
+}
+
+// ----------------------------------------------------------------------------
 // Exports (test hooks)
 // ----------------------------------------------------------------------------
 __device__ inline bool state_ok(const Hdr *h, int64_t n) {
@@ -622,6 +819,7 @@ __device__ inline bool state_ok(const Hdr *h, int64_t n) {
 
 __global__ __launch_bounds__(256) void k_export_rows(const float4 *__restrict__ P, int64_t n,
                                                      int32_t nb, int64_t row0, int64_t nrows,
+                                                     const int32_t *__restrict__ inv,
                                                      float *__restrict__ out, Hdr *h) {
   if (!state_ok(h, n)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
@@ -631,7 +829,7 @@ __global__ __launch_bounds__(256) void k_export_rows(const float4 *__restrict__ 
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= nrows * n) return;
   const int64_t rr = idx / n, j = idx % n;
-  int64_t i = row0 + rr, jj = j;
+  int64_t i = inv[row0 + rr], jj = inv[j];  // internal positions of the caller's (row, column)
   if (i / T > jj / T) {  // lower triangle: read the mirrored entry
     int64_t tmp = i;
     i = jj;
@@ -651,19 +849,20 @@ __global__ __launch_bounds__(256) void k_export_rows(const float4 *__restrict__ 
 __global__ void k_export_stats(int64_t n, const double *__restrict__ beta,
                                const float *__restrict__ m, const double *__restrict__ S,
                                const double *__restrict__ H, const int32_t *__restrict__ ev,
-                               double *ob, float *om, double *oS, double *oH, int32_t *oe,
-                               Hdr *h) {
+                               const int32_t *__restrict__ inv, double *ob, float *om, double *oS,
+                               double *oH, int32_t *oe, Hdr *h) {
   if (!(h->magic == kMagic && h->n == n)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  if (ob) ob[i] = beta[i];
-  if (om) om[i] = m[i];
-  if (oS) oS[i] = S[i];
-  if (oH) oH[i] = H[i];
-  if (oe) oe[i] = ev[i];
+  const int64_t r = inv[i];
+  if (ob) ob[i] = beta[r];
+  if (om) om[i] = m[r];
+  if (oS) oS[i] = S[r];
+  if (oH) oH[i] = H[r];
+  if (oe) oe[i] = ev[r];
 }
 
 __global__ void k_export_scalars(int64_t n, const Hdr *h, double *out) {
@@ -681,7 +880,7 @@ __global__ void k_export_scalars(int64_t n, const Hdr *h, double *out) {
 // Host-side sequencing
 // ----------------------------------------------------------------------------
 hipError_t launch_affinities(const Layout &L, const float *x, double perplexity, int max_bisect,
-                             double tol_h, void *ws, hipStream_t st) {
+                             double tol_h, int reorder, void *ws, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(64), 0, st, h, L.n, L.d, L.mode, perplexity);
   double *mean = at<double>(ws, L.xmean);
@@ -689,46 +888,56 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
   double *norms = at<double>(ws, L.norms);
   float *dblock = at<float>(ws, L.dblock);
   float4 *P = at<float4>(ws, L.P);
+  int32_t *perm = at<int32_t>(ws, L.perm), *inv = at<int32_t>(ws, L.inv);
+  const unsigned pgrid = (unsigned)((L.npad + 255) / 256);
   hipLaunchKernelGGL(k_colmean, dim3(L.d), dim3(256), 0, st, x, L.n, L.d, mean);
-  hipLaunchKernelGGL(k_centre, dim3((unsigned)((L.npad + 255) / 256)), dim3(256), 0, st, x, L.n,
-                     L.d, L.npad, L.dpad, mean, xcT, norms, h);
+  hipLaunchKernelGGL(k_centre, dim3(pgrid), dim3(256), 0, st, x, L.n, L.d, L.npad, L.dpad, mean,
+                     xcT, norms, h);
+  hipLaunchKernelGGL(k_reorder_init, dim3(pgrid), dim3(256), 0, st, L.n, L.npad, perm, inv);
   CalOut co{at<double>(ws, L.beta), at<double>(ws, L.S), at<double>(ws, L.H),
             at<float>(ws, L.m),     at<float>(ws, L.a),  at<float>(ws, L.r),
             at<int32_t>(ws, L.evals)};
   const double logu = log(perplexity);
   const int64_t vpt_need = (L.n + kCalThreads - 1) / kCalThreads;
-  const unsigned pgrid = (unsigned)((L.npad + 255) / 256);
   const int32_t k32 = (L.d + 31) / 32 * 32;
   float *norms32 = at<float>(ws, L.norms32);
   float *xfT = at<float>(ws, L.xfT);
   __bf16 *xa_b = at<__bf16>(ws, L.xa), *xb_b = at<__bf16>(ws, L.xb);
   _Float16 *xa_h = at<_Float16>(ws, L.xa), *xb_h = at<_Float16>(ws, L.xb);
-  switch (L.mode) {
-    case TSNE_DIST_FP32:
-      hipLaunchKernelGGL(k_prep_f32, dim3(pgrid), dim3(256), 0, st, xcT, L.npad, L.dpad, xfT,
-                         norms32);
-      break;
-    case TSNE_DIST_BF16:
-      hipLaunchKernelGGL((k_prep_lp<__bf16, false, false>), dim3(pgrid), dim3(256), 0, st, xcT,
-                         L.npad, L.d, k32, xa_b, xb_b, norms32, h);
-      break;
-    case TSNE_DIST_BF16X3:
-      hipLaunchKernelGGL((k_prep_lp<__bf16, true, false>), dim3(pgrid), dim3(256), 0, st, xcT,
-                         L.npad, L.d, k32, xa_b, xb_b, norms32, h);
-      break;
-    case TSNE_DIST_FP16:
-      hipLaunchKernelGGL((k_prep_lp<_Float16, false, true>), dim3(pgrid), dim3(256), 0, st, xcT,
-                         L.npad, L.d, k32, xa_h, xb_h, norms32, h);
-      break;
-    case TSNE_DIST_FP16X3:
-      hipLaunchKernelGGL((k_prep_lp<_Float16, true, true>), dim3(pgrid), dim3(256), 0, st, xcT,
-                         L.npad, L.d, k32, xa_h, xb_h, norms32, h);
-      break;
-    default:
-      break;
-  }
   const dim3 dgrid((unsigned)(L.npad / 256), T / 64);
-  for (int b = 0; b < L.nb; ++b) {
+  double2 *ppart = at<double2>(ws, L.ppart);
+  uint8_t *nz = at<uint8_t>(ws, L.nz);
+
+  // Reduced-precision operands of the contraction, from centred X in the
+  // current order.
+  auto prep = [&](const double *xc) {
+    switch (L.mode) {
+      case TSNE_DIST_FP32:
+        hipLaunchKernelGGL(k_prep_f32, dim3(pgrid), dim3(256), 0, st, xc, L.npad, L.dpad, xfT,
+                           norms32);
+        break;
+      case TSNE_DIST_BF16:
+        hipLaunchKernelGGL((k_prep_lp<__bf16, false, false>), dim3(pgrid), dim3(256), 0, st, xc,
+                           L.npad, L.d, k32, xa_b, xb_b, norms32, h);
+        break;
+      case TSNE_DIST_BF16X3:
+        hipLaunchKernelGGL((k_prep_lp<__bf16, true, false>), dim3(pgrid), dim3(256), 0, st, xc,
+                           L.npad, L.d, k32, xa_b, xb_b, norms32, h);
+        break;
+      case TSNE_DIST_FP16:
+        hipLaunchKernelGGL((k_prep_lp<_Float16, false, true>), dim3(pgrid), dim3(256), 0, st, xc,
+                           L.npad, L.d, k32, xa_h, xb_h, norms32, h);
+        break;
+      case TSNE_DIST_FP16X3:
+        hipLaunchKernelGGL((k_prep_lp<_Float16, true, true>), dim3(pgrid), dim3(256), 0, st, xc,
+                           L.npad, L.d, k32, xa_h, xb_h, norms32, h);
+        break;
+      default:
+        break;
+    }
+  };
+  // Distances of row block b (into the block scratch).
+  auto dist = [&](int b, const double *xc, const double *nrm) {
     switch (L.mode) {
       case TSNE_DIST_FP32:
         hipLaunchKernelGGL(k_dist_f32, dgrid, dim3(256), 0, st, xfT, norms32, L.npad, L.dpad, b,
@@ -745,9 +954,11 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
                            norms32, L.npad, L.kk, b, dblock, h);
         break;
       default:
-        hipLaunchKernelGGL(k_dist_f64, dgrid, dim3(256), 0, st, xcT, norms, L.npad, L.dpad, b,
+        hipLaunchKernelGGL(k_dist_f64, dgrid, dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b,
                            dblock);
     }
+  };
+  auto calibrate = [&](int b) {
     const int rows = (int)((L.n - (int64_t)b * T) < T ? (L.n - (int64_t)b * T) : T);
     dim3 g(rows), blk(kCalThreads);
     if (vpt_need <= 1)
@@ -774,12 +985,49 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
     else
       hipLaunchKernelGGL(k_calibrate<0>, g, blk, 0, st, dblock, L.n, L.npad, b, logu, max_bisect,
                          tol_h, co, h);
+  };
+  auto pack = [&]() {
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)L.nt), dim3(256), 0, st, P, co.a, co.m, co.r, L.n,
+                       L.nb, ppart, nz);
+    hipLaunchKernelGGL(k_pack_reduce, dim3(1), dim3(1024), 0, st, ppart, L.nt, h);
+  };
+
+  const double *xc = xcT, *nrm = norms;
+  if (reorder && L.nb >= 2 && L.d <= kTreeMaxD) {
+    // Internal order: bisection tree over the centred X, then X in that order.
+    uint64_t *keys = at<uint64_t>(ws, L.keys);
+    int32_t *vals = at<int32_t>(ws, L.vals);
+    double *wbuf = reinterpret_cast<double *>(dblock);  // idle until the distances
+    const unsigned kgrid = (unsigned)((L.npow2 + 255) / 256);
+    const unsigned ngrid = (unsigned)((L.n + 255) / 256);
+    int levels = 0;
+    while ((1 << levels) < L.nb) ++levels;
+    for (int lev = 0; lev < levels; ++lev) {
+      hipLaunchKernelGGL(k_tree_level, dim3(1u << lev), dim3(kTreeThreads), 0, st, xcT, L.npad,
+                         L.d, L.n, L.nb, lev, perm, wbuf, keys, vals);
+      if (L.npow2 > L.n)
+        hipLaunchKernelGGL(k_tree_pad, dim3((unsigned)((L.npow2 - L.n + 255) / 256)), dim3(256),
+                           0, st, L.n, L.npow2, keys, vals);
+      for (int64_t k = 2; k <= L.npow2; k <<= 1)
+        for (int64_t j = k >> 1; j > 0; j >>= 1)
+          hipLaunchKernelGGL(k_bitonic, dim3(kgrid), dim3(256), 0, st, keys, vals, L.npow2, j, k);
+      hipLaunchKernelGGL(k_tree_apply, dim3(ngrid), dim3(256), 0, st, vals, L.n, perm);
+    }
+    hipLaunchKernelGGL(k_inverse, dim3(pgrid), dim3(256), 0, st, perm, L.npad, inv);
+    double *xcT2 = at<double>(ws, L.xcT2), *norms2 = at<double>(ws, L.norms2);
+    hipLaunchKernelGGL(k_permute_x, dim3(pgrid), dim3(256), 0, st, xcT, norms, perm, L.n, L.npad,
+                       L.dpad, xcT2, norms2);
+    xc = xcT2;
+    nrm = norms2;
+  }
+  // Distances, calibration and staging block by block, then P.
+  prep(xc);
+  for (int b = 0; b < L.nb; ++b) {
+    dist(b, xc, nrm);
+    calibrate(b);
     hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
   }
-  double2 *ppart = at<double2>(ws, L.ppart);
-  hipLaunchKernelGGL(k_pack, dim3((unsigned)L.nt), dim3(256), 0, st, P, co.a, co.m, co.r, L.n,
-                     L.nb, ppart, at<uint8_t>(ws, L.nz));
-  hipLaunchKernelGGL(k_pack_reduce, dim3(1), dim3(1024), 0, st, ppart, L.nt, h);
+  pack();
   return hipGetLastError();
 }
 
@@ -788,7 +1036,8 @@ hipError_t launch_export_p_rows(const Layout &L, void *ws, int64_t row0, int64_t
   const int64_t total = nrows * L.n;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_export_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                     at<const float4>(ws, L.P), L.n, L.nb, row0, nrows, out, at<Hdr>(ws, L.hdr));
+                     at<const float4>(ws, L.P), L.n, L.nb, row0, nrows,
+                     at<const int32_t>(ws, L.inv), out, at<Hdr>(ws, L.hdr));
   return hipGetLastError();
 }
 
@@ -797,7 +1046,8 @@ hipError_t launch_export_rowstats(const Layout &L, void *ws, double *beta, float
   hipLaunchKernelGGL(k_export_stats, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, L.n,
                      at<const double>(ws, L.beta), at<const float>(ws, L.m),
                      at<const double>(ws, L.S), at<const double>(ws, L.H),
-                     at<const int32_t>(ws, L.evals), beta, m, S, H, evals, at<Hdr>(ws, L.hdr));
+                     at<const int32_t>(ws, L.evals), at<const int32_t>(ws, L.inv), beta, m, S, H,
+                     evals, at<Hdr>(ws, L.hdr));
   return hipGetLastError();
 }
 

@@ -45,12 +45,20 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.ppart = take((size_t)L.nt * 16);
   L.meanpart = take((size_t)L.nb * 16);
   L.nz = take((size_t)L.nt);
+  L.perm = take(np * 4);
+  L.inv = take(np * 4);
   L.iter_end = o;
   // affinity-stage scratch (only needed inside tsne_affinities)
   L.xmean = take((size_t)L.dpad * 8);
   L.xcT = take((size_t)L.dpad * np * 8);
   L.norms = take(np * 8);
   L.dblock = take((size_t)T * np * 4);
+  L.npow2 = 1;
+  while (L.npow2 < n) L.npow2 <<= 1;
+  L.xcT2 = take((size_t)L.dpad * np * 8);
+  L.norms2 = take(np * 8);
+  L.keys = take((size_t)L.npow2 * 8);
+  L.vals = take((size_t)L.npow2 * 4);
   if (mode == TSNE_DIST_FP32) {
     L.xfT = take((size_t)L.dpad * np * 4);
     L.norms32 = take(np * 4);
@@ -105,15 +113,15 @@ size_t tsne_workspace_bytes(int64_t n, int32_t d, int32_t dist_mode) {
 
 int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
                     const tsne_aff_opts *opts, void *ws, size_t ws_bytes, void *stream) {
-  tsne_aff_opts o = {TSNE_DIST_FP64, 200, 1e-6};
+  tsne_aff_opts o = {TSNE_DIST_FP64, 200, 1e-6, 1, 0};
   if (opts) o = *opts;
   if (!x || !ws) return fail(TSNE_E_ARG, "tsne_affinities: null pointer");
   if (!valid_n(n)) return fail(TSNE_E_ARG, "tsne_affinities: n = %lld out of range", (long long)n);
   if (d < 1 || d > 65536) return fail(TSNE_E_ARG, "tsne_affinities: d = %d out of range", d);
   if (o.dist_mode < TSNE_DIST_FP64 || o.dist_mode > TSNE_DIST_FP16X3)
     return fail(TSNE_E_ARG, "tsne_affinities: unknown distance mode %d", o.dist_mode);
-  if (o.max_bisect < 1 || !(o.tol_h > 0.0))
-    return fail(TSNE_E_ARG, "tsne_affinities: max_bisect >= 1 and tol_h > 0 required");
+  if (o.max_bisect < 1 || !(o.tol_h > 0.0) || o.reserved != 0)
+    return fail(TSNE_E_ARG, "tsne_affinities: max_bisect >= 1, tol_h > 0, reserved = 0 required");
   if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))
     return fail(TSNE_E_PERPLEXITY, "tsne_affinities: perplexity %g not in (1, n-1 = %lld)",
                 perplexity, (long long)(n - 1));
@@ -122,8 +130,8 @@ int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
   if (ws_bytes < L.total)
     return fail(TSNE_E_WORKSPACE, "tsne_affinities: workspace %zu bytes, need %zu", ws_bytes,
                 L.total);
-  return hip_check(tsne::launch_affinities(L, x, perplexity, o.max_bisect, o.tol_h, ws,
-                                           (hipStream_t)stream),
+  return hip_check(tsne::launch_affinities(L, x, perplexity, o.max_bisect, o.tol_h,
+                                           o.reorder != 0, ws, (hipStream_t)stream),
                    "tsne_affinities");
 }
 
@@ -235,6 +243,20 @@ int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *
                    "tsne_export_p_rows");
 }
 
+int tsne_export_order(void *ws, int64_t n, int32_t *perm, uint8_t *flags, void *stream) {
+  if (int rc = check_iter_args("tsne_export_order", ws, n)) return rc;
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (perm)
+    e = hipMemcpyAsync(perm, tsne::at<const int32_t>(ws, L.perm), (size_t)n * 4,
+                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && flags)
+    e = hipMemcpyAsync(flags, tsne::at<const uint8_t>(ws, L.nz), (size_t)L.nt,
+                       hipMemcpyDeviceToDevice, st);
+  return hip_check(e, "tsne_export_order");
+}
+
 size_t tsne_batch_workspace_bytes(int32_t count) {
   if (count < 1 || count > (1 << 20)) return 0;
   return tsne::kBatchHdrBytes + (size_t)count * sizeof(tsne::BatchEntry);
@@ -292,6 +314,7 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.zpart = tsne::at<double>(ws, L.zpart);
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
+    e.perm = tsne::at<const int32_t>(ws, L.perm);
     e.h = tsne::at<tsne::Hdr>(ws, L.hdr);
     e.n = L.n;
     e.nt = L.nt;

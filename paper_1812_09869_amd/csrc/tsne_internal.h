@@ -56,10 +56,14 @@ struct Layout {
   // byte offsets from the workspace base
   size_t hdr = 0, beta = 0, S = 0, H = 0, m = 0, a = 0, r = 0, evals = 0;
   size_t P = 0, part = 0, zpart = 0, cpart = 0, ppart = 0, meanpart = 0;
-  size_t nz = 0;  // per tile: 1 if any stored p_ij of the tile is nonzero
+  size_t nz = 0;    // per tile: 1 if any stored p_ij of the tile is nonzero
+  size_t perm = 0;  // int32 [npad]: internal position -> caller's index
+  size_t inv = 0;   // int32 [npad]: caller's index -> internal position
   size_t iter_end = 0;  // end of the part that tsne_step needs
   int32_t kk = 0;  // K of the reduced-precision contraction (d rounded up, x3 for split modes)
   size_t xmean = 0, xcT = 0, norms = 0, dblock = 0;
+  size_t xcT2 = 0, norms2 = 0, keys = 0, vals = 0;  // reordering
+  int64_t npow2 = 0;
   size_t xfT = 0, norms32 = 0, xa = 0, xb = 0;  // reduced-precision operands
   size_t total = 0;
 };
@@ -90,6 +94,7 @@ struct BatchEntry {
   double *zpart;
   double2 *meanpart;
   const uint8_t *nz;
+  const int32_t *perm;
   Hdr *h;
   int64_t n, nt, tile0;  // tile0: first global tile index of this problem
   int32_t nb, blk0;      // blk0: first global row-block index of this problem
@@ -114,7 +119,7 @@ inline P *at(void *ws, size_t off) {
 // Launch wrappers (all asynchronous on `stream`)
 // ---------------------------------------------------------------------------
 hipError_t launch_affinities(const Layout &L, const float *x, double perplexity, int max_bisect,
-                             double tol_h, void *ws, hipStream_t stream);
+                             double tol_h, int reorder, void *ws, hipStream_t stream);
 hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t stream);
 hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
                          float mu, float eta, float min_gain, int recentre, float *grad_out,

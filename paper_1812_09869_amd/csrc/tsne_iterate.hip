@@ -214,7 +214,8 @@ __device__ __forceinline__ void tile_rows_zero(const float2 *yrow, const float2 
 
 // One workgroup's share of the force pass: tile number `tile` of a problem.
 __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
-                                         const float2 *__restrict__ Y, int64_t n, int32_t nb,
+                                         const float2 *__restrict__ Y,
+                                         const int32_t *__restrict__ perm, int64_t n, int32_t nb,
                                          float4 *__restrict__ part, double *__restrict__ zpart,
                                          const uint8_t *__restrict__ nz, Hdr *h, int64_t tile,
                                          ForceSmem &sm) {
@@ -235,11 +236,11 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
     const bool vi = i < n, vj = j < n;
     rvalid |= vi ? (1u << k) : 0u;
     cvalid |= vj ? (1u << k) : 0u;
-    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
+    yc[k] = vj ? Y[perm[j]] : make_float2(0.f, 0.f);
   }
   {
     const int64_t i = (int64_t)I * T + t;
-    sm.yrow[t] = i < n ? Y[i] : make_float2(0.f, 0.f);
+    sm.yrow[t] = i < n ? Y[perm[i]] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   float4 *wring = &sm.ring[w][0][0][0];
@@ -308,12 +309,13 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 }
 
 __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
-                                                  const float2 *__restrict__ Y, int64_t n,
+                                                  const float2 *__restrict__ Y,
+                                                  const int32_t *__restrict__ perm, int64_t n,
                                                   int32_t nb, float4 *__restrict__ part,
                                                   double *__restrict__ zpart,
                                                   const uint8_t *__restrict__ nz, Hdr *h) {
   __shared__ ForceSmem sm;
-  force_wg(P, Y, n, nb, part, zpart, nz, h, blockIdx.x, sm);
+  force_wg(P, Y, perm, n, nb, part, zpart, nz, h, blockIdx.x, sm);
 }
 
 // Z = sum of the tile partials in tile order (one workgroup of 1024 threads).
@@ -358,6 +360,7 @@ __device__ inline float2 row_gradient(const float4 *__restrict__ part, int32_t n
 // Update (Eq. 10, descent): gains, momentum, position; per-block sums of the
 // new positions for the re-centring.
 __device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64_t n, int32_t nb,
+                                          const int32_t *__restrict__ perm,
                                           float2 *__restrict__ Y, float2 *__restrict__ U,
                                           float2 *__restrict__ G, float alpha, float mu, float eta,
                                           float min_gain, float2 *__restrict__ grad_out,
@@ -365,10 +368,11 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64
                                           double (&red)[2][4]) {
   if (!state_ok(h, n)) return;
   const int r = threadIdx.x;
-  const int64_t i = (int64_t)b * T + r;
+  const int64_t ir = (int64_t)b * T + r;  // internal position
   double sx = 0.0, sy = 0.0;
   bool bad = false;
-  if (i < n) {
+  if (ir < n) {
+    const int64_t i = perm[ir];
     const float2 g = row_gradient(part, nb, b, r, (double)alpha, h->z);
     if (grad_out) grad_out[i] = g;
     float2 u = U[i], gn = G[i], y = Y[i];
@@ -401,14 +405,15 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64
 }
 
 __global__ __launch_bounds__(256) void k_update(const float4 *__restrict__ part, int64_t n,
-                                                int32_t nb, float2 *__restrict__ Y,
+                                                int32_t nb, const int32_t *__restrict__ perm,
+                                                float2 *__restrict__ Y,
                                                 float2 *__restrict__ U, float2 *__restrict__ G,
                                                 float alpha, float mu, float eta, float min_gain,
                                                 float2 *__restrict__ grad_out,
                                                 double2 *__restrict__ meanpart, Hdr *h) {
   __shared__ double red[2][4];
-  update_wg(part, n, nb, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h, blockIdx.x,
-            red);
+  update_wg(part, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h,
+            blockIdx.x, red);
 }
 
 // Subtract the mean of the map from the rows of block `blk`.
@@ -481,7 +486,7 @@ __global__ __launch_bounds__(256, 2) void k_force_batched(const BatchHdr *__rest
   const BatchEntry &e = tab[p];
   const int64_t tile = (int64_t)blockIdx.x - e.tile0;
   if (tile < 0 || tile >= e.nt) return;
-  force_wg(e.P, e.Y, e.n, e.nb, e.part, e.zpart, e.nz, e.h, tile, sm);
+  force_wg(e.P, e.Y, e.perm, e.n, e.nb, e.part, e.zpart, e.nz, e.h, tile, sm);
 }
 
 __global__ __launch_bounds__(1024) void k_zreduce_batched(const BatchHdr *__restrict__ bh,
@@ -504,7 +509,7 @@ __global__ __launch_bounds__(256) void k_update_batched(const BatchHdr *__restri
   const BatchEntry &e = tab[p];
   const int64_t b = (int64_t)blockIdx.x - e.blk0;
   if (b < 0 || b >= e.nb) return;
-  update_wg(e.part, e.n, e.nb, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
+  update_wg(e.part, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
             (int)b, red);
 }
 
@@ -522,14 +527,15 @@ __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__rest
 }
 
 __global__ __launch_bounds__(256) void k_grad_only(const float4 *__restrict__ part, int64_t n,
-                                                   int32_t nb, float alpha,
-                                                   float2 *__restrict__ grad_out, Hdr *h) {
+                                                   int32_t nb, const int32_t *__restrict__ perm,
+                                                   float alpha, float2 *__restrict__ grad_out,
+                                                   Hdr *h) {
   if (!state_ok(h, n)) return;
   const int b = blockIdx.x, r = threadIdx.x;
-  const int64_t i = (int64_t)b * T + r;
-  if (i < n) {
+  const int64_t ir = (int64_t)b * T + r;
+  if (ir < n) {
     const float2 g = row_gradient(part, nb, b, r, (double)alpha, h->z);
-    grad_out[i] = g;
+    grad_out[perm[ir]] = g;
     if (!(isfinite(g.x) && isfinite(g.y))) flag_error(h, kErrNonFinite);
   }
 }
@@ -569,10 +575,12 @@ __device__ __forceinline__ void cost_tile(const float4 *__restrict__ tp,
 }
 
 __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
-                                                 const float2 *__restrict__ Y, int64_t n,
+                                                 const float2 *__restrict__ Y,
+                                                 const int32_t *__restrict__ perm, int64_t n,
                                                  int32_t nb, double2 *__restrict__ cpart,
                                                  const uint8_t *__restrict__ nz, Hdr *h) {
   __shared__ double red[2][4];
+  __shared__ float2 ys[T];
   if (!state_ok(h, n)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
@@ -590,9 +598,14 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
     const bool vi = i < n, vj = j < n;
     rvalid |= vi ? (1u << k) : 0u;
     cvalid |= vj ? (1u << k) : 0u;
-    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
+    yc[k] = vj ? Y[perm[j]] : make_float2(0.f, 0.f);
   }
-  const float2 *yrow = Y + (int64_t)I * T + tr;
+  {
+    const int64_t i = (int64_t)I * T + t;
+    ys[t] = i < n ? Y[perm[i]] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float2 *yrow = ys + tr;
   const bool edge = ((int64_t)(J + 1) * T > n);
   const float4 *tp = P + (size_t)blockIdx.x * TT4;
   float plq = 0.f, z = 0.f;
@@ -672,7 +685,8 @@ __global__ __launch_bounds__(1024) void k_cost_reduce(const double2 *__restrict_
 hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_force, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
-                     reinterpret_cast<const float2 *>(y), L.n, L.nb, at<float4>(ws, L.part),
+                     reinterpret_cast<const float2 *>(y), at<const int32_t>(ws, L.perm), L.n,
+                     L.nb, at<float4>(ws, L.part),
                      at<double>(ws, L.zpart), at<const uint8_t>(ws, L.nz), h);
   return hipGetLastError();
 }
@@ -685,7 +699,7 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
                      L.n, h, z_out);
   double2 *mp = at<double2>(ws, L.meanpart);
   hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(256), 0, st, at<const float4>(ws, L.part), L.n,
-                     L.nb, reinterpret_cast<float2 *>(y), reinterpret_cast<float2 *>(u),
+                     L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y), reinterpret_cast<float2 *>(u),
                      reinterpret_cast<float2 *>(g), alpha, mu, eta, min_gain,
                      reinterpret_cast<float2 *>(grad_out), mp, h);
   if (recentre)
@@ -700,7 +714,8 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
   hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
                      L.n, h, z_out);
   hipLaunchKernelGGL(k_grad_only, dim3(L.nb), dim3(256), 0, st, at<const float4>(ws, L.part),
-                     L.n, L.nb, alpha, reinterpret_cast<float2 *>(grad_out), h);
+                     L.n, L.nb, at<const int32_t>(ws, L.perm), alpha,
+                     reinterpret_cast<float2 *>(grad_out), h);
   return hipGetLastError();
 }
 
@@ -708,8 +723,8 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, h
   Hdr *h = at<Hdr>(ws, L.hdr);
   double2 *cp = at<double2>(ws, L.cpart);
   hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
-                     reinterpret_cast<const float2 *>(y), L.n, L.nb, cp, at<const uint8_t>(ws, L.nz),
-                     h);
+                     reinterpret_cast<const float2 *>(y), at<const int32_t>(ws, L.perm), L.n, L.nb,
+                     cp, at<const uint8_t>(ws, L.nz), h);
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
   return hipGetLastError();
 }

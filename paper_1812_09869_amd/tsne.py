@@ -37,14 +37,14 @@ class Schedule:
 
 class ExactTSNE:
     def __init__(self, x: torch.Tensor, perplexity: float, dist_mode="fp64", max_bisect: int = 200,
-                 tol_h: float = 1e-6, ws: torch.Tensor | None = None):
+                 tol_h: float = 1e-6, ws: torch.Tensor | None = None, reorder: bool = True):
         if x.dim() != 2:
             raise ValueError("x must be n x d")
         self.n, self.d = x.shape
         self.perplexity = float(perplexity)
         self.ws = ws if ws is not None else _lib.new_workspace(self.n, self.d, dist_mode,
                                                                device=x.device)
-        _lib.affinities(x, perplexity, self.ws, dist_mode, max_bisect, tol_h)
+        _lib.affinities(x, perplexity, self.ws, dist_mode, max_bisect, tol_h, reorder)
         self._z = torch.zeros(1, dtype=torch.float64, device=x.device)
         self._cost = torch.zeros(2, dtype=torch.float64, device=x.device)
 
