@@ -628,9 +628,11 @@ __global__ __launch_bounds__(1024) void k_pack_reduce(const double2 *__restrict_
 // halves at the next level are the two sides of that direction. Every step is
 // deterministic (fixed reduction orders, a fixed sorting network).
 // ----------------------------------------------------------------------------
-constexpr int kTreeThreads = 1024;
+constexpr int kTreeThreads = 256;
 constexpr int kTreeMaxD = 2048;
 constexpr int kTreePowerIters = 4;
+constexpr int kTreeTargetGroups = 1024;  // workgroups per level at the shallow levels
+constexpr int kSortBlock = 4096;         // keys per workgroup in the LDS sorting stages
 
 __global__ void k_reorder_init(int64_t n, int64_t npad, int32_t *__restrict__ perm,
                                int32_t *__restrict__ inv) {
@@ -640,8 +642,21 @@ __global__ void k_reorder_init(int64_t n, int64_t npad, int32_t *__restrict__ pe
   inv[i] = (int32_t)i;
 }
 
-// Sum of acc[0..7] over the workgroup (kTreeThreads threads) into out[0..7]
-// (LDS), in a fixed order.
+// Segment s of level `level`: internal positions [lo, hi).
+struct TreeSeg {
+  int64_t lo, hi;
+};
+
+__device__ inline TreeSeg tree_segment(int64_t s, int level, int32_t nb, int64_t n) {
+  TreeSeg g;
+  g.lo = ((s * nb) >> level) * T;
+  g.hi = (((s + 1) * nb) >> level) * T;
+  if (g.lo > n) g.lo = n;
+  if (g.hi > n) g.hi = n;
+  return g;
+}
+
+// Sum of acc[0..7] over the workgroup into out[0..7] (LDS), in a fixed order.
 __device__ inline void tree_block_sum8(double (&acc)[8], double (*red)[8], double *out) {
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
 #pragma unroll
@@ -664,94 +679,128 @@ __device__ inline uint32_t orderable_f32(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// One level of the tree: segment blockIdx.x of 2^level. Writes the sort keys
-// (segment << 32 | projection) and the caller indices of its positions.
-__global__ __launch_bounds__(kTreeThreads) void k_tree_level(
+// Partial sums of one chunk (workgroup blockIdx.x = s * C + c) of a segment:
+//   MODE 0: sum_r x_r                       (for the mean)
+//   MODE 1: sum_r (x_r - mean) w_r, w_r = (x_r - mean) . v   (power iteration)
+// into part[blockIdx.x][0 .. d). Each thread keeps w_r of its own rows in
+// wbuf and reads back only what it wrote.
+template <int MODE>
+__global__ __launch_bounds__(kTreeThreads) void k_tree_partial(
     const double *__restrict__ xcT, int64_t npad, int32_t d, int64_t n, int32_t nb, int level,
-    const int32_t *__restrict__ perm, double *__restrict__ wbuf, uint64_t *__restrict__ keys,
-    int32_t *__restrict__ vals) {
-  __shared__ double mean[kTreeMaxD], v[kTreeMaxD];
+    int32_t C, const int32_t *__restrict__ perm, const double *__restrict__ segmean,
+    const double *__restrict__ segv, double *__restrict__ wbuf, double *__restrict__ part) {
+  __shared__ double mean[MODE ? kTreeMaxD : 1], v[MODE ? kTreeMaxD : 1];
   __shared__ double red[kTreeThreads / 64][8];
   __shared__ double out8[8];
-  __shared__ double nrm;
   const int t = threadIdx.x;
-  const int64_t s = blockIdx.x;
-  const int64_t lo = ((s * nb) >> level) * T;
-  int64_t hi = (((s + 1) * nb) >> level) * T;
-  if (hi > n) hi = n;
-  if (lo >= hi) return;
-  const uint64_t seg = (uint64_t)s << 32;
-  if (hi - lo <= T) {  // a leaf: keep its order
-    for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
-      keys[r] = seg | (uint64_t)(r - lo);
-      vals[r] = perm[r];
+  const int64_t s = blockIdx.x / C, c = blockIdx.x % C;
+  const TreeSeg g = tree_segment(s, level, nb, n);
+  if (g.hi - g.lo <= T) return;  // leaves are not split
+  const int64_t len = g.hi - g.lo;
+  const int64_t r0 = g.lo + len * c / C, r1 = g.lo + len * (c + 1) / C;
+  double *out = part + (int64_t)blockIdx.x * d;
+  if (MODE == 1) {
+    for (int k = t; k < d; k += kTreeThreads) {
+      mean[k] = segmean[s * d + k];
+      v[k] = segv[s * d + k];
     }
-    return;
-  }
-  const double inv_cnt = 1.0 / (double)(hi - lo);
-  // segment mean, 8 coordinates at a time
-  for (int k0 = 0; k0 < d; k0 += 8) {
-    double acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
-      const int64_t i = perm[r];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (k0 + q < d) acc[q] += xcT[(int64_t)(k0 + q) * npad + i];
-    }
-    tree_block_sum8(acc, red, out8);
-    if (t < 8 && k0 + t < d) mean[k0 + t] = out8[t] * inv_cnt;
-  }
-  // fixed start vector
-  for (int k = t; k < d; k += kTreeThreads) {
-    const uint32_t hsh = (uint32_t)(k + 1) * 2654435761u;
-    v[k] = 0.5 + (double)(hsh >> 8) * (1.0 / 16777216.0);
-  }
-  __syncthreads();
-  for (int it = 0; it <= kTreePowerIters; ++it) {
-    // w_r = (x_r - mean) . v for this thread's rows (each thread reads back
-    // only what it wrote)
-    for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
+    __syncthreads();
+    for (int64_t r = r0 + t; r < r1; r += kTreeThreads) {
       const int64_t i = perm[r];
       double wsum = 0.0;
       for (int k = 0; k < d; ++k) wsum += (xcT[(int64_t)k * npad + i] - mean[k]) * v[k];
       wbuf[r] = wsum;
     }
-    if (it == kTreePowerIters) break;
-    // v' = sum_r (x_r - mean) w_r, then normalise
-    __syncthreads();
-    double ss = 0.0;
-    for (int k0 = 0; k0 < d; k0 += 8) {
-      double acc[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-      for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
-        const int64_t i = perm[r];
-        const double wr = wbuf[r];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (k0 + q < d) acc[q] += (xcT[(int64_t)(k0 + q) * npad + i] - mean[k0 + q]) * wr;
-      }
-      tree_block_sum8(acc, red, out8);
-      if (t < 8 && k0 + t < d) v[k0 + t] = out8[t];
-      if (t == 0)
-        for (int q = 0; q < 8 && k0 + q < d; ++q) ss += out8[q] * out8[q];
-    }
-    if (t == 0) nrm = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
-    __syncthreads();
-    if (nrm == 0.0) {  // all points of the segment coincide: keep the order
-      for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
-        keys[r] = seg | (uint64_t)(r - lo);
-        vals[r] = perm[r];
-      }
-      return;
-    }
-    for (int k = t; k < d; k += kTreeThreads) v[k] *= nrm;
-    __syncthreads();
   }
-  for (int64_t r = lo + t; r < hi; r += kTreeThreads) {
-    keys[r] = seg | (uint64_t)orderable_f32((float)wbuf[r]);
+  for (int k0 = 0; k0 < d; k0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int64_t r = r0 + t; r < r1; r += kTreeThreads) {
+      const int64_t i = perm[r];
+      const double wr = MODE ? wbuf[r] : 1.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + q < d) {
+          const double xv = xcT[(int64_t)(k0 + q) * npad + i];
+          acc[q] += MODE ? (xv - mean[MODE ? k0 + q : 0]) * wr : xv;
+        }
+    }
+    tree_block_sum8(acc, red, out8);
+    if (t < 8 && k0 + t < d) out[k0 + t] = out8[t];
+  }
+}
+
+// Per segment: MODE 0 turns the chunk sums into the mean and sets the fixed
+// start vector; MODE 1 turns them into the next (normalised) direction.
+template <int MODE>
+__global__ __launch_bounds__(kTreeThreads) void k_tree_reduce(const double *__restrict__ part,
+                                                              int32_t d, int64_t n, int32_t nb,
+                                                              int level, int32_t C,
+                                                              double *__restrict__ segmean,
+                                                              double *__restrict__ segv) {
+  __shared__ double red[kTreeThreads / 64];
+  __shared__ double scale;
+  const int t = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  const TreeSeg g = tree_segment(s, level, nb, n);
+  if (g.hi - g.lo <= T) return;
+  double ss = 0.0;
+  for (int k = t; k < d; k += kTreeThreads) {
+    double sum = 0.0;
+    for (int c = 0; c < C; ++c) sum += part[(s * C + c) * d + k];
+    if (MODE == 0) {
+      segmean[s * d + k] = sum / (double)(g.hi - g.lo);
+      const uint32_t hsh = (uint32_t)(k + 1) * 2654435761u;
+      segv[s * d + k] = 0.5 + (double)(hsh >> 8) * (1.0 / 16777216.0);
+    } else {
+      segv[s * d + k] = sum;
+      ss += sum * sum;
+    }
+  }
+  if (MODE == 0) return;
+  ss = wave_sum_d(ss);
+  if ((t & 63) == 0) red[t >> 6] = ss;
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;
+    for (int q = 0; q < kTreeThreads / 64; ++q) tot += red[q];
+    scale = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;  // coincident points: projections all 0
+  }
+  __syncthreads();
+  for (int k = t; k < d; k += kTreeThreads) segv[s * d + k] *= scale;
+}
+
+// Sort keys (segment << 32 | projection on the segment's direction) and the
+// caller indices of the positions; leaves keep their order.
+__global__ __launch_bounds__(kTreeThreads) void k_tree_keys(
+    const double *__restrict__ xcT, int64_t npad, int32_t d, int64_t n, int32_t nb, int level,
+    int32_t C, const int32_t *__restrict__ perm, const double *__restrict__ segmean,
+    const double *__restrict__ segv, uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+  __shared__ double mean[kTreeMaxD], v[kTreeMaxD];
+  const int t = threadIdx.x;
+  const int64_t s = blockIdx.x / C, c = blockIdx.x % C;
+  const TreeSeg g = tree_segment(s, level, nb, n);
+  const int64_t len = g.hi - g.lo;
+  const int64_t r0 = g.lo + len * c / C, r1 = g.lo + len * (c + 1) / C;
+  const uint64_t seg = (uint64_t)s << 32;
+  if (len <= T) {
+    for (int64_t r = r0 + t; r < r1; r += kTreeThreads) {
+      keys[r] = seg | (uint64_t)(r - g.lo);
+      vals[r] = perm[r];
+    }
+    return;
+  }
+  for (int k = t; k < d; k += kTreeThreads) {
+    mean[k] = segmean[s * d + k];
+    v[k] = segv[s * d + k];
+  }
+  __syncthreads();
+  for (int64_t r = r0 + t; r < r1; r += kTreeThreads) {
+    const int64_t i = perm[r];
+    double p = 0.0;
+    for (int k = 0; k < d; ++k) p += (xcT[(int64_t)k * npad + i] - mean[k]) * v[k];
+    keys[r] = seg | (uint64_t)orderable_f32((float)p);
     vals[r] = perm[r];
   }
 }
@@ -765,8 +814,9 @@ __global__ void k_tree_pad(int64_t n, int64_t npow2, uint64_t *__restrict__ keys
   vals[r] = (int32_t)(r < INT32_MAX ? r : INT32_MAX);
 }
 
-// One compare-exchange stage of a bitonic sort (ascending) of (key, value)
-// pairs over npow2 entries.
+// Bitonic sort (ascending) of (key, value) pairs over npow2 entries.
+// Global stage: one compare-exchange distance j >= kSortBlock / 2 ... of
+// merge size k.
 __global__ void k_bitonic(uint64_t *__restrict__ keys, int32_t *__restrict__ vals, int64_t npow2,
                           int64_t j, int64_t k) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -781,6 +831,47 @@ __global__ void k_bitonic(uint64_t *__restrict__ keys, int32_t *__restrict__ val
     const int32_t va = vals[i];
     vals[i] = vals[l];
     vals[l] = va;
+  }
+}
+
+// LDS stages on blocks of `blk` consecutive entries (blk a power of two, at
+// most kSortBlock): with k0 = 0, every merge size k = 2 .. blk and all its
+// distances (a full sort of each block in the global direction pattern);
+// otherwise the distances blk / 2 .. 1 of merge size k0.
+__global__ __launch_bounds__(1024) void k_bitonic_local(uint64_t *__restrict__ keys,
+                                                        int32_t *__restrict__ vals, int64_t blk,
+                                                        int64_t k0) {
+  __shared__ uint64_t sk[kSortBlock];
+  __shared__ int32_t sv[kSortBlock];
+  const int64_t base = (int64_t)blockIdx.x * blk;
+  for (int64_t e = threadIdx.x; e < blk; e += 1024) {
+    sk[e] = keys[base + e];
+    sv[e] = vals[base + e];
+  }
+  __syncthreads();
+  const int64_t kfirst = k0 ? k0 : 2, klast = k0 ? k0 : blk;
+  for (int64_t k = kfirst; k <= klast; k <<= 1) {
+    for (int64_t j = (k0 ? blk : k) >> 1; j > 0; j >>= 1) {
+      for (int64_t e = threadIdx.x; e < blk; e += 1024) {
+        const int64_t l = e ^ j;
+        if (l > e) {
+          const uint64_t a = sk[e], b = sk[l];
+          const bool up = ((base + e) & k) == 0;
+          if ((a > b) == up) {
+            sk[e] = b;
+            sk[l] = a;
+            const int32_t va = sv[e];
+            sv[e] = sv[l];
+            sv[l] = va;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int64_t e = threadIdx.x; e < blk; e += 1024) {
+    keys[base + e] = sk[e];
+    vals[base + e] = sv[e];
   }
 }
 
@@ -997,20 +1088,46 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
     // Internal order: bisection tree over the centred X, then X in that order.
     uint64_t *keys = at<uint64_t>(ws, L.keys);
     int32_t *vals = at<int32_t>(ws, L.vals);
-    double *wbuf = reinterpret_cast<double *>(dblock);  // idle until the distances
-    const unsigned kgrid = (unsigned)((L.npow2 + 255) / 256);
+    // tree scratch in the (still idle) distance block: w per row, chunk
+    // partial sums, segment means and directions (each at most nb x d)
+    double *wbuf = reinterpret_cast<double *>(dblock);
+    double *part = wbuf + L.npad;
+    double *segmean = part + (size_t)L.nb * L.d;
+    double *segv = segmean + (size_t)L.nb * L.d;
     const unsigned ngrid = (unsigned)((L.n + 255) / 256);
+    const int64_t blk = L.npow2 < kSortBlock ? L.npow2 : kSortBlock;
     int levels = 0;
     while ((1 << levels) < L.nb) ++levels;
     for (int lev = 0; lev < levels; ++lev) {
-      hipLaunchKernelGGL(k_tree_level, dim3(1u << lev), dim3(kTreeThreads), 0, st, xcT, L.npad,
-                         L.d, L.n, L.nb, lev, perm, wbuf, keys, vals);
+      const int32_t S = 1 << lev;
+      int32_t C = kTreeTargetGroups / S;
+      if (C > L.nb / S) C = L.nb / S;  // at least a tile of rows per chunk on average
+      if (C < 1) C = 1;
+      const dim3 chunks((unsigned)(S * C)), segs((unsigned)S), tb(kTreeThreads);
+      hipLaunchKernelGGL(k_tree_partial<0>, chunks, tb, 0, st, xcT, L.npad, L.d, L.n, L.nb, lev, C,
+                         perm, segmean, segv, wbuf, part);
+      hipLaunchKernelGGL(k_tree_reduce<0>, segs, tb, 0, st, part, L.d, L.n, L.nb, lev, C, segmean,
+                         segv);
+      for (int it = 0; it < kTreePowerIters; ++it) {
+        hipLaunchKernelGGL(k_tree_partial<1>, chunks, tb, 0, st, xcT, L.npad, L.d, L.n, L.nb, lev,
+                           C, perm, segmean, segv, wbuf, part);
+        hipLaunchKernelGGL(k_tree_reduce<1>, segs, tb, 0, st, part, L.d, L.n, L.nb, lev, C,
+                           segmean, segv);
+      }
+      hipLaunchKernelGGL(k_tree_keys, chunks, tb, 0, st, xcT, L.npad, L.d, L.n, L.nb, lev, C, perm,
+                         segmean, segv, keys, vals);
       if (L.npow2 > L.n)
         hipLaunchKernelGGL(k_tree_pad, dim3((unsigned)((L.npow2 - L.n + 255) / 256)), dim3(256),
                            0, st, L.n, L.npow2, keys, vals);
-      for (int64_t k = 2; k <= L.npow2; k <<= 1)
-        for (int64_t j = k >> 1; j > 0; j >>= 1)
-          hipLaunchKernelGGL(k_bitonic, dim3(kgrid), dim3(256), 0, st, keys, vals, L.npow2, j, k);
+      const unsigned nblk = (unsigned)(L.npow2 / blk);
+      hipLaunchKernelGGL(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys, vals, blk,
+                         (int64_t)0);
+      for (int64_t k = 2 * blk; k <= L.npow2; k <<= 1) {
+        for (int64_t j = k >> 1; j >= blk; j >>= 1)
+          hipLaunchKernelGGL(k_bitonic, dim3((unsigned)(L.npow2 / 256)), dim3(256), 0, st, keys,
+                             vals, L.npow2, j, k);
+        hipLaunchKernelGGL(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys, vals, blk, k);
+      }
       hipLaunchKernelGGL(k_tree_apply, dim3(ngrid), dim3(256), 0, st, vals, L.n, perm);
     }
     hipLaunchKernelGGL(k_inverse, dim3(pgrid), dim3(256), 0, st, perm, L.npad, inv);

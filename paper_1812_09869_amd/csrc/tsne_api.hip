@@ -47,6 +47,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.nz = take((size_t)L.nt);
   L.perm = take(np * 4);
   L.inv = take(np * 4);
+  L.yp = take(np * 8);
   L.iter_end = o;
   // affinity-stage scratch (only needed inside tsne_affinities)
   L.xmean = take((size_t)L.dpad * 8);
@@ -315,6 +316,7 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
     e.perm = tsne::at<const int32_t>(ws, L.perm);
+    e.yp = tsne::at<float2>(ws, L.yp);
     e.h = tsne::at<tsne::Hdr>(ws, L.hdr);
     e.n = L.n;
     e.nt = L.nt;

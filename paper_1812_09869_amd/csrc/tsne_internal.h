@@ -59,6 +59,7 @@ struct Layout {
   size_t nz = 0;    // per tile: 1 if any stored p_ij of the tile is nonzero
   size_t perm = 0;  // int32 [npad]: internal position -> caller's index
   size_t inv = 0;   // int32 [npad]: caller's index -> internal position
+  size_t yp = 0;    // float2 [npad]: the map in the internal order (per force pass)
   size_t iter_end = 0;  // end of the part that tsne_step needs
   int32_t kk = 0;  // K of the reduced-precision contraction (d rounded up, x3 for split modes)
   size_t xmean = 0, xcT = 0, norms = 0, dblock = 0;
@@ -95,6 +96,7 @@ struct BatchEntry {
   double2 *meanpart;
   const uint8_t *nz;
   const int32_t *perm;
+  float2 *yp;  // positions in the internal order (refreshed by every force pass)
   Hdr *h;
   int64_t n, nt, tile0;  // tile0: first global tile index of this problem
   int32_t nb, blk0;      // blk0: first global row-block index of this problem

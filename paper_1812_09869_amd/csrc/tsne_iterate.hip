@@ -212,10 +212,23 @@ __device__ __forceinline__ void tile_rows_zero(const float2 *yrow, const float2 
   }
 }
 
+// The map in the internal order, zero-padded to whole tiles (read by the
+// force and cost passes, so that their loads are contiguous).
+__device__ __forceinline__ void gather_rows(const float2 *__restrict__ Y,
+                                            const int32_t *__restrict__ perm, int64_t n,
+                                            float2 *__restrict__ Yp, int64_t r) {
+  Yp[r] = r < n ? Y[perm[r]] : make_float2(0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_gather_y(const float2 *__restrict__ Y,
+                                                  const int32_t *__restrict__ perm, int64_t n,
+                                                  float2 *__restrict__ Yp) {
+  gather_rows(Y, perm, n, Yp, (int64_t)blockIdx.x * T + threadIdx.x);
+}
+
 // One workgroup's share of the force pass: tile number `tile` of a problem.
 __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
-                                         const float2 *__restrict__ Y,
-                                         const int32_t *__restrict__ perm, int64_t n, int32_t nb,
+                                         const float2 *__restrict__ Y, int64_t n, int32_t nb,
                                          float4 *__restrict__ part, double *__restrict__ zpart,
                                          const uint8_t *__restrict__ nz, Hdr *h, int64_t tile,
                                          ForceSmem &sm) {
@@ -236,11 +249,11 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
     const bool vi = i < n, vj = j < n;
     rvalid |= vi ? (1u << k) : 0u;
     cvalid |= vj ? (1u << k) : 0u;
-    yc[k] = vj ? Y[perm[j]] : make_float2(0.f, 0.f);
+    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
   }
   {
     const int64_t i = (int64_t)I * T + t;
-    sm.yrow[t] = i < n ? Y[perm[i]] : make_float2(0.f, 0.f);
+    sm.yrow[t] = i < n ? Y[i] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   float4 *wring = &sm.ring[w][0][0][0];
@@ -309,13 +322,12 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 }
 
 __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
-                                                  const float2 *__restrict__ Y,
-                                                  const int32_t *__restrict__ perm, int64_t n,
+                                                  const float2 *__restrict__ Y, int64_t n,
                                                   int32_t nb, float4 *__restrict__ part,
                                                   double *__restrict__ zpart,
                                                   const uint8_t *__restrict__ nz, Hdr *h) {
   __shared__ ForceSmem sm;
-  force_wg(P, Y, perm, n, nb, part, zpart, nz, h, blockIdx.x, sm);
+  force_wg(P, Y, n, nb, part, zpart, nz, h, blockIdx.x, sm);
 }
 
 // Z = sum of the tile partials in tile order (one workgroup of 1024 threads).
@@ -486,7 +498,19 @@ __global__ __launch_bounds__(256, 2) void k_force_batched(const BatchHdr *__rest
   const BatchEntry &e = tab[p];
   const int64_t tile = (int64_t)blockIdx.x - e.tile0;
   if (tile < 0 || tile >= e.nt) return;
-  force_wg(e.P, e.Y, e.perm, e.n, e.nb, e.part, e.zpart, e.nz, e.h, tile, sm);
+  force_wg(e.P, e.yp, e.n, e.nb, e.part, e.zpart, e.nz, e.h, tile, sm);
+}
+
+__global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restrict__ bh,
+                                                        int count, int64_t tiles,
+                                                        int64_t blocks) {
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry *tab = batch_table(bh);
+  const int p = find_entry(tab, count, blockIdx.x, false);
+  const BatchEntry &e = tab[p];
+  const int64_t b = (int64_t)blockIdx.x - e.blk0;
+  if (b < 0 || b >= e.nb) return;
+  gather_rows(e.Y, e.perm, e.n, e.yp, b * T + threadIdx.x);
 }
 
 __global__ __launch_bounds__(1024) void k_zreduce_batched(const BatchHdr *__restrict__ bh,
@@ -575,12 +599,10 @@ __device__ __forceinline__ void cost_tile(const float4 *__restrict__ tp,
 }
 
 __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
-                                                 const float2 *__restrict__ Y,
-                                                 const int32_t *__restrict__ perm, int64_t n,
+                                                 const float2 *__restrict__ Y, int64_t n,
                                                  int32_t nb, double2 *__restrict__ cpart,
                                                  const uint8_t *__restrict__ nz, Hdr *h) {
   __shared__ double red[2][4];
-  __shared__ float2 ys[T];
   if (!state_ok(h, n)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
@@ -598,14 +620,9 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
     const bool vi = i < n, vj = j < n;
     rvalid |= vi ? (1u << k) : 0u;
     cvalid |= vj ? (1u << k) : 0u;
-    yc[k] = vj ? Y[perm[j]] : make_float2(0.f, 0.f);
+    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
   }
-  {
-    const int64_t i = (int64_t)I * T + t;
-    ys[t] = i < n ? Y[perm[i]] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  const float2 *yrow = ys + tr;
+  const float2 *yrow = Y + (int64_t)I * T + tr;
   const bool edge = ((int64_t)(J + 1) * T > n);
   const float4 *tp = P + (size_t)blockIdx.x * TT4;
   float plq = 0.f, z = 0.f;
@@ -684,9 +701,11 @@ __global__ __launch_bounds__(1024) void k_cost_reduce(const double2 *__restrict_
 // ----------------------------------------------------------------------------
 hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
+  float2 *yp = at<float2>(ws, L.yp);
+  hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
+                     at<const int32_t>(ws, L.perm), L.n, yp);
   hipLaunchKernelGGL(k_force, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
-                     reinterpret_cast<const float2 *>(y), at<const int32_t>(ws, L.perm), L.n,
-                     L.nb, at<float4>(ws, L.part),
+                     yp, L.n, L.nb, at<float4>(ws, L.part),
                      at<double>(ws, L.zpart), at<const uint8_t>(ws, L.nz), h);
   return hipGetLastError();
 }
@@ -722,9 +741,11 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
 hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   double2 *cp = at<double2>(ws, L.cpart);
-  hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
-                     reinterpret_cast<const float2 *>(y), at<const int32_t>(ws, L.perm), L.n, L.nb,
-                     cp, at<const uint8_t>(ws, L.nz), h);
+  float2 *yp = at<float2>(ws, L.yp);
+  hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
+                     at<const int32_t>(ws, L.perm), L.n, yp);
+  hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P), yp,
+                     L.n, L.nb, cp, at<const uint8_t>(ws, L.nz), h);
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
   return hipGetLastError();
 }
@@ -733,6 +754,8 @@ hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tile
                              int64_t total_blocks, float alpha, float mu, float eta,
                              float min_gain, int recentre, hipStream_t st) {
   const BatchHdr *bh = reinterpret_cast<const BatchHdr *>(batch_ws);
+  hipLaunchKernelGGL(k_gather_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh, count,
+                     total_tiles, total_blocks);
   hipLaunchKernelGGL(k_force_batched, dim3((unsigned)total_tiles), dim3(256), 0, st, bh, count,
                      total_tiles, total_blocks);
   hipLaunchKernelGGL(k_zreduce_batched, dim3(count), dim3(1024), 0, st, bh, count, total_tiles,
