@@ -354,38 +354,62 @@ __global__ __launch_bounds__(1024) void k_zreduce(const double *__restrict__ zpa
   zreduce_wg(zpart, nt, n, h, z_out, red);
 }
 
-// Gradient of row i from its nb slots: g = 4 (alpha A - R / Z).
+// Row reductions use kUpd threads per block of T rows: thread (r, q) sums the
+// slots s = q, q + kUpdSplit, ... of row r in order; the kUpdSplit partial
+// sums then meet in LDS and are added in q order (a fixed order).
+constexpr int kUpd = 1024;
+constexpr int kUpdSplit = kUpd / T;
+
+struct UpdSmem {
+  double4 part[kUpdSplit - 1][T];
+  double red[2][kUpd / 64];
+};
+
+// Gradient of row r of block b from its nb slots, g = 4 (alpha A - R / Z);
+// every thread of the workgroup must call it, the result is valid for q == 0.
 __device__ inline float2 row_gradient(const float4 *__restrict__ part, int32_t nb, int b, int r,
-                                      double alpha, double Z) {
+                                      int q, double alpha, double Z, UpdSmem &sm) {
   double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
   const float4 *pp = part + (size_t)b * nb * T + r;
-  for (int s = 0; s < nb; ++s) {
+  for (int s = q; s < nb; s += kUpdSplit) {
     const float4 v = pp[(size_t)s * T];
     ax += v.x;
     ay += v.y;
     rx += v.z;
     ry += v.w;
   }
+  if (q > 0) sm.part[q - 1][r] = make_double4(ax, ay, rx, ry);
+  __syncthreads();
+  if (q == 0) {
+#pragma unroll
+    for (int g = 0; g < kUpdSplit - 1; ++g) {
+      const double4 v = sm.part[g][r];
+      ax += v.x;
+      ay += v.y;
+      rx += v.z;
+      ry += v.w;
+    }
+  }
   return make_float2((float)(4.0 * (alpha * ax - rx / Z)), (float)(4.0 * (alpha * ay - ry / Z)));
 }
 
 // Update (Eq. 10, descent): gains, momentum, position; per-block sums of the
-// new positions for the re-centring.
+// new positions for the re-centring. kUpd threads per block of T rows.
 __device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64_t n, int32_t nb,
                                           const int32_t *__restrict__ perm,
                                           float2 *__restrict__ Y, float2 *__restrict__ U,
                                           float2 *__restrict__ G, float alpha, float mu, float eta,
                                           float min_gain, float2 *__restrict__ grad_out,
                                           double2 *__restrict__ meanpart, Hdr *h, int b,
-                                          double (&red)[2][4]) {
+                                          UpdSmem &sm) {
   if (!state_ok(h, n)) return;
-  const int r = threadIdx.x;
+  const int t = threadIdx.x, r = t % T, q = t / T;
   const int64_t ir = (int64_t)b * T + r;  // internal position
+  const float2 g = row_gradient(part, nb, b, r, q, (double)alpha, h->z, sm);
   double sx = 0.0, sy = 0.0;
   bool bad = false;
-  if (ir < n) {
+  if (q == 0 && ir < n) {
     const int64_t i = perm[ir];
-    const float2 g = row_gradient(part, nb, b, r, (double)alpha, h->z);
     if (grad_out) grad_out[i] = g;
     float2 u = U[i], gn = G[i], y = Y[i];
     gn.x = ((g.x > 0.f) != (u.x > 0.f)) ? gn.x + 0.2f : gn.x * 0.8f;
@@ -406,26 +430,31 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64
   if (bad) flag_error(h, kErrNonFinite);
   sx = wave_sum_d(sx);
   sy = wave_sum_d(sy);
-  if ((r & 63) == 0) {
-    red[0][r >> 6] = sx;
-    red[1][r >> 6] = sy;
+  if ((t & 63) == 0) {
+    sm.red[0][t >> 6] = sx;
+    sm.red[1][t >> 6] = sy;
   }
   __syncthreads();
-  if (r == 0)
-    meanpart[b] = make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
-                               red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+  if (t == 0) {  // the waves of q == 0 hold the rows
+    double mx = 0.0, my = 0.0;
+    for (int w = 0; w < T / 64; ++w) {
+      mx += sm.red[0][w];
+      my += sm.red[1][w];
+    }
+    meanpart[b] = make_double2(mx, my);
+  }
 }
 
-__global__ __launch_bounds__(256) void k_update(const float4 *__restrict__ part, int64_t n,
-                                                int32_t nb, const int32_t *__restrict__ perm,
-                                                float2 *__restrict__ Y,
-                                                float2 *__restrict__ U, float2 *__restrict__ G,
-                                                float alpha, float mu, float eta, float min_gain,
-                                                float2 *__restrict__ grad_out,
-                                                double2 *__restrict__ meanpart, Hdr *h) {
-  __shared__ double red[2][4];
+__global__ __launch_bounds__(kUpd) void k_update(const float4 *__restrict__ part, int64_t n,
+                                                 int32_t nb, const int32_t *__restrict__ perm,
+                                                 float2 *__restrict__ Y,
+                                                 float2 *__restrict__ U, float2 *__restrict__ G,
+                                                 float alpha, float mu, float eta, float min_gain,
+                                                 float2 *__restrict__ grad_out,
+                                                 double2 *__restrict__ meanpart, Hdr *h) {
+  __shared__ UpdSmem sm;
   update_wg(part, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h,
-            blockIdx.x, red);
+            blockIdx.x, sm);
 }
 
 // Subtract the mean of the map from the rows of block `blk`.
@@ -433,13 +462,15 @@ __device__ __forceinline__ void recentre_wg(const double2 *__restrict__ meanpart
                                             int32_t nb, float2 *__restrict__ Y, Hdr *h, int blk,
                                             float2 &smean) {
   if (!state_ok(h, n)) return;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {  // one wave: strided partial sums, then a fixed-order wave sum
     double mx = 0.0, my = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = threadIdx.x; b < nb; b += 64) {
       mx += meanpart[b].x;
       my += meanpart[b].y;
     }
-    smean = make_float2((float)(mx / (double)n), (float)(my / (double)n));
+    mx = wave_sum_d(mx);
+    my = wave_sum_d(my);
+    if (threadIdx.x == 0) smean = make_float2((float)(mx / (double)n), (float)(my / (double)n));
   }
   __syncthreads();
   const int64_t i = (int64_t)blk * 256 + threadIdx.x;
@@ -522,11 +553,11 @@ __global__ __launch_bounds__(1024) void k_zreduce_batched(const BatchHdr *__rest
   zreduce_wg(e.zpart, e.nt, e.n, e.h, nullptr, red);
 }
 
-__global__ __launch_bounds__(256) void k_update_batched(const BatchHdr *__restrict__ bh,
+__global__ __launch_bounds__(kUpd) void k_update_batched(const BatchHdr *__restrict__ bh,
                                                         int count, int64_t tiles, int64_t blocks,
                                                         float alpha, float mu, float eta,
                                                         float min_gain) {
-  __shared__ double red[2][4];
+  __shared__ UpdSmem sm;
   if (!batch_ok(bh, count, tiles, blocks)) return;
   const BatchEntry *tab = batch_table(bh);
   const int p = find_entry(tab, count, blockIdx.x, false);
@@ -534,7 +565,7 @@ __global__ __launch_bounds__(256) void k_update_batched(const BatchHdr *__restri
   const int64_t b = (int64_t)blockIdx.x - e.blk0;
   if (b < 0 || b >= e.nb) return;
   update_wg(e.part, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
-            (int)b, red);
+            (int)b, sm);
 }
 
 __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__restrict__ bh,
@@ -550,15 +581,16 @@ __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__rest
   recentre_wg(e.meanpart, e.n, e.nb, e.Y, e.h, (int)b, smean);
 }
 
-__global__ __launch_bounds__(256) void k_grad_only(const float4 *__restrict__ part, int64_t n,
-                                                   int32_t nb, const int32_t *__restrict__ perm,
-                                                   float alpha, float2 *__restrict__ grad_out,
-                                                   Hdr *h) {
+__global__ __launch_bounds__(kUpd) void k_grad_only(const float4 *__restrict__ part, int64_t n,
+                                                    int32_t nb, const int32_t *__restrict__ perm,
+                                                    float alpha, float2 *__restrict__ grad_out,
+                                                    Hdr *h) {
+  __shared__ UpdSmem sm;
   if (!state_ok(h, n)) return;
-  const int b = blockIdx.x, r = threadIdx.x;
+  const int b = blockIdx.x, t = threadIdx.x, r = t % T, q = t / T;
   const int64_t ir = (int64_t)b * T + r;
-  if (ir < n) {
-    const float2 g = row_gradient(part, nb, b, r, (double)alpha, h->z);
+  const float2 g = row_gradient(part, nb, b, r, q, (double)alpha, h->z, sm);
+  if (q == 0 && ir < n) {
     grad_out[perm[ir]] = g;
     if (!(isfinite(g.x) && isfinite(g.y))) flag_error(h, kErrNonFinite);
   }
@@ -717,7 +749,7 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
   hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
                      L.n, h, z_out);
   double2 *mp = at<double2>(ws, L.meanpart);
-  hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(256), 0, st, at<const float4>(ws, L.part), L.n,
+  hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part), L.n,
                      L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y), reinterpret_cast<float2 *>(u),
                      reinterpret_cast<float2 *>(g), alpha, mu, eta, min_gain,
                      reinterpret_cast<float2 *>(grad_out), mp, h);
@@ -732,7 +764,7 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
                      L.n, h, z_out);
-  hipLaunchKernelGGL(k_grad_only, dim3(L.nb), dim3(256), 0, st, at<const float4>(ws, L.part),
+  hipLaunchKernelGGL(k_grad_only, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part),
                      L.n, L.nb, at<const int32_t>(ws, L.perm), alpha,
                      reinterpret_cast<float2 *>(grad_out), h);
   return hipGetLastError();
@@ -760,7 +792,7 @@ hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tile
                      total_tiles, total_blocks);
   hipLaunchKernelGGL(k_zreduce_batched, dim3(count), dim3(1024), 0, st, bh, count, total_tiles,
                      total_blocks);
-  hipLaunchKernelGGL(k_update_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh, count,
+  hipLaunchKernelGGL(k_update_batched, dim3((unsigned)total_blocks), dim3(kUpd), 0, st, bh, count,
                      total_tiles, total_blocks, alpha, mu, eta, min_gain);
   if (recentre)
     hipLaunchKernelGGL(k_recentre_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh,
