@@ -12,7 +12,10 @@
 // Each tile writes its row-side partials into the slot (I, J) of block I and
 // its column-side partials into the slot (J, I) of block J; every slot is
 // written exactly once per pass and the update sums the slots of a row in a
-// fixed order in FP64, so results are bitwise reproducible.
+// fixed order in FP64, so results are bitwise reproducible. The partial-sum
+// buffer holds two float2 arrays of nb x nb x T: the repulsive sums (R_x,
+// R_y) of every slot, then the attractive sums (A_x, A_y), written and read
+// only for slots whose tile holds nonzero P.
 #include <math.h>
 
 #include "tsne_internal.h"
@@ -23,6 +26,17 @@ namespace {
 
 constexpr double kLn2 = 0.69314718055994530942;
 
+__device__ inline float2 *part_rep(float4 *part) { return reinterpret_cast<float2 *>(part); }
+__device__ inline float2 *part_att(float4 *part, int32_t nb) {
+  return reinterpret_cast<float2 *>(part) + (size_t)nb * nb * T;
+}
+__device__ inline const float2 *part_rep(const float4 *part) {
+  return reinterpret_cast<const float2 *>(part);
+}
+__device__ inline const float2 *part_att(const float4 *part, int32_t nb) {
+  return reinterpret_cast<const float2 *>(part) + (size_t)nb * nb * T;
+}
+
 __device__ inline void flag_error(Hdr *h, uint32_t bit) { atomicOr(&h->err, bit); }
 
 __device__ inline double wave_sum_d(double v) {
@@ -32,12 +46,14 @@ __device__ inline double wave_sum_d(double v) {
 }
 
 // Sum over the 16 lanes of a DPP row (rotations by 8, 4, 2, 1); every lane of
-// the row ends with the total.
+// the row ends with the total. A rotation reads no lane outside the row, so
+// bound_ctrl does not change the result; setting it lets the compiler fold
+// each move into its add (one v_add_f32 with a DPP operand).
 __device__ inline float row16_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xf, 0xf, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, true));
   return v;
 }
 
@@ -141,6 +157,7 @@ __device__ __forceinline__ void read_row(uint32_t p_addr, uint32_t y_addr, float
 struct ForceSmem {
   union {
     float4 colbuf[16][T + 4];        // [row group tr][column], padded rows
+    float2 colbuf2[16][T + 4];       // the same for the repulsive pair only
     float4 ring[4][kStages][4][64];  // [wave][slot][float4 of the row][lane]
   };
   float2 yrow[T];                    // positions of the tile's rows
@@ -266,7 +283,8 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 #pragma unroll
   for (int m = 0; m < 16; ++m) colacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
   float z = 0.f;
-  if (!nz[tile]) {
+  const bool nzt = nz[tile] != 0;
+  if (!nzt) {
     if (I == J) {
       if (edge)
         tile_rows_zero<true, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
@@ -294,28 +312,50 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
                               myrow, colacc, z);
   }
   // row side: this thread holds row tr + 16 tc
-  part[((size_t)I * nb + J) * T + tr + 16 * tc] = myrow;
+  float2 *prep = part_rep(part), *patt = part_att(part, nb);
+  const size_t rslot = ((size_t)I * nb + J) * T + tr + 16 * tc;
+  prep[rslot] = make_float2(myrow.z, myrow.w);
+  if (nzt) patt[rslot] = make_float2(myrow.x, myrow.y);
   // column side: reduce over the 16 row groups through LDS (colbuf overlays
   // the P ring, so every wave must be done with its ring first)
   __syncthreads();
   if (I != J) {
+    if (nzt) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) sm.colbuf[tr][tc + 16 * m] = colacc[m];
+      for (int m = 0; m < 16; ++m) sm.colbuf[tr][tc + 16 * m] = colacc[m];
+    } else {
+#pragma unroll
+      for (int m = 0; m < 16; ++m)
+        sm.colbuf2[tr][tc + 16 * m] = make_float2(colacc[m].z, colacc[m].w);
+    }
   }
   const double zd = wave_sum_d((double)z);
   if (l == 0) sm.zred[w] = zd;
   __syncthreads();
   if (I != J) {
-    float4 s4 = sm.colbuf[0][t];
+    const size_t cslot = ((size_t)J * nb + I) * T + t;
+    if (nzt) {
+      float4 s4 = sm.colbuf[0][t];
 #pragma unroll
-    for (int g = 1; g < 16; ++g) {
-      const float4 v = sm.colbuf[g][t];
-      s4.x += v.x;
-      s4.y += v.y;
-      s4.z += v.z;
-      s4.w += v.w;
+      for (int g = 1; g < 16; ++g) {
+        const float4 v = sm.colbuf[g][t];
+        s4.x += v.x;
+        s4.y += v.y;
+        s4.z += v.z;
+        s4.w += v.w;
+      }
+      prep[cslot] = make_float2(s4.z, s4.w);
+      patt[cslot] = make_float2(s4.x, s4.y);
+    } else {
+      float2 s2 = sm.colbuf2[0][t];
+#pragma unroll
+      for (int g = 1; g < 16; ++g) {
+        const float2 v = sm.colbuf2[g][t];
+        s2.x += v.x;
+        s2.y += v.y;
+      }
+      prep[cslot] = s2;
     }
-    part[((size_t)J * nb + I) * T + t] = s4;
   }
   if (t == 0)
     zpart[tile] = (sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (I == J ? 1.0 : 2.0);
@@ -334,8 +374,17 @@ __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
 __device__ __forceinline__ void zreduce_wg(const double *__restrict__ zpart, int64_t nt, int64_t n,
                                            Hdr *h, double *z_out, double (&red)[16]) {
   if (!state_ok(h, n)) return;
-  double s = 0.0;
-  for (int64_t q = threadIdx.x; q < nt; q += 1024) s += zpart[q];
+  // four independent strided sums per thread (loads in flight), fixed order
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t q = threadIdx.x;
+  for (; q + 3 * 1024 < nt; q += 4 * 1024) {
+    s0 += zpart[q];
+    s1 += zpart[q + 1024];
+    s2 += zpart[q + 2 * 1024];
+    s3 += zpart[q + 3 * 1024];
+  }
+  for (; q < nt; q += 1024) s0 += zpart[q];
+  double s = (s0 + s1) + (s2 + s3);
   s = wave_sum_d(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -367,16 +416,23 @@ struct UpdSmem {
 
 // Gradient of row r of block b from its nb slots, g = 4 (alpha A - R / Z);
 // every thread of the workgroup must call it, the result is valid for q == 0.
-__device__ inline float2 row_gradient(const float4 *__restrict__ part, int32_t nb, int b, int r,
+__device__ inline float2 row_gradient(const float4 *__restrict__ part,
+                                      const uint8_t *__restrict__ nz, int32_t nb, int b, int r,
                                       int q, double alpha, double Z, UpdSmem &sm) {
   double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
-  const float4 *pp = part + (size_t)b * nb * T + r;
+  const float2 *pr = part_rep(part) + (size_t)b * nb * T + r;
+  const float2 *pa = part_att(part, nb) + (size_t)b * nb * T + r;
   for (int s = q; s < nb; s += kUpdSplit) {
-    const float4 v = pp[(size_t)s * T];
-    ax += v.x;
-    ay += v.y;
-    rx += v.z;
-    ry += v.w;
+    const float2 v = pr[(size_t)s * T];
+    rx += v.x;
+    ry += v.y;
+    // slot s of block b: row side of tile (b, s) or column side of tile (s, b)
+    const int64_t tile = s >= b ? tile_start(b, nb) + (s - b) : tile_start(s, nb) + (b - s);
+    if (nz[tile]) {
+      const float2 a = pa[(size_t)s * T];
+      ax += a.x;
+      ay += a.y;
+    }
   }
   if (q > 0) sm.part[q - 1][r] = make_double4(ax, ay, rx, ry);
   __syncthreads();
@@ -395,7 +451,8 @@ __device__ inline float2 row_gradient(const float4 *__restrict__ part, int32_t n
 
 // Update (Eq. 10, descent): gains, momentum, position; per-block sums of the
 // new positions for the re-centring. kUpd threads per block of T rows.
-__device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64_t n, int32_t nb,
+__device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
+                                          const uint8_t *__restrict__ nz, int64_t n, int32_t nb,
                                           const int32_t *__restrict__ perm,
                                           float2 *__restrict__ Y, float2 *__restrict__ U,
                                           float2 *__restrict__ G, float alpha, float mu, float eta,
@@ -405,7 +462,7 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64
   if (!state_ok(h, n)) return;
   const int t = threadIdx.x, r = t % T, q = t / T;
   const int64_t ir = (int64_t)b * T + r;  // internal position
-  const float2 g = row_gradient(part, nb, b, r, q, (double)alpha, h->z, sm);
+  const float2 g = row_gradient(part, nz, nb, b, r, q, (double)alpha, h->z, sm);
   double sx = 0.0, sy = 0.0;
   bool bad = false;
   if (q == 0 && ir < n) {
@@ -445,7 +502,8 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part, int64
   }
 }
 
-__global__ __launch_bounds__(kUpd) void k_update(const float4 *__restrict__ part, int64_t n,
+__global__ __launch_bounds__(kUpd) void k_update(const float4 *__restrict__ part,
+                                                 const uint8_t *__restrict__ nz, int64_t n,
                                                  int32_t nb, const int32_t *__restrict__ perm,
                                                  float2 *__restrict__ Y,
                                                  float2 *__restrict__ U, float2 *__restrict__ G,
@@ -453,7 +511,7 @@ __global__ __launch_bounds__(kUpd) void k_update(const float4 *__restrict__ part
                                                  float2 *__restrict__ grad_out,
                                                  double2 *__restrict__ meanpart, Hdr *h) {
   __shared__ UpdSmem sm;
-  update_wg(part, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h,
+  update_wg(part, nz, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h,
             blockIdx.x, sm);
 }
 
@@ -564,7 +622,7 @@ __global__ __launch_bounds__(kUpd) void k_update_batched(const BatchHdr *__restr
   const BatchEntry &e = tab[p];
   const int64_t b = (int64_t)blockIdx.x - e.blk0;
   if (b < 0 || b >= e.nb) return;
-  update_wg(e.part, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
+  update_wg(e.part, e.nz, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
             (int)b, sm);
 }
 
@@ -581,7 +639,8 @@ __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__rest
   recentre_wg(e.meanpart, e.n, e.nb, e.Y, e.h, (int)b, smean);
 }
 
-__global__ __launch_bounds__(kUpd) void k_grad_only(const float4 *__restrict__ part, int64_t n,
+__global__ __launch_bounds__(kUpd) void k_grad_only(const float4 *__restrict__ part,
+                                                    const uint8_t *__restrict__ nz, int64_t n,
                                                     int32_t nb, const int32_t *__restrict__ perm,
                                                     float alpha, float2 *__restrict__ grad_out,
                                                     Hdr *h) {
@@ -589,7 +648,7 @@ __global__ __launch_bounds__(kUpd) void k_grad_only(const float4 *__restrict__ p
   if (!state_ok(h, n)) return;
   const int b = blockIdx.x, t = threadIdx.x, r = t % T, q = t / T;
   const int64_t ir = (int64_t)b * T + r;
-  const float2 g = row_gradient(part, nb, b, r, q, (double)alpha, h->z, sm);
+  const float2 g = row_gradient(part, nz, nb, b, r, q, (double)alpha, h->z, sm);
   if (q == 0 && ir < n) {
     grad_out[perm[ir]] = g;
     if (!(isfinite(g.x) && isfinite(g.y))) flag_error(h, kErrNonFinite);
@@ -749,7 +808,8 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
   hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
                      L.n, h, z_out);
   double2 *mp = at<double2>(ws, L.meanpart);
-  hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part), L.n,
+  hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part),
+                     at<const uint8_t>(ws, L.nz), L.n,
                      L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y), reinterpret_cast<float2 *>(u),
                      reinterpret_cast<float2 *>(g), alpha, mu, eta, min_gain,
                      reinterpret_cast<float2 *>(grad_out), mp, h);
@@ -765,7 +825,7 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
   hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
                      L.n, h, z_out);
   hipLaunchKernelGGL(k_grad_only, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part),
-                     L.n, L.nb, at<const int32_t>(ws, L.perm), alpha,
+                     at<const uint8_t>(ws, L.nz), L.n, L.nb, at<const int32_t>(ws, L.perm), alpha,
                      reinterpret_cast<float2 *>(grad_out), h);
   return hipGetLastError();
 }
