@@ -57,6 +57,16 @@ __device__ inline float row16_sum(float v) {
   return v;
 }
 
+// Bit k set when position off + 16 k of a tile is a real row (or column):
+// rem = n - (first index of the tile's block), which may exceed T.
+__device__ inline uint32_t valid_bits(int64_t rem, int off) {
+  if (rem >= T) return 0xFFFFu;
+  const int64_t c = rem - off;
+  if (c <= 0) return 0u;
+  const int64_t cnt = (c + 15) / 16;
+  return cnt >= 16 ? 0xFFFFu : ((1u << cnt) - 1u);
+}
+
 // Header check shared by the iteration kernels: the workspace must hold
 // affinities for exactly this n.
 __device__ inline bool state_ok(Hdr *h, int64_t n) {
@@ -198,7 +208,7 @@ __device__ __forceinline__ void tile_rows(const float4 *__restrict__ tp, float4 
 template <bool DIAG, bool EDGE>
 __device__ __forceinline__ void tile_rows_zero(const float2 *yrow, const float2 yc[16],
                                                uint32_t rvalid, uint32_t cvalid, int tr, int tc,
-                                               float4 &myrow, float4 colacc[16], float &z) {
+                                               float2 &myrow, float2 colrep[16], float &z) {
 #pragma unroll 1
   for (int k = 0; k < 16; ++k) {
     const float2 yi = yrow[tr + 16 * k];
@@ -219,13 +229,13 @@ __device__ __forceinline__ void tile_rows_zero(const float2 *yrow, const float2 
       rx = fmaf(w2, dx, rx);
       ry = fmaf(w2, dy, ry);
       if (!DIAG) {
-        colacc[m].z = fmaf(-w2, dx, colacc[m].z);
-        colacc[m].w = fmaf(-w2, dy, colacc[m].w);
+        colrep[m].x = fmaf(-w2, dx, colrep[m].x);
+        colrep[m].y = fmaf(-w2, dy, colrep[m].y);
       }
     }
     rx = row16_sum(rx);
     ry = row16_sum(ry);
-    if (tc == k) myrow = make_float4(0.f, 0.f, rx, ry);
+    if (tc == k) myrow = make_float2(rx, ry);
   }
 }
 
@@ -257,84 +267,93 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
   tile_coords(tile, nb, I, J);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
+  // Y is the zero-padded internal-order copy, so whole tiles load unguarded
+  const uint32_t rvalid = valid_bits(n - (int64_t)I * T, tr);
+  const uint32_t cvalid = valid_bits(n - (int64_t)J * T, tc);
   float2 yc[16];
-  uint32_t rvalid = 0, cvalid = 0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int64_t i = (int64_t)I * T + tr + 16 * k;
-    const int64_t j = (int64_t)J * T + tc + 16 * k;
-    const bool vi = i < n, vj = j < n;
-    rvalid |= vi ? (1u << k) : 0u;
-    cvalid |= vj ? (1u << k) : 0u;
-    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
-  }
-  {
-    const int64_t i = (int64_t)I * T + t;
-    sm.yrow[t] = i < n ? Y[i] : make_float2(0.f, 0.f);
-  }
+  for (int k = 0; k < 16; ++k) yc[k] = Y[(int64_t)J * T + tc + 16 * k];
+  sm.yrow[t] = Y[(int64_t)I * T + t];
   __syncthreads();
-  float4 *wring = &sm.ring[w][0][0][0];
-  const uint32_t lane_addr = (uint32_t)(size_t)((lds_void_t *)wring) + (uint32_t)l * 16u;
-  const uint32_t yrow_addr = (uint32_t)(size_t)((lds_void_t *)(sm.yrow + tr));
   const bool edge = ((int64_t)(J + 1) * T > n);
-  const float4 *tp = P + (size_t)tile * TT4;
-  float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 colacc[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) colacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
-  float z = 0.f;
   const bool nzt = nz[tile] != 0;
+  float2 *prep = part_rep(part), *patt = part_att(part, nb);
+  const size_t rslot = ((size_t)I * nb + J) * T + tr + 16 * tc;  // row tr + 16 tc
+  const size_t cslot = ((size_t)J * nb + I) * T + t;             // column t
+  float z = 0.f;
   if (!nzt) {
+    // all-zero P: repulsion and Z only, no P traffic, float2 accumulators
+    float2 myrow = make_float2(0.f, 0.f);
+    float2 colrep[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) colrep[m] = make_float2(0.f, 0.f);
     if (I == J) {
       if (edge)
-        tile_rows_zero<true, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+        tile_rows_zero<true, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
       else
-        tile_rows_zero<true, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+        tile_rows_zero<true, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
     } else {
       if (edge)
-        tile_rows_zero<false, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+        tile_rows_zero<false, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
       else
-        tile_rows_zero<false, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colacc, z);
+        tile_rows_zero<false, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
     }
-  } else if (I == J) {
-    if (edge)
-      tile_rows<true, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc, myrow,
-                            colacc, z);
-    else
-      tile_rows<true, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
-                             myrow, colacc, z);
+    prep[rslot] = myrow;
+    // column side: the 16 row groups' sums meet in LDS
+    if (I != J) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) sm.colbuf2[tr][tc + 16 * m] = colrep[m];
+    }
+    const double zd = wave_sum_d((double)z);
+    if (l == 0) sm.zred[w] = zd;
+    __syncthreads();
+    if (I != J) {
+      float2 s2 = sm.colbuf2[0][t];
+#pragma unroll
+      for (int g = 1; g < 16; ++g) {
+        const float2 v = sm.colbuf2[g][t];
+        s2.x += v.x;
+        s2.y += v.y;
+      }
+      prep[cslot] = s2;
+    }
   } else {
-    if (edge)
-      tile_rows<false, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
-                             myrow, colacc, z);
-    else
-      tile_rows<false, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
+    float4 *wring = &sm.ring[w][0][0][0];
+    const uint32_t lane_addr = (uint32_t)(size_t)((lds_void_t *)wring) + (uint32_t)l * 16u;
+    const uint32_t yrow_addr = (uint32_t)(size_t)((lds_void_t *)(sm.yrow + tr));
+    const float4 *tp = P + (size_t)tile * TT4;
+    float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 colacc[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) colacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (I == J) {
+      if (edge)
+        tile_rows<true, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
                               myrow, colacc, z);
-  }
-  // row side: this thread holds row tr + 16 tc
-  float2 *prep = part_rep(part), *patt = part_att(part, nb);
-  const size_t rslot = ((size_t)I * nb + J) * T + tr + 16 * tc;
-  prep[rslot] = make_float2(myrow.z, myrow.w);
-  if (nzt) patt[rslot] = make_float2(myrow.x, myrow.y);
-  // column side: reduce over the 16 row groups through LDS (colbuf overlays
-  // the P ring, so every wave must be done with its ring first)
-  __syncthreads();
-  if (I != J) {
-    if (nzt) {
+      else
+        tile_rows<true, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
+                               myrow, colacc, z);
+    } else {
+      if (edge)
+        tile_rows<false, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
+                               myrow, colacc, z);
+      else
+        tile_rows<false, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
+                                myrow, colacc, z);
+    }
+    prep[rslot] = make_float2(myrow.z, myrow.w);
+    patt[rslot] = make_float2(myrow.x, myrow.y);
+    // column side: the 16 row groups' sums meet in LDS (colbuf overlays the P
+    // ring, so every wave must be done with its ring first)
+    __syncthreads();
+    if (I != J) {
 #pragma unroll
       for (int m = 0; m < 16; ++m) sm.colbuf[tr][tc + 16 * m] = colacc[m];
-    } else {
-#pragma unroll
-      for (int m = 0; m < 16; ++m)
-        sm.colbuf2[tr][tc + 16 * m] = make_float2(colacc[m].z, colacc[m].w);
     }
-  }
-  const double zd = wave_sum_d((double)z);
-  if (l == 0) sm.zred[w] = zd;
-  __syncthreads();
-  if (I != J) {
-    const size_t cslot = ((size_t)J * nb + I) * T + t;
-    if (nzt) {
+    const double zd = wave_sum_d((double)z);
+    if (l == 0) sm.zred[w] = zd;
+    __syncthreads();
+    if (I != J) {
       float4 s4 = sm.colbuf[0][t];
 #pragma unroll
       for (int g = 1; g < 16; ++g) {
@@ -346,15 +365,6 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
       }
       prep[cslot] = make_float2(s4.z, s4.w);
       patt[cslot] = make_float2(s4.x, s4.y);
-    } else {
-      float2 s2 = sm.colbuf2[0][t];
-#pragma unroll
-      for (int g = 1; g < 16; ++g) {
-        const float2 v = sm.colbuf2[g][t];
-        s2.x += v.x;
-        s2.y += v.y;
-      }
-      prep[cslot] = s2;
     }
   }
   if (t == 0)
@@ -702,17 +712,11 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
   tile_coords(blockIdx.x, nb, I, J);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
+  const uint32_t rvalid = valid_bits(n - (int64_t)I * T, tr);
+  const uint32_t cvalid = valid_bits(n - (int64_t)J * T, tc);
   float2 yc[16];
-  uint32_t rvalid = 0, cvalid = 0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int64_t i = (int64_t)I * T + tr + 16 * k;
-    const int64_t j = (int64_t)J * T + tc + 16 * k;
-    const bool vi = i < n, vj = j < n;
-    rvalid |= vi ? (1u << k) : 0u;
-    cvalid |= vj ? (1u << k) : 0u;
-    yc[k] = vj ? Y[j] : make_float2(0.f, 0.f);
-  }
+  for (int k = 0; k < 16; ++k) yc[k] = Y[(int64_t)J * T + tc + 16 * k];
   const float2 *yrow = Y + (int64_t)I * T + tr;
   const bool edge = ((int64_t)(J + 1) * T > n);
   const float4 *tp = P + (size_t)blockIdx.x * TT4;
