@@ -86,6 +86,139 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(const __bf16 *__restrict__ A, 
   }
 }
 
+// ----------------------------------------------------------------------------
+// Fused inference: one wave carries kInferRows rows through both wide layers
+// and the output layer without leaving registers (no intermediate HBM
+// traffic, no LDS).
+//
+// Layer 1 is computed transposed, H1^T = W1 X^T (M = hidden, N = rows), so
+// that lane l = 16g + c receives H1^T[16t + 4g + r][16a + c] for hidden tile
+// t and row tile a. Rounded to BF16, these values are the A operand of
+// layer 2 (H2 = H1 W2^T, M = rows) for the K step s that covers hidden tiles
+// 2s and 2s + 1, provided the K order inside the step is permuted: slot
+// (g, j) of the step holds hidden unit 32s + 4g + j for j < 4 and
+// 32s + 16 + 4g + (j - 4) for j >= 4. The B operand (rows of W2) is loaded
+// in the same permuted order, so every dot product is the same sum of the
+// same BF16 products. The output layer reduces the FP32 h2 of each row over
+// the 16 lanes of a DPP row.
+// ----------------------------------------------------------------------------
+constexpr int kInferRows = 32;  // rows per wave (two 16-row tiles)
+constexpr int kInferWaves = 4;  // waves per workgroup
+
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+
+__device__ inline float row16_sum_f(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x122, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x121, 0xf, 0xf, true));
+  return v;
+}
+
+template <int H>
+__global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(
+    const float *__restrict__ x, int64_t n, int d_in, const float *__restrict__ mean,
+    const float *__restrict__ invstd, const __bf16 *__restrict__ w1b,
+    const float *__restrict__ b1, const __bf16 *__restrict__ w2b, const float *__restrict__ b2,
+    const float *__restrict__ w3, const float *__restrict__ b3, float *__restrict__ out) {
+  constexpr int HT = H / 16;  // hidden tiles
+  constexpr int KS = H / 32;  // K steps of layer 2
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = l & 15, g = l >> 4;
+  const int64_t row0 = ((int64_t)blockIdx.x * kInferWaves + wv) * kInferRows;
+  if (row0 >= n) return;  // uniform per wave; no workgroup barrier follows
+  // layer-1 B operand: standardised rows 16a + c, inputs 32s + 8g .. + 7
+  v8bf xb[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int64_t row = row0 + 16 * a + c;
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = 32 * st + 8 * g + j;
+        float v = 0.f;
+        if (row < n && k < d_in) v = (x[row * d_in + k] - mean[k]) * invstd[k];
+        xb[a][st][j] = (__bf16)v;
+      }
+  }
+  // layer 1 (transposed)
+  v4f acc1[HT][2];
+#pragma unroll
+  for (int t = 0; t < HT; ++t)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) acc1[t][a] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int t = 0; t < HT; ++t) {
+      const v8bf wa = *reinterpret_cast<const v8bf *>(w1b + (16 * t + c) * kK1 + 32 * st + 8 * g);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        acc1[t][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, xb[a][st], acc1[t][a], 0, 0, 0);
+    }
+  // bias, ReLU, BF16: the layer-2 A operand in the permuted K order
+  v8bf a2[2][KS];
+#pragma unroll
+  for (int st = 0; st < KS; ++st)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int t = 2 * st + (j >> 2), r = j & 3;
+      const float bias = b1[16 * t + 4 * g + r];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) a2[a][st][j] = (__bf16)fmaxf(acc1[t][a][r] + bias, 0.f);
+    }
+  // layer 2
+  v4f acc2[2][HT];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int e = 0; e < HT; ++e) acc2[a][e] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int st = 0; st < KS; ++st)
+#pragma unroll
+    for (int e = 0; e < HT; ++e) {
+      const __bf16 *wr = w2b + (int64_t)(16 * e + c) * H + 32 * st + 4 * g;
+      const v4bf lo = *reinterpret_cast<const v4bf *>(wr);
+      const v4bf hi = *reinterpret_cast<const v4bf *>(wr + 16);
+      const v8bf bw = (v8bf){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        acc2[a][e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[a][st], bw, acc2[a][e], 0, 0, 0);
+    }
+  // output layer: lane (g, c) holds h2[16a + 4g + r][16e + c]
+  float o[2][4][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[a][r][0] = o[a][r][1] = 0.f;
+#pragma unroll
+  for (int e = 0; e < HT; ++e) {
+    const int hcol = 16 * e + c;
+    const float bias = b2[hcol], u0 = w3[hcol], u1 = w3[H + hcol];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float h = fmaxf(acc2[a][e][r] + bias, 0.f);
+        o[a][r][0] = fmaf(u0, h, o[a][r][0]);
+        o[a][r][1] = fmaf(u1, h, o[a][r][1]);
+      }
+  }
+  const float c0 = b3[0], c1 = b3[1];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float s0 = row16_sum_f(o[a][r][0]), s1 = row16_sum_f(o[a][r][1]);
+      const int64_t row = row0 + 16 * a + 4 * g + r;
+      if (c == 0 && row < n) {
+        out[2 * row] = s0 + c0;
+        out[2 * row + 1] = s1 + c1;
+      }
+    }
+}
+
 // BF16 copies of W1 (zero-padded to [H][kK1]), W2 and W2 transposed.
 __global__ void k_mlp_cast(const float *__restrict__ p, int d_in, int H, __bf16 *__restrict__ w1b,
                            __bf16 *__restrict__ w2b, __bf16 *__restrict__ w2tb) {
@@ -282,36 +415,6 @@ static Epi epi() {
 }
 
 // Forward pass of rows [row0, row0 + B) (or idx[0..B)) of x into out.
-static void forward_chunk(const MlpLayout &L, const float *params, const float *mean,
-                          const float *invstd, const float *x, const int32_t *idx, int64_t row0,
-                          int64_t B, float *out, void *ws, hipStream_t st) {
-  const int H = L.H;
-  const int64_t Bpad = (B + 63) / 64 * 64;
-  const float *b1 = params + (int64_t)H * L.d_in, *b2 = b1 + H + (int64_t)H * H;
-  const float *w3 = b2 + H, *b3 = w3 + 2 * H;
-  __bf16 *xb = at<__bf16>(ws, L.xb), *h1b = at<__bf16>(ws, L.h1b);
-  float *h2 = at<float>(ws, L.h2);
-  hipLaunchKernelGGL(k_mlp_gather, dim3((unsigned)((Bpad + 255) / 256)), dim3(256), 0, st, x,
-                     L.d_in, mean, invstd, idx, row0, B, Bpad, nullptr, xb, nullptr, nullptr);
-  Epi e1 = epi();
-  e1.bias = b1;
-  e1.relu = 1;
-  e1.outB = h1b;
-  e1.ldb = H;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, xb, kK1,
-                     at<const __bf16>(ws, L.w1b), kK1, kK1, e1);
-  Epi e2 = epi();
-  e2.bias = b2;
-  e2.relu = 1;
-  e2.outF = h2;
-  e2.ldf = H;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, h1b, H,
-                     at<const __bf16>(ws, L.w2b), H, H, e2);
-  hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)((Bpad + 255) / 256)), dim3(256), 0, st, h2, H,
-                     w3, b3, B, Bpad, nullptr, 0.0, out, row0 * (idx ? 0 : 1), nullptr, nullptr,
-                     nullptr, nullptr, nullptr);
-}
-
 hipError_t launch_mlp_cast(const MlpLayout &L, const float *params, void *ws, hipStream_t st) {
   const int64_t cnt = (int64_t)L.H * (L.H > kK1 ? L.H : kK1);
   hipLaunchKernelGGL(k_mlp_cast, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, params,
@@ -324,12 +427,31 @@ hipError_t launch_mlp_forward(const MlpLayout &L, const float *params, const flo
                               const float *invstd, const float *x, int64_t n, float *out, void *ws,
                               hipStream_t st) {
   hipError_t e = launch_mlp_cast(L, params, ws, st);
-  for (int64_t r = 0; r < n && e == hipSuccess; r += L.Bpad) {
-    const int64_t B = (n - r) < L.Bpad ? (n - r) : L.Bpad;
-    forward_chunk(L, params, mean, invstd, x, nullptr, r, B, out, ws, st);
-    e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int H = L.H;
+  const float *b1 = params + (int64_t)H * L.d_in, *b2 = b1 + H + (int64_t)H * H;
+  const float *w3 = b2 + H, *b3 = w3 + 2 * H;
+  const __bf16 *w1b = at<const __bf16>(ws, L.w1b), *w2b = at<const __bf16>(ws, L.w2b);
+  const int64_t rows_per_block = (int64_t)kInferRows * kInferWaves;
+  const dim3 grid((unsigned)((n + rows_per_block - 1) / rows_per_block)), block(64 * kInferWaves);
+  switch (H) {
+    case 64:
+      hipLaunchKernelGGL(k_mlp_infer<64>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b, b1,
+                         w2b, b2, w3, b3, out);
+      break;
+    case 128:
+      hipLaunchKernelGGL(k_mlp_infer<128>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b,
+                         b1, w2b, b2, w3, b3, out);
+      break;
+    case 192:
+      hipLaunchKernelGGL(k_mlp_infer<192>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b,
+                         b1, w2b, b2, w3, b3, out);
+      break;
+    default:
+      hipLaunchKernelGGL(k_mlp_infer<256>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b,
+                         b1, w2b, b2, w3, b3, out);
   }
-  return e;
+  return hipGetLastError();
 }
 
 hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const float *mean,

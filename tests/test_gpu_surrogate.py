@@ -68,16 +68,22 @@ def test_gradient_parity(B):
         assert rel_f <= 5e-2
 
 
-def test_forward_parity_chunked():
-    """n = 1000 rows through a workspace sized for 256: three full chunks and a ragged one."""
+@pytest.mark.parametrize("hidden", [256, 128])
+def test_forward_parity(hidden):
+    """n = 1000 rows (31 full 32-row wave tiles and a ragged one) through the fused inference
+    kernel, against the oracle with the GPU's BF16 rounding."""
     n = 1000
-    p, x, _, mean, invstd = _setup(n, seed=5)
-    ref = oracle.mlp_forward(p, x, mean, invstd, H, emulate=True)
-    ws = _lib.mlp_new_workspace(D, H, 256, False)
+    rng = np.random.Generator(np.random.PCG64(5))
+    p = (rng.standard_normal(oracle.mlp_param_count(D, hidden)) * 0.08).astype(np.float32)
+    x, _ = synth.gmm_aniso(n, sample_seed=5)
+    mean = x.mean(axis=0).astype(np.float32)
+    invstd = (1.0 / x.std(axis=0)).astype(np.float32)
+    ref = oracle.mlp_forward(p, x, mean, invstd, hidden, emulate=True)
+    ws = _lib.mlp_new_workspace(D, hidden, 256, False)
     out = torch.empty((n, 2), device="cuda")
-    _lib.mlp_forward(_t(p), D, H, _t(mean), _t(invstd), _t(x), out, ws)
+    _lib.mlp_forward(_t(p), D, hidden, _t(mean), _t(invstd), _t(x), out, ws)
     rel = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
-    print(f"\n  forward rel-L2 vs bf16-emulating oracle {rel:.2e}")
+    print(f"\n  H={hidden} forward rel-L2 vs bf16-emulating oracle {rel:.2e}")
     assert rel <= 1e-4
 
 
