@@ -87,23 +87,28 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(const __bf16 *__restrict__ A, 
 }
 
 // ----------------------------------------------------------------------------
-// Fused inference: one wave carries kInferRows rows through both wide layers
-// and the output layer without leaving registers (no intermediate HBM
-// traffic, no LDS).
+// Fused inference. A persistent workgroup of four waves keeps the weights in
+// registers and runs tiles of kInferRows rows through the whole network:
+//
+//   wave w owns hidden units [H/4 w, H/4 (w + 1)) of both wide layers: its
+//   slice of W1 (as the A operand of the transposed first layer) and its
+//   column slice of W2 (as the B operand of the second) stay in registers
+//   for the life of the workgroup;
+//   the standardised BF16 input tile and the BF16 first-layer output tile
+//   live in LDS, shared by the four waves;
+//   the output layer's partial sums of the four waves meet in LDS.
 //
 // Layer 1 is computed transposed, H1^T = W1 X^T (M = hidden, N = rows), so
-// that lane l = 16g + c receives H1^T[16t + 4g + r][16a + c] for hidden tile
-// t and row tile a. Rounded to BF16, these values are the A operand of
-// layer 2 (H2 = H1 W2^T, M = rows) for the K step s that covers hidden tiles
-// 2s and 2s + 1, provided the K order inside the step is permuted: slot
-// (g, j) of the step holds hidden unit 32s + 4g + j for j < 4 and
-// 32s + 16 + 4g + (j - 4) for j >= 4. The B operand (rows of W2) is loaded
-// in the same permuted order, so every dot product is the same sum of the
-// same BF16 products. The output layer reduces the FP32 h2 of each row over
-// the 16 lanes of a DPP row.
+// lane l = 16g + c receives H1^T[16t + 4g + r][16a + c]: four consecutive
+// hidden units of one row, stored to LDS as one 8-byte write. Layer 2 (M =
+// rows, N = its hidden slice) reads its A operand for the K step s in a
+// permuted order, slot (g, j) holding hidden unit 32s + 4g + j for j < 4 and
+// 32s + 16 + 4g + (j - 4) otherwise (two 8-byte LDS reads); the W2 slice in
+// registers is held in the same permuted order, so every dot product is the
+// same sum of the same BF16 products.
 // ----------------------------------------------------------------------------
-constexpr int kInferRows = 32;  // rows per wave (two 16-row tiles)
-constexpr int kInferWaves = 4;  // waves per workgroup
+constexpr int kInferRows = 64;   // rows per tile
+constexpr int kXPitch = kK1 + 8;  // BF16 elements per LDS row of the input tile
 
 typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 
@@ -116,107 +121,149 @@ __device__ inline float row16_sum_f(float v) {
 }
 
 template <int H>
-__global__ __launch_bounds__(64 * kInferWaves) void k_mlp_infer(
+__global__ __launch_bounds__(256, 1) void k_mlp_infer(
     const float *__restrict__ x, int64_t n, int d_in, const float *__restrict__ mean,
     const float *__restrict__ invstd, const __bf16 *__restrict__ w1b,
     const float *__restrict__ b1, const __bf16 *__restrict__ w2b, const float *__restrict__ b2,
     const float *__restrict__ w3, const float *__restrict__ b3, float *__restrict__ out) {
-  constexpr int HT = H / 16;  // hidden tiles
-  constexpr int KS = H / 32;  // K steps of layer 2
-  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int HW = H / 4;          // hidden units per wave
+  constexpr int TW = HW / 16;        // hidden tiles per wave
+  constexpr int KS = H / 32;         // K steps of layer 2
+  constexpr int RA = kInferRows / 16;  // row tiles
+  constexpr int HPitch = H + 8;      // BF16 elements per LDS row of the hidden tile
+  __shared__ __bf16 xs[kInferRows][kXPitch];
+  __shared__ __bf16 hs[kInferRows][HPitch];
+  __shared__ float po[4][kInferRows][2];
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int c = l & 15, g = l >> 4;
-  const int64_t row0 = ((int64_t)blockIdx.x * kInferWaves + wv) * kInferRows;
-  if (row0 >= n) return;  // uniform per wave; no workgroup barrier follows
-  // layer-1 B operand: standardised rows 16a + c, inputs 32s + 8g .. + 7
-  v8bf xb[2][2];
+  const int h0 = w * HW;  // first hidden unit of this wave
+  // weights of this wave, in registers
+  v8bf wa[TW][2];  // W1 rows h0 + 16i + c, inputs 32s + 8g .. + 7
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int64_t row = row0 + 16 * a + c;
+  for (int i = 0; i < TW; ++i)
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+      wa[i][st] = *reinterpret_cast<const v8bf *>(w1b + (h0 + 16 * i + c) * kK1 + 32 * st + 8 * g);
+  v8bf wb[TW][KS];  // W2 rows h0 + 16e + c, hidden units of step s in the permuted order
+#pragma unroll
+  for (int e = 0; e < TW; ++e)
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      const __bf16 *wr = w2b + (int64_t)(h0 + 16 * e + c) * H + 32 * st + 4 * g;
+      const v4bf lo = *reinterpret_cast<const v4bf *>(wr);
+      const v4bf hi = *reinterpret_cast<const v4bf *>(wr + 16);
+      wb[e][st] = (v8bf){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+  float bias1[TW][4], bias2[TW], u0[TW], u1[TW];
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias1[i][r] = b1[h0 + 16 * i + 4 * g + r];
+    bias2[i] = b2[h0 + 16 * i + c];
+    u0[i] = w3[h0 + 16 * i + c];
+    u1[i] = w3[H + h0 + 16 * i + c];
+  }
+  const float c0 = b3[0], c1 = b3[1];
+  const int64_t ntiles = (n + kInferRows - 1) / kInferRows;
+  // input staging: thread t always handles input k = t % 64 of rows t / 64 + 4m
+  constexpr int XM = kInferRows * kK1 / 256;
+  const int xk = t & (kK1 - 1), xr = t / kK1;
+  const bool kin = xk < d_in;
+  const float xmean = kin ? mean[xk] : 0.f, xinv = kin ? invstd[xk] : 0.f;
+  float xv[XM];
+  auto load_x = [&](int64_t tl) {
+#pragma unroll
+    for (int m = 0; m < XM; ++m) {
+      const int64_t row = tl * kInferRows + xr + 4 * m;
+      xv[m] = (kin && tl < ntiles && row < n) ? x[row * d_in + xk] : 0.f;
+    }
+  };
+  auto store_x = [&]() {
+#pragma unroll
+    for (int m = 0; m < XM; ++m)
+      xs[xr + 4 * m][xk] = (__bf16)(kin ? (xv[m] - xmean) * xinv : 0.f);
+  };
+  load_x(blockIdx.x);
+  store_x();
+  __syncthreads();
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * kInferRows;
+    load_x(tile + gridDim.x);  // next tile's inputs, in flight during this tile
+    // layer 1, transposed: acc1[i][a] = H1^T[h0 + 16i + 4g + r][16a + c]
+    v4f acc1[TW][RA];
+#pragma unroll
+    for (int i = 0; i < TW; ++i)
+#pragma unroll
+      for (int a = 0; a < RA; ++a) acc1[i][a] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int st = 0; st < 2; ++st)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = 32 * st + 8 * g + j;
-        float v = 0.f;
-        if (row < n && k < d_in) v = (x[row * d_in + k] - mean[k]) * invstd[k];
-        xb[a][st][j] = (__bf16)v;
+      for (int a = 0; a < RA; ++a) {
+        const v8bf xb = *reinterpret_cast<const v8bf *>(&xs[16 * a + c][32 * st + 8 * g]);
+#pragma unroll
+        for (int i = 0; i < TW; ++i)
+          acc1[i][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[i][st], xb, acc1[i][a], 0, 0, 0);
       }
-  }
-  // layer 1 (transposed)
-  v4f acc1[HT][2];
+    // bias, ReLU, BF16 into the shared hidden tile
 #pragma unroll
-  for (int t = 0; t < HT; ++t)
+    for (int i = 0; i < TW; ++i)
 #pragma unroll
-    for (int a = 0; a < 2; ++a) acc1[t][a] = (v4f){0.f, 0.f, 0.f, 0.f};
+      for (int a = 0; a < RA; ++a) {
+        v4bf hv;
 #pragma unroll
-  for (int st = 0; st < 2; ++st)
+        for (int r = 0; r < 4; ++r) hv[r] = (__bf16)fmaxf(acc1[i][a][r] + bias1[i][r], 0.f);
+        *reinterpret_cast<v4bf *>(&hs[16 * a + c][h0 + 16 * i + 4 * g]) = hv;
+      }
+    __syncthreads();
+    store_x();  // every wave is past layer 1: the input tile may be replaced
+    // layer 2: acc2[a][e] = H2[16a + 4g + r][h0 + 16e + c]
+    v4f acc2[RA][TW];
 #pragma unroll
-    for (int t = 0; t < HT; ++t) {
-      const v8bf wa = *reinterpret_cast<const v8bf *>(w1b + (16 * t + c) * kK1 + 32 * st + 8 * g);
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-        acc1[t][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa, xb[a][st], acc1[t][a], 0, 0, 0);
-    }
-  // bias, ReLU, BF16: the layer-2 A operand in the permuted K order
-  v8bf a2[2][KS];
+      for (int e = 0; e < TW; ++e) acc2[a][e] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int st = 0; st < KS; ++st)
+    for (int st = 0; st < KS; ++st)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int t = 2 * st + (j >> 2), r = j & 3;
-      const float bias = b1[16 * t + 4 * g + r];
+      for (int a = 0; a < RA; ++a) {
+        const __bf16 *hr = &hs[16 * a + c][32 * st + 4 * g];
+        const v4bf lo = *reinterpret_cast<const v4bf *>(hr);
+        const v4bf hi = *reinterpret_cast<const v4bf *>(hr + 16);
+        const v8bf av = (v8bf){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 #pragma unroll
-      for (int a = 0; a < 2; ++a) a2[a][st][j] = (__bf16)fmaxf(acc1[t][a][r] + bias, 0.f);
-    }
-  // layer 2
-  v4f acc2[2][HT];
+        for (int e = 0; e < TW; ++e)
+          acc2[a][e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wb[e][st], acc2[a][e], 0, 0, 0);
+      }
+    // output layer: this wave's share of every row, reduced over the 16 lanes
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int e = 0; e < HT; ++e) acc2[a][e] = (v4f){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int st = 0; st < KS; ++st)
-#pragma unroll
-    for (int e = 0; e < HT; ++e) {
-      const __bf16 *wr = w2b + (int64_t)(16 * e + c) * H + 32 * st + 4 * g;
-      const v4bf lo = *reinterpret_cast<const v4bf *>(wr);
-      const v4bf hi = *reinterpret_cast<const v4bf *>(wr + 16);
-      const v8bf bw = (v8bf){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-        acc2[a][e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[a][st], bw, acc2[a][e], 0, 0, 0);
-    }
-  // output layer: lane (g, c) holds h2[16a + 4g + r][16e + c]
-  float o[2][4][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o[a][r][0] = o[a][r][1] = 0.f;
-#pragma unroll
-  for (int e = 0; e < HT; ++e) {
-    const int hcol = 16 * e + c;
-    const float bias = b2[hcol], u0 = w3[hcol], u1 = w3[H + hcol];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float h = fmaxf(acc2[a][e][r] + bias, 0.f);
-        o[a][r][0] = fmaf(u0, h, o[a][r][0]);
-        o[a][r][1] = fmaf(u1, h, o[a][r][1]);
-      }
-  }
-  const float c0 = b3[0], c1 = b3[1];
+        float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float s0 = row16_sum_f(o[a][r][0]), s1 = row16_sum_f(o[a][r][1]);
-      const int64_t row = row0 + 16 * a + 4 * g + r;
-      if (c == 0 && row < n) {
-        out[2 * row] = s0 + c0;
-        out[2 * row + 1] = s1 + c1;
+        for (int e = 0; e < TW; ++e) {
+          const float hh = fmaxf(acc2[a][e][r] + bias2[e], 0.f);
+          s0 = fmaf(u0[e], hh, s0);
+          s1 = fmaf(u1[e], hh, s1);
+        }
+        s0 = row16_sum_f(s0);
+        s1 = row16_sum_f(s1);
+        if (c == 0) {
+          po[w][16 * a + 4 * g + r][0] = s0;
+          po[w][16 * a + 4 * g + r][1] = s1;
+        }
       }
+    __syncthreads();
+    if (t < kInferRows * 2) {
+      const int rr = t >> 1, o = t & 1;
+      const int64_t row = row0 + rr;
+      if (row < n)
+        out[2 * row + o] =
+            ((po[0][rr][o] + po[1][rr][o]) + (po[2][rr][o] + po[3][rr][o])) + (o ? c1 : c0);
     }
+    // hs and po are rewritten in the next tile only after its first barrier,
+    // which every wave reaches after this tile's last LDS read
+  }
 }
 
 // BF16 copies of W1 (zero-padded to [H][kK1]), W2 and W2 transposed.
@@ -432,8 +479,10 @@ hipError_t launch_mlp_forward(const MlpLayout &L, const float *params, const flo
   const float *b1 = params + (int64_t)H * L.d_in, *b2 = b1 + H + (int64_t)H * H;
   const float *w3 = b2 + H, *b3 = w3 + 2 * H;
   const __bf16 *w1b = at<const __bf16>(ws, L.w1b), *w2b = at<const __bf16>(ws, L.w2b);
-  const int64_t rows_per_block = (int64_t)kInferRows * kInferWaves;
-  const dim3 grid((unsigned)((n + rows_per_block - 1) / rows_per_block)), block(64 * kInferWaves);
+  // persistent: at most one workgroup per compute unit (the weights fill the
+  // registers of a wave per SIMD), fewer when there are fewer tiles
+  const int64_t ntiles = (n + kInferRows - 1) / kInferRows;
+  const dim3 grid((unsigned)(ntiles < 256 ? ntiles : 256)), block(256);
   switch (H) {
     case 64:
       hipLaunchKernelGGL(k_mlp_infer<64>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b, b1,
