@@ -965,6 +965,38 @@ __global__ void k_export_scalars(int64_t n, const Hdr *h, double *out) {
   out[3] = ok ? h->perplexity : NAN;
 }
 
+// Per row block b, the slots s (tiles (b, s) or (s, b)) whose P is not all
+// zero, in increasing s: the update reads the attractive partial sums of
+// these slots only. One workgroup per block; a fixed-order prefix count.
+__global__ __launch_bounds__(256) void k_slot_lists(const uint8_t *__restrict__ nz, int32_t nb,
+                                                    int32_t *__restrict__ slots,
+                                                    int32_t *__restrict__ nslots) {
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t base;
+  const int b = blockIdx.x, t = threadIdx.x, l = t & 63, w = t >> 6;
+  if (t == 0) base = 0;
+  __syncthreads();
+  for (int s0 = 0; s0 < nb; s0 += 256) {
+    const int s = s0 + t;
+    int f = 0;
+    if (s < nb) {
+      const int64_t tile = s >= b ? tile_start(b, nb) + (s - b) : tile_start(s, nb) + (b - s);
+      f = nz[tile] != 0;
+    }
+    const uint64_t mask = __ballot(f);
+    const int before = __popcll(mask & ((l == 0) ? 0ull : (~0ull >> (64 - l))));
+    if (l == 0) wsum[w] = __popcll(mask);
+    __syncthreads();
+    int off = base;
+    for (int q = 0; q < w; ++q) off += wsum[q];
+    if (f) slots[(int64_t)b * nb + off + before] = s;
+    __syncthreads();
+    if (t == 0) base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  if (t == 0) nslots[b] = base;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -1081,6 +1113,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
     hipLaunchKernelGGL(k_pack, dim3((unsigned)L.nt), dim3(256), 0, st, P, co.a, co.m, co.r, L.n,
                        L.nb, ppart, nz);
     hipLaunchKernelGGL(k_pack_reduce, dim3(1), dim3(1024), 0, st, ppart, L.nt, h);
+    hipLaunchKernelGGL(k_slot_lists, dim3(L.nb), dim3(256), 0, st, nz, L.nb,
+                       at<int32_t>(ws, L.slots), at<int32_t>(ws, L.nslots));
   };
 
   const double *xc = xcT, *nrm = norms;

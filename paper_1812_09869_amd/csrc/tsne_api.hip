@@ -45,6 +45,8 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.ppart = take((size_t)L.nt * 16);
   L.meanpart = take((size_t)L.nb * 16);
   L.nz = take((size_t)L.nt);
+  L.slots = take((size_t)L.nb * L.nb * 4);
+  L.nslots = take((size_t)L.nb * 4);
   L.perm = take(np * 4);
   L.inv = take(np * 4);
   L.yp = take(np * 8);
@@ -315,6 +317,8 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.zpart = tsne::at<double>(ws, L.zpart);
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
+    e.slots = tsne::at<const int32_t>(ws, L.slots);
+    e.nslots = tsne::at<const int32_t>(ws, L.nslots);
     e.perm = tsne::at<const int32_t>(ws, L.perm);
     e.yp = tsne::at<float2>(ws, L.yp);
     e.h = tsne::at<tsne::Hdr>(ws, L.hdr);

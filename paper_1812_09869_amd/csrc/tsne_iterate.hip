@@ -419,16 +419,25 @@ __global__ __launch_bounds__(1024) void k_zreduce(const double *__restrict__ zpa
 constexpr int kUpd = 1024;
 constexpr int kUpdSplit = kUpd / T;
 
+constexpr int kSlotLds = 4096;  // nonzero-slot list entries staged in LDS
+
 struct UpdSmem {
   double4 part[kUpdSplit - 1][T];
   double red[2][kUpd / 64];
+  int32_t slots[kSlotLds];
 };
 
 // Gradient of row r of block b from its nb slots, g = 4 (alpha A - R / Z);
 // every thread of the workgroup must call it, the result is valid for q == 0.
 __device__ inline float2 row_gradient(const float4 *__restrict__ part,
-                                      const uint8_t *__restrict__ nz, int32_t nb, int b, int r,
+                                      const int32_t *__restrict__ slots,
+                                      const int32_t *__restrict__ nslots, int32_t nb, int b, int r,
                                       int q, double alpha, double Z, UpdSmem &sm) {
+  // the block's list of slots with nonzero P (attractive sums exist only there)
+  const int cnt = nslots[b];
+  const int32_t *gl = slots + (int64_t)b * nb;
+  for (int m = threadIdx.x; m < cnt && m < kSlotLds; m += kUpd) sm.slots[m] = gl[m];
+  __syncthreads();
   double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
   const float2 *pr = part_rep(part) + (size_t)b * nb * T + r;
   const float2 *pa = part_att(part, nb) + (size_t)b * nb * T + r;
@@ -436,13 +445,12 @@ __device__ inline float2 row_gradient(const float4 *__restrict__ part,
     const float2 v = pr[(size_t)s * T];
     rx += v.x;
     ry += v.y;
-    // slot s of block b: row side of tile (b, s) or column side of tile (s, b)
-    const int64_t tile = s >= b ? tile_start(b, nb) + (s - b) : tile_start(s, nb) + (b - s);
-    if (nz[tile]) {
-      const float2 a = pa[(size_t)s * T];
-      ax += a.x;
-      ay += a.y;
-    }
+  }
+  for (int m = q; m < cnt; m += kUpdSplit) {
+    const int s = m < kSlotLds ? sm.slots[m] : gl[m];
+    const float2 a = pa[(size_t)s * T];
+    ax += a.x;
+    ay += a.y;
   }
   if (q > 0) sm.part[q - 1][r] = make_double4(ax, ay, rx, ry);
   __syncthreads();
@@ -462,7 +470,8 @@ __device__ inline float2 row_gradient(const float4 *__restrict__ part,
 // Update (Eq. 10, descent): gains, momentum, position; per-block sums of the
 // new positions for the re-centring. kUpd threads per block of T rows.
 __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
-                                          const uint8_t *__restrict__ nz, int64_t n, int32_t nb,
+                                          const int32_t *__restrict__ slots,
+                                          const int32_t *__restrict__ nslots, int64_t n, int32_t nb,
                                           const int32_t *__restrict__ perm,
                                           float2 *__restrict__ Y, float2 *__restrict__ U,
                                           float2 *__restrict__ G, float alpha, float mu, float eta,
@@ -472,7 +481,7 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
   if (!state_ok(h, n)) return;
   const int t = threadIdx.x, r = t % T, q = t / T;
   const int64_t ir = (int64_t)b * T + r;  // internal position
-  const float2 g = row_gradient(part, nz, nb, b, r, q, (double)alpha, h->z, sm);
+  const float2 g = row_gradient(part, slots, nslots, nb, b, r, q, (double)alpha, h->z, sm);
   double sx = 0.0, sy = 0.0;
   bool bad = false;
   if (q == 0 && ir < n) {
@@ -513,7 +522,8 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
 }
 
 __global__ __launch_bounds__(kUpd) void k_update(const float4 *__restrict__ part,
-                                                 const uint8_t *__restrict__ nz, int64_t n,
+                                                 const int32_t *__restrict__ slots,
+                                                 const int32_t *__restrict__ nslots, int64_t n,
                                                  int32_t nb, const int32_t *__restrict__ perm,
                                                  float2 *__restrict__ Y,
                                                  float2 *__restrict__ U, float2 *__restrict__ G,
@@ -521,7 +531,7 @@ __global__ __launch_bounds__(kUpd) void k_update(const float4 *__restrict__ part
                                                  float2 *__restrict__ grad_out,
                                                  double2 *__restrict__ meanpart, Hdr *h) {
   __shared__ UpdSmem sm;
-  update_wg(part, nz, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h,
+  update_wg(part, slots, nslots, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h,
             blockIdx.x, sm);
 }
 
@@ -632,7 +642,7 @@ __global__ __launch_bounds__(kUpd) void k_update_batched(const BatchHdr *__restr
   const BatchEntry &e = tab[p];
   const int64_t b = (int64_t)blockIdx.x - e.blk0;
   if (b < 0 || b >= e.nb) return;
-  update_wg(e.part, e.nz, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
+  update_wg(e.part, e.slots, e.nslots, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
             (int)b, sm);
 }
 
@@ -650,7 +660,8 @@ __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__rest
 }
 
 __global__ __launch_bounds__(kUpd) void k_grad_only(const float4 *__restrict__ part,
-                                                    const uint8_t *__restrict__ nz, int64_t n,
+                                                    const int32_t *__restrict__ slots,
+                                                    const int32_t *__restrict__ nslots, int64_t n,
                                                     int32_t nb, const int32_t *__restrict__ perm,
                                                     float alpha, float2 *__restrict__ grad_out,
                                                     Hdr *h) {
@@ -658,7 +669,7 @@ __global__ __launch_bounds__(kUpd) void k_grad_only(const float4 *__restrict__ p
   if (!state_ok(h, n)) return;
   const int b = blockIdx.x, t = threadIdx.x, r = t % T, q = t / T;
   const int64_t ir = (int64_t)b * T + r;
-  const float2 g = row_gradient(part, nz, nb, b, r, q, (double)alpha, h->z, sm);
+  const float2 g = row_gradient(part, slots, nslots, nb, b, r, q, (double)alpha, h->z, sm);
   if (q == 0 && ir < n) {
     grad_out[perm[ir]] = g;
     if (!(isfinite(g.x) && isfinite(g.y))) flag_error(h, kErrNonFinite);
@@ -813,7 +824,7 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
                      L.n, h, z_out);
   double2 *mp = at<double2>(ws, L.meanpart);
   hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part),
-                     at<const uint8_t>(ws, L.nz), L.n,
+                     at<const int32_t>(ws, L.slots), at<const int32_t>(ws, L.nslots), L.n,
                      L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y), reinterpret_cast<float2 *>(u),
                      reinterpret_cast<float2 *>(g), alpha, mu, eta, min_gain,
                      reinterpret_cast<float2 *>(grad_out), mp, h);
@@ -829,7 +840,7 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
   hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
                      L.n, h, z_out);
   hipLaunchKernelGGL(k_grad_only, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part),
-                     at<const uint8_t>(ws, L.nz), L.n, L.nb, at<const int32_t>(ws, L.perm), alpha,
+                     at<const int32_t>(ws, L.slots), at<const int32_t>(ws, L.nslots), L.n, L.nb, at<const int32_t>(ws, L.perm), alpha,
                      reinterpret_cast<float2 *>(grad_out), h);
   return hipGetLastError();
 }
