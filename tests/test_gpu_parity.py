@@ -30,6 +30,7 @@ CASES = [
     (600, 50, 30.0, "aniso"),
     (1000, 128, 50.0, "gauss"),
     (2000, 10, 30.0, "small"),
+    (600, 2100, 30.0, "gauss"),  # above the ordering tree's dimension limit: caller's order
 ]
 
 
@@ -78,6 +79,11 @@ def test_affinity_parity(case):
     fro, mx = _p_errors(pg, P)
     print(f"  P rel-Frobenius {fro:.2e} max-rel {mx:.2e} beta max-rel {rel_beta.max():.2e}")
     assert fro <= 1e-5 and mx <= 1e-5
+    perm, _ = _lib.export_order(model.ws, n)
+    perm = perm.cpu().numpy()
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    if case["d"] > 2048 or n <= 256:
+        assert np.array_equal(perm, np.arange(n))
 
 
 @pytest.mark.parametrize("alpha", [1.0, 12.0])
