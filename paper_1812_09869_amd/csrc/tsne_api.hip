@@ -43,7 +43,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.zpart = take((size_t)L.nt * 8);
   L.cpart = take((size_t)L.nt * 16);
   L.ppart = take((size_t)L.nt * 16);
-  L.meanpart = take((size_t)L.nb * 16);
+  L.meanpart = take((size_t)L.nb * kMeanPartsPerBlock * 16);
   L.nz = take((size_t)L.nt);
   L.slots = take((size_t)L.nb * L.nb * 4);
   L.nslots = take((size_t)L.nb * 4);

@@ -380,59 +380,59 @@ __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
   force_wg(P, Y, n, nb, part, zpart, nz, h, blockIdx.x, sm);
 }
 
-// Z = sum of the tile partials in tile order (one workgroup of 1024 threads).
-__device__ __forceinline__ void zreduce_wg(const double *__restrict__ zpart, int64_t nt, int64_t n,
-                                           Hdr *h, double *z_out, double (&red)[16]) {
-  if (!state_ok(h, n)) return;
-  // four independent strided sums per thread (loads in flight), fixed order
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t q = threadIdx.x;
-  for (; q + 3 * 1024 < nt; q += 4 * 1024) {
-    s0 += zpart[q];
-    s1 += zpart[q + 1024];
-    s2 += zpart[q + 2 * 1024];
-    s3 += zpart[q + 3 * 1024];
-  }
-  for (; q < nt; q += 1024) s0 += zpart[q];
-  double s = (s0 + s1) + (s2 + s3);
-  s = wave_sum_d(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double Z = 0.0;
-    for (int q = 0; q < 16; ++q) Z += red[q];
-    h->z = Z;
-    if (z_out) *z_out = Z;
-    if (!isfinite(Z) || !(Z > 0.0)) flag_error(h, kErrNonFinite);
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_zreduce(const double *__restrict__ zpart, int64_t nt,
-                                                  int64_t n, Hdr *h, double *z_out) {
-  __shared__ double red[16];
-  zreduce_wg(zpart, nt, n, h, z_out, red);
-}
-
-// Row reductions use kUpd threads per block of T rows: thread (r, q) sums the
-// slots s = q, q + kUpdSplit, ... of row r in order; the kUpdSplit partial
-// sums then meet in LDS and are added in q order (a fixed order).
+// ----------------------------------------------------------------------------
+// Reduce + update. kUpdPerBlock workgroups of kUpd threads per block of T
+// rows; thread (r, q) of a workgroup sums the slots s = q, q + kUpdSplit, ...
+// of its row r in order, and the kUpdSplit partial sums meet in LDS in q
+// order (a fixed order). Every workgroup also forms Z from the tile partials
+// in the same fixed order (so all of them hold the same value) instead of a
+// separate launch; workgroup 0 stores it.
+// ----------------------------------------------------------------------------
 constexpr int kUpd = 1024;
-constexpr int kUpdSplit = kUpd / T;
-
-constexpr int kSlotLds = 4096;  // nonzero-slot list entries staged in LDS
+constexpr int kUpdRows = 128;                 // rows per workgroup
+constexpr int kUpdPerBlock = T / kUpdRows;    // workgroups per row block
+static_assert(kUpdPerBlock == kMeanPartsPerBlock, "one re-centring partial per update workgroup");
+constexpr int kUpdSplit = kUpd / kUpdRows;    // threads per row
+constexpr int kSlotLds = 4096;                // nonzero-slot list entries staged in LDS
 
 struct UpdSmem {
-  double4 part[kUpdSplit - 1][T];
+  double4 part[kUpdSplit - 1][kUpdRows];
   double red[2][kUpd / 64];
+  double z;
   int32_t slots[kSlotLds];
 };
 
-// Gradient of row r of block b from its nb slots, g = 4 (alpha A - R / Z);
-// every thread of the workgroup must call it, the result is valid for q == 0.
-__device__ inline float2 row_gradient(const float4 *__restrict__ part,
-                                      const int32_t *__restrict__ slots,
-                                      const int32_t *__restrict__ nslots, int32_t nb, int b, int r,
-                                      int q, double alpha, double Z, UpdSmem &sm) {
+// Z = sum of the tile partials: four strided sums per thread (loads in
+// flight), the wave sums, then the 16 wave results in order.
+__device__ inline double z_total(const double *__restrict__ zpart, int64_t nt, UpdSmem &sm) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t q = threadIdx.x;
+  for (; q + 3 * kUpd < nt; q += 4 * kUpd) {
+    s0 += zpart[q];
+    s1 += zpart[q + kUpd];
+    s2 += zpart[q + 2 * kUpd];
+    s3 += zpart[q + 3 * kUpd];
+  }
+  for (; q < nt; q += kUpd) s0 += zpart[q];
+  double s = wave_sum_d((s0 + s1) + (s2 + s3));
+  if ((threadIdx.x & 63) == 0) sm.red[0][threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double Z = 0.0;
+    for (int w = 0; w < kUpd / 64; ++w) Z += sm.red[0][w];
+    sm.z = Z;
+  }
+  __syncthreads();
+  return sm.z;
+}
+
+// Row sums (A_x, A_y, R_x, R_y) of row r (0 .. T-1) of block b from its nb
+// slots; every thread of the workgroup must call it, the result is valid for
+// q == 0.
+__device__ inline double4 row_sums(const float4 *__restrict__ part,
+                                   const int32_t *__restrict__ slots,
+                                   const int32_t *__restrict__ nslots, int32_t nb, int b, int r,
+                                   int q, UpdSmem &sm) {
   // the block's list of slots with nonzero P (attractive sums exist only there)
   const int cnt = nslots[b];
   const int32_t *gl = slots + (int64_t)b * nb;
@@ -452,36 +452,53 @@ __device__ inline float2 row_gradient(const float4 *__restrict__ part,
     ax += a.x;
     ay += a.y;
   }
-  if (q > 0) sm.part[q - 1][r] = make_double4(ax, ay, rx, ry);
+  const int rl = r % kUpdRows;
+  if (q > 0) sm.part[q - 1][rl] = make_double4(ax, ay, rx, ry);
   __syncthreads();
   if (q == 0) {
 #pragma unroll
     for (int g = 0; g < kUpdSplit - 1; ++g) {
-      const double4 v = sm.part[g][r];
+      const double4 v = sm.part[g][rl];
       ax += v.x;
       ay += v.y;
       rx += v.z;
       ry += v.w;
     }
   }
-  return make_float2((float)(4.0 * (alpha * ax - rx / Z)), (float)(4.0 * (alpha * ay - ry / Z)));
+  return make_double4(ax, ay, rx, ry);
 }
 
-// Update (Eq. 10, descent): gains, momentum, position; per-block sums of the
-// new positions for the re-centring. kUpd threads per block of T rows.
+// g = 4 (alpha A - R / Z)
+__device__ inline float2 gradient_of(double4 s, double alpha, double Z) {
+  return make_float2((float)(4.0 * (alpha * s.x - s.z / Z)), (float)(4.0 * (alpha * s.y - s.w / Z)));
+}
+
+// Update (Eq. 10, descent): gains, momentum, position; per-workgroup sums of
+// the new positions for the re-centring. Workgroup wg of the problem covers
+// rows (wg % kUpdPerBlock) * kUpdRows ... of block wg / kUpdPerBlock.
 __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
                                           const int32_t *__restrict__ slots,
-                                          const int32_t *__restrict__ nslots, int64_t n, int32_t nb,
-                                          const int32_t *__restrict__ perm,
+                                          const int32_t *__restrict__ nslots,
+                                          const double *__restrict__ zpart, int64_t nt,
+                                          int64_t n, int32_t nb, const int32_t *__restrict__ perm,
                                           float2 *__restrict__ Y, float2 *__restrict__ U,
                                           float2 *__restrict__ G, float alpha, float mu, float eta,
                                           float min_gain, float2 *__restrict__ grad_out,
-                                          double2 *__restrict__ meanpart, Hdr *h, int b,
+                                          double *__restrict__ z_out,
+                                          double2 *__restrict__ meanpart, Hdr *h, int wg,
                                           UpdSmem &sm) {
   if (!state_ok(h, n)) return;
-  const int t = threadIdx.x, r = t % T, q = t / T;
-  const int64_t ir = (int64_t)b * T + r;  // internal position
-  const float2 g = row_gradient(part, slots, nslots, nb, b, r, q, (double)alpha, h->z, sm);
+  const int b = wg / kUpdPerBlock;
+  const int t = threadIdx.x, q = t / kUpdRows;
+  const int r = (wg % kUpdPerBlock) * kUpdRows + t % kUpdRows;  // row within the block
+  const int64_t ir = (int64_t)b * T + r;                         // internal position
+  const double Z = z_total(zpart, nt, sm);
+  if (wg == 0 && t == 0) {
+    h->z = Z;
+    if (z_out) *z_out = Z;
+    if (!isfinite(Z) || !(Z > 0.0)) flag_error(h, kErrNonFinite);
+  }
+  const float2 g = gradient_of(row_sums(part, slots, nslots, nb, b, r, q, sm), (double)alpha, Z);
   double sx = 0.0, sy = 0.0;
   bool bad = false;
   if (q == 0 && ir < n) {
@@ -513,26 +530,24 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
   __syncthreads();
   if (t == 0) {  // the waves of q == 0 hold the rows
     double mx = 0.0, my = 0.0;
-    for (int w = 0; w < T / 64; ++w) {
+    for (int w = 0; w < kUpdRows / 64; ++w) {
       mx += sm.red[0][w];
       my += sm.red[1][w];
     }
-    meanpart[b] = make_double2(mx, my);
+    meanpart[wg] = make_double2(mx, my);
   }
 }
 
-__global__ __launch_bounds__(kUpd) void k_update(const float4 *__restrict__ part,
-                                                 const int32_t *__restrict__ slots,
-                                                 const int32_t *__restrict__ nslots, int64_t n,
-                                                 int32_t nb, const int32_t *__restrict__ perm,
-                                                 float2 *__restrict__ Y,
-                                                 float2 *__restrict__ U, float2 *__restrict__ G,
-                                                 float alpha, float mu, float eta, float min_gain,
-                                                 float2 *__restrict__ grad_out,
-                                                 double2 *__restrict__ meanpart, Hdr *h) {
+__global__ __launch_bounds__(kUpd) void k_update(
+    const float4 *__restrict__ part, const int32_t *__restrict__ slots,
+    const int32_t *__restrict__ nslots, const double *__restrict__ zpart, int64_t nt, int64_t n,
+    int32_t nb, const int32_t *__restrict__ perm, float2 *__restrict__ Y, float2 *__restrict__ U,
+    float2 *__restrict__ G, float alpha, float mu, float eta, float min_gain,
+    float2 *__restrict__ grad_out, double *__restrict__ z_out, double2 *__restrict__ meanpart,
+    Hdr *h) {
   __shared__ UpdSmem sm;
-  update_wg(part, slots, nslots, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain, grad_out, meanpart, h,
-            blockIdx.x, sm);
+  update_wg(part, slots, nslots, zpart, nt, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain,
+            grad_out, z_out, meanpart, h, blockIdx.x, sm);
 }
 
 // Subtract the mean of the map from the rows of block `blk`.
@@ -542,7 +557,7 @@ __device__ __forceinline__ void recentre_wg(const double2 *__restrict__ meanpart
   if (!state_ok(h, n)) return;
   if (threadIdx.x < 64) {  // one wave: strided partial sums, then a fixed-order wave sum
     double mx = 0.0, my = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 64) {
+    for (int b = threadIdx.x; b < nb * kUpdPerBlock; b += 64) {
       mx += meanpart[b].x;
       my += meanpart[b].y;
     }
@@ -622,15 +637,6 @@ __global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restri
   gather_rows(e.Y, e.perm, e.n, e.yp, b * T + threadIdx.x);
 }
 
-__global__ __launch_bounds__(1024) void k_zreduce_batched(const BatchHdr *__restrict__ bh,
-                                                          int count, int64_t tiles,
-                                                          int64_t blocks) {
-  __shared__ double red[16];
-  if (!batch_ok(bh, count, tiles, blocks)) return;
-  const BatchEntry &e = batch_table(bh)[blockIdx.x];
-  zreduce_wg(e.zpart, e.nt, e.n, e.h, nullptr, red);
-}
-
 __global__ __launch_bounds__(kUpd) void k_update_batched(const BatchHdr *__restrict__ bh,
                                                         int count, int64_t tiles, int64_t blocks,
                                                         float alpha, float mu, float eta,
@@ -638,12 +644,14 @@ __global__ __launch_bounds__(kUpd) void k_update_batched(const BatchHdr *__restr
   __shared__ UpdSmem sm;
   if (!batch_ok(bh, count, tiles, blocks)) return;
   const BatchEntry *tab = batch_table(bh);
-  const int p = find_entry(tab, count, blockIdx.x, false);
+  const int64_t gb = (int64_t)blockIdx.x / kUpdPerBlock;  // global row block
+  const int p = find_entry(tab, count, gb, false);
   const BatchEntry &e = tab[p];
-  const int64_t b = (int64_t)blockIdx.x - e.blk0;
+  const int64_t b = gb - e.blk0;
   if (b < 0 || b >= e.nb) return;
-  update_wg(e.part, e.slots, e.nslots, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu, eta, min_gain, nullptr, e.meanpart, e.h,
-            (int)b, sm);
+  update_wg(e.part, e.slots, e.nslots, e.zpart, e.nt, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu,
+            eta, min_gain, nullptr, nullptr, e.meanpart, e.h,
+            (int)(b * kUpdPerBlock + blockIdx.x % kUpdPerBlock), sm);
 }
 
 __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__restrict__ bh,
@@ -659,17 +667,23 @@ __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__rest
   recentre_wg(e.meanpart, e.n, e.nb, e.Y, e.h, (int)b, smean);
 }
 
-__global__ __launch_bounds__(kUpd) void k_grad_only(const float4 *__restrict__ part,
-                                                    const int32_t *__restrict__ slots,
-                                                    const int32_t *__restrict__ nslots, int64_t n,
-                                                    int32_t nb, const int32_t *__restrict__ perm,
-                                                    float alpha, float2 *__restrict__ grad_out,
-                                                    Hdr *h) {
+__global__ __launch_bounds__(kUpd) void k_grad_only(
+    const float4 *__restrict__ part, const int32_t *__restrict__ slots,
+    const int32_t *__restrict__ nslots, const double *__restrict__ zpart, int64_t nt, int64_t n,
+    int32_t nb, const int32_t *__restrict__ perm, float alpha, float2 *__restrict__ grad_out,
+    double *__restrict__ z_out, Hdr *h) {
   __shared__ UpdSmem sm;
   if (!state_ok(h, n)) return;
-  const int b = blockIdx.x, t = threadIdx.x, r = t % T, q = t / T;
+  const int wg = blockIdx.x, b = wg / kUpdPerBlock, t = threadIdx.x, q = t / kUpdRows;
+  const int r = (wg % kUpdPerBlock) * kUpdRows + t % kUpdRows;
   const int64_t ir = (int64_t)b * T + r;
-  const float2 g = row_gradient(part, slots, nslots, nb, b, r, q, (double)alpha, h->z, sm);
+  const double Z = z_total(zpart, nt, sm);
+  if (wg == 0 && t == 0) {
+    h->z = Z;
+    if (z_out) *z_out = Z;
+    if (!isfinite(Z) || !(Z > 0.0)) flag_error(h, kErrNonFinite);
+  }
+  const float2 g = gradient_of(row_sums(part, slots, nslots, nb, b, r, q, sm), (double)alpha, Z);
   if (q == 0 && ir < n) {
     grad_out[perm[ir]] = g;
     if (!(isfinite(g.x) && isfinite(g.y))) flag_error(h, kErrNonFinite);
@@ -820,14 +834,13 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
                          float mu, float eta, float min_gain, int recentre, float *grad_out,
                          double *z_out, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
-  hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
-                     L.n, h, z_out);
   double2 *mp = at<double2>(ws, L.meanpart);
-  hipLaunchKernelGGL(k_update, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part),
-                     at<const int32_t>(ws, L.slots), at<const int32_t>(ws, L.nslots), L.n,
-                     L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y), reinterpret_cast<float2 *>(u),
-                     reinterpret_cast<float2 *>(g), alpha, mu, eta, min_gain,
-                     reinterpret_cast<float2 *>(grad_out), mp, h);
+  hipLaunchKernelGGL(k_update, dim3((unsigned)(L.nb * kUpdPerBlock)), dim3(kUpd), 0, st,
+                     at<const float4>(ws, L.part), at<const int32_t>(ws, L.slots),
+                     at<const int32_t>(ws, L.nslots), at<const double>(ws, L.zpart), L.nt, L.n,
+                     L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y),
+                     reinterpret_cast<float2 *>(u), reinterpret_cast<float2 *>(g), alpha, mu, eta,
+                     min_gain, reinterpret_cast<float2 *>(grad_out), z_out, mp, h);
   if (recentre)
     hipLaunchKernelGGL(k_recentre, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, mp, L.n,
                        L.nb, reinterpret_cast<float2 *>(y), h);
@@ -837,11 +850,11 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
 hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *grad_out,
                                 double *z_out, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
-  hipLaunchKernelGGL(k_zreduce, dim3(1), dim3(1024), 0, st, at<const double>(ws, L.zpart), L.nt,
-                     L.n, h, z_out);
-  hipLaunchKernelGGL(k_grad_only, dim3(L.nb), dim3(kUpd), 0, st, at<const float4>(ws, L.part),
-                     at<const int32_t>(ws, L.slots), at<const int32_t>(ws, L.nslots), L.n, L.nb, at<const int32_t>(ws, L.perm), alpha,
-                     reinterpret_cast<float2 *>(grad_out), h);
+  hipLaunchKernelGGL(k_grad_only, dim3((unsigned)(L.nb * kUpdPerBlock)), dim3(kUpd), 0, st,
+                     at<const float4>(ws, L.part), at<const int32_t>(ws, L.slots),
+                     at<const int32_t>(ws, L.nslots), at<const double>(ws, L.zpart), L.nt, L.n,
+                     L.nb, at<const int32_t>(ws, L.perm), alpha,
+                     reinterpret_cast<float2 *>(grad_out), z_out, h);
   return hipGetLastError();
 }
 
@@ -865,9 +878,8 @@ hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tile
                      total_tiles, total_blocks);
   hipLaunchKernelGGL(k_force_batched, dim3((unsigned)total_tiles), dim3(256), 0, st, bh, count,
                      total_tiles, total_blocks);
-  hipLaunchKernelGGL(k_zreduce_batched, dim3(count), dim3(1024), 0, st, bh, count, total_tiles,
-                     total_blocks);
-  hipLaunchKernelGGL(k_update_batched, dim3((unsigned)total_blocks), dim3(kUpd), 0, st, bh, count,
+  hipLaunchKernelGGL(k_update_batched, dim3((unsigned)(total_blocks * kUpdPerBlock)), dim3(kUpd),
+                     0, st, bh, count,
                      total_tiles, total_blocks, alpha, mu, eta, min_gain);
   if (recentre)
     hipLaunchKernelGGL(k_recentre_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh,
