@@ -13,7 +13,7 @@ struct MlpLayout {
   int64_t Bpad = 0;
   size_t w1b = 0, w2b = 0, w2tb = 0, xb = 0, h1b = 0, h2 = 0, loss_part = 0;
   size_t xbt = 0, yb = 0, h1 = 0, h1t = 0, dout = 0, dh2 = 0, dh2b = 0, dh2t = 0, dh1 = 0,
-         dh1t = 0, gw1 = 0;
+         dh1t = 0, gw1 = 0, colpart = 0;
   size_t total = 0;
 };
 

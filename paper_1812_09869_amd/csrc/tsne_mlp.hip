@@ -40,18 +40,24 @@ struct Epi {
   int ldt;
 };
 
-__global__ __launch_bounds__(64) void k_gemm_bf16(const __bf16 *__restrict__ A, int lda,
-                                                  const __bf16 *__restrict__ Bm, int ldbm, int K,
-                                                  Epi e) {
+// KW waves per workgroup split K evenly (K / KW a multiple of 32); their
+// 64 x 64 partial results meet in LDS and wave 0 adds them in wave order
+// (a fixed order) before the epilogue.
+template <int KW>
+__global__ __launch_bounds__(64 * KW) void k_gemm_bf16(const __bf16 *__restrict__ A, int lda,
+                                                       const __bf16 *__restrict__ Bm, int ldbm,
+                                                       int K, Epi e) {
+  __shared__ v4f red[KW > 1 ? KW - 1 : 1][16][64];
   const int64_t m0 = (int64_t)blockIdx.x * 64;
   const int n0 = blockIdx.y * 64;
-  const int l = threadIdx.x, li = l & 15, lk = l >> 4;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, li = l & 15, lk = l >> 4;
   v4f acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = (v4f){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  const int kpw = K / KW;
+  for (int k0 = wv * kpw; k0 < (wv + 1) * kpw; k0 += 32) {
     v8bf av[4], bv[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -65,6 +71,21 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(const __bf16 *__restrict__ A, 
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[c], acc[a][c], 0, 0, 0);
+  }
+  if (KW > 1) {
+    if (wv > 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[wv - 1][4 * a + c][l] = acc[a][c];
+    }
+    __syncthreads();
+    if (wv > 0) return;
+    for (int w = 0; w < KW - 1; ++w)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] += red[w][4 * a + c][l];
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -362,34 +383,60 @@ __global__ __launch_bounds__(256) void k_mlp_head(
   }
 }
 
-// Column sums over the batch: out[n] = sum_b D[b][n] (one thread per column).
-__global__ void k_colsum(const float *__restrict__ D, int64_t B, int N, float *__restrict__ out) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int64_t b = 0; b < B; ++b) s += D[b * N + n];
-  out[n] = s;
+// Column sums over the batch, out[n] = sum_b wgt(b) D[b][n] with wgt(b) = 1
+// or w[b * wstride]: kColChunks chunks of rows summed in parallel (four
+// independent accumulators per thread), then the chunks added in order.
+// Several independent sums share one launch (blockIdx.z picks the job).
+constexpr int kColChunks = 32;
+constexpr int kColJobs = 4;
+
+struct ColJob {
+  const float *D;
+  const float *w;
+  float *part;  // [kColChunks][N]
+  float *out;   // [N]
+  int ldd, wstride, N;
+};
+struct ColJobs {
+  ColJob j[kColJobs];
+};
+
+__global__ __launch_bounds__(256) void k_colsum_part(ColJobs jobs, int64_t B) {
+  const ColJob &jb = jobs.j[blockIdx.z];
+  const int n = blockIdx.x * 256 + threadIdx.x, ch = blockIdx.y;
+  if (!jb.D || n >= jb.N) return;
+  const int64_t b0 = B * ch / kColChunks, b1 = B * (ch + 1) / kColChunks;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int64_t b = b0;
+  for (; b + 3 < b1; b += 4) {
+    const float d0 = jb.D[b * jb.ldd + n], d1 = jb.D[(b + 1) * jb.ldd + n];
+    const float d2 = jb.D[(b + 2) * jb.ldd + n], d3 = jb.D[(b + 3) * jb.ldd + n];
+    if (jb.w) {
+      s0 = fmaf(jb.w[b * jb.wstride], d0, s0);
+      s1 = fmaf(jb.w[(b + 1) * jb.wstride], d1, s1);
+      s2 = fmaf(jb.w[(b + 2) * jb.wstride], d2, s2);
+      s3 = fmaf(jb.w[(b + 3) * jb.wstride], d3, s3);
+    } else {
+      s0 += d0;
+      s1 += d1;
+      s2 += d2;
+      s3 += d3;
+    }
+  }
+  for (; b < b1; ++b) {
+    const float d = jb.D[b * jb.ldd + n];
+    s0 = jb.w ? fmaf(jb.w[b * jb.wstride], d, s0) : s0 + d;
+  }
+  jb.part[(int64_t)ch * jb.N + n] = (s0 + s1) + (s2 + s3);
 }
 
-// dW3[c][k] = sum_b dout[b][c] h2[b][k]; db3[c] = sum_b dout[b][c].
-__global__ void k_head_wgrad(const float *__restrict__ dout, const float *__restrict__ h2, int64_t B,
-                             int H, float *__restrict__ gw3, float *__restrict__ gb3) {
-  const int k = threadIdx.x;
-  if (k < H) {
-    float s0 = 0.f, s1 = 0.f;
-    for (int64_t b = 0; b < B; ++b) {
-      const float h = h2[b * H + k];
-      s0 = fmaf(dout[2 * b], h, s0);
-      s1 = fmaf(dout[2 * b + 1], h, s1);
-    }
-    gw3[k] = s0;
-    gw3[H + k] = s1;
-  }
-  if (k < 2) {
-    float s = 0.f;
-    for (int64_t b = 0; b < B; ++b) s += dout[2 * b + k];
-    gb3[k] = s;
-  }
+__global__ __launch_bounds__(256) void k_colsum_fin(ColJobs jobs) {
+  const ColJob &jb = jobs.j[blockIdx.z];
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (!jb.D || n >= jb.N) return;
+  float s = 0.f;
+  for (int ch = 0; ch < kColChunks; ++ch) s += jb.part[(int64_t)ch * jb.N + n];
+  jb.out[n] = s;
 }
 
 __global__ void k_loss_reduce(const double *__restrict__ part, int nparts, double inv_batch,
@@ -450,6 +497,7 @@ MlpLayout make_mlp_layout(int d_in, int H, int64_t Bpad, bool train) {
     L.dh1 = take(B * Hs * 4);
     L.dh1t = take(B * Hs * 2);
     L.gw1 = take(Hs * kK1 * 4);
+    L.colpart = take((size_t)kColChunks * (4 * Hs + 2) * 4);
   }
   L.total = o;
   return L;
@@ -534,28 +582,40 @@ hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const fl
   e1.ldb = H;
   e1.outBT = h1t;
   e1.ldt = (int)Bpad;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, xb, kK1,
+  hipLaunchKernelGGL(k_gemm_bf16<1>, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, xb, kK1,
                      at<const __bf16>(ws, L.w1b), kK1, kK1, e1);
   Epi e2 = epi();
   e2.bias = b2;
   e2.relu = 1;
   e2.outF = h2;
   e2.ldf = H;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, h1b, H,
+  hipLaunchKernelGGL(k_gemm_bf16<1>, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, h1b, H,
                      at<const __bf16>(ws, L.w2b), H, H, e2);
   hipLaunchKernelGGL(k_mlp_head, g256, dim3(256), 0, st, h2, H, w3, b3, B, Bpad, yb,
                      1.0 / (double)B, nullptr, (int64_t)0, dout, dh2, dh2b, dh2t, lp);
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, st, lp, (int)g256.x, 1.0 / (double)B,
                      loss);
-  // output layer gradients
-  hipLaunchKernelGGL(k_head_wgrad, dim3(1), dim3(256), 0, st, dout, h2, Bpad, H, g_w3, g_b3);
-  // second layer: dW2 = dh2^T h1, db2 = colsum(dh2), dh1 = (dh2 W2) masked by h1 > 0
+  // output layer gradients and db2: dW3[c][k] = sum_b dout[b][c] h2[b][k],
+  // db3[c] = sum_b dout[b][c], db2 = colsum(dh2)
+  float *cpart = at<float>(ws, L.colpart);
+  const size_t cstride = (size_t)kColChunks * H;
+  ColJobs jh{};
+  jh.j[0] = ColJob{h2, dout, cpart, g_w3, H, 2, H};
+  jh.j[1] = ColJob{h2, dout + 1, cpart + cstride, g_w3 + H, H, 2, H};
+  jh.j[2] = ColJob{dh2, nullptr, cpart + 2 * cstride, g_b2, H, 0, H};
+  jh.j[3] = ColJob{dout, nullptr, cpart + 4 * cstride, g_b3, 2, 0, 2};
+  const unsigned cgx = (unsigned)((H + 255) / 256);
+  hipLaunchKernelGGL(k_colsum_part, dim3(cgx, kColChunks, 4), dim3(256), 0, st, jh, Bpad);
+  // second layer: dW2 = dh2^T h1, dh1 = (dh2 W2) masked by h1 > 0
   Epi ew2 = epi();
   ew2.outF = g_w2;
   ew2.ldf = H;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(H / 64, H / 64), dim3(64), 0, st, dh2t, (int)Bpad, h1t,
-                     (int)Bpad, (int)Bpad, ew2);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, dh2, Bpad, H, g_b2);
+  if (Bpad % 256 == 0)
+    hipLaunchKernelGGL(k_gemm_bf16<4>, dim3(H / 64, H / 64), dim3(256), 0, st, dh2t, (int)Bpad,
+                       h1t, (int)Bpad, (int)Bpad, ew2);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16<1>, dim3(H / 64, H / 64), dim3(64), 0, st, dh2t, (int)Bpad,
+                       h1t, (int)Bpad, (int)Bpad, ew2);
   Epi ed1 = epi();
   ed1.mask = h1;
   ed1.ldm = H;
@@ -563,16 +623,28 @@ hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const fl
   ed1.ldf = H;
   ed1.outBT = dh1t;
   ed1.ldt = (int)Bpad;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, dh2b, H,
+  hipLaunchKernelGGL(k_gemm_bf16<1>, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, dh2b, H,
                      at<const __bf16>(ws, L.w2tb), H, H, ed1);
   // first layer: dW1 = dh1^T xh (columns beyond d_in dropped), db1 = colsum(dh1)
   Epi ew1 = epi();
   ew1.outF = g_w1;
   ew1.ldf = d_in;
   ew1.nvalid = d_in;
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(H / 64, kK1 / 64), dim3(64), 0, st, dh1t, (int)Bpad, xbt,
-                     (int)Bpad, (int)Bpad, ew1);
-  hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, st, dh1, Bpad, H, g_b1);
+  if (Bpad % 256 == 0)
+    hipLaunchKernelGGL(k_gemm_bf16<8>, dim3(H / 64, kK1 / 64), dim3(512), 0, st, dh1t, (int)Bpad,
+                       xbt, (int)Bpad, (int)Bpad, ew1);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16<1>, dim3(H / 64, kK1 / 64), dim3(64), 0, st, dh1t, (int)Bpad,
+                       xbt, (int)Bpad, (int)Bpad, ew1);
+  ColJobs j1{};
+  j1.j[0] = ColJob{dh1, nullptr, cpart + 3 * cstride, g_b1, H, 0, H};
+  hipLaunchKernelGGL(k_colsum_part, dim3(cgx, kColChunks, 1), dim3(256), 0, st, j1, Bpad);
+  ColJobs jf = jh;
+  jf.j[3] = j1.j[0];
+  ColJobs jb3{};
+  jb3.j[0] = jh.j[3];
+  hipLaunchKernelGGL(k_colsum_fin, dim3(cgx, 1, 4), dim3(256), 0, st, jf);
+  hipLaunchKernelGGL(k_colsum_fin, dim3(1, 1, 1), dim3(256), 0, st, jb3);
   return hipGetLastError();
 }
 
