@@ -310,77 +310,68 @@ __global__ void k_mlp_gather(const float *__restrict__ x, int d_in, const float 
                              int64_t row0, int64_t B, int64_t Bpad, const float *__restrict__ y,
                              __bf16 *__restrict__ xb, __bf16 *__restrict__ xbt,
                              float *__restrict__ yb) {
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (b >= Bpad) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;  // one (row, input) element
+  if (e >= Bpad * kK1) return;
+  const int64_t b = e / kK1;
+  const int k = (int)(e % kK1);
   const bool ok = b < B;
   const int64_t r = ok ? (idx ? (int64_t)idx[b] : row0 + b) : 0;
-  for (int k = 0; k < kK1; ++k) {
-    float v = 0.f;
-    if (ok && k < d_in) v = (x[r * d_in + k] - mean[k]) * invstd[k];
-    const __bf16 hv = (__bf16)v;
-    xb[b * kK1 + k] = hv;
-    if (xbt) xbt[(int64_t)k * Bpad + b] = hv;
-  }
-  if (yb) {
-    yb[2 * b] = ok ? y[2 * r] : 0.f;
-    yb[2 * b + 1] = ok ? y[2 * r + 1] : 0.f;
-  }
+  float v = 0.f;
+  if (ok && k < d_in) v = (x[r * d_in + k] - mean[k]) * invstd[k];
+  const __bf16 hv = (__bf16)v;
+  xb[e] = hv;
+  if (xbt) xbt[(int64_t)k * Bpad + b] = hv;
+  if (yb && k < 2) yb[2 * b + k] = ok ? y[2 * r + k] : 0.f;
 }
 
-// Output layer out = W3 h2 + b3 (FP32), one thread per row. With targets:
-// dout = (out - y) / B_total, per-row loss 0.5 |out - y|^2 summed per block,
-// and dh2 = (W3^T dout) masked by h2 > 0 (FP32, BF16 and BF16 transposed).
+// Output layer of a training batch and its backward pass: out = W3 h2 + b3
+// (FP32), dout = (out - y) / B_total, per-row loss 0.5 |out - y|^2 summed per
+// workgroup, dh2 = (W3^T dout) masked by h2 > 0 (FP32, BF16 and BF16
+// transposed). Sixteen threads per row, each covering H / 16 consecutive
+// hidden units; the two outputs are summed over the 16 lanes of a DPP row.
 __global__ __launch_bounds__(256) void k_mlp_head(
     const float *__restrict__ h2, int H, const float *__restrict__ w3, const float *__restrict__ b3,
-    int64_t B, int64_t Bpad, const float *__restrict__ yb, double inv_batch, float *__restrict__ out,
-    int64_t out_row0, float *__restrict__ dout, float *__restrict__ dh2, __bf16 *__restrict__ dh2b,
+    int64_t B, int64_t Bpad, const float *__restrict__ yb, double inv_batch,
+    float *__restrict__ dout, float *__restrict__ dh2, __bf16 *__restrict__ dh2b,
     __bf16 *__restrict__ dh2t, double *__restrict__ loss_part) {
-  __shared__ float sw[2 * 256];
   __shared__ double red[4];
-  for (int k = threadIdx.x; k < 2 * H; k += 256) sw[k] = w3[k];
-  __syncthreads();
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int t = threadIdx.x, p = t & 15;
+  const int64_t b = (int64_t)blockIdx.x * 16 + (t >> 4);  // < Bpad: the grid is Bpad / 16
+  const int per = H / 16, k0 = p * per;
+  const float *hr = h2 + b * H + k0;
+  float o0 = 0.f, o1 = 0.f;
+  for (int j = 0; j < per; ++j) {
+    const float h = hr[j];
+    o0 = fmaf(w3[k0 + j], h, o0);
+    o1 = fmaf(w3[H + k0 + j], h, o1);
+  }
+  o0 = row16_sum_f(o0) + b3[0];
+  o1 = row16_sum_f(o1) + b3[1];
+  float d0 = 0.f, d1 = 0.f;
   double lsum = 0.0;
-  if (b < Bpad) {
-    const float *hr = h2 + b * H;
-    float o0 = 0.f, o1 = 0.f;
-    for (int k = 0; k < H; ++k) {
-      const float h = hr[k];
-      o0 = fmaf(sw[k], h, o0);
-      o1 = fmaf(sw[H + k], h, o1);
-    }
-    o0 += b3[0];
-    o1 += b3[1];
-    if (b < B && out) {
-      out[2 * (out_row0 + b)] = o0;
-      out[2 * (out_row0 + b) + 1] = o1;
-    }
-    if (yb) {
-      float d0 = 0.f, d1 = 0.f;
-      if (b < B) {
-        const float e0 = o0 - yb[2 * b], e1 = o1 - yb[2 * b + 1];
-        lsum = 0.5 * ((double)e0 * e0 + (double)e1 * e1);
-        d0 = (float)(e0 * inv_batch);
-        d1 = (float)(e1 * inv_batch);
-      }
-      dout[2 * b] = d0;
-      dout[2 * b + 1] = d1;
-      for (int k = 0; k < H; ++k) {
-        float g = fmaf(d0, sw[k], d1 * sw[H + k]);
-        if (!(hr[k] > 0.f)) g = 0.f;
-        dh2[b * H + k] = g;
-        dh2b[b * H + k] = (__bf16)g;
-        dh2t[(int64_t)k * Bpad + b] = (__bf16)g;
-      }
-    }
+  if (b < B) {
+    const float e0 = o0 - yb[2 * b], e1 = o1 - yb[2 * b + 1];
+    if (p == 0) lsum = 0.5 * ((double)e0 * e0 + (double)e1 * e1);
+    d0 = (float)(e0 * inv_batch);
+    d1 = (float)(e1 * inv_batch);
   }
-  if (loss_part) {
+  if (p == 0) {
+    dout[2 * b] = d0;
+    dout[2 * b + 1] = d1;
+  }
+  for (int j = 0; j < per; ++j) {
+    const int k = k0 + j;
+    float g = fmaf(d0, w3[k], d1 * w3[H + k]);
+    if (!(hr[j] > 0.f)) g = 0.f;
+    dh2[b * H + k] = g;
+    dh2b[b * H + k] = (__bf16)g;
+    dh2t[(int64_t)k * Bpad + b] = (__bf16)g;
+  }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
-    __syncthreads();
-    if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-  }
+  for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+  if ((t & 63) == 0) red[t >> 6] = lsum;
+  __syncthreads();
+  if (t == 0) loss_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Column sums over the batch, out[n] = sum_b wgt(b) D[b][n] with wgt(b) = 1
@@ -484,7 +475,7 @@ MlpLayout make_mlp_layout(int d_in, int H, int64_t Bpad, bool train) {
   L.xb = take(B * kK1 * 2);
   L.h1b = take(B * Hs * 2);
   L.h2 = take(B * Hs * 4);
-  L.loss_part = take((B / 256 + 1) * 8);
+  L.loss_part = take((B / 16 + 1) * 8);
   if (train) {
     L.xbt = take(B * kK1 * 2);
     L.yb = take(B * 2 * 4);
@@ -507,6 +498,25 @@ static Epi epi() {
   Epi e{};
   e.nvalid = 1 << 30;
   return e;
+}
+
+// C = A B^T on (M / 64) x (N / 64) workgroups, splitting K over as many waves
+// (8, 4, 2 or 1) as divide its 32-wide steps, so that short grids with long
+// K still have enough loads in flight.
+static void gemm(int64_t M, int N, const __bf16 *A, int lda, const __bf16 *Bm, int ldb, int K,
+                 const Epi &e, hipStream_t st) {
+  const dim3 grid((unsigned)(M / 64), (unsigned)(N / 64));
+  const int steps = K / 32;
+  const int64_t tiles = M / 64 * (N / 64);
+  const int want = tiles >= 256 ? 1 : (tiles >= 64 ? 4 : 8);
+  if (want >= 8 && steps % 8 == 0)
+    hipLaunchKernelGGL(k_gemm_bf16<8>, grid, dim3(512), 0, st, A, lda, Bm, ldb, K, e);
+  else if (want >= 4 && steps % 4 == 0)
+    hipLaunchKernelGGL(k_gemm_bf16<4>, grid, dim3(256), 0, st, A, lda, Bm, ldb, K, e);
+  else if (want >= 2 && steps % 2 == 0)
+    hipLaunchKernelGGL(k_gemm_bf16<2>, grid, dim3(128), 0, st, A, lda, Bm, ldb, K, e);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16<1>, grid, dim3(64), 0, st, A, lda, Bm, ldb, K, e);
 }
 
 // Forward pass of rows [row0, row0 + B) (or idx[0..B)) of x into out.
@@ -569,9 +579,8 @@ hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const fl
   double *lp = at<double>(ws, L.loss_part);
   hipError_t err = launch_mlp_cast(L, params, ws, st);
   if (err != hipSuccess) return err;
-  const dim3 g256((unsigned)((Bpad + 255) / 256));
-  hipLaunchKernelGGL(k_mlp_gather, g256, dim3(256), 0, st, x, d_in, mean, invstd, idx, 0, B, Bpad,
-                     y, xb, xbt, yb);
+  hipLaunchKernelGGL(k_mlp_gather, dim3((unsigned)(Bpad * kK1 / 256)), dim3(256), 0, st, x, d_in,
+                     mean, invstd, idx, 0, B, Bpad, y, xb, xbt, yb);
   // forward
   Epi e1 = epi();
   e1.bias = b1;
@@ -582,18 +591,17 @@ hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const fl
   e1.ldb = H;
   e1.outBT = h1t;
   e1.ldt = (int)Bpad;
-  hipLaunchKernelGGL(k_gemm_bf16<1>, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, xb, kK1,
-                     at<const __bf16>(ws, L.w1b), kK1, kK1, e1);
+  gemm(Bpad, H, xb, kK1, at<const __bf16>(ws, L.w1b), kK1, kK1, e1, st);
   Epi e2 = epi();
   e2.bias = b2;
   e2.relu = 1;
   e2.outF = h2;
   e2.ldf = H;
-  hipLaunchKernelGGL(k_gemm_bf16<1>, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, h1b, H,
-                     at<const __bf16>(ws, L.w2b), H, H, e2);
-  hipLaunchKernelGGL(k_mlp_head, g256, dim3(256), 0, st, h2, H, w3, b3, B, Bpad, yb,
-                     1.0 / (double)B, nullptr, (int64_t)0, dout, dh2, dh2b, dh2t, lp);
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, st, lp, (int)g256.x, 1.0 / (double)B,
+  gemm(Bpad, H, h1b, H, at<const __bf16>(ws, L.w2b), H, H, e2, st);
+  const unsigned hgrid = (unsigned)(Bpad / 16);
+  hipLaunchKernelGGL(k_mlp_head, dim3(hgrid), dim3(256), 0, st, h2, H, w3, b3, B, Bpad, yb,
+                     1.0 / (double)B, dout, dh2, dh2b, dh2t, lp);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(64), 0, st, lp, (int)hgrid, 1.0 / (double)B,
                      loss);
   // output layer gradients and db2: dW3[c][k] = sum_b dout[b][c] h2[b][k],
   // db3[c] = sum_b dout[b][c], db2 = colsum(dh2)
@@ -610,12 +618,7 @@ hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const fl
   Epi ew2 = epi();
   ew2.outF = g_w2;
   ew2.ldf = H;
-  if (Bpad % 256 == 0)
-    hipLaunchKernelGGL(k_gemm_bf16<4>, dim3(H / 64, H / 64), dim3(256), 0, st, dh2t, (int)Bpad,
-                       h1t, (int)Bpad, (int)Bpad, ew2);
-  else
-    hipLaunchKernelGGL(k_gemm_bf16<1>, dim3(H / 64, H / 64), dim3(64), 0, st, dh2t, (int)Bpad,
-                       h1t, (int)Bpad, (int)Bpad, ew2);
+  gemm(H, H, dh2t, (int)Bpad, h1t, (int)Bpad, (int)Bpad, ew2, st);
   Epi ed1 = epi();
   ed1.mask = h1;
   ed1.ldm = H;
@@ -623,19 +626,13 @@ hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const fl
   ed1.ldf = H;
   ed1.outBT = dh1t;
   ed1.ldt = (int)Bpad;
-  hipLaunchKernelGGL(k_gemm_bf16<1>, dim3((unsigned)(Bpad / 64), H / 64), dim3(64), 0, st, dh2b, H,
-                     at<const __bf16>(ws, L.w2tb), H, H, ed1);
+  gemm(Bpad, H, dh2b, H, at<const __bf16>(ws, L.w2tb), H, H, ed1, st);
   // first layer: dW1 = dh1^T xh (columns beyond d_in dropped), db1 = colsum(dh1)
   Epi ew1 = epi();
   ew1.outF = g_w1;
   ew1.ldf = d_in;
   ew1.nvalid = d_in;
-  if (Bpad % 256 == 0)
-    hipLaunchKernelGGL(k_gemm_bf16<8>, dim3(H / 64, kK1 / 64), dim3(512), 0, st, dh1t, (int)Bpad,
-                       xbt, (int)Bpad, (int)Bpad, ew1);
-  else
-    hipLaunchKernelGGL(k_gemm_bf16<1>, dim3(H / 64, kK1 / 64), dim3(64), 0, st, dh1t, (int)Bpad,
-                       xbt, (int)Bpad, (int)Bpad, ew1);
+  gemm(H, kK1, dh1t, (int)Bpad, xbt, (int)Bpad, (int)Bpad, ew1, st);
   ColJobs j1{};
   j1.j[0] = ColJob{dh1, nullptr, cpart + 3 * cstride, g_b1, H, 0, H};
   hipLaunchKernelGGL(k_colsum_part, dim3(cgx, kColChunks, 1), dim3(256), 0, st, j1, Bpad);
