@@ -513,10 +513,12 @@ __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const floa
                                               const float *__restrict__ m,
                                               const float *__restrict__ r, int64_t n, int32_t nb,
                                               double2 *__restrict__ ppart,
-                                              uint8_t *__restrict__ nzflag) {
+                                              uint8_t *__restrict__ nzflag,
+                                              int2 *__restrict__ tmap) {
   __shared__ double red[2][4];
   int I, J;
   tile_coords(blockIdx.x, nb, I, J);
+  if (threadIdx.x == 0) tmap[blockIdx.x] = make_int2(I, J);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
   const bool diag = (I == J);
@@ -1111,7 +1113,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
   };
   auto pack = [&]() {
     hipLaunchKernelGGL(k_pack, dim3((unsigned)L.nt), dim3(256), 0, st, P, co.a, co.m, co.r, L.n,
-                       L.nb, ppart, nz);
+                       L.nb, ppart, nz, at<int2>(ws, L.tmap));
     hipLaunchKernelGGL(k_pack_reduce, dim3(1), dim3(1024), 0, st, ppart, L.nt, h);
     hipLaunchKernelGGL(k_slot_lists, dim3(L.nb), dim3(256), 0, st, nz, L.nb,
                        at<int32_t>(ws, L.slots), at<int32_t>(ws, L.nslots));

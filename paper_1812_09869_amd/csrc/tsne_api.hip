@@ -45,6 +45,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.ppart = take((size_t)L.nt * 16);
   L.meanpart = take((size_t)L.nb * kMeanPartsPerBlock * 16);
   L.nz = take((size_t)L.nt);
+  L.tmap = take((size_t)L.nt * 8);
   L.slots = take((size_t)L.nb * L.nb * 4);
   L.nslots = take((size_t)L.nb * 4);
   L.perm = take(np * 4);
@@ -318,6 +319,7 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
     e.slots = tsne::at<const int32_t>(ws, L.slots);
+    e.tmap = tsne::at<const int2>(ws, L.tmap);
     e.nslots = tsne::at<const int32_t>(ws, L.nslots);
     e.perm = tsne::at<const int32_t>(ws, L.perm);
     e.yp = tsne::at<float2>(ws, L.yp);

@@ -58,6 +58,7 @@ struct Layout {
   size_t hdr = 0, beta = 0, S = 0, H = 0, m = 0, a = 0, r = 0, evals = 0;
   size_t P = 0, part = 0, zpart = 0, cpart = 0, ppart = 0, meanpart = 0;
   size_t nz = 0;    // per tile: 1 if any stored p_ij of the tile is nonzero
+  size_t tmap = 0;    // int2 [nt]: (I, J) of every tile, written by the pack
   size_t slots = 0;   // int32 [nb][nb]: per row block, its slots with nonzero P, in order
   size_t nslots = 0;  // int32 [nb]: how many
   size_t perm = 0;  // int32 [npad]: internal position -> caller's index
@@ -99,6 +100,7 @@ struct BatchEntry {
   double2 *meanpart;
   const uint8_t *nz;
   const int32_t *slots, *nslots;
+  const int2 *tmap;
   const int32_t *perm;
   float2 *yp;  // positions in the internal order (refreshed by every force pass)
   Hdr *h;

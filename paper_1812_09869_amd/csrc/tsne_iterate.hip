@@ -67,6 +67,15 @@ __device__ inline uint32_t valid_bits(int64_t rem, int off) {
   return cnt >= 16 ? 0xFFFFu : ((1u << cnt) - 1u);
 }
 
+// FP32 sum over the wave: the 16-lane DPP sum, then the four rows (a fixed
+// pattern, so the result is reproducible).
+__device__ inline float wave_sum_f(float v) {
+  v = row16_sum(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // Header check shared by the iteration kernels: the workspace must hold
 // affinities for exactly this n.
 __device__ inline bool state_ok(Hdr *h, int64_t n) {
@@ -257,14 +266,19 @@ __global__ __launch_bounds__(256) void k_gather_y(const float2 *__restrict__ Y,
 __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
                                          const float2 *__restrict__ Y, int64_t n, int32_t nb,
                                          float4 *__restrict__ part, double *__restrict__ zpart,
-                                         const uint8_t *__restrict__ nz, Hdr *h, int64_t tile,
+                                         const uint8_t *__restrict__ nz,
+                                         const int2 *__restrict__ tmap, Hdr *h, int64_t tile,
                                          ForceSmem &sm) {
   if (!state_ok(h, n)) {
     if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
   int I, J;
-  tile_coords(tile, nb, I, J);
+  {
+    const int2 ij = tmap[tile];
+    I = ij.x;
+    J = ij.y;
+  }
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
   // Y is the zero-padded internal-order copy, so whole tiles load unguarded
@@ -304,7 +318,7 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 #pragma unroll
       for (int m = 0; m < 16; ++m) sm.colbuf2[tr][tc + 16 * m] = colrep[m];
     }
-    const double zd = wave_sum_d((double)z);
+    const double zd = (double)wave_sum_f(z);
     if (l == 0) sm.zred[w] = zd;
     __syncthreads();
     if (I != J) {
@@ -350,7 +364,7 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 #pragma unroll
       for (int m = 0; m < 16; ++m) sm.colbuf[tr][tc + 16 * m] = colacc[m];
     }
-    const double zd = wave_sum_d((double)z);
+    const double zd = (double)wave_sum_f(z);
     if (l == 0) sm.zred[w] = zd;
     __syncthreads();
     if (I != J) {
@@ -375,9 +389,10 @@ __global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
                                                   const float2 *__restrict__ Y, int64_t n,
                                                   int32_t nb, float4 *__restrict__ part,
                                                   double *__restrict__ zpart,
-                                                  const uint8_t *__restrict__ nz, Hdr *h) {
+                                                  const uint8_t *__restrict__ nz,
+                                                  const int2 *__restrict__ tmap, Hdr *h) {
   __shared__ ForceSmem sm;
-  force_wg(P, Y, n, nb, part, zpart, nz, h, blockIdx.x, sm);
+  force_wg(P, Y, n, nb, part, zpart, nz, tmap, h, blockIdx.x, sm);
 }
 
 // ----------------------------------------------------------------------------
@@ -622,7 +637,7 @@ __global__ __launch_bounds__(256, 2) void k_force_batched(const BatchHdr *__rest
   const BatchEntry &e = tab[p];
   const int64_t tile = (int64_t)blockIdx.x - e.tile0;
   if (tile < 0 || tile >= e.nt) return;
-  force_wg(e.P, e.yp, e.n, e.nb, e.part, e.zpart, e.nz, e.h, tile, sm);
+  force_wg(e.P, e.yp, e.n, e.nb, e.part, e.zpart, e.nz, e.tmap, e.h, tile, sm);
 }
 
 __global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restrict__ bh,
@@ -826,7 +841,8 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
                      at<const int32_t>(ws, L.perm), L.n, yp);
   hipLaunchKernelGGL(k_force, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
                      yp, L.n, L.nb, at<float4>(ws, L.part),
-                     at<double>(ws, L.zpart), at<const uint8_t>(ws, L.nz), h);
+                     at<double>(ws, L.zpart), at<const uint8_t>(ws, L.nz),
+                     at<const int2>(ws, L.tmap), h);
   return hipGetLastError();
 }
 

@@ -6,8 +6,9 @@
 * On the four smallest problems of the 64-problem workload: the gradient at
   oracle states of iterations 0, 249 and 499 (oracle FP64 trajectories cast to
   FP32) matches the oracle to 1e-4, and the batched 500-iteration run ends
-  within 2% of the oracle's final KL (the chaos floor measured on the
-  2,000-point workload is about 1%).
+  within twice the spread of the oracle's own final KL over seven starts one
+  FP32 ulp apart (the chaos floor: trajectories that differ only in rounding
+  separate, so the final KL is only determined up to that spread).
 """
 import numpy as np
 import pytest
@@ -72,9 +73,18 @@ def test_batched_matches_oracle_on_smallest_problems():
             assert rel <= 1e-4
         y_end, _, _ = oracle.run(P, y0s[k], 1, start=499, state=state)
         kl_ref = oracle.cost(P, y_end)[0]
+        # chaos band of the final KL: the oracle from initial maps one FP32 ulp apart
+        kls = [kl_ref]
+        for row, coord in ((0, 0), (0, 1), (1, 0), (1, 1), (2, 0), (2, 1)):
+            y0p = y0s[k].copy()
+            y0p[row, coord] = np.nextafter(y0p[row, coord], np.float32(np.inf))
+            y_p, _, _ = oracle.run(P, y0p, 500)
+            kls.append(oracle.cost(P, y_p)[0])
+        band = max(kls) - min(kls)
         kl_gpu = float(model.cost(batched.states[k][0]).cpu()[0])
-        print(f"  final KL gpu {kl_gpu:.5f} oracle {kl_ref:.5f} rel {abs(kl_gpu - kl_ref) / kl_ref:.2e}")
-        assert abs(kl_gpu - kl_ref) <= 0.02 * kl_ref
+        print(f"  final KL gpu {kl_gpu:.5f} oracle {kl_ref:.5f} rel {abs(kl_gpu - kl_ref) / kl_ref:.2e}"
+              f"; oracle band over 1-ulp starts {band / kl_ref:.2e}")
+        assert abs(kl_gpu - kl_ref) <= max(2.0 * band, 2e-3 * kl_ref)
         assert model.status() == 0
 
 
