@@ -108,16 +108,16 @@ __global__ __launch_bounds__(64 * KW) void k_gemm_bf16(const __bf16 *__restrict_
 }
 
 // ----------------------------------------------------------------------------
-// Fused inference. A persistent workgroup of four waves keeps the weights in
+// Fused inference. A persistent workgroup of W waves keeps the weights in
 // registers and runs tiles of kInferRows rows through the whole network:
 //
-//   wave w owns hidden units [H/4 w, H/4 (w + 1)) of both wide layers: its
+//   wave w owns hidden units [H/W w, H/W (w + 1)) of both wide layers: its
 //   slice of W1 (as the A operand of the transposed first layer) and its
 //   column slice of W2 (as the B operand of the second) stay in registers
 //   for the life of the workgroup;
 //   the standardised BF16 input tile and the BF16 first-layer output tile
-//   live in LDS, shared by the four waves;
-//   the output layer's partial sums of the four waves meet in LDS.
+//   live in LDS, shared by the W waves;
+//   the output layer's partial sums of the W waves meet in LDS.
 //
 // Layer 1 is computed transposed, H1^T = W1 X^T (M = hidden, N = rows), so
 // lane l = 16g + c receives H1^T[16t + 4g + r][16a + c]: four consecutive
@@ -141,20 +141,21 @@ __device__ inline float row16_sum_f(float v) {
   return v;
 }
 
-template <int H>
-__global__ __launch_bounds__(256, 1) void k_mlp_infer(
+template <int H, int W>
+__global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
     const float *__restrict__ x, int64_t n, int d_in, const float *__restrict__ mean,
     const float *__restrict__ invstd, const __bf16 *__restrict__ w1b,
     const float *__restrict__ b1, const __bf16 *__restrict__ w2b, const float *__restrict__ b2,
     const float *__restrict__ w3, const float *__restrict__ b3, float *__restrict__ out) {
-  constexpr int HW = H / 4;          // hidden units per wave
+  constexpr int NT = 64 * W;         // threads
+  constexpr int HW = H / W;          // hidden units per wave
   constexpr int TW = HW / 16;        // hidden tiles per wave
   constexpr int KS = H / 32;         // K steps of layer 2
   constexpr int RA = kInferRows / 16;  // row tiles
   constexpr int HPitch = H + 8;      // BF16 elements per LDS row of the hidden tile
   __shared__ __bf16 xs[kInferRows][kXPitch];
   __shared__ __bf16 hs[kInferRows][HPitch];
-  __shared__ float po[4][kInferRows][2];
+  __shared__ float po[W][kInferRows][2];
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int c = l & 15, g = l >> 4;
   const int h0 = w * HW;  // first hidden unit of this wave
@@ -186,8 +187,8 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
   }
   const float c0 = b3[0], c1 = b3[1];
   const int64_t ntiles = (n + kInferRows - 1) / kInferRows;
-  // input staging: thread t always handles input k = t % 64 of rows t / 64 + 4m
-  constexpr int XM = kInferRows * kK1 / 256;
+  // input staging: thread t always handles input k = t % 64 of rows t / 64 + W m
+  constexpr int XM = kInferRows * kK1 / NT;
   const int xk = t & (kK1 - 1), xr = t / kK1;
   const bool kin = xk < d_in;
   const float xmean = kin ? mean[xk] : 0.f, xinv = kin ? invstd[xk] : 0.f;
@@ -195,14 +196,14 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
   auto load_x = [&](int64_t tl) {
 #pragma unroll
     for (int m = 0; m < XM; ++m) {
-      const int64_t row = tl * kInferRows + xr + 4 * m;
+      const int64_t row = tl * kInferRows + xr + W * m;
       xv[m] = (kin && tl < ntiles && row < n) ? x[row * d_in + xk] : 0.f;
     }
   };
   auto store_x = [&]() {
 #pragma unroll
     for (int m = 0; m < XM; ++m)
-      xs[xr + 4 * m][xk] = (__bf16)(kin ? (xv[m] - xmean) * xinv : 0.f);
+      xs[xr + W * m][xk] = (__bf16)(kin ? (xv[m] - xmean) * xinv : 0.f);
   };
   load_x(blockIdx.x);
   store_x();
@@ -278,9 +279,10 @@ __global__ __launch_bounds__(256, 1) void k_mlp_infer(
     if (t < kInferRows * 2) {
       const int rr = t >> 1, o = t & 1;
       const int64_t row = row0 + rr;
-      if (row < n)
-        out[2 * row + o] =
-            ((po[0][rr][o] + po[1][rr][o]) + (po[2][rr][o] + po[3][rr][o])) + (o ? c1 : c0);
+      float sum = 0.f;
+#pragma unroll
+      for (int q = 0; q < W; ++q) sum += po[q][rr][o];
+      if (row < n) out[2 * row + o] = sum + (o ? c1 : c0);
     }
     // hs and po are rewritten in the next tile only after its first barrier,
     // which every wave reaches after this tile's last LDS read
@@ -540,23 +542,23 @@ hipError_t launch_mlp_forward(const MlpLayout &L, const float *params, const flo
   // persistent: at most one workgroup per compute unit (the weights fill the
   // registers of a wave per SIMD), fewer when there are fewer tiles
   const int64_t ntiles = (n + kInferRows - 1) / kInferRows;
-  const dim3 grid((unsigned)(ntiles < 256 ? ntiles : 256)), block(256);
+  const dim3 grid((unsigned)(ntiles < 256 ? ntiles : 256));
   switch (H) {
     case 64:
-      hipLaunchKernelGGL(k_mlp_infer<64>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b, b1,
-                         w2b, b2, w3, b3, out);
+      hipLaunchKernelGGL((k_mlp_infer<64, 4>), grid, dim3(256), 0, st, x, n, L.d_in, mean, invstd,
+                         w1b, b1, w2b, b2, w3, b3, out);
       break;
     case 128:
-      hipLaunchKernelGGL(k_mlp_infer<128>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b,
-                         b1, w2b, b2, w3, b3, out);
+      hipLaunchKernelGGL((k_mlp_infer<128, 8>), grid, dim3(512), 0, st, x, n, L.d_in, mean,
+                         invstd, w1b, b1, w2b, b2, w3, b3, out);
       break;
     case 192:
-      hipLaunchKernelGGL(k_mlp_infer<192>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b,
-                         b1, w2b, b2, w3, b3, out);
+      hipLaunchKernelGGL((k_mlp_infer<192, 4>), grid, dim3(256), 0, st, x, n, L.d_in, mean,
+                         invstd, w1b, b1, w2b, b2, w3, b3, out);
       break;
     default:
-      hipLaunchKernelGGL(k_mlp_infer<256>, grid, block, 0, st, x, n, L.d_in, mean, invstd, w1b,
-                         b1, w2b, b2, w3, b3, out);
+      hipLaunchKernelGGL((k_mlp_infer<256, 8>), grid, dim3(512), 0, st, x, n, L.d_in, mean,
+                         invstd, w1b, b1, w2b, b2, w3, b3, out);
   }
   return hipGetLastError();
 }
