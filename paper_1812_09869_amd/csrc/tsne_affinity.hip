@@ -967,6 +967,63 @@ __global__ void k_export_scalars(int64_t n, const Hdr *h, double *out) {
   out[3] = ok ? h->perplexity : NAN;
 }
 
+// Tile lists for the force pass: all-zero tiles in ascending order, then the
+// others in ascending order (one workgroup; ballot prefix counts in a fixed
+// order).
+__global__ __launch_bounds__(1024) void k_tile_lists(const uint8_t *__restrict__ nz, int64_t nt,
+                                                     int32_t *__restrict__ tlist,
+                                                     int32_t *__restrict__ tcount) {
+  __shared__ int32_t wz[16], wn[16];
+  __shared__ int32_t zbase, nbase, zeros;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  // pass 1: number of all-zero tiles
+  int32_t cnt = 0;
+  for (int64_t q = t; q < nt; q += 1024) cnt += nz[q] == 0;
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if (l == 0) wz[w] = cnt;
+  __syncthreads();
+  if (t == 0) {
+    int32_t z = 0;
+    for (int q = 0; q < 16; ++q) z += wz[q];
+    zeros = z;
+    zbase = 0;
+    nbase = z;
+  }
+  __syncthreads();
+  // pass 2: positions
+  for (int64_t q0 = 0; q0 < nt; q0 += 1024) {
+    const int64_t q = q0 + t;
+    const bool valid = q < nt;
+    const bool isz = valid && nz[q] == 0, isn = valid && nz[q] != 0;
+    const uint64_t mz = __ballot(isz), mn = __ballot(isn);
+    const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    if (l == 0) {
+      wz[w] = __popcll(mz);
+      wn[w] = __popcll(mn);
+    }
+    __syncthreads();
+    int32_t oz = zbase, on = nbase;
+    for (int k = 0; k < w; ++k) {
+      oz += wz[k];
+      on += wn[k];
+    }
+    if (isz) tlist[oz + __popcll(mz & below)] = (int32_t)q;
+    if (isn) tlist[on + __popcll(mn & below)] = (int32_t)q;
+    __syncthreads();
+    if (t == 0) {
+      for (int k = 0; k < 16; ++k) {
+        zbase += wz[k];
+        nbase += wn[k];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    tcount[0] = zeros;
+    tcount[1] = (int32_t)(nt - zeros);
+  }
+}
+
 // Per row block b, the slots s (tiles (b, s) or (s, b)) whose P is not all
 // zero, in increasing s: the update reads the attractive partial sums of
 // these slots only. One workgroup per block; a fixed-order prefix count.
@@ -1117,6 +1174,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
     hipLaunchKernelGGL(k_pack_reduce, dim3(1), dim3(1024), 0, st, ppart, L.nt, h);
     hipLaunchKernelGGL(k_slot_lists, dim3(L.nb), dim3(256), 0, st, nz, L.nb,
                        at<int32_t>(ws, L.slots), at<int32_t>(ws, L.nslots));
+    hipLaunchKernelGGL(k_tile_lists, dim3(1), dim3(1024), 0, st, nz, L.nt,
+                       at<int32_t>(ws, L.tlist), at<int32_t>(ws, L.tcount));
   };
 
   const double *xc = xcT, *nrm = norms;

@@ -46,6 +46,8 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.meanpart = take((size_t)L.nb * kMeanPartsPerBlock * 16);
   L.nz = take((size_t)L.nt);
   L.tmap = take((size_t)L.nt * 8);
+  L.tlist = take((size_t)L.nt * 4);
+  L.tcount = take(8);
   L.slots = take((size_t)L.nb * L.nb * 4);
   L.nslots = take((size_t)L.nb * 4);
   L.perm = take(np * 4);

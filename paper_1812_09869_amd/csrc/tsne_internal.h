@@ -59,6 +59,8 @@ struct Layout {
   size_t P = 0, part = 0, zpart = 0, cpart = 0, ppart = 0, meanpart = 0;
   size_t nz = 0;    // per tile: 1 if any stored p_ij of the tile is nonzero
   size_t tmap = 0;    // int2 [nt]: (I, J) of every tile, written by the pack
+  size_t tlist = 0;   // int32 [nt]: all-zero tiles ascending, then the others ascending
+  size_t tcount = 0;  // int32 [2]: number of all-zero tiles, number of the others
   size_t slots = 0;   // int32 [nb][nb]: per row block, its slots with nonzero P, in order
   size_t nslots = 0;  // int32 [nb]: how many
   size_t perm = 0;  // int32 [npad]: internal position -> caller's index

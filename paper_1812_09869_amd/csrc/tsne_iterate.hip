@@ -18,6 +18,8 @@
 // only for slots whose tile holds nonzero P.
 #include <math.h>
 
+#include <mutex>
+
 #include "tsne_internal.h"
 
 namespace tsne {
@@ -262,7 +264,161 @@ __global__ __launch_bounds__(256) void k_gather_y(const float2 *__restrict__ Y,
   gather_rows(Y, perm, n, Yp, (int64_t)blockIdx.x * T + threadIdx.x);
 }
 
-// One workgroup's share of the force pass: tile number `tile` of a problem.
+// LDS of the all-zero-tile kernel: no P ring, so four workgroups fit a CU.
+constexpr int64_t kFullGrid = 256;  // persistent workgroups of the nonzero-tile kernel
+
+struct ZeroSmem {
+  float2 colbuf2[16][T + 4];
+  float2 yrow[T];
+  double zred[4];
+};
+
+// Set-up shared by both tile bodies: coordinates, valid-row masks, the
+// column positions in registers and the row positions in LDS.
+struct TileCtx {
+  int I, J, t, w, l, tc, tr;
+  uint32_t rvalid, cvalid;
+  bool edge;
+  size_t rslot, cslot;
+};
+
+template <class Smem>
+__device__ __forceinline__ TileCtx tile_begin(const float2 *__restrict__ Y, int64_t n, int32_t nb,
+                                              const int2 *__restrict__ tmap, int64_t tile,
+                                              float2 (&yc)[16], Smem &sm) {
+  TileCtx c;
+  const int2 ij = tmap[tile];
+  c.I = ij.x;
+  c.J = ij.y;
+  c.t = threadIdx.x;
+  c.w = c.t >> 6;
+  c.l = c.t & 63;
+  c.tc = c.l & 15;
+  c.tr = (c.l >> 4) + 4 * c.w;
+  // Y is the zero-padded internal-order copy, so whole tiles load unguarded
+  c.rvalid = valid_bits(n - (int64_t)c.I * T, c.tr);
+  c.cvalid = valid_bits(n - (int64_t)c.J * T, c.tc);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) yc[k] = Y[(int64_t)c.J * T + c.tc + 16 * k];
+  sm.yrow[c.t] = Y[(int64_t)c.I * T + c.t];
+  c.edge = ((int64_t)(c.J + 1) * T > n);
+  c.rslot = ((size_t)c.I * nb + c.J) * T + c.tr + 16 * c.tc;  // row tr + 16 tc
+  c.cslot = ((size_t)c.J * nb + c.I) * T + c.t;               // column t
+  __syncthreads();
+  return c;
+}
+
+// A tile whose stored P is all zero: repulsion and Z only, no P traffic,
+// float2 accumulators. Ends with a workgroup barrier.
+template <class Smem>
+__device__ __forceinline__ void zero_tile_body(const TileCtx &c, const float2 (&yc)[16],
+                                               float4 *__restrict__ part,
+                                               double *__restrict__ zpart, int64_t tile,
+                                               Smem &sm) {
+  float2 *prep = part_rep(part);
+  float z = 0.f;
+  float2 myrow = make_float2(0.f, 0.f);
+  float2 colrep[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) colrep[m] = make_float2(0.f, 0.f);
+  if (c.I == c.J) {
+    if (c.edge)
+      tile_rows_zero<true, true>(sm.yrow, yc, c.rvalid, c.cvalid, c.tr, c.tc, myrow, colrep, z);
+    else
+      tile_rows_zero<true, false>(sm.yrow, yc, c.rvalid, c.cvalid, c.tr, c.tc, myrow, colrep, z);
+  } else {
+    if (c.edge)
+      tile_rows_zero<false, true>(sm.yrow, yc, c.rvalid, c.cvalid, c.tr, c.tc, myrow, colrep, z);
+    else
+      tile_rows_zero<false, false>(sm.yrow, yc, c.rvalid, c.cvalid, c.tr, c.tc, myrow, colrep,
+                                   z);
+  }
+  prep[c.rslot] = myrow;
+  // column side: the 16 row groups' sums meet in LDS
+  if (c.I != c.J) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) sm.colbuf2[c.tr][c.tc + 16 * m] = colrep[m];
+  }
+  const double zd = (double)wave_sum_f(z);
+  if (c.l == 0) sm.zred[c.w] = zd;
+  __syncthreads();
+  if (c.I != c.J) {
+    float2 s2 = sm.colbuf2[0][c.t];
+#pragma unroll
+    for (int g = 1; g < 16; ++g) {
+      const float2 v = sm.colbuf2[g][c.t];
+      s2.x += v.x;
+      s2.y += v.y;
+    }
+    prep[c.cslot] = s2;
+  }
+  if (c.t == 0)
+    zpart[tile] = (sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (c.I == c.J ? 1.0 : 2.0);
+}
+
+// A tile with nonzero P: attraction and repulsion, P streamed through the
+// per-wave LDS rings. Ends with a workgroup barrier.
+__device__ __forceinline__ void full_tile_body(const TileCtx &c, const float2 (&yc)[16],
+                                               const float4 *__restrict__ P,
+                                               float4 *__restrict__ part, int32_t nb,
+                                               double *__restrict__ zpart, int64_t tile,
+                                               ForceSmem &sm) {
+  float2 *prep = part_rep(part), *patt = part_att(part, nb);
+  float z = 0.f;
+  float4 *wring = &sm.ring[c.w][0][0][0];
+  const uint32_t lane_addr = (uint32_t)(size_t)((lds_void_t *)wring) + (uint32_t)c.l * 16u;
+  const uint32_t yrow_addr = (uint32_t)(size_t)((lds_void_t *)(sm.yrow + c.tr));
+  const float4 *tp = P + (size_t)tile * TT4;
+  float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 colacc[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) colacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (c.I == c.J) {
+    if (c.edge)
+      tile_rows<true, true>(tp, wring, lane_addr, yrow_addr, yc, c.rvalid, c.cvalid, c.t, c.tr,
+                            c.tc, myrow, colacc, z);
+    else
+      tile_rows<true, false>(tp, wring, lane_addr, yrow_addr, yc, c.rvalid, c.cvalid, c.t, c.tr,
+                             c.tc, myrow, colacc, z);
+  } else {
+    if (c.edge)
+      tile_rows<false, true>(tp, wring, lane_addr, yrow_addr, yc, c.rvalid, c.cvalid, c.t, c.tr,
+                             c.tc, myrow, colacc, z);
+    else
+      tile_rows<false, false>(tp, wring, lane_addr, yrow_addr, yc, c.rvalid, c.cvalid, c.t,
+                              c.tr, c.tc, myrow, colacc, z);
+  }
+  prep[c.rslot] = make_float2(myrow.z, myrow.w);
+  patt[c.rslot] = make_float2(myrow.x, myrow.y);
+  // column side: the 16 row groups' sums meet in LDS (colbuf overlays the P
+  // ring, so every wave must be done with its ring first)
+  __syncthreads();
+  if (c.I != c.J) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) sm.colbuf[c.tr][c.tc + 16 * m] = colacc[m];
+  }
+  const double zd = (double)wave_sum_f(z);
+  if (c.l == 0) sm.zred[c.w] = zd;
+  __syncthreads();
+  if (c.I != c.J) {
+    float4 s4 = sm.colbuf[0][c.t];
+#pragma unroll
+    for (int g = 1; g < 16; ++g) {
+      const float4 v = sm.colbuf[g][c.t];
+      s4.x += v.x;
+      s4.y += v.y;
+      s4.z += v.z;
+      s4.w += v.w;
+    }
+    prep[c.cslot] = make_float2(s4.z, s4.w);
+    patt[c.cslot] = make_float2(s4.x, s4.y);
+  }
+  if (c.t == 0)
+    zpart[tile] = (sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (c.I == c.J ? 1.0 : 2.0);
+}
+
+// One workgroup's share of a mixed force pass: tile number `tile` of a
+// problem, either body by its flag (the batched iteration).
 __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
                                          const float2 *__restrict__ Y, int64_t n, int32_t nb,
                                          float4 *__restrict__ part, double *__restrict__ zpart,
@@ -273,126 +429,59 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
     if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
-  int I, J;
-  {
-    const int2 ij = tmap[tile];
-    I = ij.x;
-    J = ij.y;
-  }
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int tc = l & 15, tr = (l >> 4) + 4 * w;
-  // Y is the zero-padded internal-order copy, so whole tiles load unguarded
-  const uint32_t rvalid = valid_bits(n - (int64_t)I * T, tr);
-  const uint32_t cvalid = valid_bits(n - (int64_t)J * T, tc);
   float2 yc[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) yc[k] = Y[(int64_t)J * T + tc + 16 * k];
-  sm.yrow[t] = Y[(int64_t)I * T + t];
-  __syncthreads();
-  const bool edge = ((int64_t)(J + 1) * T > n);
-  const bool nzt = nz[tile] != 0;
-  float2 *prep = part_rep(part), *patt = part_att(part, nb);
-  const size_t rslot = ((size_t)I * nb + J) * T + tr + 16 * tc;  // row tr + 16 tc
-  const size_t cslot = ((size_t)J * nb + I) * T + t;             // column t
-  float z = 0.f;
-  if (!nzt) {
-    // all-zero P: repulsion and Z only, no P traffic, float2 accumulators
-    float2 myrow = make_float2(0.f, 0.f);
-    float2 colrep[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) colrep[m] = make_float2(0.f, 0.f);
-    if (I == J) {
-      if (edge)
-        tile_rows_zero<true, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
-      else
-        tile_rows_zero<true, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
-    } else {
-      if (edge)
-        tile_rows_zero<false, true>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
-      else
-        tile_rows_zero<false, false>(sm.yrow, yc, rvalid, cvalid, tr, tc, myrow, colrep, z);
-    }
-    prep[rslot] = myrow;
-    // column side: the 16 row groups' sums meet in LDS
-    if (I != J) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m) sm.colbuf2[tr][tc + 16 * m] = colrep[m];
-    }
-    const double zd = (double)wave_sum_f(z);
-    if (l == 0) sm.zred[w] = zd;
-    __syncthreads();
-    if (I != J) {
-      float2 s2 = sm.colbuf2[0][t];
-#pragma unroll
-      for (int g = 1; g < 16; ++g) {
-        const float2 v = sm.colbuf2[g][t];
-        s2.x += v.x;
-        s2.y += v.y;
-      }
-      prep[cslot] = s2;
-    }
-  } else {
-    float4 *wring = &sm.ring[w][0][0][0];
-    const uint32_t lane_addr = (uint32_t)(size_t)((lds_void_t *)wring) + (uint32_t)l * 16u;
-    const uint32_t yrow_addr = (uint32_t)(size_t)((lds_void_t *)(sm.yrow + tr));
-    const float4 *tp = P + (size_t)tile * TT4;
-    float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 colacc[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) colacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (I == J) {
-      if (edge)
-        tile_rows<true, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
-                              myrow, colacc, z);
-      else
-        tile_rows<true, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
-                               myrow, colacc, z);
-    } else {
-      if (edge)
-        tile_rows<false, true>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
-                               myrow, colacc, z);
-      else
-        tile_rows<false, false>(tp, wring, lane_addr, yrow_addr, yc, rvalid, cvalid, t, tr, tc,
-                                myrow, colacc, z);
-    }
-    prep[rslot] = make_float2(myrow.z, myrow.w);
-    patt[rslot] = make_float2(myrow.x, myrow.y);
-    // column side: the 16 row groups' sums meet in LDS (colbuf overlays the P
-    // ring, so every wave must be done with its ring first)
-    __syncthreads();
-    if (I != J) {
-#pragma unroll
-      for (int m = 0; m < 16; ++m) sm.colbuf[tr][tc + 16 * m] = colacc[m];
-    }
-    const double zd = (double)wave_sum_f(z);
-    if (l == 0) sm.zred[w] = zd;
-    __syncthreads();
-    if (I != J) {
-      float4 s4 = sm.colbuf[0][t];
-#pragma unroll
-      for (int g = 1; g < 16; ++g) {
-        const float4 v = sm.colbuf[g][t];
-        s4.x += v.x;
-        s4.y += v.y;
-        s4.z += v.z;
-        s4.w += v.w;
-      }
-      prep[cslot] = make_float2(s4.z, s4.w);
-      patt[cslot] = make_float2(s4.x, s4.y);
-    }
-  }
-  if (t == 0)
-    zpart[tile] = (sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (I == J ? 1.0 : 2.0);
+  const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
+  if (nz[tile])
+    full_tile_body(c, yc, P, part, nb, zpart, tile, sm);
+  else
+    zero_tile_body(c, yc, part, zpart, tile, sm);
 }
 
-__global__ __launch_bounds__(256, 2) void k_force(const float4 *__restrict__ P,
-                                                  const float2 *__restrict__ Y, int64_t n,
-                                                  int32_t nb, float4 *__restrict__ part,
-                                                  double *__restrict__ zpart,
-                                                  const uint8_t *__restrict__ nz,
-                                                  const int2 *__restrict__ tmap, Hdr *h) {
+// Force kernels of a single problem, one per kind of tile, over the tile
+// lists built after the pack (zero tiles in ascending order at the front of
+// the list, then the nonzero tiles). They write disjoint slots and may run
+// concurrently. The all-zero kernel runs one tile per workgroup (launched
+// over every tile; workgroups past the count exit at once) with four
+// workgroups per CU; the full kernel is persistent.
+__global__ __launch_bounds__(256, 4) void k_force_zero(const float2 *__restrict__ Y, int64_t n,
+                                                       int32_t nb, float4 *__restrict__ part,
+                                                       double *__restrict__ zpart,
+                                                       const int32_t *__restrict__ tlist,
+                                                       const int32_t *__restrict__ tcount,
+                                                       const int2 *__restrict__ tmap, Hdr *h) {
+  __shared__ ZeroSmem sm;
+  // the header check comes first: with a workspace for another n, the lists
+  // are not where this layout puts them
+  if (!state_ok(h, n)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    return;
+  }
+  if ((int32_t)blockIdx.x >= tcount[0]) return;
+  const int64_t tile = tlist[blockIdx.x];
+  float2 yc[16];
+  const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
+  zero_tile_body(c, yc, part, zpart, tile, sm);
+}
+
+__global__ __launch_bounds__(256, 2) void k_force_full(const float4 *__restrict__ P,
+                                                       const float2 *__restrict__ Y, int64_t n,
+                                                       int32_t nb, float4 *__restrict__ part,
+                                                       double *__restrict__ zpart,
+                                                       const int32_t *__restrict__ tlist,
+                                                       const int32_t *__restrict__ tcount,
+                                                       const int2 *__restrict__ tmap, Hdr *h) {
   __shared__ ForceSmem sm;
-  force_wg(P, Y, n, nb, part, zpart, nz, tmap, h, blockIdx.x, sm);
+  if (!state_ok(h, n)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    return;
+  }
+  const int32_t count = tcount[1], first = tcount[0];
+  for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const int64_t tile = tlist[first + i];
+    float2 yc[16];
+    const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
+    full_tile_body(c, yc, P, part, nb, zpart, tile, sm);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -834,16 +923,60 @@ __global__ __launch_bounds__(1024) void k_cost_reduce(const double2 *__restrict_
 // ----------------------------------------------------------------------------
 // Host-side sequencing
 // ----------------------------------------------------------------------------
+// A second stream per device for the all-zero-tile kernel, forked from and
+// joined back into the caller's stream with events, so that the two force
+// kernels share the GPU (the nonzero-tile one is bound by its P stream, the
+// all-zero one by the vector ALUs). Default priority. The enqueue sequence is
+// serialised by a mutex, so concurrent callers never interleave on the
+// shared events.
+namespace {
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+SideStream g_side[64];
+
+hipError_t side_stream(SideStream *&out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  SideStream &ss = g_side[dev];
+  if (!ss.s) {
+    if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  out = &ss;
+  return hipSuccess;
+}
+}  // namespace
+
 hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
                      at<const int32_t>(ws, L.perm), L.n, yp);
-  hipLaunchKernelGGL(k_force, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P),
-                     yp, L.n, L.nb, at<float4>(ws, L.part),
-                     at<double>(ws, L.zpart), at<const uint8_t>(ws, L.nz),
-                     at<const int2>(ws, L.tmap), h);
-  return hipGetLastError();
+  const int32_t *tl = at<const int32_t>(ws, L.tlist), *tc = at<const int32_t>(ws, L.tcount);
+  const int2 *tm = at<const int2>(ws, L.tmap);
+  float4 *part = at<float4>(ws, L.part);
+  double *zp = at<double>(ws, L.zpart);
+  const unsigned full_grid = (unsigned)(L.nt < kFullGrid ? L.nt : kFullGrid);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStream *ss = nullptr;
+  hipError_t e = side_stream(ss);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(ss->fork, st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_force_zero, dim3((unsigned)L.nt), dim3(256), 0, ss->s, (const float2 *)yp,
+                     L.n, L.nb, part, zp, tl, tc, tm, h);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_force_full, dim3(full_grid), dim3(256), 0, st, at<const float4>(ws, L.P),
+                     (const float2 *)yp, L.n, L.nb, part, zp, tl, tc, tm, h);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipStreamWaitEvent(st, ss->join, 0);
 }
 
 hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
