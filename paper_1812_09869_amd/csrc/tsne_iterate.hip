@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_gather_y(const float2 *__restrict__ Y,
 }
 
 // LDS of the all-zero-tile kernel: no P ring, so four workgroups fit a CU.
-constexpr int64_t kFullGrid = 256;  // persistent workgroups of the nonzero-tile kernel
+constexpr int64_t kFullGrid = 512;  // persistent workgroups of the nonzero-tile kernel (at most)
 
 struct ZeroSmem {
   float2 colbuf2[16][T + 4];
@@ -476,7 +476,11 @@ __global__ __launch_bounds__(256, 2) void k_force_full(const float4 *__restrict_
     return;
   }
   const int32_t count = tcount[1], first = tcount[0];
-  for (int32_t i = blockIdx.x; i < count; i += gridDim.x) {
+  // one workgroup per CU leaves room for the all-zero kernel beside it; when
+  // most tiles hold P, two per CU keep enough of P in flight
+  const int32_t active = (int32_t)min((int64_t)gridDim.x, count > first ? kFullGrid : kFullGrid / 2);
+  if ((int32_t)blockIdx.x >= active) return;
+  for (int32_t i = blockIdx.x; i < count; i += active) {
     const int64_t tile = tlist[first + i];
     float2 yc[16];
     const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
