@@ -127,7 +127,7 @@ def force_roofline(ws, n, force_ms):
     p_bytes = 4.0 * pairs_nz
     traffic = measured_traffic(n)
     return {
-        "kernel": "k_force",
+        "kernel": "force pass: k_force_full (tiles with P) concurrent with k_force_zero (all-zero tiles)",
         "bound": "alu",
         "achieved": achieved,
         "peak": PEAK_FP32_VALU_TFLOPS,
