@@ -972,14 +972,14 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
   hipError_t e = side_stream(ss);
   if (e != hipSuccess) return e;
   if ((e = hipEventRecord(ss->fork, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_force_full, dim3(full_grid), dim3(256), 0, st, at<const float4>(ws, L.P),
+                     (const float2 *)yp, L.n, L.nb, part, zp, tl, tc, tm, h);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_force_zero, dim3((unsigned)L.nt), dim3(256), 0, ss->s, (const float2 *)yp,
                      L.n, L.nb, part, zp, tl, tc, tm, h);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_force_full, dim3(full_grid), dim3(256), 0, st, at<const float4>(ws, L.P),
-                     (const float2 *)yp, L.n, L.nb, part, zp, tl, tc, tm, h);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipStreamWaitEvent(st, ss->join, 0);
 }
 
