@@ -317,7 +317,7 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.U = reinterpret_cast<float2 *>(problems[p].u);
     e.G = reinterpret_cast<float2 *>(problems[p].g);
     e.part = tsne::at<float4>(ws, L.part);
-    e.zpart = tsne::at<double>(ws, L.zpart);
+    e.zpart = tsne::at<float>(ws, L.zpart);
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
     e.slots = tsne::at<const int32_t>(ws, L.slots);

@@ -98,7 +98,7 @@ struct BatchEntry {
   const float4 *P;
   float2 *Y, *U, *G;
   float4 *part;
-  double *zpart;
+  float *zpart;
   double2 *meanpart;
   const uint8_t *nz;
   const int32_t *slots, *nslots;

@@ -313,7 +313,7 @@ __device__ __forceinline__ TileCtx tile_begin(const float2 *__restrict__ Y, int6
 template <class Smem>
 __device__ __forceinline__ void zero_tile_body(const TileCtx &c, const float2 (&yc)[16],
                                                float4 *__restrict__ part,
-                                               double *__restrict__ zpart, int64_t tile,
+                                               float *__restrict__ zpart, int64_t tile,
                                                Smem &sm) {
   float2 *prep = part_rep(part);
   float z = 0.f;
@@ -353,7 +353,8 @@ __device__ __forceinline__ void zero_tile_body(const TileCtx &c, const float2 (&
     prep[c.cslot] = s2;
   }
   if (c.t == 0)
-    zpart[tile] = (sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (c.I == c.J ? 1.0 : 2.0);
+    zpart[tile] =
+        (float)((sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (c.I == c.J ? 1.0 : 2.0));
 }
 
 // A tile with nonzero P: attraction and repulsion, P streamed through the
@@ -361,7 +362,7 @@ __device__ __forceinline__ void zero_tile_body(const TileCtx &c, const float2 (&
 __device__ __forceinline__ void full_tile_body(const TileCtx &c, const float2 (&yc)[16],
                                                const float4 *__restrict__ P,
                                                float4 *__restrict__ part, int32_t nb,
-                                               double *__restrict__ zpart, int64_t tile,
+                                               float *__restrict__ zpart, int64_t tile,
                                                ForceSmem &sm) {
   float2 *prep = part_rep(part), *patt = part_att(part, nb);
   float z = 0.f;
@@ -414,14 +415,15 @@ __device__ __forceinline__ void full_tile_body(const TileCtx &c, const float2 (&
     patt[c.cslot] = make_float2(s4.x, s4.y);
   }
   if (c.t == 0)
-    zpart[tile] = (sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (c.I == c.J ? 1.0 : 2.0);
+    zpart[tile] =
+        (float)((sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (c.I == c.J ? 1.0 : 2.0));
 }
 
 // One workgroup's share of a mixed force pass: tile number `tile` of a
 // problem, either body by its flag (the batched iteration).
 __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
                                          const float2 *__restrict__ Y, int64_t n, int32_t nb,
-                                         float4 *__restrict__ part, double *__restrict__ zpart,
+                                         float4 *__restrict__ part, float *__restrict__ zpart,
                                          const uint8_t *__restrict__ nz,
                                          const int2 *__restrict__ tmap, Hdr *h, int64_t tile,
                                          ForceSmem &sm) {
@@ -445,7 +447,7 @@ __device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
 // workgroups per CU; the full kernel is persistent.
 __global__ __launch_bounds__(256, 4) void k_force_zero(const float2 *__restrict__ Y, int64_t n,
                                                        int32_t nb, float4 *__restrict__ part,
-                                                       double *__restrict__ zpart,
+                                                       float *__restrict__ zpart,
                                                        const int32_t *__restrict__ tlist,
                                                        const int32_t *__restrict__ tcount,
                                                        const int2 *__restrict__ tmap, Hdr *h) {
@@ -466,7 +468,7 @@ __global__ __launch_bounds__(256, 4) void k_force_zero(const float2 *__restrict_
 __global__ __launch_bounds__(256, 2) void k_force_full(const float4 *__restrict__ P,
                                                        const float2 *__restrict__ Y, int64_t n,
                                                        int32_t nb, float4 *__restrict__ part,
-                                                       double *__restrict__ zpart,
+                                                       float *__restrict__ zpart,
                                                        const int32_t *__restrict__ tlist,
                                                        const int32_t *__restrict__ tcount,
                                                        const int2 *__restrict__ tmap, Hdr *h) {
@@ -510,9 +512,10 @@ struct UpdSmem {
   int32_t slots[kSlotLds];
 };
 
-// Z = sum of the tile partials: four strided sums per thread (loads in
-// flight), the wave sums, then the 16 wave results in order.
-__device__ inline double z_total(const double *__restrict__ zpart, int64_t nt, UpdSmem &sm) {
+// Z = sum of the tile partials (FP32 per tile, FP64 sums): four strided
+// sums per thread (loads in flight), the wave sums, then the 16 wave results
+// in order.
+__device__ inline double z_total(const float *__restrict__ zpart, int64_t nt, UpdSmem &sm) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int64_t q = threadIdx.x;
   for (; q + 3 * kUpd < nt; q += 4 * kUpd) {
@@ -587,7 +590,7 @@ __device__ inline float2 gradient_of(double4 s, double alpha, double Z) {
 __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
                                           const int32_t *__restrict__ slots,
                                           const int32_t *__restrict__ nslots,
-                                          const double *__restrict__ zpart, int64_t nt,
+                                          const float *__restrict__ zpart, int64_t nt,
                                           int64_t n, int32_t nb, const int32_t *__restrict__ perm,
                                           float2 *__restrict__ Y, float2 *__restrict__ U,
                                           float2 *__restrict__ G, float alpha, float mu, float eta,
@@ -648,7 +651,7 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
 
 __global__ __launch_bounds__(kUpd) void k_update(
     const float4 *__restrict__ part, const int32_t *__restrict__ slots,
-    const int32_t *__restrict__ nslots, const double *__restrict__ zpart, int64_t nt, int64_t n,
+    const int32_t *__restrict__ nslots, const float *__restrict__ zpart, int64_t nt, int64_t n,
     int32_t nb, const int32_t *__restrict__ perm, float2 *__restrict__ Y, float2 *__restrict__ U,
     float2 *__restrict__ G, float alpha, float mu, float eta, float min_gain,
     float2 *__restrict__ grad_out, double *__restrict__ z_out, double2 *__restrict__ meanpart,
@@ -777,7 +780,7 @@ __global__ __launch_bounds__(256) void k_recentre_batched(const BatchHdr *__rest
 
 __global__ __launch_bounds__(kUpd) void k_grad_only(
     const float4 *__restrict__ part, const int32_t *__restrict__ slots,
-    const int32_t *__restrict__ nslots, const double *__restrict__ zpart, int64_t nt, int64_t n,
+    const int32_t *__restrict__ nslots, const float *__restrict__ zpart, int64_t nt, int64_t n,
     int32_t nb, const int32_t *__restrict__ perm, float alpha, float2 *__restrict__ grad_out,
     double *__restrict__ z_out, Hdr *h) {
   __shared__ UpdSmem sm;
@@ -965,7 +968,7 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
   const int32_t *tl = at<const int32_t>(ws, L.tlist), *tc = at<const int32_t>(ws, L.tcount);
   const int2 *tm = at<const int2>(ws, L.tmap);
   float4 *part = at<float4>(ws, L.part);
-  double *zp = at<double>(ws, L.zpart);
+  float *zp = at<float>(ws, L.zpart);
   const unsigned full_grid = (unsigned)(L.nt < kFullGrid ? L.nt : kFullGrid);
   std::lock_guard<std::mutex> lock(g_side_mu);
   SideStream *ss = nullptr;
@@ -990,7 +993,7 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
   double2 *mp = at<double2>(ws, L.meanpart);
   hipLaunchKernelGGL(k_update, dim3((unsigned)(L.nb * kUpdPerBlock)), dim3(kUpd), 0, st,
                      at<const float4>(ws, L.part), at<const int32_t>(ws, L.slots),
-                     at<const int32_t>(ws, L.nslots), at<const double>(ws, L.zpart), L.nt, L.n,
+                     at<const int32_t>(ws, L.nslots), at<const float>(ws, L.zpart), L.nt, L.n,
                      L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y),
                      reinterpret_cast<float2 *>(u), reinterpret_cast<float2 *>(g), alpha, mu, eta,
                      min_gain, reinterpret_cast<float2 *>(grad_out), z_out, mp, h);
@@ -1005,7 +1008,7 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_grad_only, dim3((unsigned)(L.nb * kUpdPerBlock)), dim3(kUpd), 0, st,
                      at<const float4>(ws, L.part), at<const int32_t>(ws, L.slots),
-                     at<const int32_t>(ws, L.nslots), at<const double>(ws, L.zpart), L.nt, L.n,
+                     at<const int32_t>(ws, L.nslots), at<const float>(ws, L.zpart), L.nt, L.n,
                      L.nb, at<const int32_t>(ws, L.perm), alpha,
                      reinterpret_cast<float2 *>(grad_out), z_out, h);
   return hipGetLastError();
