@@ -111,34 +111,36 @@ __global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int
 // in accumulator element r (rows interleaved by 4, unlike the FP32/BF16
 // 16x16 variants, whose element r holds row 4(l/16) + r). X is stored transposed (k-major), so the 16
 // lanes that share a k read 16 consecutive doubles. A wave computes a
-// 64 x 64 block (4 x 4 MFMA tiles); a workgroup of 4 waves covers 64 rows x
-// 256 columns.
+// 64 x 16 kDistCT block (4 x kDistCT MFMA tiles, small enough for two waves
+// per SIMD); a workgroup of 4 waves covers 64 rows x 64 kDistCT columns.
 // ----------------------------------------------------------------------------
+constexpr int kDistCT = 2;  // 16-column MFMA tiles per wave (a wave covers 64 x 16 kDistCT)
+
 __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
                                                   const double *__restrict__ norms, int64_t npad,
                                                   int32_t dpad, int32_t b,
                                                   float *__restrict__ dblock) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  const int64_t col0 = (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
-  v4d acc[4][4];
+  v4d acc[4][kDistCT];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < kDistCT; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < dpad; k0 += 4) {
     const double *xk = xcT + (int64_t)(k0 + lk) * npad;
-    double av[4], bv[4];
+    double av[4], bv[kDistCT];
 #pragma unroll
     for (int a = 0; a < 4; ++a) av[a] = xk[row0 + a * 16 + li];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) bv[c] = xk[col0 + c * 16 + li];
+    for (int c = 0; c < kDistCT; ++c) bv[c] = xk[col0 + c * 16 + li];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
+      for (int c = 0; c < kDistCT; ++c)
         acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
   }
 #pragma unroll
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT
       const int il = row0_loc + a * 16 + lk + 4 * r;
       const double ni = norms[(int64_t)b * T + il];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < kDistCT; ++c) {
         const int64_t j = col0 + c * 16 + li;
         double dd = ni + norms[j] - 2.0 * acc[a][c][r];
         dblock[(int64_t)il * npad + j] = (float)fmax(dd, 0.0);
@@ -1136,8 +1138,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
                            norms32, L.npad, L.kk, b, dblock, h);
         break;
       default:
-        hipLaunchKernelGGL(k_dist_f64, dgrid, dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b,
-                           dblock);
+        hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64),
+                           dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b, dblock);
     }
   };
   auto calibrate = [&](int b) {
