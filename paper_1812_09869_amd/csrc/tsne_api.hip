@@ -322,6 +322,8 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
     e.slots = tsne::at<const int32_t>(ws, L.slots);
     e.tmap = tsne::at<const int2>(ws, L.tmap);
+    e.tlist = tsne::at<const int32_t>(ws, L.tlist);
+    e.tcount = tsne::at<const int32_t>(ws, L.tcount);
     e.nslots = tsne::at<const int32_t>(ws, L.nslots);
     e.perm = tsne::at<const int32_t>(ws, L.perm);
     e.yp = tsne::at<float2>(ws, L.yp);

@@ -103,6 +103,7 @@ struct BatchEntry {
   const uint8_t *nz;
   const int32_t *slots, *nslots;
   const int2 *tmap;
+  const int32_t *tlist, *tcount;
   const int32_t *perm;
   float2 *yp;  // positions in the internal order (refreshed by every force pass)
   Hdr *h;

@@ -419,26 +419,6 @@ __device__ __forceinline__ void full_tile_body(const TileCtx &c, const float2 (&
         (float)((sm.zred[0] + sm.zred[1] + sm.zred[2] + sm.zred[3]) * (c.I == c.J ? 1.0 : 2.0));
 }
 
-// One workgroup's share of a mixed force pass: tile number `tile` of a
-// problem, either body by its flag (the batched iteration).
-__device__ __forceinline__ void force_wg(const float4 *__restrict__ P,
-                                         const float2 *__restrict__ Y, int64_t n, int32_t nb,
-                                         float4 *__restrict__ part, float *__restrict__ zpart,
-                                         const uint8_t *__restrict__ nz,
-                                         const int2 *__restrict__ tmap, Hdr *h, int64_t tile,
-                                         ForceSmem &sm) {
-  if (!state_ok(h, n)) {
-    if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
-    return;
-  }
-  float2 yc[16];
-  const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
-  if (nz[tile])
-    full_tile_body(c, yc, P, part, nb, zpart, tile, sm);
-  else
-    zero_tile_body(c, yc, part, zpart, tile, sm);
-}
-
 // Force kernels of a single problem, one per kind of tile, over the tile
 // lists built after the pack (zero tiles in ascending order at the front of
 // the list, then the nonzero tiles). They write disjoint slots and may run
@@ -723,17 +703,46 @@ __device__ inline const BatchEntry *batch_table(const BatchHdr *bh) {
                                               kBatchHdrBytes);
 }
 
-__global__ __launch_bounds__(256, 2) void k_force_batched(const BatchHdr *__restrict__ bh,
-                                                          int count, int64_t tiles,
-                                                          int64_t blocks) {
+// Force kernels of the batch: launched over every tile of every problem
+// (the problem found by binary search on its first tile); a workgroup whose
+// position within its problem is past the count of its kind exits at once.
+__global__ __launch_bounds__(256, 4) void k_force_zero_batched(const BatchHdr *__restrict__ bh,
+                                                               int count, int64_t tiles,
+                                                               int64_t blocks) {
+  __shared__ ZeroSmem sm;
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry *tab = batch_table(bh);
+  const int p = find_entry(tab, count, blockIdx.x, true);
+  const BatchEntry &e = tab[p];
+  const int64_t i = (int64_t)blockIdx.x - e.tile0;
+  if (i < 0 || i >= e.nt) return;
+  if (!state_ok(e.h, e.n)) {
+    if (i == 0 && threadIdx.x == 0) flag_error(e.h, kErrState);
+    return;
+  }
+  if (i >= e.tcount[0]) return;
+  const int64_t tile = e.tlist[i];
+  float2 yc[16];
+  const TileCtx c = tile_begin(e.yp, e.n, e.nb, e.tmap, tile, yc, sm);
+  zero_tile_body(c, yc, e.part, e.zpart, tile, sm);
+}
+
+__global__ __launch_bounds__(256, 2) void k_force_full_batched(const BatchHdr *__restrict__ bh,
+                                                               int count, int64_t tiles,
+                                                               int64_t blocks) {
   __shared__ ForceSmem sm;
   if (!batch_ok(bh, count, tiles, blocks)) return;
   const BatchEntry *tab = batch_table(bh);
   const int p = find_entry(tab, count, blockIdx.x, true);
   const BatchEntry &e = tab[p];
-  const int64_t tile = (int64_t)blockIdx.x - e.tile0;
-  if (tile < 0 || tile >= e.nt) return;
-  force_wg(e.P, e.yp, e.n, e.nb, e.part, e.zpart, e.nz, e.tmap, e.h, tile, sm);
+  const int64_t i = (int64_t)blockIdx.x - e.tile0;
+  if (i < 0 || i >= e.nt) return;
+  if (!state_ok(e.h, e.n)) return;
+  if (i >= e.tcount[1]) return;
+  const int64_t tile = e.tlist[e.tcount[0] + i];
+  float2 yc[16];
+  const TileCtx c = tile_begin(e.yp, e.n, e.nb, e.tmap, tile, yc, sm);
+  full_tile_body(c, yc, e.P, e.part, e.nb, e.zpart, tile, sm);
 }
 
 __global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restrict__ bh,
@@ -1032,8 +1041,22 @@ hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tile
   const BatchHdr *bh = reinterpret_cast<const BatchHdr *>(batch_ws);
   hipLaunchKernelGGL(k_gather_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh, count,
                      total_tiles, total_blocks);
-  hipLaunchKernelGGL(k_force_batched, dim3((unsigned)total_tiles), dim3(256), 0, st, bh, count,
-                     total_tiles, total_blocks);
+  {
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    SideStream *ss = nullptr;
+    hipError_t e = side_stream(ss);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventRecord(ss->fork, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_force_full_batched, dim3((unsigned)total_tiles), dim3(256), 0, st, bh,
+                       count, total_tiles, total_blocks);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_force_zero_batched, dim3((unsigned)total_tiles), dim3(256), 0, ss->s, bh,
+                       count, total_tiles, total_blocks);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, ss->join, 0)) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_update_batched, dim3((unsigned)(total_blocks * kUpdPerBlock)), dim3(kUpd),
                      0, st, bh, count,
                      total_tiles, total_blocks, alpha, mu, eta, min_gain);
