@@ -83,13 +83,27 @@ typedef struct {
   int32_t reserved;   /* must be 0 */
 } tsne_aff_opts;
 
+/* Learning-rate rules of an update. */
+typedef enum {
+  /* the given learning_rate, scaled per coordinate by adaptive gains (the
+   * conventional t-SNE schedule of Eq. 10 and the paragraph after it) */
+  TSNE_LR_GAINS = 0,
+  /* the paper's own rule (Eq. 11, section "Internal parametric
+   * configuration"): eta = ln(n - 1) (Y_max - Y_min) / 2, where
+   * Y_max - Y_min is the larger of the two coordinate ranges of the map the
+   * gradient is taken at; no gains (g is neither read nor written and may be
+   * NULL), learning_rate and min_gain are ignored */
+  TSNE_LR_RANGE = 1
+} tsne_lr_rule;
+
 /* Parameters of one update (Eq. 10 and the paragraph after it). */
 typedef struct {
   float exaggeration;  /* alpha: multiplies p_ij in the gradient (early exaggeration) */
   float momentum;      /* mu */
-  float learning_rate; /* eta */
-  float min_gain;      /* floor of the adaptive gains */
+  float learning_rate; /* eta (TSNE_LR_GAINS) */
+  float min_gain;      /* floor of the adaptive gains (TSNE_LR_GAINS) */
   int32_t recentre;    /* nonzero: subtract the mean of the map after the update */
+  int32_t lr_rule;     /* tsne_lr_rule; anything else is TSNE_E_ARG */
 } tsne_step_params;
 
 /* Bytes of workspace for n points in d dimensions with the given distance
@@ -117,6 +131,9 @@ TSNE_API int tsne_affinities(const float *x, int64_t n, int32_t d, double perple
  *   g <- (grad > 0) != (u > 0) ? g + 0.2 : 0.8 g;  g <- max(g, min_gain)
  *   u <- momentum u - learning_rate g grad;  y <- y + u           (Eq. 10)
  *   y <- y - mean(y) if recentre.
+ * With lr_rule TSNE_LR_RANGE the gains step is skipped and
+ *   u <- momentum u - eta grad,  eta = ln(n - 1) (Y_max - Y_min) / 2 (Eq. 11)
+ * at the map y passed in.
  * grad_out (nullable, n x 2 FP32) receives the gradient; z_out (nullable,
  * device double) receives Z. Requires a workspace filled by
  * tsne_affinities for the same n. Z and all row sums are reduced in FP64 in

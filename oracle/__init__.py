@@ -57,6 +57,10 @@ def _load():
         "orc_cost": (None, [_f64p, _i64, _f64p, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
         "orc_step": (None, [_f64p, _i64, _f64p, _f64p, _f64p, _d, _d, _d, _d, ctypes.c_int,
                             ctypes.c_void_p, ctypes.c_void_p]),
+        "orc_adaptive_eta": (_d, [_f64p, _i64]),
+        "orc_embedding_size": (_d, [_f64p, _i64]),
+        "orc_step_range": (None, [_f64p, _i64, _f64p, _f64p, _d, _d, ctypes.c_int,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "orc_knn_overlap": (_d, [_f64p, _i64, _i32, _f64p, _i64p, _i64, ctypes.c_int]),
         "orc_mlp_param_count": (_i64, [ctypes.c_int, ctypes.c_int]),
         "orc_bf16_round": (None, [_f64p, _i64, _f64p]),
@@ -240,6 +244,34 @@ def run(P, y0, iters: int, start: int = 0, state=None, sched=schedule):
     for t in range(start, start + iters):
         step(P, y, u, gains, sched(t))
     return y, u, gains
+
+
+def adaptive_eta(y) -> float:
+    """Eq. 11: ln(n - 1) (Y_max - Y_min) / 2, Y_max - Y_min the larger coordinate range."""
+    y = _f64(y)
+    return _load().orc_adaptive_eta(y, y.shape[0])
+
+
+def embedding_size(y) -> float:
+    """Diagonal of the box spanned by the map (the embedding-size monitor)."""
+    y = _f64(y)
+    return _load().orc_embedding_size(y, y.shape[0])
+
+
+def step_range(P, y, u, mu: float, alpha: float = 1.0, recentre: bool = True,
+               want_grad: bool = False):
+    """One update of (Y, U) in place with the paper's optimiser (Eqs. 10-11,
+    descent reading, no gains); returns (g, Z, eta)."""
+    for a in (y, u):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    n = y.shape[0]
+    g = np.empty_like(y) if want_grad else None
+    zz, ee = _d(), _d()
+    _load().orc_step_range(_f64(P), n, y, u, float(alpha), float(mu), int(recentre),
+                           g.ctypes.data_as(ctypes.c_void_p) if g is not None else None,
+                           ctypes.cast(ctypes.pointer(zz), ctypes.c_void_p),
+                           ctypes.cast(ctypes.pointer(ee), ctypes.c_void_p))
+    return g, zz.value, ee.value
 
 
 def knn_overlap(x, y, rows, k: int = 10) -> float:

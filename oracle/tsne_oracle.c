@@ -24,6 +24,9 @@
  *   - mapping update with momentum, learning rate,
  *     adaptive gains and early exaggeration         (Eq. 10 and the paragraph
  *     after it, section "Internal parametric configuration")
+ *   - the paper's own learning rate from the extent
+ *     of the map, and the embedding size            (Eq. 11; section
+ *     "Comparison of t-SNE and ptSNE" for the size as the diagonal)
  *
  * Readings of points where the paper is silent or garbled:
  *   - entropy in nats; the target is ln(perplexity), identical to Eq. 2's
@@ -35,7 +38,10 @@
  *     plus sign in front of the gradient term);
  *   - gains: +0.2 where sign(g) differs from sign(U), x0.8 otherwise, floor
  *     min_gain; (g > 0) is compared with (U > 0);
- *   - the map is re-centred to zero mean after every update.
+ *   - the map is re-centred to zero mean after every update (optional);
+ *   - Eq. 11's Y_max - Y_min is the larger of the two coordinate ranges of
+ *     the map the gradient is taken at, ln is the natural logarithm, and the
+ *     rule replaces the gains (eta is the only internal parameter).
  *
  * Parallel loops run over rows with OpenMP; every reduction is written into a
  * per-row array first and summed afterwards in row order, so results do not
@@ -367,6 +373,71 @@ ORC_API void orc_step(const double *P, int64_t n, double *Y, double *U, double *
   }
   if (g_out) memcpy(g_out, g, (size_t)n * 2 * sizeof(double));
   if (Z_out) *Z_out = Z;
+  free(g);
+}
+
+/* Extent of a 2-D map: range of each coordinate, max_i y_ic - min_i y_ic. */
+static void map_ranges(const double *Y, int64_t n, double *rx, double *ry) {
+  double lox = Y[0], hix = Y[0], loy = Y[1], hiy = Y[1];
+  for (int64_t i = 1; i < n; ++i) {
+    if (Y[2 * i] < lox) lox = Y[2 * i];
+    if (Y[2 * i] > hix) hix = Y[2 * i];
+    if (Y[2 * i + 1] < loy) loy = Y[2 * i + 1];
+    if (Y[2 * i + 1] > hiy) hiy = Y[2 * i + 1];
+  }
+  *rx = hix - lox;
+  *ry = hiy - loy;
+}
+
+/* Learning rate of Eq. 11: eta = ln(n - 1) * (Y_max - Y_min) / 2, with
+ * Y_max - Y_min the larger coordinate range of the map. */
+ORC_API double orc_adaptive_eta(const double *Y, int64_t n) {
+  double rx, ry;
+  map_ranges(Y, n, &rx, &ry);
+  return log((double)n - 1.0) * (rx > ry ? rx : ry) / 2.0;
+}
+
+/* Embedding size: length of the diagonal of the box spanned by the map. */
+ORC_API double orc_embedding_size(const double *Y, int64_t n) {
+  double rx, ry;
+  map_ranges(Y, n, &rx, &ry);
+  return sqrt(rx * rx + ry * ry);
+}
+
+/*
+ * One iteration with the paper's own optimiser (Eqs. 10 and 11, descent
+ * reading, no gains):
+ *   g = gradient(P, Y, alpha);  eta = orc_adaptive_eta(Y) at the same Y
+ *   U <- mu U - eta g;  Y <- Y + U;  Y <- Y - mean(Y) if recentre
+ * Optionally returns g, Z and eta.
+ */
+ORC_API void orc_step_range(const double *P, int64_t n, double *Y, double *U, double alpha,
+                            double mu, int recentre, double *g_out, double *Z_out,
+                            double *eta_out) {
+  double *g = (double *)malloc((size_t)n * 2 * sizeof(double));
+  double Z = 0.0;
+  orc_gradient(P, n, Y, alpha, g, &Z);
+  const double eta = orc_adaptive_eta(Y, n);
+  for (int64_t k = 0; k < 2 * n; ++k) {
+    U[k] = mu * U[k] - eta * g[k];
+    Y[k] += U[k];
+  }
+  if (recentre) {
+    double mx = 0.0, my = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      mx += Y[2 * i];
+      my += Y[2 * i + 1];
+    }
+    mx /= (double)n;
+    my /= (double)n;
+    for (int64_t i = 0; i < n; ++i) {
+      Y[2 * i] -= mx;
+      Y[2 * i + 1] -= my;
+    }
+  }
+  if (g_out) memcpy(g_out, g, (size_t)n * 2 * sizeof(double));
+  if (Z_out) *Z_out = Z;
+  if (eta_out) *eta_out = eta;
   free(g);
 }
 

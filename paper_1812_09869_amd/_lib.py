@@ -74,7 +74,7 @@ class BatchProblem(ctypes.Structure):
 class StepParams(ctypes.Structure):
     _fields_ = [("exaggeration", ctypes.c_float), ("momentum", ctypes.c_float),
                 ("learning_rate", ctypes.c_float), ("min_gain", ctypes.c_float),
-                ("recentre", ctypes.c_int32)]
+                ("recentre", ctypes.c_int32), ("lr_rule", ctypes.c_int32)]
 
 
 _lib = None
@@ -177,9 +177,19 @@ def affinities(x: torch.Tensor, perplexity: float, ws: torch.Tensor, dist_mode="
                                   ws.numel(), _stream()))
 
 
+LR_RULES = {"gains": 0, "range": 1}
+
+
+def _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule):
+    rule = LR_RULES[lr_rule] if isinstance(lr_rule, str) else int(lr_rule)
+    return StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0, rule)
+
+
 def step(ws, n, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True,
-         grad_out=None, z_out=None):
-    prm = StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0)
+         grad_out=None, z_out=None, lr_rule="gains"):
+    """One iteration. lr_rule "gains": fixed rate with adaptive gains; "range":
+    the rate of Eq. 11 from the map's extent, no gains (g may be None)."""
+    prm = _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule)
     sh = (n, 2)
     _check(load().tsne_step(_ptr(ws, torch.uint8, name="ws"), n, _ptr(y, shape=sh, name="y"),
                             _ptr(u, shape=sh, name="u"), _ptr(g, shape=sh, name="g"),
@@ -193,8 +203,8 @@ def forces(ws, n, y):
 
 
 def update(ws, n, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True,
-           grad_out=None, z_out=None):
-    prm = StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0)
+           grad_out=None, z_out=None, lr_rule="gains"):
+    prm = _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule)
     sh = (n, 2)
     _check(load().tsne_update(_ptr(ws, torch.uint8, name="ws"), n, _ptr(y, shape=sh, name="y"),
                               _ptr(u, shape=sh, name="u"), _ptr(g, shape=sh, name="g"),
@@ -320,7 +330,8 @@ def batch_plan(arr, device="cuda"):
     return bws
 
 
-def batch_step(arr, bws, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True):
-    prm = StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0)
+def batch_step(arr, bws, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True,
+               lr_rule="gains"):
+    prm = _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule)
     _check(load().tsne_batch_step(arr, len(arr), _ptr(bws, torch.uint8), ctypes.byref(prm),
                                   _stream()))

@@ -53,6 +53,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.perm = take(np * 4);
   L.inv = take(np * 4);
   L.yp = take(np * 8);
+  L.extent = take((size_t)L.nb * 16);
   L.iter_end = o;
   // affinity-stage scratch (only needed inside tsne_affinities)
   L.xmean = take((size_t)L.dpad * 8);
@@ -141,6 +142,15 @@ int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
                    "tsne_affinities");
 }
 
+static int check_params(const char *fn, const tsne_step_params *prm) {
+  if (!(prm->learning_rate >= 0.f) || !(prm->min_gain >= 0.f) || !isfinite(prm->momentum) ||
+      !isfinite(prm->exaggeration))
+    return fail(TSNE_E_ARG, "%s: invalid parameters", fn);
+  if (prm->lr_rule != TSNE_LR_GAINS && prm->lr_rule != TSNE_LR_RANGE)
+    return fail(TSNE_E_ARG, "%s: unknown lr_rule %d", fn, (int)prm->lr_rule);
+  return TSNE_OK;
+}
+
 static int check_iter_args(const char *fn, void *ws, int64_t n) {
   if (!ws) return fail(TSNE_E_ARG, "%s: null workspace", fn);
   if (!valid_n(n)) return fail(TSNE_E_ARG, "%s: n = %lld out of range", fn, (long long)n);
@@ -151,16 +161,15 @@ static int check_iter_args(const char *fn, void *ws, int64_t n) {
 int tsne_step(void *ws, int64_t n, float *y, float *u, float *g, const tsne_step_params *prm,
               float *grad_out, double *z_out, void *stream) {
   if (int rc = check_iter_args("tsne_step", ws, n)) return rc;
-  if (!y || !u || !g || !prm) return fail(TSNE_E_ARG, "tsne_step: null pointer");
-  if (!(prm->learning_rate >= 0.f) || !(prm->min_gain >= 0.f) || !isfinite(prm->momentum) ||
-      !isfinite(prm->exaggeration))
-    return fail(TSNE_E_ARG, "tsne_step: invalid parameters");
+  if (!y || !u || !prm || (!g && prm->lr_rule != TSNE_LR_RANGE))
+    return fail(TSNE_E_ARG, "tsne_step: null pointer");
+  if (int rc = check_params("tsne_step", prm)) return rc;
   const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = tsne::launch_force(L, ws, y, st);
   if (e == hipSuccess)
     e = tsne::launch_update(L, ws, y, u, g, prm->exaggeration, prm->momentum, prm->learning_rate,
-                            prm->min_gain, prm->recentre, grad_out, z_out, st);
+                            prm->min_gain, prm->recentre, prm->lr_rule, grad_out, z_out, st);
   return hip_check(e, "tsne_step");
 }
 
@@ -174,14 +183,13 @@ int tsne_forces(void *ws, int64_t n, const float *y, void *stream) {
 int tsne_update(void *ws, int64_t n, float *y, float *u, float *g, const tsne_step_params *prm,
                 float *grad_out, double *z_out, void *stream) {
   if (int rc = check_iter_args("tsne_update", ws, n)) return rc;
-  if (!y || !u || !g || !prm) return fail(TSNE_E_ARG, "tsne_update: null pointer");
-  if (!(prm->learning_rate >= 0.f) || !(prm->min_gain >= 0.f) || !isfinite(prm->momentum) ||
-      !isfinite(prm->exaggeration))
-    return fail(TSNE_E_ARG, "tsne_update: invalid parameters");
+  if (!y || !u || !prm || (!g && prm->lr_rule != TSNE_LR_RANGE))
+    return fail(TSNE_E_ARG, "tsne_update: null pointer");
+  if (int rc = check_params("tsne_update", prm)) return rc;
   const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
   return hip_check(tsne::launch_update(L, ws, y, u, g, prm->exaggeration, prm->momentum,
                                        prm->learning_rate, prm->min_gain, prm->recentre,
-                                       grad_out, z_out, (hipStream_t)stream),
+                                       prm->lr_rule, grad_out, z_out, (hipStream_t)stream),
                    "tsne_update");
 }
 
@@ -319,6 +327,7 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.part = tsne::at<float4>(ws, L.part);
     e.zpart = tsne::at<float>(ws, L.zpart);
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
+    e.extent = tsne::at<float4>(ws, L.extent);
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
     e.slots = tsne::at<const int32_t>(ws, L.slots);
     e.tmap = tsne::at<const int2>(ws, L.tmap);
@@ -348,12 +357,10 @@ int tsne_batch_step(const tsne_batch_problem *problems, int32_t count, const voi
   int64_t tiles, blocks;
   if (int rc = batch_totals("tsne_batch_step", problems, count, tiles, blocks)) return rc;
   if (!batch_ws || !prm) return fail(TSNE_E_ARG, "tsne_batch_step: null pointer");
-  if (!(prm->learning_rate >= 0.f) || !(prm->min_gain >= 0.f) || !isfinite(prm->momentum) ||
-      !isfinite(prm->exaggeration))
-    return fail(TSNE_E_ARG, "tsne_batch_step: invalid parameters");
+  if (int rc = check_params("tsne_batch_step", prm)) return rc;
   return hip_check(tsne::launch_batch_step(batch_ws, count, tiles, blocks, prm->exaggeration,
                                            prm->momentum, prm->learning_rate, prm->min_gain,
-                                           prm->recentre, (hipStream_t)stream),
+                                           prm->recentre, prm->lr_rule, (hipStream_t)stream),
                    "tsne_batch_step");
 }
 

@@ -66,6 +66,7 @@ struct Layout {
   size_t perm = 0;  // int32 [npad]: internal position -> caller's index
   size_t inv = 0;   // int32 [npad]: caller's index -> internal position
   size_t yp = 0;    // float2 [npad]: the map in the internal order (per force pass)
+  size_t extent = 0;  // float4 [nb]: per-block {min x, max x, min y, max y} of that map
   size_t iter_end = 0;  // end of the part that tsne_step needs
   int32_t kk = 0;  // K of the reduced-precision contraction (d rounded up, x3 for split modes)
   size_t xmean = 0, xcT = 0, norms = 0, dblock = 0;
@@ -100,6 +101,7 @@ struct BatchEntry {
   float4 *part;
   float *zpart;
   double2 *meanpart;
+  float4 *extent;
   const uint8_t *nz;
   const int32_t *slots, *nslots;
   const int2 *tmap;
@@ -133,15 +135,15 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
                              double tol_h, int reorder, void *ws, hipStream_t stream);
 hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t stream);
 hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
-                         float mu, float eta, float min_gain, int recentre, float *grad_out,
-                         double *z_out, hipStream_t stream);
+                         float mu, float eta, float min_gain, int recentre, int lr_rule,
+                         float *grad_out, double *z_out, hipStream_t stream);
 hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *grad_out,
                                 double *z_out, hipStream_t stream);
 hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out,
                        hipStream_t stream);
 hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tiles,
                              int64_t total_blocks, float alpha, float mu, float eta,
-                             float min_gain, int recentre, hipStream_t stream);
+                             float min_gain, int recentre, int lr_rule, hipStream_t stream);
 hipError_t launch_export_p_rows(const Layout &L, void *ws, int64_t row0, int64_t nrows,
                                 float *out, hipStream_t stream);
 hipError_t launch_export_scalars(const Layout &L, void *ws, double *out, hipStream_t stream);

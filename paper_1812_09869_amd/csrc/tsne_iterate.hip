@@ -252,16 +252,47 @@ __device__ __forceinline__ void tile_rows_zero(const float2 *yrow, const float2 
 
 // The map in the internal order, zero-padded to whole tiles (read by the
 // force and cost passes, so that their loads are contiguous).
+// Gathers the rows of block b into the internal order and writes the block's
+// extent of the map, {min x, max x, min y, max y}, for the adaptive learning
+// rate (exact: the order of min and max does not matter).
 __device__ __forceinline__ void gather_rows(const float2 *__restrict__ Y,
                                             const int32_t *__restrict__ perm, int64_t n,
-                                            float2 *__restrict__ Yp, int64_t r) {
-  Yp[r] = r < n ? Y[perm[r]] : make_float2(0.f, 0.f);
+                                            float2 *__restrict__ Yp, float4 *__restrict__ extent,
+                                            int64_t b) {
+  __shared__ float4 red[T / 64];
+  const int64_t r = b * T + threadIdx.x;
+  const bool ok = r < n;
+  const float2 v = ok ? Y[perm[r]] : make_float2(0.f, 0.f);
+  Yp[r] = v;
+  float lox = ok ? v.x : INFINITY, hix = ok ? v.x : -INFINITY;
+  float loy = ok ? v.y : INFINITY, hiy = ok ? v.y : -INFINITY;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lox = fminf(lox, __shfl_xor(lox, o));
+    hix = fmaxf(hix, __shfl_xor(hix, o));
+    loy = fminf(loy, __shfl_xor(loy, o));
+    hiy = fmaxf(hiy, __shfl_xor(hiy, o));
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_float4(lox, hix, loy, hiy);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float4 e = red[0];
+#pragma unroll
+    for (int w = 1; w < T / 64; ++w) {
+      e.x = fminf(e.x, red[w].x);
+      e.y = fmaxf(e.y, red[w].y);
+      e.z = fminf(e.z, red[w].z);
+      e.w = fmaxf(e.w, red[w].w);
+    }
+    extent[b] = e;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gather_y(const float2 *__restrict__ Y,
                                                   const int32_t *__restrict__ perm, int64_t n,
-                                                  float2 *__restrict__ Yp) {
-  gather_rows(Y, perm, n, Yp, (int64_t)blockIdx.x * T + threadIdx.x);
+                                                  float2 *__restrict__ Yp,
+                                                  float4 *__restrict__ extent) {
+  gather_rows(Y, perm, n, Yp, extent, blockIdx.x);
 }
 
 // LDS of the all-zero-tile kernel: no P ring, so four workgroups fit a CU.
@@ -489,6 +520,7 @@ struct UpdSmem {
   double4 part[kUpdSplit - 1][kUpdRows];
   double red[2][kUpd / 64];
   double z;
+  float eta;
   int32_t slots[kSlotLds];
 };
 
@@ -559,6 +591,34 @@ __device__ inline double4 row_sums(const float4 *__restrict__ part,
   return make_double4(ax, ay, rx, ry);
 }
 
+// The paper's learning rate (Eq. 11): eta = ln(n - 1) (Y_max - Y_min) / 2,
+// with Y_max - Y_min the larger of the two coordinate ranges of the map the
+// gradient is taken at (the extents its gather wrote per block). One wave
+// reduces the block extents; the result is published by the next barrier.
+__device__ inline void adaptive_eta(const float4 *__restrict__ extent, int32_t nb, int64_t n,
+                                    UpdSmem &sm) {
+  if (threadIdx.x >= 64) return;
+  float lox = INFINITY, hix = -INFINITY, loy = INFINITY, hiy = -INFINITY;
+  for (int b = threadIdx.x; b < nb; b += 64) {
+    const float4 e = extent[b];
+    lox = fminf(lox, e.x);
+    hix = fmaxf(hix, e.y);
+    loy = fminf(loy, e.z);
+    hiy = fmaxf(hiy, e.w);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lox = fminf(lox, __shfl_xor(lox, o));
+    hix = fmaxf(hix, __shfl_xor(hix, o));
+    loy = fminf(loy, __shfl_xor(loy, o));
+    hiy = fmaxf(hiy, __shfl_xor(hiy, o));
+  }
+  if (threadIdx.x == 0) {
+    const double range = fmax((double)hix - (double)lox, (double)hiy - (double)loy);
+    sm.eta = (float)(log((double)(n - 1)) * range * 0.5);
+  }
+}
+
 // g = 4 (alpha A - R / Z)
 __device__ inline float2 gradient_of(double4 s, double alpha, double Z) {
   return make_float2((float)(4.0 * (alpha * s.x - s.z / Z)), (float)(4.0 * (alpha * s.y - s.w / Z)));
@@ -567,6 +627,8 @@ __device__ inline float2 gradient_of(double4 s, double alpha, double Z) {
 // Update (Eq. 10, descent): gains, momentum, position; per-workgroup sums of
 // the new positions for the re-centring. Workgroup wg of the problem covers
 // rows (wg % kUpdPerBlock) * kUpdRows ... of block wg / kUpdPerBlock.
+// lr_rule 0: the given eta with adaptive gains; lr_rule 1: eta of Eq. 11 and
+// no gains (G is neither read nor written).
 __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
                                           const int32_t *__restrict__ slots,
                                           const int32_t *__restrict__ nslots,
@@ -574,16 +636,20 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
                                           int64_t n, int32_t nb, const int32_t *__restrict__ perm,
                                           float2 *__restrict__ Y, float2 *__restrict__ U,
                                           float2 *__restrict__ G, float alpha, float mu, float eta,
-                                          float min_gain, float2 *__restrict__ grad_out,
+                                          float min_gain, int lr_rule,
+                                          const float4 *__restrict__ extent,
+                                          float2 *__restrict__ grad_out,
                                           double *__restrict__ z_out,
                                           double2 *__restrict__ meanpart, Hdr *h, int wg,
                                           UpdSmem &sm) {
   if (!state_ok(h, n)) return;
+  if (lr_rule) adaptive_eta(extent, nb, n, sm);
   const int b = wg / kUpdPerBlock;
   const int t = threadIdx.x, q = t / kUpdRows;
   const int r = (wg % kUpdPerBlock) * kUpdRows + t % kUpdRows;  // row within the block
   const int64_t ir = (int64_t)b * T + r;                         // internal position
-  const double Z = z_total(zpart, nt, sm);
+  const double Z = z_total(zpart, nt, sm);  // its barriers also publish sm.eta
+  if (lr_rule) eta = sm.eta;
   if (wg == 0 && t == 0) {
     h->z = Z;
     if (z_out) *z_out = Z;
@@ -595,17 +661,23 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
   if (q == 0 && ir < n) {
     const int64_t i = perm[ir];
     if (grad_out) grad_out[i] = g;
-    float2 u = U[i], gn = G[i], y = Y[i];
-    gn.x = ((g.x > 0.f) != (u.x > 0.f)) ? gn.x + 0.2f : gn.x * 0.8f;
-    gn.y = ((g.y > 0.f) != (u.y > 0.f)) ? gn.y + 0.2f : gn.y * 0.8f;
-    gn.x = fmaxf(gn.x, min_gain);
-    gn.y = fmaxf(gn.y, min_gain);
-    u.x = mu * u.x - eta * (gn.x * g.x);
-    u.y = mu * u.y - eta * (gn.y * g.y);
+    float2 u = U[i], y = Y[i];
+    if (lr_rule) {
+      u.x = mu * u.x - eta * g.x;
+      u.y = mu * u.y - eta * g.y;
+    } else {
+      float2 gn = G[i];
+      gn.x = ((g.x > 0.f) != (u.x > 0.f)) ? gn.x + 0.2f : gn.x * 0.8f;
+      gn.y = ((g.y > 0.f) != (u.y > 0.f)) ? gn.y + 0.2f : gn.y * 0.8f;
+      gn.x = fmaxf(gn.x, min_gain);
+      gn.y = fmaxf(gn.y, min_gain);
+      u.x = mu * u.x - eta * (gn.x * g.x);
+      u.y = mu * u.y - eta * (gn.y * g.y);
+      G[i] = gn;
+    }
     y.x += u.x;
     y.y += u.y;
     U[i] = u;
-    G[i] = gn;
     Y[i] = y;
     sx = y.x;
     sy = y.y;
@@ -633,12 +705,12 @@ __global__ __launch_bounds__(kUpd) void k_update(
     const float4 *__restrict__ part, const int32_t *__restrict__ slots,
     const int32_t *__restrict__ nslots, const float *__restrict__ zpart, int64_t nt, int64_t n,
     int32_t nb, const int32_t *__restrict__ perm, float2 *__restrict__ Y, float2 *__restrict__ U,
-    float2 *__restrict__ G, float alpha, float mu, float eta, float min_gain,
-    float2 *__restrict__ grad_out, double *__restrict__ z_out, double2 *__restrict__ meanpart,
-    Hdr *h) {
+    float2 *__restrict__ G, float alpha, float mu, float eta, float min_gain, int lr_rule,
+    const float4 *__restrict__ extent, float2 *__restrict__ grad_out, double *__restrict__ z_out,
+    double2 *__restrict__ meanpart, Hdr *h) {
   __shared__ UpdSmem sm;
   update_wg(part, slots, nslots, zpart, nt, n, nb, perm, Y, U, G, alpha, mu, eta, min_gain,
-            grad_out, z_out, meanpart, h, blockIdx.x, sm);
+            lr_rule, extent, grad_out, z_out, meanpart, h, blockIdx.x, sm);
 }
 
 // Subtract the mean of the map from the rows of block `blk`.
@@ -754,13 +826,13 @@ __global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restri
   const BatchEntry &e = tab[p];
   const int64_t b = (int64_t)blockIdx.x - e.blk0;
   if (b < 0 || b >= e.nb) return;
-  gather_rows(e.Y, e.perm, e.n, e.yp, b * T + threadIdx.x);
+  gather_rows(e.Y, e.perm, e.n, e.yp, e.extent, b);
 }
 
 __global__ __launch_bounds__(kUpd) void k_update_batched(const BatchHdr *__restrict__ bh,
                                                         int count, int64_t tiles, int64_t blocks,
                                                         float alpha, float mu, float eta,
-                                                        float min_gain) {
+                                                        float min_gain, int lr_rule) {
   __shared__ UpdSmem sm;
   if (!batch_ok(bh, count, tiles, blocks)) return;
   const BatchEntry *tab = batch_table(bh);
@@ -770,7 +842,7 @@ __global__ __launch_bounds__(kUpd) void k_update_batched(const BatchHdr *__restr
   const int64_t b = gb - e.blk0;
   if (b < 0 || b >= e.nb) return;
   update_wg(e.part, e.slots, e.nslots, e.zpart, e.nt, e.n, e.nb, e.perm, e.Y, e.U, e.G, alpha, mu,
-            eta, min_gain, nullptr, nullptr, e.meanpart, e.h,
+            eta, min_gain, lr_rule, e.extent, nullptr, nullptr, e.meanpart, e.h,
             (int)(b * kUpdPerBlock + blockIdx.x % kUpdPerBlock), sm);
 }
 
@@ -973,7 +1045,7 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
   Hdr *h = at<Hdr>(ws, L.hdr);
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
-                     at<const int32_t>(ws, L.perm), L.n, yp);
+                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent));
   const int32_t *tl = at<const int32_t>(ws, L.tlist), *tc = at<const int32_t>(ws, L.tcount);
   const int2 *tm = at<const int2>(ws, L.tmap);
   float4 *part = at<float4>(ws, L.part);
@@ -996,8 +1068,8 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
 }
 
 hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
-                         float mu, float eta, float min_gain, int recentre, float *grad_out,
-                         double *z_out, hipStream_t st) {
+                         float mu, float eta, float min_gain, int recentre, int lr_rule,
+                         float *grad_out, double *z_out, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   double2 *mp = at<double2>(ws, L.meanpart);
   hipLaunchKernelGGL(k_update, dim3((unsigned)(L.nb * kUpdPerBlock)), dim3(kUpd), 0, st,
@@ -1005,7 +1077,8 @@ hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g
                      at<const int32_t>(ws, L.nslots), at<const float>(ws, L.zpart), L.nt, L.n,
                      L.nb, at<const int32_t>(ws, L.perm), reinterpret_cast<float2 *>(y),
                      reinterpret_cast<float2 *>(u), reinterpret_cast<float2 *>(g), alpha, mu, eta,
-                     min_gain, reinterpret_cast<float2 *>(grad_out), z_out, mp, h);
+                     min_gain, lr_rule, at<const float4>(ws, L.extent),
+                     reinterpret_cast<float2 *>(grad_out), z_out, mp, h);
   if (recentre)
     hipLaunchKernelGGL(k_recentre, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, mp, L.n,
                        L.nb, reinterpret_cast<float2 *>(y), h);
@@ -1028,7 +1101,7 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, h
   double2 *cp = at<double2>(ws, L.cpart);
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
-                     at<const int32_t>(ws, L.perm), L.n, yp);
+                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent));
   hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P), yp,
                      L.n, L.nb, cp, at<const uint8_t>(ws, L.nz), h);
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
@@ -1037,7 +1110,7 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, h
 
 hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tiles,
                              int64_t total_blocks, float alpha, float mu, float eta,
-                             float min_gain, int recentre, hipStream_t st) {
+                             float min_gain, int recentre, int lr_rule, hipStream_t st) {
   const BatchHdr *bh = reinterpret_cast<const BatchHdr *>(batch_ws);
   hipLaunchKernelGGL(k_gather_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh, count,
                      total_tiles, total_blocks);
@@ -1059,7 +1132,7 @@ hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tile
   }
   hipLaunchKernelGGL(k_update_batched, dim3((unsigned)(total_blocks * kUpdPerBlock)), dim3(kUpd),
                      0, st, bh, count,
-                     total_tiles, total_blocks, alpha, mu, eta, min_gain);
+                     total_tiles, total_blocks, alpha, mu, eta, min_gain, lr_rule);
   if (recentre)
     hipLaunchKernelGGL(k_recentre_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh,
                        count, total_tiles, total_blocks);

@@ -14,6 +14,14 @@ import torch
 from . import _lib
 
 
+def paper_schedule(momentum: float = 0.8) -> "Schedule":
+    """The paper's own optimiser (section "Internal parametric configuration"):
+    no early exaggeration, a constant external momentum and the learning rate
+    of Eq. 11 computed on the device from the extent of the map."""
+    return Schedule(switch=0, exaggeration=1.0, mom_early=momentum, mom_late=momentum,
+                    learning_rate=0.0, lr_rule="range")
+
+
 @dataclass
 class Schedule:
     """Early exaggeration and momentum switch at ``switch``; constant learning rate.
@@ -28,6 +36,7 @@ class Schedule:
     mom_late: float = 0.8
     learning_rate: float = 200.0
     min_gain: float = 0.01
+    lr_rule: str = "gains"  # "range": the learning rate of Eq. 11, no gains
 
     def __call__(self, t: int):
         early = t < self.switch
@@ -55,7 +64,8 @@ class ExactTSNE:
     def step(self, t: int, state, sched: Schedule, grad_out=None, z_out=None):
         y, u, g = state
         alpha, mu, eta = sched(t)
-        _lib.step(self.ws, self.n, y, u, g, alpha, mu, eta, sched.min_gain, True, grad_out, z_out)
+        _lib.step(self.ws, self.n, y, u, g, alpha, mu, eta, sched.min_gain, True, grad_out, z_out,
+                  lr_rule=sched.lr_rule)
 
     def run(self, state, iters: int, start: int = 0, sched: Schedule | None = None):
         sched = sched or Schedule()
@@ -108,7 +118,8 @@ class BatchedTSNE:
 
     def step(self, t: int, sched: Schedule):
         alpha, mu, eta = sched(t)
-        _lib.batch_step(self._arr, self._bws, alpha, mu, eta, sched.min_gain, True)
+        _lib.batch_step(self._arr, self._bws, alpha, mu, eta, sched.min_gain, True,
+                        lr_rule=sched.lr_rule)
 
     def run(self, iters: int, start: int = 0, sched: Schedule | None = None):
         sched = sched or Schedule()

@@ -16,7 +16,7 @@ import torch
 
 import oracle
 from paper_1812_09869_amd import _lib, synth
-from paper_1812_09869_amd.tsne import BatchedTSNE, ExactTSNE, Schedule
+from paper_1812_09869_amd.tsne import BatchedTSNE, ExactTSNE, Schedule, paper_schedule
 
 pytestmark = pytest.mark.gpu
 
@@ -25,14 +25,15 @@ def _t(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def test_batched_bitwise_equals_single():
+@pytest.mark.parametrize("rule", ["gains", "range"])
+def test_batched_bitwise_equals_single(rule):
     sizes = [(300, 5), (257, 3), (1000, 10), (40, 2), (2048, 7)]
     rng = np.random.Generator(np.random.PCG64(9))
     probs = [((rng.standard_normal((n, d)) * 3).astype(np.float32), 8.0) for n, d in sizes]
     y0s = [synth.embedding_init(n, seed=20 + k) for k, (n, _) in enumerate(sizes)]
     batched = BatchedTSNE([(_t(x), p) for x, p in probs])
     batched.init_states([_t(y) for y in y0s])
-    sched = Schedule(switch=2)
+    sched = Schedule(switch=2) if rule == "gains" else paper_schedule(0.8)
     batched.run(4, sched=sched)
     for k, ((x, p), y0) in enumerate(zip(probs, y0s)):
         single = ExactTSNE(_t(x), p)

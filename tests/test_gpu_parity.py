@@ -125,6 +125,33 @@ def test_step_parity(case):
     assert model.status() == 0
 
 
+def test_step_range_parity(case):
+    """Updates with the paper's learning rate (Eq. 11, no gains) from a spread
+    map with nonzero momentum, against the oracle step by step."""
+    n, model, P, lab = case["n"], case["model"], case["P"], case["lab"]
+    if n < 3:
+        pytest.skip("eta = 0 at n = 2")
+    y0 = synth.clustered_state(lab, seed=7)
+    u0 = (np.random.Generator(np.random.PCG64(8)).standard_normal((n, 2)) * 0.05).astype(
+        np.float32)
+    yr, ur = y0.astype(np.float64), u0.astype(np.float64)
+    y, u = torch.from_numpy(y0).cuda(), torch.from_numpy(u0).cuda()
+    grad = torch.empty_like(y)
+    for it in range(3):
+        gr, _, eta = oracle.step_range(P, yr, ur, mu=0.8, want_grad=True)
+        _lib.step(model.ws, n, y, u, None, 1.0, 0.8, 0.0, grad_out=grad, lr_rule="range")
+        if it == 0:
+            g = grad.cpu().numpy().astype(np.float64)
+            relg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+            print(f"  eta {eta:.4f}; gradient rel {relg:.2e}")
+            assert relg <= 1e-4
+    rel = np.linalg.norm(y.cpu().numpy() - yr) / np.linalg.norm(yr)
+    relu = np.linalg.norm(u.cpu().numpy() - ur) / np.linalg.norm(ur)
+    print(f"  Y after 3 steps rel {rel:.2e}, U rel {relu:.2e}")
+    assert rel <= 1e-4 and relu <= 1e-3
+    assert model.status() == 0
+
+
 def test_determinism(case):
     n, model, lab = case["n"], case["model"], case["lab"]
     y = torch.from_numpy(synth.clustered_state(lab, seed=5)).cuda()

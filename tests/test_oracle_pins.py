@@ -298,6 +298,82 @@ def test_gain_floor():
     np.testing.assert_array_equal(gains, np.full((2, 2), 0.01))
 
 
+def test_adaptive_eta_hand_worked():
+    """Eq. 11 on a 3-point map with coordinate ranges 3 (x) and 4 (y).
+
+    eta = ln(n - 1) * max(3, 4) / 2 = 2 ln 2; the embedding size (diagonal of
+    the box) is the 3-4-5 hypotenuse. A base-2 or base-10 logarithm, n for
+    n - 1, the diagonal or the smaller range in Eq. 11, or a missing halving
+    all give other values.
+    """
+    y = np.array([[0.0, 0.0], [3.0, 1.0], [1.0, -3.0]])
+    assert oracle.adaptive_eta(y) == pytest.approx(2.0 * math.log(2.0), rel=1e-15)
+    assert oracle.embedding_size(y) == pytest.approx(5.0, rel=1e-15)
+
+
+def test_adaptive_eta_invariances():
+    """eta is translation and order invariant and scales with the map (Eq. 11)."""
+    y = _rng(21).standard_normal((50, 2)) * 4.0
+    e = oracle.adaptive_eta(y)
+    assert oracle.adaptive_eta(y + [7.0, -3.0]) == pytest.approx(e, rel=1e-14)
+    assert oracle.adaptive_eta(y[::-1].copy()) == e
+    assert oracle.adaptive_eta(2.5 * y) == pytest.approx(2.5 * e, rel=1e-14)
+    assert oracle.adaptive_eta(y[:, ::-1].copy()) == e
+    s = oracle.embedding_size(y)
+    assert oracle.embedding_size(3.0 * y + 1.0) == pytest.approx(3.0 * s, rel=1e-14)
+
+
+def test_step_range_hand_worked():
+    """Three collinear points (-1,0), (0,0), (1,0) with uniform p_ij = 1/6.
+
+    w = 1/2 for the two unit pairs, 1/5 for the outer pair; Z = 2 (1/2 + 1/2 +
+    1/5) = 2.4, q = 5/24 and 1/12. Eq. 6 for point 1:
+    4 [(1/6 - 5/24)(1/2)(-1) + (1/6 - 1/12)(1/5)(-2)] = 4 (1/48 - 1/30) = -1/20,
+    point 2 has zero gradient by symmetry and point 3 the opposite of point 1.
+    Ranges 2 (x) and 0 (y): eta = ln 2 * 2 / 2 = ln 2 (Eq. 11). With
+    mu = 0.8 and U_1 = (0.1, 0.2): U_1 <- (0.08 + 0.05 ln 2, 0.16),
+    U_3 <- (-0.05 ln 2, 0); Y <- Y + U, then the mean is removed.
+    """
+    P = np.full((3, 3), 1.0 / 6.0)
+    np.fill_diagonal(P, 0.0)
+    y = np.array([[-1.0, 0.0], [0.0, 0.0], [1.0, 0.0]])
+    u = np.array([[0.1, 0.2], [0.0, 0.0], [0.0, 0.0]])
+    g, zz, eta = oracle.step_range(P, y, u, mu=0.8, want_grad=True)
+    assert zz == pytest.approx(2.4, rel=1e-15)
+    assert eta == pytest.approx(math.log(2.0), rel=1e-15)
+    np.testing.assert_allclose(g, [[-0.05, 0.0], [0.0, 0.0], [0.05, 0.0]], rtol=1e-13,
+                               atol=1e-17)
+    l2 = math.log(2.0)
+    np.testing.assert_allclose(u, [[0.08 + 0.05 * l2, 0.16], [0.0, 0.0], [-0.05 * l2, 0.0]],
+                               rtol=1e-13, atol=1e-17)
+    yb = np.array([[-1.0 + 0.08 + 0.05 * l2, 0.16], [0.0, 0.0], [1.0 - 0.05 * l2, 0.0]])
+    np.testing.assert_allclose(y, yb - yb.mean(axis=0), rtol=1e-13, atol=1e-16)
+
+
+def test_step_range_two_points_is_pure_momentum():
+    """n = 2: ln(n - 1) = 0, so eta = 0 and only the momentum term moves Y."""
+    P = np.array([[0.0, 0.5], [0.5, 0.0]])
+    y = np.array([[0.0, 0.0], [2.0, 1.0]])
+    u = np.array([[0.3, -0.1], [0.1, 0.4]])
+    _, _, eta = oracle.step_range(P, y, u, mu=0.5, recentre=False)
+    assert eta == 0.0
+    np.testing.assert_allclose(u, [[0.15, -0.05], [0.05, 0.2]], rtol=1e-15)
+    np.testing.assert_allclose(y, [[0.15, -0.05], [2.05, 1.2]], rtol=1e-15)
+
+
+def test_step_range_preserves_mean_without_recentring():
+    """The gradient of Eq. 6 sums to zero, so from U = 0 the mean of the map
+    stays where it is even when the map is not re-centred."""
+    x, _ = synth.plain_small(120, seed=23)
+    P = oracle.joint_p(x, oracle.calibrate(x, 15.0))
+    y = _rng(24).standard_normal((120, 2)) + [3.0, -1.0]
+    m0 = y.mean(axis=0)
+    u = np.zeros_like(y)
+    for _ in range(5):
+        oracle.step_range(P, y, u, mu=0.8, recentre=False)
+    np.testing.assert_allclose(y.mean(axis=0), m0, rtol=0, atol=1e-11)
+
+
 def test_bitwise_resume(small_problem):
     """Running 3 + 4 iterations through a saved state equals 7 straight through."""
     _, P, y = small_problem
