@@ -23,6 +23,14 @@ Workloads (sizes and recipes):
 * ``batch_problem(p)``: problem p of the 64-instance batch: N ~ U{1000..20000},
   D in {10, 50}, K ~ U{4..16} isotropic equal-weight components; perplexity 30.
 * ``embedding_init``: initial 2-D map ~ N(0, 1e-4 I), i.e. std 0.01.
+* ``disk_init``: initial map of the parallel scheme, uniform in the unit disk
+  (section "Parallelized implementation").
+* ``epoch_orders``: one random permutation of the points per epoch (the
+  master's mixing draw of the parallel scheme).
+* ``digits_like``: stand-in for the whitened 30-D digits set of the paper's
+  rounds figure: N=60,000, D=30, 10 anisotropic components (Dirichlet(5)
+  weights, means ~ N(0, 25 I), covariance log-uniform in [0.1, 10] along Haar
+  axes); run with 120 threads, 2 layers and perplexity 400.
 """
 from __future__ import annotations
 
@@ -39,6 +47,9 @@ __all__ = [
     "batch_problem",
     "embedding_init",
     "clustered_state",
+    "disk_init",
+    "epoch_orders",
+    "digits_like",
     "SEEDS",
 ]
 
@@ -51,6 +62,9 @@ SEEDS = {
     "init_aniso": 2002,
     "surrogate_new": 5001,
     "surrogate_init": 6001,
+    "digits_like": 1005,
+    "pt_init": 2005,
+    "pt_orders": 3005,
 }
 
 
@@ -178,3 +192,31 @@ def clustered_state(labels: np.ndarray, seed: int, spread: float = 8.0, jitter: 
     centres = rng.standard_normal((k, 2)) * spread
     y = centres[labels] + jitter * rng.standard_normal((labels.shape[0], 2))
     return y.astype(np.float32)
+
+
+def disk_init(n: int, seed: int) -> np.ndarray:
+    """Initial 2-D map uniform in the disk of radius 1, cast to FP32."""
+    rng = _rng(seed)
+    r = np.sqrt(rng.uniform(0.0, 1.0, n))
+    a = rng.uniform(0.0, 2.0 * np.pi, n)
+    return np.stack([r * np.cos(a), r * np.sin(a)], axis=1).astype(np.float32)
+
+
+def epoch_orders(n: int, epochs: int, seed: int) -> np.ndarray:
+    """``epochs`` independent random permutations of 0..n-1 (int32, epochs x n)."""
+    rng = _rng(seed)
+    return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+
+
+def digits_like(n: int = 60000, seed: int = SEEDS["digits_like"], k: int = 10, d: int = 30):
+    """N points from a 10-component anisotropic mixture in D=30."""
+    rng = _rng(seed)
+    w = rng.dirichlet(np.full(k, 5.0))
+    means = rng.standard_normal((k, d)) * 5.0
+    factors = np.empty((k, d, d))
+    for c in range(k):
+        q = _haar_orthogonal(rng, d, d)
+        lam = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=d))
+        factors[c] = q * np.sqrt(lam)
+    x, lab = Mixture(w, means, factors).sample(rng, n)
+    return x.astype(np.float32), lab
