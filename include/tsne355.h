@@ -221,6 +221,72 @@ TSNE_API int tsne_batch_step(const tsne_batch_problem *problems, int32_t count,
                              const void *batch_ws, const tsne_step_params *prm, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Parallel scheme, ptSNE (section "Parallelized implementation"). The n
+ * points are split into `threads` chunks, contiguous pieces of a per-epoch
+ * order of the points (sizes differ by at most one, larger chunks first).
+ * Partial t-SNE k runs on chunks k, k+1, ..., k+layers-1 (cyclic), so every
+ * chunk is shared by `layers` successive partial problems and every point has
+ * one 2-D position per layer. An epoch (subsection "epochs"):
+ *   mix:     chunk (k + l) mod threads enters partial problem k at its points'
+ *            layer-l positions; momentum state starts at zero;
+ *   run:     affinities of the partial problem's own points (Eqs. 1-3), then
+ *            `iters` iterations of Eqs. 10-11 (learning rate from the map's
+ *            extent, external momentum, no exaggeration, no gains, no
+ *            re-centring), all partial problems in one batched launch per
+ *            phase;
+ *   pool:    every partial result is written back to the layer it was read
+ *            from, so each (point, layer) is read and written exactly once.
+ * A round is floor(sqrt(n)) epochs; `iters` defaults to ceil(sqrt(z)) with
+ * the thread size z = n layers / threads (subsections "thread-size" and
+ * "rounds"). Monitors (section comparing t-SNE and ptSNE): the mean over the
+ * partial problems of their pseudo-normalised cost (Eq. 9) and the mean over
+ * the layers of the embedding size, the diagonal of the layer's box.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t threads;    /* partial problems, 1 <= threads <= n */
+  int32_t layers;     /* chunks per partial problem, 1 <= layers <= threads */
+  double perplexity;  /* of every partial problem, in (1, smallest thread size - 1) */
+  float momentum;     /* the external momentum of Eq. 10 */
+  int32_t iters;      /* iterations per epoch; <= 0: ceil(sqrt(n layers / threads)) */
+  int32_t dist_mode;  /* tsne_dist_mode of the partial affinities */
+  int32_t reorder;    /* tsne_aff_opts.reorder of the partial affinities */
+  int32_t reserved;   /* must be 0 */
+} tsne_pt_opts;
+
+/* Bytes of the ptSNE workspace (device, 256-byte aligned) for n points in d
+ * dimensions; 0 if the options are invalid. Host-only. It holds the pooled
+ * rows of all partial problems, their workspaces and the batch table. */
+TSNE_API size_t tsne_pt_workspace_bytes(int64_t n, int32_t d, const tsne_pt_opts *opts);
+
+/* Iterations per epoch for these options (opts->iters if positive). */
+TSNE_API int32_t tsne_pt_iterations(int64_t n, const tsne_pt_opts *opts);
+
+/* Prepares the workspace (thread table, batch plan); synchronises the stream.
+ * Errors: TSNE_E_ARG, TSNE_E_PERPLEXITY, TSNE_E_WORKSPACE, TSNE_E_DEVICE. */
+TSNE_API int tsne_pt_init(int64_t n, int32_t d, const tsne_pt_opts *opts, void *ws, size_t bytes,
+                          void *stream);
+
+/* One epoch. x: n x d FP32; order: int32[n], a permutation of 0..n-1 (the
+ * master's mixing draw; entries outside [0, n) are recorded as TSNE_E_ARG for
+ * tsne_pt_sync_status and the epoch's result is then undefined); maps:
+ * layers x n x 2 FP32, read and updated in place; monitors: nullable device
+ * double[2] = {mean partial C_norm, mean layer size} after the epoch. All
+ * pointers are device pointers; asynchronous on `stream`. The workspace must
+ * have been prepared by tsne_pt_init with the same n, d and options. */
+TSNE_API int tsne_pt_epoch(const float *x, int64_t n, int32_t d, const tsne_pt_opts *opts,
+                           const int32_t *order, float *maps, void *ws, size_t bytes,
+                           double *monitors, void *stream);
+
+/* Synchronises the stream; returns the first condition recorded by the
+ * epochs (an order entry out of range) or by any partial problem's
+ * workspace (tsne_sync_status), else TSNE_OK. */
+TSNE_API int tsne_pt_sync_status(int64_t n, int32_t d, const tsne_pt_opts *opts, void *ws,
+                                 size_t bytes, void *stream);
+
+/* Message of the last failing tsne_pt_* call on this thread. */
+TSNE_API const char *tsne_pt_last_error(void);
+
+/* ------------------------------------------------------------------------
  * Learned surrogate (not in the paper): an MLP d_in -> H -> H -> 2 with ReLU
  * that maps input points to their embedding, trained on (x, y) pairs that
  * the exact path produced. Exact t-SNE (tsne_step) stays the fallback: a

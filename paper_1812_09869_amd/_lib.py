@@ -51,6 +51,12 @@ EXPORTED = [
     "tsne_mlp_forward",
     "tsne_mlp_gradient",
     "tsne_mlp_adam",
+    "tsne_pt_workspace_bytes",
+    "tsne_pt_iterations",
+    "tsne_pt_init",
+    "tsne_pt_epoch",
+    "tsne_pt_sync_status",
+    "tsne_pt_last_error",
 ]
 
 
@@ -75,6 +81,13 @@ class StepParams(ctypes.Structure):
     _fields_ = [("exaggeration", ctypes.c_float), ("momentum", ctypes.c_float),
                 ("learning_rate", ctypes.c_float), ("min_gain", ctypes.c_float),
                 ("recentre", ctypes.c_int32), ("lr_rule", ctypes.c_int32)]
+
+
+class PtOpts(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("layers", ctypes.c_int32),
+                ("perplexity", ctypes.c_double), ("momentum", ctypes.c_float),
+                ("iters", ctypes.c_int32), ("dist_mode", ctypes.c_int32),
+                ("reorder", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -123,6 +136,15 @@ def load(path: str = LIB_PATH):
                                              _vp, _vp, ctypes.c_size_t, _vp]),
         "tsne_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float,
                                          ctypes.c_float, ctypes.c_float, _i32, _vp]),
+        "tsne_pt_workspace_bytes": (ctypes.c_size_t, [_i64, _i32, ctypes.POINTER(PtOpts)]),
+        "tsne_pt_iterations": (_i32, [_i64, ctypes.POINTER(PtOpts)]),
+        "tsne_pt_init": (ctypes.c_int, [_i64, _i32, ctypes.POINTER(PtOpts), _vp, ctypes.c_size_t,
+                                        _vp]),
+        "tsne_pt_epoch": (ctypes.c_int, [_vp, _i64, _i32, ctypes.POINTER(PtOpts), _vp, _vp, _vp,
+                                         ctypes.c_size_t, _vp, _vp]),
+        "tsne_pt_sync_status": (ctypes.c_int, [_i64, _i32, ctypes.POINTER(PtOpts), _vp,
+                                               ctypes.c_size_t, _vp]),
+        "tsne_pt_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -335,3 +357,52 @@ def batch_step(arr, bws, exaggeration, momentum, learning_rate, min_gain=0.01, r
     prm = _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule)
     _check(load().tsne_batch_step(arr, len(arr), _ptr(bws, torch.uint8), ctypes.byref(prm),
                                   _stream()))
+
+
+# --------------------------------------------------------------------------
+# Parallel scheme (ptSNE)
+# --------------------------------------------------------------------------
+
+def _check_pt(rc: int):
+    if rc != TSNE_OK:
+        raise TsneError(rc, load().tsne_pt_last_error().decode())
+
+
+def pt_opts(threads, layers, perplexity, momentum=0.8, iters=0, dist_mode="fp64",
+            reorder=False) -> PtOpts:
+    mode = DIST_MODES[dist_mode] if isinstance(dist_mode, str) else int(dist_mode)
+    return PtOpts(int(threads), int(layers), float(perplexity), float(momentum), int(iters), mode,
+                  1 if reorder else 0, 0)
+
+
+def pt_iterations(n: int, opts: PtOpts) -> int:
+    return int(load().tsne_pt_iterations(n, ctypes.byref(opts)))
+
+
+def pt_new_workspace(n: int, d: int, opts: PtOpts, device="cuda") -> torch.Tensor:
+    nbytes = int(load().tsne_pt_workspace_bytes(n, d, ctypes.byref(opts)))
+    if nbytes == 0:
+        _check_pt(load().tsne_pt_init(n, d, ctypes.byref(opts), None, 0, None))
+        raise TsneError(1, "invalid ptSNE options")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def pt_init(n: int, d: int, opts: PtOpts, ws: torch.Tensor):
+    _check_pt(load().tsne_pt_init(n, d, ctypes.byref(opts), _ptr(ws, torch.uint8, name="ws"),
+                                  ws.numel(), _stream()))
+
+
+def pt_epoch(x, opts: PtOpts, order, maps, ws, monitors=None):
+    n, d = x.shape
+    _check_pt(load().tsne_pt_epoch(_ptr(x, name="x"), n, d, ctypes.byref(opts),
+                                   _ptr(order, torch.int32, shape=(n,), name="order"),
+                                   _ptr(maps, shape=(opts.layers, n, 2), name="maps"),
+                                   _ptr(ws, torch.uint8, name="ws"), ws.numel(),
+                                   _ptr(monitors, torch.float64, shape=(2,), name="monitors"),
+                                   _stream()))
+
+
+def pt_sync_status(n: int, d: int, opts: PtOpts, ws) -> int:
+    return int(load().tsne_pt_sync_status(n, d, ctypes.byref(opts),
+                                          _ptr(ws, torch.uint8, name="ws"), ws.numel(),
+                                          _stream()))

@@ -7,6 +7,7 @@ parameters.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import torch
@@ -126,3 +127,42 @@ class BatchedTSNE:
         for t in range(start, start + iters):
             self.step(t, sched)
         return self.states
+
+
+class PTSNE:
+    """The parallel scheme (ptSNE) over the C ABI: partial t-SNEs on shared
+    chunks, run for short epochs and pooled into ``layers`` maps.
+
+    Every epoch is one ``tsne_pt_epoch`` call (mix, affinities, batched
+    iterations with the rate of Eq. 11, monitors, pool, all on the device);
+    this class only allocates and passes the per-epoch order.
+    """
+
+    def __init__(self, x: torch.Tensor, threads: int, layers: int, perplexity: float,
+                 momentum: float = 0.8, iters: int = 0, dist_mode="fp64", reorder: bool = False):
+        if x.dim() != 2:
+            raise ValueError("x must be n x d")
+        self.x = x.contiguous()
+        self.n, self.d = x.shape
+        self.opts = _lib.pt_opts(threads, layers, perplexity, momentum, iters, dist_mode, reorder)
+        self.ws = _lib.pt_new_workspace(self.n, self.d, self.opts, device=x.device)
+        _lib.pt_init(self.n, self.d, self.opts, self.ws)
+        self.iters = _lib.pt_iterations(self.n, self.opts)
+        self.epochs_per_round = int(math.isqrt(self.n))
+        self.monitors = torch.zeros(2, dtype=torch.float64, device=x.device)
+        self.maps = None
+
+    def init_maps(self, y0: torch.Tensor):
+        """Every layer starts at the same map y0 (n x 2)."""
+        y0 = y0.detach().to(device=self.x.device, dtype=torch.float32)
+        self.maps = y0.unsqueeze(0).repeat(self.opts.layers, 1, 1).contiguous()
+        return self.maps
+
+    def epoch(self, order: torch.Tensor):
+        """One epoch with the given permutation (int32 device tensor of n);
+        returns the device monitors {mean partial C_norm, mean layer size}."""
+        _lib.pt_epoch(self.x, self.opts, order, self.maps, self.ws, self.monitors)
+        return self.monitors
+
+    def status(self) -> int:
+        return _lib.pt_sync_status(self.n, self.d, self.opts, self.ws)

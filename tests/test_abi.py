@@ -45,3 +45,26 @@ def test_workspace_bytes_host_only():
     assert n65 > 32896 * 256 * 256 * 4
     assert _lib.workspace_bytes(1, 10) == 0
     assert _lib.workspace_bytes(100, 0) == 0
+
+
+def test_pt_host_logic_matches_the_paper_examples():
+    """Iterations per epoch and option checks of the ptSNE entry points are
+    host arithmetic; the iteration count follows the paper's worked numbers
+    (the same fixture that pins the oracle)."""
+    import json
+    from paper_1812_09869_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libtsne355.so not built")
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "ptsne_paper_examples.json")))
+    g = gold["rounds_digits"]
+    opts = _lib.pt_opts(g["threads"], g["layers"], 400.0)
+    assert _lib.pt_iterations(g["n"], opts) == g["iterations"]
+    assert _lib.pt_iterations(g["n"], _lib.pt_opts(120, 2, 400.0, iters=7)) == 7
+    lib = _lib.load()
+    ok = lib.tsne_pt_workspace_bytes(2000, 10, ctypes.byref(_lib.pt_opts(5, 2, 20.0)))
+    assert ok > 5 * _lib.workspace_bytes(800, 10)  # five partial workspaces of 800 points
+    for bad in (_lib.pt_opts(5, 6, 20.0),        # layers > threads
+                _lib.pt_opts(0, 1, 20.0),        # no threads
+                _lib.pt_opts(5, 2, 799.5),       # perplexity >= z - 1
+                _lib.pt_opts(5, 2, 1.0)):        # perplexity <= 1
+        assert lib.tsne_pt_workspace_bytes(2000, 10, ctypes.byref(bad)) == 0

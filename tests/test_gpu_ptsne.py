@@ -1,0 +1,78 @@
+"""GPU parity of the parallel scheme (ptSNE) against the FP64 oracle.
+
+Workload: 1,000 points of the 2,000-point recipe's mixture, 5 threads and 2
+layers (z = 400, ceil(sqrt z) = 20 iterations per epoch), perplexity 20,
+momentum 0.8, start map uniform in the unit disk, three epochs with seeded
+orders. Over these epochs the oracle itself is stable: runs whose start maps
+differ by one FP32 ulp stay within 3e-9 relative of each other, so the gates
+bound the FP32 arithmetic of the GPU path, not a chaotic divergence:
+  maps (all layers) relative L2 <= 1e-4 after every epoch,
+  mean partial C_norm absolute <= 1e-5, mean layer size relative <= 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ptsne
+from paper_1812_09869_amd import synth
+from paper_1812_09869_amd.tsne import PTSNE
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n=1000, threads=5, layers=2, perp=20.0, epochs=3, seed=61):
+    x, _ = synth.plain_small(n, seed=seed)
+    y0 = synth.disk_init(n, seed + 1)
+    orders = synth.epoch_orders(n, epochs, seed + 2)
+    return x, y0, orders, threads, layers, perp
+
+
+@pytest.mark.parametrize("threads,layers,reorder", [(5, 2, False), (4, 3, True), (1, 1, False)])
+def test_epochs_match_oracle(threads, layers, reorder):
+    x, y0, orders, _, _, perp = _setup()
+    n = x.shape[0]
+    print(f"\n[pt] n={n} threads={threads} layers={layers} reorder={reorder}", flush=True)
+    pt = PTSNE(torch.from_numpy(x).cuda(), threads, layers, perp, momentum=0.8, reorder=reorder)
+    it = ptsne.iterations_per_epoch(ptsne.thread_size(n, threads, layers))
+    assert pt.iters == it
+    pt.init_maps(torch.from_numpy(y0).cuda())
+    maps = np.repeat(y0.astype(np.float64)[None], layers, axis=0)
+    for e, order in enumerate(orders):
+        mon = pt.epoch(torch.from_numpy(order).cuda()).cpu().numpy()
+        maps, c, s, _ = ptsne.epoch(x, maps, order, threads, layers, perp, it, 0.8)
+        g = pt.maps.cpu().numpy().astype(np.float64)
+        rel = np.linalg.norm(g - maps) / np.linalg.norm(maps)
+        print(f"  epoch {e}: maps rel {rel:.2e}; cost {mon[0]:.7f} vs {c:.7f}; "
+              f"size {mon[1]:.5f} vs {s:.5f}")
+        assert rel <= 1e-4
+        assert abs(mon[0] - c) <= 1e-5
+        assert abs(mon[1] - s) <= 1e-4 * s
+    assert pt.status() == 0
+
+
+def test_ragged_chunks_and_many_threads():
+    """n not a multiple of threads (chunk sizes differ by one), 16 threads x 4
+    layers, one epoch against the oracle."""
+    x, y0, orders, _, _, _ = _setup(n=1003, epochs=1, seed=71)
+    n, threads, layers, perp = 1003, 16, 4, 15.0
+    pt = PTSNE(torch.from_numpy(x).cuda(), threads, layers, perp, momentum=0.5)
+    pt.init_maps(torch.from_numpy(y0).cuda())
+    mon = pt.epoch(torch.from_numpy(orders[0]).cuda()).cpu().numpy()
+    maps0 = np.repeat(y0.astype(np.float64)[None], layers, axis=0)
+    maps, c, s, _ = ptsne.epoch(x, maps0, orders[0], threads, layers, perp, pt.iters, 0.5)
+    g = pt.maps.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(g - maps) / np.linalg.norm(maps)
+    print(f"\n  maps rel {rel:.2e}; cost {mon[0]:.7f} vs {c:.7f}; size {mon[1]:.5f} vs {s:.5f}")
+    assert rel <= 1e-4 and abs(mon[0] - c) <= 1e-5 and abs(mon[1] - s) <= 1e-4 * s
+    assert pt.status() == 0
+
+
+def test_order_out_of_range_is_reported():
+    """An order entry outside [0, n) is clamped on the device and reported."""
+    x, y0, orders, threads, layers, perp = _setup(n=600, epochs=1, seed=81)
+    pt = PTSNE(torch.from_numpy(x).cuda(), threads, layers, perp)
+    pt.init_maps(torch.from_numpy(y0).cuda())
+    bad = orders[0].copy()
+    bad[17] = 600
+    pt.epoch(torch.from_numpy(bad).cuda())
+    assert pt.status() == 1  # TSNE_E_ARG
