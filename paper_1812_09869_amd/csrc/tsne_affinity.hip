@@ -511,16 +511,16 @@ __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock,
 // Also per tile: sum p and sum p ln p over ordered pairs (off-diagonal tiles
 // stand for both (i, j) and (j, i)).
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const float *__restrict__ a,
-                                              const float *__restrict__ m,
-                                              const float *__restrict__ r, int64_t n, int32_t nb,
-                                              double2 *__restrict__ ppart,
-                                              uint8_t *__restrict__ nzflag,
-                                              int2 *__restrict__ tmap) {
+__device__ __forceinline__ void pack_tile(float4 *__restrict__ P, const float *__restrict__ a,
+                                          const float *__restrict__ m,
+                                          const float *__restrict__ r, int64_t n, int32_t nb,
+                                          double2 *__restrict__ ppart,
+                                          uint8_t *__restrict__ nzflag, int2 *__restrict__ tmap,
+                                          int64_t tile) {
   __shared__ double red[2][4];
   int I, J;
-  tile_coords(blockIdx.x, nb, I, J);
-  if (threadIdx.x == 0) tmap[blockIdx.x] = make_int2(I, J);
+  tile_coords(tile, nb, I, J);
+  if (threadIdx.x == 0) tmap[tile] = make_int2(I, J);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
   const bool diag = (I == J);
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const floa
     mc[k] = ok ? m[j] : 0.f;
     rc[k] = ok ? r[j] : 0.f;
   }
-  float4 *tp = P + (size_t)blockIdx.x * TT4;
+  float4 *tp = P + (size_t)tile * TT4;
   float psum = 0.f, plp = 0.f;
   bool any = false;
 #pragma unroll 2
@@ -581,16 +581,25 @@ __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const floa
   }
   const int tile_any = __syncthreads_or(any ? 1 : 0);
   if (t == 0) {
-    nzflag[blockIdx.x] = tile_any ? 1 : 0;
+    nzflag[tile] = tile_any ? 1 : 0;
     double mult = diag ? 1.0 : 2.0;
     double S = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     double Lg = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    ppart[blockIdx.x] = make_double2(mult * S, mult * Lg * kLn2);
+    ppart[tile] = make_double2(mult * S, mult * Lg * kLn2);
   }
 }
 
-__global__ __launch_bounds__(1024) void k_pack_reduce(const double2 *__restrict__ ppart,
-                                                      int64_t nt, Hdr *h) {
+__global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const float *__restrict__ a,
+                                              const float *__restrict__ m,
+                                              const float *__restrict__ r, int64_t n, int32_t nb,
+                                              double2 *__restrict__ ppart,
+                                              uint8_t *__restrict__ nzflag,
+                                              int2 *__restrict__ tmap) {
+  pack_tile(P, a, m, r, n, nb, ppart, nzflag, tmap, blockIdx.x);
+}
+
+__device__ __forceinline__ void pack_reduce_wg(const double2 *__restrict__ ppart, int64_t nt,
+                                               Hdr *h) {
   __shared__ double red[2][16];
   double s = 0.0, lg = 0.0;
   for (int64_t q = threadIdx.x; q < nt; q += 1024) {
@@ -615,6 +624,11 @@ __global__ __launch_bounds__(1024) void k_pack_reduce(const double2 *__restrict_
     if (!isfinite(S) || !isfinite(Lg)) atomicOr(&h->err, kErrNonFinite);
     h->ready = 1;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_pack_reduce(const double2 *__restrict__ ppart,
+                                                      int64_t nt, Hdr *h) {
+  pack_reduce_wg(ppart, nt, h);
 }
 
 // ----------------------------------------------------------------------------
@@ -972,9 +986,9 @@ __global__ void k_export_scalars(int64_t n, const Hdr *h, double *out) {
 // Tile lists for the force pass: all-zero tiles in ascending order, then the
 // others in ascending order (one workgroup; ballot prefix counts in a fixed
 // order).
-__global__ __launch_bounds__(1024) void k_tile_lists(const uint8_t *__restrict__ nz, int64_t nt,
-                                                     int32_t *__restrict__ tlist,
-                                                     int32_t *__restrict__ tcount) {
+__device__ __forceinline__ void tile_lists_wg(const uint8_t *__restrict__ nz, int64_t nt,
+                                              int32_t *__restrict__ tlist,
+                                              int32_t *__restrict__ tcount) {
   __shared__ int32_t wz[16], wn[16];
   __shared__ int32_t zbase, nbase, zeros;
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
@@ -1026,15 +1040,21 @@ __global__ __launch_bounds__(1024) void k_tile_lists(const uint8_t *__restrict__
   }
 }
 
+__global__ __launch_bounds__(1024) void k_tile_lists(const uint8_t *__restrict__ nz, int64_t nt,
+                                                     int32_t *__restrict__ tlist,
+                                                     int32_t *__restrict__ tcount) {
+  tile_lists_wg(nz, nt, tlist, tcount);
+}
+
 // Per row block b, the slots s (tiles (b, s) or (s, b)) whose P is not all
 // zero, in increasing s: the update reads the attractive partial sums of
 // these slots only. One workgroup per block; a fixed-order prefix count.
-__global__ __launch_bounds__(256) void k_slot_lists(const uint8_t *__restrict__ nz, int32_t nb,
-                                                    int32_t *__restrict__ slots,
-                                                    int32_t *__restrict__ nslots) {
+__device__ __forceinline__ void slot_list_wg(const uint8_t *__restrict__ nz, int32_t nb,
+                                             int32_t *__restrict__ slots,
+                                             int32_t *__restrict__ nslots, int b) {
   __shared__ int32_t wsum[4];
   __shared__ int32_t base;
-  const int b = blockIdx.x, t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
   if (t == 0) base = 0;
   __syncthreads();
   for (int s0 = 0; s0 < nb; s0 += 256) {
@@ -1056,6 +1076,206 @@ __global__ __launch_bounds__(256) void k_slot_lists(const uint8_t *__restrict__ 
     __syncthreads();
   }
   if (t == 0) nslots[b] = base;
+}
+
+__global__ __launch_bounds__(256) void k_slot_lists(const uint8_t *__restrict__ nz, int32_t nb,
+                                                    int32_t *__restrict__ slots,
+                                                    int32_t *__restrict__ nslots) {
+  slot_list_wg(nz, nb, slots, nslots, blockIdx.x);
+}
+
+// ----------------------------------------------------------------------------
+// 5. Many small problems at once (the partial problems of the parallel
+// scheme). Same method as above with one wave per row: the row's squared
+// distances (FP64 direct differences, rounded to FP32 like the distance
+// block of the large path) stay in registers for the bisection, whose sums
+// are wave reductions, so no workgroup barrier sits inside the search. The
+// four rows of a workgroup belong to one problem and share the staging of
+// the other points' coordinates in LDS. The distances of tiles (I, J >= I)
+// go straight into the P store in consumer order; the pack, reduction and
+// list steps are the same device code as the single-problem path.
+// ----------------------------------------------------------------------------
+constexpr int kSmallRows = 4;  // rows (waves) per workgroup
+
+__device__ inline int small_find(const SmallEntry *tab, int count, int64_t key, int which) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t start = which == 0 ? tab[mid].wg0 : which == 1 ? tab[mid].tile0 : tab[mid].blk0;
+    if (start <= key)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Position of element (il, jl) of a tile in the consumer order of the P store
+// (the order the stage and pack kernels use), as a float index in the tile.
+__device__ inline int small_pos(int il, int jl) {
+  const int tr = il & 15, k = il >> 4, tc = jl & 15, mm = jl >> 4;
+  const int s = k * 4 + (mm >> 2), t = 64 * (tr >> 2) + tc + 16 * (tr & 3);
+  return (s * 256 + t) * 4 + (mm & 3);
+}
+
+// Header and identity order of every problem: one workgroup per row block.
+__global__ __launch_bounds__(256) void k_small_init(const SmallEntry *__restrict__ tab, int count) {
+  const int p = small_find(tab, count, blockIdx.x, 2);
+  const SmallEntry &e = tab[p];
+  const int64_t b = (int64_t)blockIdx.x - e.blk0;
+  if (b < 0 || b >= e.nb) return;
+  if (b == 0 && threadIdx.x == 0) {
+    Hdr *h = e.h;
+    h->magic = kMagic;
+    h->n = e.n;
+    h->d = e.d;
+    h->ready = 0;
+    h->err = 0;
+    h->mode = TSNE_DIST_FP64;
+    h->perplexity = e.perplexity;
+    h->z = 0.0;
+    h->c_p = 0.0;
+    h->p_sum = 0.0;
+    h->xmax = 0.f;
+  }
+  const int64_t i = b * T + threadIdx.x;
+  e.perm[i] = (int32_t)i;
+  e.inv[i] = (int32_t)i;
+}
+
+template <int VPT>
+__global__ __launch_bounds__(256) void k_small_calibrate(const SmallEntry *__restrict__ tab,
+                                                         int count, int32_t dstride,
+                                                         int max_bisect, double tol_h) {
+  extern __shared__ float sx[];  // [64][dstride] other points, then [4][dstride] own rows
+  const int p = small_find(tab, count, blockIdx.x, 0);
+  const SmallEntry &e = tab[p];
+  const int64_t n = e.n;
+  const int32_t d = e.d;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t i = ((int64_t)blockIdx.x - e.wg0) * kSmallRows + w;
+  const bool row_ok = i < n;
+  float *own = sx + 64 * dstride;
+  for (int q = threadIdx.x; q < kSmallRows * d; q += 256) {
+    const int rr = q / d, k = q - rr * d;
+    const int64_t ii = ((int64_t)blockIdx.x - e.wg0) * kSmallRows + rr;
+    own[rr * dstride + k] = ii < n ? e.x[ii * d + k] : 0.f;
+  }
+  const int I = (int)(i / T), il = (int)(i - (int64_t)I * T);
+  float v[VPT];
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < VPT; ++q) {
+    v[q] = INFINITY;
+    if ((int64_t)q * 64 < n) {  // uniform over the workgroup
+      __syncthreads();
+      const int64_t c0 = (int64_t)q * 64;
+      const int rows = (int)((n - c0) < 64 ? (n - c0) : 64);
+      for (int idx = threadIdx.x; idx < rows * d; idx += 256) {
+        const int rr = idx / d, k = idx - rr * d;
+        sx[rr * dstride + k] = e.x[(c0 + rr) * d + k];
+      }
+      __syncthreads();
+      const int64_t j = c0 + l;
+      if (row_ok && j < n) {
+        double acc = 0.0;
+        const float *xj = sx + l * dstride, *xi = own + w * dstride;
+        for (int k = 0; k < d; ++k) {
+          const double df = (double)xj[k] - (double)xi[k];
+          acc = fma(df, df, acc);
+        }
+        const float dv = (float)acc;
+        bad |= !isfinite(dv);
+        const int J = (int)(j / T);
+        if (J >= I) {
+          const int jl = (int)(j - (int64_t)J * T);
+          float *tp = reinterpret_cast<float *>(e.P + (size_t)(tile_start(I, e.nb) + (J - I)) * TT4);
+          tp[small_pos(il, jl)] = dv;
+        }
+        if (j != i) v[q] = dv;
+      }
+    }
+  }
+  if (!row_ok) return;  // no barrier below this point
+  float mn = INFINITY;
+#pragma unroll
+  for (int q = 0; q < VPT; ++q) mn = fminf(mn, v[q]);
+  const float m = wave_min_f(mn);
+#pragma unroll
+  for (int q = 0; q < VPT; ++q) v[q] = (v[q] == INFINITY) ? kBig : v[q] - m;
+  const double logu = log(e.perplexity);
+  double beta = 1.0, lo = 0.0, hi = INFINITY, S = 0.0, H = 0.0;
+  float a = 0.f;
+  int it = 0, done = 0;
+  while (!done) {
+    ++it;
+    a = fmaxf((float)(beta * kLog2e), 1e-30f);
+    float s = 0.f, tt = 0.f;
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const float ex = __builtin_amdgcn_exp2f(-a * v[q]);
+      s += ex;
+      tt = fmaf(v[q], ex, tt);
+    }
+    // butterfly sums: every lane holds the same totals, so the search below
+    // takes the same branch in every lane
+    const double SS = wave_sum_d((double)s), TT = wave_sum_d((double)tt);
+    const double beff = (double)a * kLn2;
+    S = SS;
+    H = log(SS) + beff * TT / SS;
+    if (fabs(H - logu) <= tol_h) {
+      done = 1;
+    } else if (isfinite(hi) && (hi - lo) <= hi * 0x1p-24) {
+      done = 1;
+    } else if (it >= max_bisect) {
+      done = 2;
+    } else if (H > logu) {
+      lo = beta;
+      beta = isinf(hi) ? 2.0 * beta : 0.5 * (beta + hi);
+    } else {
+      hi = beta;
+      beta = 0.5 * (lo + beta);
+    }
+  }
+  bad = __any(bad);
+  if (l == 0) {
+    e.beta[i] = (double)a * kLn2;
+    e.S[i] = S;
+    e.H[i] = H;
+    e.m[i] = m;
+    e.a[i] = a;
+    e.r[i] = (float)(1.0 / (2.0 * (double)n * S));
+    e.evals[i] = done == 1 ? it : -it;
+    if (done != 1) flag_error(e.h, kErrNoConv);
+    if (bad || !isfinite(H) || !isfinite(S)) flag_error(e.h, kErrNonFinite);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_small_pack(const SmallEntry *__restrict__ tab,
+                                                    int count) {
+  const int p = small_find(tab, count, blockIdx.x, 1);
+  const SmallEntry &e = tab[p];
+  const int64_t tile = (int64_t)blockIdx.x - e.tile0;
+  if (tile < 0 || tile >= e.nt) return;
+  pack_tile(e.P, e.a, e.m, e.r, e.n, e.nb, e.ppart, e.nz, e.tmap, tile);
+}
+
+__global__ __launch_bounds__(256) void k_small_slots(const SmallEntry *__restrict__ tab,
+                                                     int count) {
+  const int p = small_find(tab, count, blockIdx.x, 2);
+  const SmallEntry &e = tab[p];
+  const int64_t b = (int64_t)blockIdx.x - e.blk0;
+  if (b < 0 || b >= e.nb) return;
+  slot_list_wg(e.nz, e.nb, e.slots, e.nslots, (int)b);
+}
+
+// One workgroup per problem: the sums of P (marks the problem ready), then
+// the tile lists.
+__global__ __launch_bounds__(1024) void k_small_lists(const SmallEntry *__restrict__ tab) {
+  const SmallEntry &e = tab[blockIdx.x];
+  pack_reduce_wg(e.ppart, e.nt, e.h);
+  __syncthreads();
+  tile_lists_wg(e.nz, e.nt, e.tlist, e.tcount);
 }
 
 }  // namespace
@@ -1242,6 +1462,61 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
     hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
   }
   pack();
+  return hipGetLastError();
+}
+
+void small_entry(const Layout &L, void *ws, const float *x, double perplexity, SmallEntry &e) {
+  e.x = x;
+  e.n = L.n;
+  e.nt = L.nt;
+  e.d = L.d;
+  e.nb = L.nb;
+  e.perplexity = perplexity;
+  e.h = at<Hdr>(ws, L.hdr);
+  e.a = at<float>(ws, L.a);
+  e.m = at<float>(ws, L.m);
+  e.r = at<float>(ws, L.r);
+  e.beta = at<double>(ws, L.beta);
+  e.S = at<double>(ws, L.S);
+  e.H = at<double>(ws, L.H);
+  e.evals = at<int32_t>(ws, L.evals);
+  e.P = at<float4>(ws, L.P);
+  e.ppart = at<double2>(ws, L.ppart);
+  e.nz = at<uint8_t>(ws, L.nz);
+  e.tmap = at<int2>(ws, L.tmap);
+  e.tlist = at<int32_t>(ws, L.tlist);
+  e.tcount = at<int32_t>(ws, L.tcount);
+  e.slots = at<int32_t>(ws, L.slots);
+  e.nslots = at<int32_t>(ws, L.nslots);
+  e.perm = at<int32_t>(ws, L.perm);
+  e.inv = at<int32_t>(ws, L.inv);
+}
+
+hipError_t launch_affinities_small(const SmallEntry *tab, int count, int64_t wgs, int64_t tiles,
+                                   int64_t blocks, int64_t nmax, int32_t dmax, int max_bisect,
+                                   double tol_h, hipStream_t st) {
+  if (nmax > kSmallMaxN || dmax > kSmallMaxD || count < 1) return hipErrorInvalidValue;
+  const int32_t dstride = dmax | 1;  // odd row stride: conflict-free LDS reads
+  const size_t lds = (size_t)(64 + kSmallRows) * dstride * sizeof(float);
+  hipLaunchKernelGGL(k_small_init, dim3((unsigned)blocks), dim3(256), 0, st, tab, count);
+  const dim3 g((unsigned)wgs), b(256);
+  const int vpt = (int)((nmax + 63) / 64);
+  if (vpt <= 4)
+    hipLaunchKernelGGL(k_small_calibrate<4>, g, b, lds, st, tab, count, dstride, max_bisect, tol_h);
+  else if (vpt <= 8)
+    hipLaunchKernelGGL(k_small_calibrate<8>, g, b, lds, st, tab, count, dstride, max_bisect, tol_h);
+  else if (vpt <= 16)
+    hipLaunchKernelGGL(k_small_calibrate<16>, g, b, lds, st, tab, count, dstride, max_bisect,
+                       tol_h);
+  else if (vpt <= 32)
+    hipLaunchKernelGGL(k_small_calibrate<32>, g, b, lds, st, tab, count, dstride, max_bisect,
+                       tol_h);
+  else
+    hipLaunchKernelGGL(k_small_calibrate<64>, g, b, lds, st, tab, count, dstride, max_bisect,
+                       tol_h);
+  hipLaunchKernelGGL(k_small_pack, dim3((unsigned)tiles), dim3(256), 0, st, tab, count);
+  hipLaunchKernelGGL(k_small_slots, dim3((unsigned)blocks), dim3(256), 0, st, tab, count);
+  hipLaunchKernelGGL(k_small_lists, dim3((unsigned)count), dim3(1024), 0, st, tab);
   return hipGetLastError();
 }
 

@@ -114,6 +114,28 @@ struct BatchEntry {
 };
 
 // Header of a batch workspace, followed by `count` BatchEntry records.
+// Affinities of many small problems at once (n <= kSmallMaxN, d <=
+// kSmallMaxD, FP64 distances, the caller's order): one launch per phase for
+// all of them. Device table entry of one problem; wg0, tile0 and blk0 are
+// the problem's first workgroup (four rows each), tile and row block.
+constexpr int64_t kSmallMaxN = 4096;
+constexpr int32_t kSmallMaxD = 128;
+struct SmallEntry {
+  const float *x;
+  int64_t n, nt, wg0, tile0, blk0;
+  int32_t d, nb;
+  double perplexity;
+  Hdr *h;
+  float *a, *m, *r;
+  double *beta, *S, *H;
+  int32_t *evals;
+  float4 *P;
+  double2 *ppart;
+  uint8_t *nz;
+  int2 *tmap;
+  int32_t *tlist, *tcount, *slots, *nslots, *perm, *inv;
+};
+
 constexpr uint64_t kBatchMagic = 0x7453424154434801ull;
 struct BatchHdr {
   uint64_t magic;
@@ -133,6 +155,13 @@ inline P *at(void *ws, size_t off) {
 // ---------------------------------------------------------------------------
 hipError_t launch_affinities(const Layout &L, const float *x, double perplexity, int max_bisect,
                              double tol_h, int reorder, void *ws, hipStream_t stream);
+// Fills the table entry of a problem whose workspace has layout L.
+void small_entry(const Layout &L, void *ws, const float *x, double perplexity, SmallEntry &e);
+// tab: device copy of `count` entries with prefix offsets filled in; wgs,
+// tiles, blocks: their totals; nmax, dmax: the largest n and d.
+hipError_t launch_affinities_small(const SmallEntry *tab, int count, int64_t wgs, int64_t tiles,
+                                   int64_t blocks, int64_t nmax, int32_t dmax, int max_bisect,
+                                   double tol_h, hipStream_t stream);
 hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t stream);
 hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
                          float mu, float eta, float min_gain, int recentre, int lr_rule,

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/tsne355.h"
+#include "tsne_internal.h"
 
 namespace {
 
@@ -46,8 +47,11 @@ struct PtLayout {
   std::vector<size_t> ws;        // offset of each partial problem's workspace
   std::vector<size_t> wsb;       // its size
   size_t hdr = 0, rowtab = 0, xk = 0, yk = 0, uk = 0, gk = 0, src = 0, lay = 0, costs = 0,
-         ext = 0, batch = 0, batch_bytes = 0, total = 0;
-  int64_t zmin = 0;
+         ext = 0, batch = 0, batch_bytes = 0, smalltab = 0, total = 0;
+  int64_t zmin = 0, zmax = 0;
+  // totals of the batched small-problem affinity path (used when `small`)
+  bool small = false;
+  int64_t small_wgs = 0, small_tiles = 0, small_blocks = 0;
 };
 
 int64_t chunk_size(int64_t n, int32_t T, int32_t c) { return n / T + (c < n % T ? 1 : 0); }
@@ -68,7 +72,22 @@ bool make_pt_layout(int64_t n, int32_t d, const tsne_pt_opts &o, PtLayout &P) {
   }
   P.rows = P.row0[P.T];
   P.zmin = P.z[0];
-  for (int64_t s : P.z) P.zmin = s < P.zmin ? s : P.zmin;
+  P.zmax = P.z[0];
+  for (int64_t s : P.z) {
+    P.zmin = s < P.zmin ? s : P.zmin;
+    P.zmax = s > P.zmax ? s : P.zmax;
+  }
+  // every partial problem small enough for the batched one-wave-per-row path
+  P.small = o.dist_mode == TSNE_DIST_FP64 && o.reorder == 0 && P.zmax <= tsne::kSmallMaxN &&
+            d <= tsne::kSmallMaxD;
+  if (P.small) {
+    for (int64_t s : P.z) {
+      const tsne::Layout L = tsne::make_layout(s, d, TSNE_DIST_FP64);
+      P.small_wgs += (s + 3) / 4;
+      P.small_tiles += L.nt;
+      P.small_blocks += L.nb;
+    }
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t at = off;
@@ -88,6 +107,7 @@ bool make_pt_layout(int64_t n, int32_t d, const tsne_pt_opts &o, PtLayout &P) {
   P.batch_bytes = tsne_batch_workspace_bytes(P.T);
   if (P.batch_bytes == 0) return false;
   P.batch = take(P.batch_bytes);
+  P.smalltab = take((size_t)P.T * sizeof(tsne::SmallEntry));
   P.ws.resize(P.T);
   P.wsb.resize(P.T);
   for (int32_t k = 0; k < P.T; ++k) {
@@ -152,6 +172,20 @@ int check_ws(void *ws, size_t bytes, const PtLayout &P) {
     return pt_fail(TSNE_E_WORKSPACE, "tsne_pt: workspace %lld bytes, need %lld", (long long)bytes,
                    (long long)P.total);
   return TSNE_OK;
+}
+
+// Prefix offsets of the small-problem table (first workgroup of four rows,
+// first tile, first row block of each problem); the totals are the layout's.
+void small_prefix(std::vector<tsne::SmallEntry> &tab) {
+  int64_t w = 0, t = 0, b = 0;
+  for (auto &e : tab) {
+    e.wg0 = w;
+    e.tile0 = t;
+    e.blk0 = b;
+    w += (e.n + 3) / 4;
+    t += e.nt;
+    b += e.nb;
+  }
 }
 
 std::vector<tsne_batch_problem> problems_of(const PtLayout &P, void *ws) {
@@ -368,6 +402,19 @@ TSNE_API int tsne_pt_init(int64_t n, int32_t d, const tsne_pt_opts *opts, void *
   std::vector<tsne_batch_problem> pr = problems_of(P, ws);
   int rc = tsne_batch_plan(pr.data(), P.T, at<char>(ws, P.batch), P.batch_bytes, stream);
   if (rc != TSNE_OK) return nested_fail(rc, "tsne_pt_init: batch plan", -1);
+  if (P.small) {
+    std::vector<tsne::SmallEntry> tab(P.T);
+    for (int32_t k = 0; k < P.T; ++k) {
+      const tsne::Layout L = tsne::make_layout(P.z[k], d, TSNE_DIST_FP64);
+      tsne::small_entry(L, at<char>(ws, P.ws[k]), at<float>(ws, P.xk) + P.row0[k] * d,
+                        opts->perplexity, tab[k]);
+    }
+    small_prefix(tab);
+    e = hipMemcpyAsync(at<char>(ws, P.smalltab), tab.data(), tab.size() * sizeof(tab[0]),
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "tsne_pt_init (small table)");
+  }
   g_pt_err[0] = '\0';
   return TSNE_OK;
 }
@@ -396,7 +443,13 @@ TSNE_API int tsne_pt_epoch(const float *x, int64_t n, int32_t d, const tsne_pt_o
 
   std::vector<tsne_batch_problem> pr = problems_of(P, ws);
   const tsne_aff_opts ao = {opts->dist_mode, 200, 1e-6, opts->reorder, 0};
-  {
+  if (P.small) {
+    // all partial problems in one launch per phase
+    e = tsne::launch_affinities_small(at<const tsne::SmallEntry>(ws, P.smalltab), P.T, P.small_wgs,
+                                      P.small_tiles, P.small_blocks, P.zmax, d, ao.max_bisect,
+                                      ao.tol_h, st);
+    if (e != hipSuccess) return hip_fail(e, "tsne_pt_epoch (affinities)");
+  } else {
     // affinities of every partial problem, spread over the side streams
     std::lock_guard<std::mutex> lock(g_pt_mu);
     PtStreams *ps = nullptr;
