@@ -283,6 +283,14 @@ TSNE_API int tsne_pt_epoch(const float *x, int64_t n, int32_t d, const tsne_pt_o
 TSNE_API int tsne_pt_sync_status(int64_t n, int32_t d, const tsne_pt_opts *opts, void *ws,
                                  size_t bytes, void *stream);
 
+/* Test hook: the workspace of partial problem k (0 <= k < threads) inside the
+ * ptSNE workspace, and its number of points. Host-only pointer arithmetic;
+ * after an epoch the single-problem export hooks read that epoch's
+ * affinities of the partial problem through it (rows in the order of the
+ * thread's chunks k, k+1, ..., each in the epoch's order). */
+TSNE_API int tsne_pt_partial(int64_t n, int32_t d, const tsne_pt_opts *opts, void *ws,
+                             size_t bytes, int32_t k, void **ws_k, int64_t *n_k);
+
 /* Message of the last failing tsne_pt_* call on this thread. */
 TSNE_API const char *tsne_pt_last_error(void);
 

@@ -57,6 +57,7 @@ EXPORTED = [
     "tsne_pt_epoch",
     "tsne_pt_sync_status",
     "tsne_pt_last_error",
+    "tsne_pt_partial",
 ]
 
 
@@ -145,6 +146,9 @@ def load(path: str = LIB_PATH):
         "tsne_pt_sync_status": (ctypes.c_int, [_i64, _i32, ctypes.POINTER(PtOpts), _vp,
                                                ctypes.c_size_t, _vp]),
         "tsne_pt_last_error": (ctypes.c_char_p, []),
+        "tsne_pt_partial": (ctypes.c_int, [_i64, _i32, ctypes.POINTER(PtOpts), _vp,
+                                           ctypes.c_size_t, _i32, ctypes.POINTER(_vp),
+                                           ctypes.POINTER(_i64)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -406,3 +410,12 @@ def pt_sync_status(n: int, d: int, opts: PtOpts, ws) -> int:
     return int(load().tsne_pt_sync_status(n, d, ctypes.byref(opts),
                                           _ptr(ws, torch.uint8, name="ws"), ws.numel(),
                                           _stream()))
+
+
+def pt_partial(n: int, d: int, opts: PtOpts, ws, k: int):
+    """(workspace view, n_k) of partial problem k (a uint8 tensor over its bytes)."""
+    ptr, nk = _vp(), _i64()
+    _check_pt(load().tsne_pt_partial(n, d, ctypes.byref(opts), _ptr(ws, torch.uint8, name="ws"),
+                                     ws.numel(), k, ctypes.byref(ptr), ctypes.byref(nk)))
+    off = ptr.value - ws.data_ptr()
+    return ws[off:off + workspace_bytes(nk.value, d, opts.dist_mode)], nk.value

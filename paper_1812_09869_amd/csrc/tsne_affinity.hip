@@ -2,8 +2,8 @@
 // Eqs. 1-3 of the bigMap paper):
 //   1. centre X (distances are translation invariant) and form row norms;
 //   2. per block of T rows: squared distances to all points on MFMA
-//      (d_ij = |x_i|^2 + |x_j|^2 - 2 x_i.x_j), a per-row bisection on the
-//      Gaussian precision beta_i so that the entropy of p_{.|i} equals
+//      (d_ij = |x_i|^2 + |x_j|^2 - 2 x_i.x_j), a per-row bracketed search on
+//      the Gaussian precision beta_i so that the entropy of p_{.|i} equals
 //      ln(perplexity), and a copy of the block's upper-triangle tiles into
 //      the P store;
 //   3. in place over the stored tiles: p_ij = (p_{j|i} + p_{i|j}) / (2n).
@@ -334,17 +334,21 @@ __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa, const
 }
 
 // ----------------------------------------------------------------------------
-// 2b. Per-row bisection on beta (Eqs. 1-2).
+// 2b. Per-row search for beta (Eqs. 1-2).
 //
 // One workgroup of 1024 threads per row. The row's distances, shifted by the
 // row minimum m, are held in registers (VPT per thread) when they fit, else
 // re-read from the block scratch on every pass. Each pass forms, with FP32
 // exponentials and FP32 per-thread partial sums combined in FP64,
 //   S = sum_j exp(-beta (d_j - m)),  T = sum_j (d_j - m) exp(-beta (d_j - m)),
-//   H = ln S + beta T / S,
-// where beta is the FP32-rounded precision actually applied. Bracket logic:
-// start at beta = 1 with [0, inf); a too-high entropy doubles beta until an
-// upper end exists, then each pass halves the bracket. Stops at
+//   Q = sum_j (d_j - m)^2 exp(-beta (d_j - m)),
+//   H = ln S + beta T / S,  dH/dbeta = -beta (Q / S - (T / S)^2),
+// where beta is the FP32-rounded precision actually applied. The paper
+// leaves the search to a supplement it does not include; H decreases in
+// beta, so any bracketed search that reaches the tolerance finds the same
+// root. Bracket logic: start at beta = 1 with [0, inf); each pass moves one
+// end of the bracket to beta, then takes the Newton step if it lands inside
+// the bracket, else doubles beta (no upper end yet) or bisects. Stops at
 // |H - ln u| <= tol_h, at a bracket narrower than FP32 resolution, or after
 // max_bisect passes (then the row is flagged as not converged).
 // ----------------------------------------------------------------------------
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restri
                                                            int64_t n, int64_t npad, int32_t b,
                                                            double logu, int max_bisect,
                                                            double tol_h, CalOut out, Hdr *h) {
-  __shared__ double sred[2][kCalThreads / 64];
+  __shared__ double sred[3][kCalThreads / 64];
   __shared__ float smin[kCalThreads / 64];
   __shared__ double sbeta;
   __shared__ int sdone;
@@ -403,37 +407,44 @@ __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restri
   for (;;) {
     ++it;
     a = fmaxf((float)(beta * kLog2e), 1e-30f);
-    float s = 0.f, tt = 0.f;
+    float s = 0.f, tt = 0.f, qq = 0.f;
     if constexpr (VPT > 0) {
 #pragma unroll
       for (int q = 0; q < VPT; ++q) {
-        float e = __builtin_amdgcn_exp2f(-a * v[q]);
+        const float e = __builtin_amdgcn_exp2f(-a * v[q]);
+        const float ve = v[q] * e;  // 0 for an excluded entry (e = 0)
         s += e;
-        tt = fmaf(v[q], e, tt);
+        tt += ve;
+        qq = fmaf(v[q], ve, qq);
       }
     } else {
       for (int64_t j = tid; j < n; j += kCalThreads) {
-        float dm = (j == i) ? kBig : row[j] - m;
-        float e = __builtin_amdgcn_exp2f(-a * dm);
+        const float dm = (j == i) ? kBig : row[j] - m;
+        const float e = __builtin_amdgcn_exp2f(-a * dm);
+        const float ve = dm * e;
         s += e;
-        tt = fmaf(dm, e, tt);
+        tt += ve;
+        qq = fmaf(dm, ve, qq);
       }
     }
-    double ds = wave_sum_d((double)s), dt = wave_sum_d((double)tt);
+    double ds = wave_sum_d((double)s), dt = wave_sum_d((double)tt), dq = wave_sum_d((double)qq);
     if (ln == 0) {
       sred[0][wv] = ds;
       sred[1][wv] = dt;
+      sred[2][wv] = dq;
     }
     __syncthreads();
     if (tid == 0) {
-      double SS = 0.0, TT = 0.0;
+      double SS = 0.0, TT = 0.0, QQ = 0.0;
       for (int q = 0; q < kCalThreads / 64; ++q) {
         SS += sred[0][q];
         TT += sred[1][q];
+        QQ += sred[2][q];
       }
       const double beff = (double)a * kLn2;
       S = SS;
-      H = log(SS) + beff * TT / SS;
+      const double mean = TT / SS;
+      H = log(SS) + beff * mean;
       int done = 0;
       if (fabs(H - logu) <= tol_h) {
         done = 1;
@@ -441,12 +452,20 @@ __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restri
         done = 1;
       } else if (it >= max_bisect) {
         done = 2;
-      } else if (H > logu) {
-        lo = beta;
-        beta = isinf(hi) ? 2.0 * beta : 0.5 * (beta + hi);
       } else {
-        hi = beta;
-        beta = 0.5 * (lo + beta);
+        // H falls with beta (dH/dbeta = -beta Var(d)): shrink the bracket of
+        // FP64 iterates, then take the Newton step if it lands inside it,
+        // else bisect (H was taken at beff, within 2^-24 of beta)
+        if (H > logu)
+          lo = beta;
+        else
+          hi = beta;
+        const double var = QQ / SS - mean * mean;
+        const double nb = beta + (H - logu) / (beff * var);
+        if (var > 0.0 && nb > lo && nb < hi && isfinite(nb))
+          beta = nb;
+        else
+          beta = isinf(hi) ? 2.0 * beta : 0.5 * (lo + hi);
       }
       sbeta = beta;
       sdone = done;
@@ -1090,12 +1109,11 @@ __global__ __launch_bounds__(256) void k_slot_lists(const uint8_t *__restrict__ 
 // distances (FP64 direct differences, rounded to FP32 like the distance
 // block of the large path) stay in registers for the bisection, whose sums
 // are wave reductions, so no workgroup barrier sits inside the search. The
-// four rows of a workgroup belong to one problem and share the staging of
+// rows of a workgroup belong to one problem and share the staging of
 // the other points' coordinates in LDS. The distances of tiles (I, J >= I)
 // go straight into the P store in consumer order; the pack, reduction and
 // list steps are the same device code as the single-problem path.
 // ----------------------------------------------------------------------------
-constexpr int kSmallRows = 4;  // rows (waves) per workgroup
 
 __device__ inline int small_find(const SmallEntry *tab, int count, int64_t key, int which) {
   int lo = 0, hi = count - 1;
@@ -1144,44 +1162,66 @@ __global__ __launch_bounds__(256) void k_small_init(const SmallEntry *__restrict
 }
 
 template <int VPT>
-__global__ __launch_bounds__(256) void k_small_calibrate(const SmallEntry *__restrict__ tab,
-                                                         int count, int32_t dstride,
-                                                         int max_bisect, double tol_h) {
-  extern __shared__ float sx[];  // [64][dstride] other points, then [4][dstride] own rows
+__global__ __launch_bounds__(kSmallRows * 64) void k_small_calibrate(
+    const SmallEntry *__restrict__ tab, int count, int32_t dstride, int max_bisect,
+    double tol_h) {
+  // LDS (FP64, converted once): two buffers of 64 points ([64][dstride]
+  // each), then the own rows
+  extern __shared__ double sx[];
+  constexpr int kThr = kSmallRows * 64;
+  constexpr int kPre = 64 * kSmallMaxD / kThr;  // prefetch registers per thread
   const int p = small_find(tab, count, blockIdx.x, 0);
   const SmallEntry &e = tab[p];
   const int64_t n = e.n;
   const int32_t d = e.d;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t i = ((int64_t)blockIdx.x - e.wg0) * kSmallRows + w;
+  const int64_t r0 = ((int64_t)blockIdx.x - e.wg0) * kSmallRows;
+  const int64_t i = r0 + w;
   const bool row_ok = i < n;
-  float *own = sx + 64 * dstride;
-  for (int q = threadIdx.x; q < kSmallRows * d; q += 256) {
+  double *own = sx + 2 * 64 * dstride;
+  for (int q = threadIdx.x; q < kSmallRows * d; q += kThr) {
     const int rr = q / d, k = q - rr * d;
-    const int64_t ii = ((int64_t)blockIdx.x - e.wg0) * kSmallRows + rr;
-    own[rr * dstride + k] = ii < n ? e.x[ii * d + k] : 0.f;
+    own[rr * dstride + k] = (r0 + rr) < n ? (double)e.x[(r0 + rr) * d + k] : 0.0;
   }
+  const int nchunk = (int)((n + 63) / 64);
+  // chunk c holds points 64c .. 64c + 63 as rows of d floats (contiguous in x)
+  auto fetch = [&](int c, float (&pre)[kPre]) {
+    const int64_t base = (int64_t)c * 64 * d, lim = (n - (int64_t)c * 64) * d;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int idx = threadIdx.x + u * kThr;
+      pre[u] = (idx < 64 * d && idx < lim) ? e.x[base + idx] : 0.f;
+    }
+  };
+  auto put = [&](int c, const float (&pre)[kPre]) {
+    double *buf = sx + (c & 1) * 64 * dstride;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int idx = threadIdx.x + u * kThr;
+      if (idx < 64 * d) {
+        const int rr = idx / d, k = idx - rr * d;
+        buf[rr * dstride + k] = (double)pre[u];
+      }
+    }
+  };
+  float pre[kPre];
+  fetch(0, pre);
+  put(0, pre);
+  __syncthreads();
   const int I = (int)(i / T), il = (int)(i - (int64_t)I * T);
   float v[VPT];
   bool bad = false;
 #pragma unroll
   for (int q = 0; q < VPT; ++q) {
     v[q] = INFINITY;
-    if ((int64_t)q * 64 < n) {  // uniform over the workgroup
-      __syncthreads();
-      const int64_t c0 = (int64_t)q * 64;
-      const int rows = (int)((n - c0) < 64 ? (n - c0) : 64);
-      for (int idx = threadIdx.x; idx < rows * d; idx += 256) {
-        const int rr = idx / d, k = idx - rr * d;
-        sx[rr * dstride + k] = e.x[(c0 + rr) * d + k];
-      }
-      __syncthreads();
-      const int64_t j = c0 + l;
+    if (q < nchunk) {  // uniform over the workgroup
+      if (q + 1 < nchunk) fetch(q + 1, pre);  // in flight while this chunk is used
+      const int64_t j = (int64_t)q * 64 + l;
       if (row_ok && j < n) {
         double acc = 0.0;
-        const float *xj = sx + l * dstride, *xi = own + w * dstride;
+        const double *xj = sx + (q & 1) * 64 * dstride + l * dstride, *xi = own + w * dstride;
         for (int k = 0; k < d; ++k) {
-          const double df = (double)xj[k] - (double)xi[k];
+          const double df = xj[k] - xi[k];
           acc = fma(df, df, acc);
         }
         const float dv = (float)acc;
@@ -1194,6 +1234,8 @@ __global__ __launch_bounds__(256) void k_small_calibrate(const SmallEntry *__res
         }
         if (j != i) v[q] = dv;
       }
+      if (q + 1 < nchunk) put(q + 1, pre);  // the other buffer: last read two chunks ago
+      __syncthreads();
     }
   }
   if (!row_ok) return;  // no barrier below this point
@@ -1210,31 +1252,44 @@ __global__ __launch_bounds__(256) void k_small_calibrate(const SmallEntry *__res
   while (!done) {
     ++it;
     a = fmaxf((float)(beta * kLog2e), 1e-30f);
-    float s = 0.f, tt = 0.f;
+    float s = 0.f, tt = 0.f, qq = 0.f;
 #pragma unroll
     for (int q = 0; q < VPT; ++q) {
       const float ex = __builtin_amdgcn_exp2f(-a * v[q]);
+      const float ve = v[q] * ex;  // 0 for an excluded entry (ex = 0)
       s += ex;
-      tt = fmaf(v[q], ex, tt);
+      tt += ve;
+      qq = fmaf(v[q], ve, qq);
     }
     // butterfly sums: every lane holds the same totals, so the search below
     // takes the same branch in every lane
     const double SS = wave_sum_d((double)s), TT = wave_sum_d((double)tt);
+    const double QQ = wave_sum_d((double)qq);
     const double beff = (double)a * kLn2;
     S = SS;
-    H = log(SS) + beff * TT / SS;
+    const double mean = TT / SS;
+    H = log(SS) + beff * mean;
     if (fabs(H - logu) <= tol_h) {
       done = 1;
     } else if (isfinite(hi) && (hi - lo) <= hi * 0x1p-24) {
       done = 1;
     } else if (it >= max_bisect) {
       done = 2;
-    } else if (H > logu) {
-      lo = beta;
-      beta = isinf(hi) ? 2.0 * beta : 0.5 * (beta + hi);
     } else {
-      hi = beta;
-      beta = 0.5 * (lo + beta);
+      // H falls with beta (dH/dbeta = -beta Var(d)): shrink the bracket,
+      // then take the Newton step if it lands inside it, else bisect
+      // (the bracket holds the FP64 iterates; H was taken at their FP32
+      // rounding beff, within 2^-24 of beta)
+      if (H > logu)
+        lo = beta;
+      else
+        hi = beta;
+      const double var = QQ / SS - mean * mean;
+      const double nb = beta + (H - logu) / (beff * var);
+      if (var > 0.0 && nb > lo && nb < hi && isfinite(nb))
+        beta = nb;
+      else
+        beta = isinf(hi) ? 2.0 * beta : 0.5 * (lo + hi);
     }
   }
   bad = __any(bad);
@@ -1497,9 +1552,9 @@ hipError_t launch_affinities_small(const SmallEntry *tab, int count, int64_t wgs
                                    double tol_h, hipStream_t st) {
   if (nmax > kSmallMaxN || dmax > kSmallMaxD || count < 1) return hipErrorInvalidValue;
   const int32_t dstride = dmax | 1;  // odd row stride: conflict-free LDS reads
-  const size_t lds = (size_t)(64 + kSmallRows) * dstride * sizeof(float);
+  const size_t lds = (size_t)(2 * 64 + kSmallRows) * dstride * sizeof(double);
   hipLaunchKernelGGL(k_small_init, dim3((unsigned)blocks), dim3(256), 0, st, tab, count);
-  const dim3 g((unsigned)wgs), b(256);
+  const dim3 g((unsigned)wgs), b(kSmallRows * 64);
   const int vpt = (int)((nmax + 63) / 64);
   if (vpt <= 4)
     hipLaunchKernelGGL(k_small_calibrate<4>, g, b, lds, st, tab, count, dstride, max_bisect, tol_h);

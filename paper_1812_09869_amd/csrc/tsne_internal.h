@@ -117,9 +117,10 @@ struct BatchEntry {
 // Affinities of many small problems at once (n <= kSmallMaxN, d <=
 // kSmallMaxD, FP64 distances, the caller's order): one launch per phase for
 // all of them. Device table entry of one problem; wg0, tile0 and blk0 are
-// the problem's first workgroup (four rows each), tile and row block.
+// the problem's first workgroup (kSmallRows rows each), tile and row block.
 constexpr int64_t kSmallMaxN = 4096;
-constexpr int32_t kSmallMaxD = 128;
+constexpr int32_t kSmallMaxD = 64;
+constexpr int kSmallRows = 8;  // rows (one wave each) per workgroup of the search
 struct SmallEntry {
   const float *x;
   int64_t n, nt, wg0, tile0, blk0;

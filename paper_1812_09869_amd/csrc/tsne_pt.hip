@@ -83,7 +83,7 @@ bool make_pt_layout(int64_t n, int32_t d, const tsne_pt_opts &o, PtLayout &P) {
   if (P.small) {
     for (int64_t s : P.z) {
       const tsne::Layout L = tsne::make_layout(s, d, TSNE_DIST_FP64);
-      P.small_wgs += (s + 3) / 4;
+      P.small_wgs += (s + tsne::kSmallRows - 1) / tsne::kSmallRows;
       P.small_tiles += L.nt;
       P.small_blocks += L.nb;
     }
@@ -174,7 +174,7 @@ int check_ws(void *ws, size_t bytes, const PtLayout &P) {
   return TSNE_OK;
 }
 
-// Prefix offsets of the small-problem table (first workgroup of four rows,
+// Prefix offsets of the small-problem table (first workgroup of kSmallRows rows,
 // first tile, first row block of each problem); the totals are the layout's.
 void small_prefix(std::vector<tsne::SmallEntry> &tab) {
   int64_t w = 0, t = 0, b = 0;
@@ -182,7 +182,7 @@ void small_prefix(std::vector<tsne::SmallEntry> &tab) {
     e.wg0 = w;
     e.tile0 = t;
     e.blk0 = b;
-    w += (e.n + 3) / 4;
+    w += (e.n + tsne::kSmallRows - 1) / tsne::kSmallRows;
     t += e.nt;
     b += e.nb;
   }
@@ -516,6 +516,19 @@ TSNE_API int tsne_pt_sync_status(int64_t n, int32_t d, const tsne_pt_opts *opts,
     int rc = tsne_sync_status(at<char>(ws, P.ws[k]), stream);
     if (rc != TSNE_OK) return nested_fail(rc, "tsne_pt: device condition", k);
   }
+  return TSNE_OK;
+}
+
+TSNE_API int tsne_pt_partial(int64_t n, int32_t d, const tsne_pt_opts *opts, void *ws,
+                             size_t bytes, int32_t k, void **ws_k, int64_t *n_k) {
+  PtLayout P;
+  if (int rc = check_pt(n, d, opts, P)) return rc;
+  if (int rc = check_ws(ws, bytes, P)) return rc;
+  if (k < 0 || k >= P.T || !ws_k || !n_k)
+    return pt_fail(TSNE_E_ARG, "tsne_pt_partial: partial problem %lld out of range", k);
+  *ws_k = at<char>(ws, P.ws[k]);
+  *n_k = P.z[k];
+  g_pt_err[0] = '\0';
   return TSNE_OK;
 }
 

@@ -76,3 +76,40 @@ def test_order_out_of_range_is_reported():
     bad[17] = 600
     pt.epoch(torch.from_numpy(bad).cuda())
     assert pt.status() == 1  # TSNE_E_ARG
+
+
+@pytest.mark.parametrize("n,threads,layers,perp", [(1000, 5, 2, 20.0), (1003, 16, 4, 15.0),
+                                                    (3000, 2, 2, 100.0)])
+def test_partial_affinities_match_oracle(n, threads, layers, perp):
+    """The affinities of every partial problem after an epoch (the batched
+    small-problem path when every partial problem has at most 4,096 points)
+    against the oracle's P of the same points (Eqs. 1-3), with the same gates
+    as the single-problem path: relative Frobenius and max-entry errors of P
+    <= 1e-5, |H_i - ln u| <= 1e-5, every row converged."""
+    import math
+
+    import oracle
+    from paper_1812_09869_amd import _lib
+    x, y0, orders, _, _, _ = _setup(n=n, epochs=1, seed=91)
+    pt = PTSNE(torch.from_numpy(x).cuda(), threads, layers, perp)
+    pt.init_maps(torch.from_numpy(y0).cuda())
+    pt.epoch(torch.from_numpy(orders[0]).cuda())
+    assert pt.status() == 0
+    passes = []
+    for k in range(threads):
+        idx, _ = ptsne.thread_members(orders[0], threads, layers, k)
+        xk = x[idx]
+        P_ref = oracle.joint_p(xk, oracle.calibrate(xk, perp))
+        ws_k, z = _lib.pt_partial(n, x.shape[1], pt.opts, pt.ws, k)
+        assert z == idx.shape[0]
+        pg = _lib.export_p_rows(ws_k, z, 0, z).cpu().numpy().astype(np.float64)
+        _, _, _, H, ev = (t.cpu().numpy() for t in _lib.export_rowstats(ws_k, z))
+        diff = pg - P_ref
+        fro = np.linalg.norm(diff) / np.linalg.norm(P_ref)
+        mx = np.abs(diff).max() / np.abs(P_ref).max()
+        assert np.array_equal(pg, pg.T) and np.all(np.diag(pg) == 0)
+        assert fro <= 1e-5 and mx <= 1e-5, (k, fro, mx)
+        assert np.all(ev > 0)
+        assert np.abs(H - math.log(perp)).max() <= 1e-5
+        passes.append(ev.mean())
+    print(f"\n  P ok for {threads} partial problems; mean search passes {np.mean(passes):.1f}")
