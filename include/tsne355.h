@@ -220,6 +220,12 @@ TSNE_API int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, 
 TSNE_API int tsne_batch_step(const tsne_batch_problem *problems, int32_t count,
                              const void *batch_ws, const tsne_step_params *prm, void *stream);
 
+/* The cost of tsne_cost (Eqs. 5 and 9) of every problem at its current map
+ * y, in one launch per phase. out: device double[2 count], {KL, C_norm} of
+ * problem p at out[2p]. */
+TSNE_API int tsne_batch_cost(const tsne_batch_problem *problems, int32_t count,
+                             const void *batch_ws, double *out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Parallel scheme, ptSNE (section "Parallelized implementation"). The n
  * points are split into `threads` chunks, contiguous pieces of a per-epoch

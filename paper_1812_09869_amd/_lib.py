@@ -46,6 +46,7 @@ EXPORTED = [
     "tsne_batch_workspace_bytes",
     "tsne_batch_plan",
     "tsne_batch_step",
+    "tsne_batch_cost",
     "tsne_mlp_param_count",
     "tsne_mlp_workspace_bytes",
     "tsne_mlp_forward",
@@ -129,6 +130,7 @@ def load(path: str = LIB_PATH):
                                            ctypes.c_size_t, _vp]),
         "tsne_batch_step": (ctypes.c_int, [ctypes.POINTER(BatchProblem), _i32, _vp,
                                            ctypes.POINTER(StepParams), _vp]),
+        "tsne_batch_cost": (ctypes.c_int, [ctypes.POINTER(BatchProblem), _i32, _vp, _vp, _vp]),
         "tsne_mlp_param_count": (ctypes.c_int64, [_i32, _i32]),
         "tsne_mlp_workspace_bytes": (ctypes.c_size_t, [_i32, _i32, _i64, _i32]),
         "tsne_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp,
@@ -354,6 +356,13 @@ def batch_plan(arr, device="cuda"):
     bws = torch.empty(nbytes, dtype=torch.uint8, device=device)
     _check(load().tsne_batch_plan(arr, count, _ptr(bws, torch.uint8), nbytes, _stream()))
     return bws
+
+
+def batch_cost(arr, bws, out):
+    """{KL, C_norm} of every problem (out: float64 device tensor of 2 x count)."""
+    _check(load().tsne_batch_cost(arr, len(arr), _ptr(bws, torch.uint8),
+                                  _ptr(out, torch.float64, shape=(len(arr), 2), name="out"),
+                                  _stream()))
 
 
 def batch_step(arr, bws, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True,

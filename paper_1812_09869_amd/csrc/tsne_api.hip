@@ -328,6 +328,7 @@ int tsne_batch_plan(const tsne_batch_problem *problems, int32_t count, void *bat
     e.zpart = tsne::at<float>(ws, L.zpart);
     e.meanpart = tsne::at<double2>(ws, L.meanpart);
     e.extent = tsne::at<float4>(ws, L.extent);
+    e.cpart = tsne::at<double2>(ws, L.cpart);
     e.nz = tsne::at<const uint8_t>(ws, L.nz);
     e.slots = tsne::at<const int32_t>(ws, L.slots);
     e.tmap = tsne::at<const int2>(ws, L.tmap);
@@ -362,6 +363,16 @@ int tsne_batch_step(const tsne_batch_problem *problems, int32_t count, const voi
                                            prm->momentum, prm->learning_rate, prm->min_gain,
                                            prm->recentre, prm->lr_rule, (hipStream_t)stream),
                    "tsne_batch_step");
+}
+
+int tsne_batch_cost(const tsne_batch_problem *problems, int32_t count, const void *batch_ws,
+                    double *out, void *stream) {
+  int64_t tiles, blocks;
+  if (int rc = batch_totals("tsne_batch_cost", problems, count, tiles, blocks)) return rc;
+  if (!batch_ws || !out) return fail(TSNE_E_ARG, "tsne_batch_cost: null pointer");
+  return hip_check(tsne::launch_batch_cost(batch_ws, count, tiles, blocks, out,
+                                           (hipStream_t)stream),
+                   "tsne_batch_cost");
 }
 
 static bool mlp_dims_ok(int32_t d_in, int32_t hidden) {

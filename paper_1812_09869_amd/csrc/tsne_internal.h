@@ -102,6 +102,7 @@ struct BatchEntry {
   float *zpart;
   double2 *meanpart;
   float4 *extent;
+  double2 *cpart;
   const uint8_t *nz;
   const int32_t *slots, *nslots;
   const int2 *tmap;
@@ -171,6 +172,8 @@ hipError_t launch_gradient_only(const Layout &L, void *ws, float alpha, float *g
                                 double *z_out, hipStream_t stream);
 hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out,
                        hipStream_t stream);
+hipError_t launch_batch_cost(const void *batch_ws, int count, int64_t total_tiles,
+                             int64_t total_blocks, double *out, hipStream_t stream);
 hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tiles,
                              int64_t total_blocks, float alpha, float mu, float eta,
                              float min_gain, int recentre, int lr_rule, hipStream_t stream);

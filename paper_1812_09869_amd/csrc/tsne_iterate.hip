@@ -916,17 +916,17 @@ __device__ __forceinline__ void cost_tile(const float4 *__restrict__ tp,
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
-                                                 const float2 *__restrict__ Y, int64_t n,
-                                                 int32_t nb, double2 *__restrict__ cpart,
-                                                 const uint8_t *__restrict__ nz, Hdr *h) {
+__device__ __forceinline__ void cost_wg(const float4 *__restrict__ P,
+                                        const float2 *__restrict__ Y, int64_t n, int32_t nb,
+                                        double2 *__restrict__ cpart,
+                                        const uint8_t *__restrict__ nz, Hdr *h, int64_t tile) {
   __shared__ double red[2][4];
   if (!state_ok(h, n)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
   int I, J;
-  tile_coords(blockIdx.x, nb, I, J);
+  tile_coords(tile, nb, I, J);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
   const uint32_t rvalid = valid_bits(n - (int64_t)I * T, tr);
@@ -936,9 +936,9 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
   for (int k = 0; k < 16; ++k) yc[k] = Y[(int64_t)J * T + tc + 16 * k];
   const float2 *yrow = Y + (int64_t)I * T + tr;
   const bool edge = ((int64_t)(J + 1) * T > n);
-  const float4 *tp = P + (size_t)blockIdx.x * TT4;
+  const float4 *tp = P + (size_t)tile * TT4;
   float plq = 0.f, z = 0.f;
-  if (!nz[blockIdx.x]) {
+  if (!nz[tile]) {
     // no p_ij in this tile: only Z
 #pragma unroll 1
     for (int k = 0; k < 16; ++k) {
@@ -971,14 +971,20 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
   __syncthreads();
   if (t == 0) {
     const double mult = (I == J) ? 1.0 : 2.0;
-    cpart[blockIdx.x] = make_double2(mult * (red[0][0] + red[0][1] + red[0][2] + red[0][3]),
+    cpart[tile] = make_double2(mult * (red[0][0] + red[0][1] + red[0][2] + red[0][3]),
                                      mult * (red[1][0] + red[1][1] + red[1][2] + red[1][3]));
   }
 }
 
-__global__ __launch_bounds__(1024) void k_cost_reduce(const double2 *__restrict__ cpart,
-                                                      int64_t nt, int64_t n, Hdr *h,
-                                                      double *out) {
+__global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
+                                                 const float2 *__restrict__ Y, int64_t n,
+                                                 int32_t nb, double2 *__restrict__ cpart,
+                                                 const uint8_t *__restrict__ nz, Hdr *h) {
+  cost_wg(P, Y, n, nb, cpart, nz, h, blockIdx.x);
+}
+
+__device__ __forceinline__ void cost_reduce_wg(const double2 *__restrict__ cpart, int64_t nt,
+                                               int64_t n, Hdr *h, double *out) {
   __shared__ double red[2][16];
   if (!state_ok(h, n)) return;
   double a = 0.0, c = 0.0;
@@ -1004,6 +1010,34 @@ __global__ __launch_bounds__(1024) void k_cost_reduce(const double2 *__restrict_
     out[1] = cross / (log((double)n) + log((double)n - 1.0));
     if (!isfinite(out[0])) flag_error(h, kErrNonFinite);
   }
+}
+
+__global__ __launch_bounds__(1024) void k_cost_reduce(const double2 *__restrict__ cpart,
+                                                      int64_t nt, int64_t n, Hdr *h,
+                                                      double *out) {
+  cost_reduce_wg(cpart, nt, n, h, out);
+}
+
+// Cost of every problem of a batch: one workgroup per tile, then one per
+// problem (out: device double[2 count], {KL, C_norm} per problem).
+__global__ __launch_bounds__(256, 2) void k_cost_batched(const BatchHdr *__restrict__ bh,
+                                                         int count, int64_t tiles,
+                                                         int64_t blocks) {
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry *tab = batch_table(bh);
+  const int p = find_entry(tab, count, blockIdx.x, true);
+  const BatchEntry &e = tab[p];
+  const int64_t i = (int64_t)blockIdx.x - e.tile0;
+  if (i < 0 || i >= e.nt) return;
+  cost_wg(e.P, e.yp, e.n, e.nb, e.cpart, e.nz, e.h, i);
+}
+
+__global__ __launch_bounds__(1024) void k_cost_reduce_batched(const BatchHdr *__restrict__ bh,
+                                                              int count, int64_t tiles,
+                                                              int64_t blocks, double *out) {
+  if (!batch_ok(bh, count, tiles, blocks)) return;
+  const BatchEntry &e = batch_table(bh)[blockIdx.x];
+  cost_reduce_wg(e.cpart, e.nt, e.n, e.h, out + 2 * (int64_t)blockIdx.x);
 }
 
 }  // namespace
@@ -1105,6 +1139,18 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, h
   hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P), yp,
                      L.n, L.nb, cp, at<const uint8_t>(ws, L.nz), h);
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_cost(const void *batch_ws, int count, int64_t total_tiles,
+                             int64_t total_blocks, double *out, hipStream_t st) {
+  const BatchHdr *bh = reinterpret_cast<const BatchHdr *>(batch_ws);
+  hipLaunchKernelGGL(k_gather_batched, dim3((unsigned)total_blocks), dim3(256), 0, st, bh, count,
+                     total_tiles, total_blocks);
+  hipLaunchKernelGGL(k_cost_batched, dim3((unsigned)total_tiles), dim3(256), 0, st, bh, count,
+                     total_tiles, total_blocks);
+  hipLaunchKernelGGL(k_cost_reduce_batched, dim3((unsigned)count), dim3(1024), 0, st, bh, count,
+                     total_tiles, total_blocks, out);
   return hipGetLastError();
 }
 

@@ -471,20 +471,10 @@ TSNE_API int tsne_pt_epoch(const float *x, int64_t n, int32_t d, const tsne_pt_o
     int rc = tsne_batch_step(pr.data(), P.T, at<char>(ws, P.batch), &prm, stream);
     if (rc != TSNE_OK) return nested_fail(rc, "tsne_pt_epoch: batched step", -1);
   }
-  // monitors of the partial problems, then pool and summarise
+  // monitors of the partial problems (one batched cost), then pool and summarise
   {
-    std::lock_guard<std::mutex> lock(g_pt_mu);
-    PtStreams *ps = nullptr;
-    if ((e = pt_streams(ps)) != hipSuccess || (e = fork_streams(*ps, st)) != hipSuccess)
-      return hip_fail(e, "tsne_pt_epoch (streams)");
-    for (int32_t k = 0; k < P.T; ++k) {
-      int rc = tsne_cost(pr[k].ws, P.z[k], pr[k].y, costs + 2 * k, ps->s[k % kPtStreams]);
-      if (rc != TSNE_OK) {
-        (void)join_streams(*ps, st);
-        return nested_fail(rc, "tsne_pt_epoch: cost", k);
-      }
-    }
-    if ((e = join_streams(*ps, st)) != hipSuccess) return hip_fail(e, "tsne_pt_epoch (join)");
+    int rc = tsne_batch_cost(pr.data(), P.T, at<char>(ws, P.batch), costs, stream);
+    if (rc != TSNE_OK) return nested_fail(rc, "tsne_pt_epoch: batched cost", -1);
   }
   hipLaunchKernelGGL(k_pt_pool, dim3((unsigned)((P.rows + 255) / 256)), dim3(256), 0, st, yk, src,
                      lay, P.rows, n, reinterpret_cast<float2 *>(maps));

@@ -42,6 +42,11 @@ def test_batched_bitwise_equals_single(rule):
         for a, b in zip(batched.states[k], st):
             assert torch.equal(a, b), k
         assert batched.models[k].status() == 0
+    # the batched cost is the single-problem cost, bitwise
+    out = torch.empty((len(sizes), 2), dtype=torch.float64, device="cuda")
+    _lib.batch_cost(batched._arr, batched._bws, out)
+    for k, m in enumerate(batched.models):
+        assert torch.equal(out[k], m.cost(batched.states[k][0])), k
 
 
 def test_batched_matches_oracle_on_smallest_problems():
