@@ -329,6 +329,54 @@ def batched_leg(sweeps=500):
     return res
 
 
+def ptsne_leg(epochs=10):
+    """The parallel scheme on the stand-in for the paper's rounds figure: 60,000
+    points in D=30, 120 threads, 2 layers (z = 1,000), perplexity 400,
+    momentum 0.8, 32 iterations per epoch, start map uniform in the unit disk.
+    One untimed epoch, then `epochs` epochs timed with HIP events on the
+    caller's stream (each epoch: mix, 120 partial affinities, 32 batched
+    iterations, 120 partial costs, pool, monitors)."""
+    import math
+
+    import torch
+
+    from paper_1812_09869_amd import synth
+    from paper_1812_09869_amd.tsne import PTSNE
+
+    n, threads, layers, perp = 60000, 120, 2, 400.0
+    x, _ = synth.digits_like(n)
+    y0 = synth.disk_init(n, synth.SEEDS["pt_init"])
+    orders = torch.from_numpy(synth.epoch_orders(n, epochs + 1, synth.SEEDS["pt_orders"])).cuda()
+    pt = PTSNE(torch.from_numpy(x).cuda(), threads, layers, perp, momentum=0.8)
+    pt.init_maps(torch.from_numpy(y0).cuda())
+    pt.epoch(orders[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for e in range(1, epochs + 1):
+        mon = pt.epoch(orders[e])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / epochs
+    z = [n // threads * layers] * threads  # n divisible by threads here
+    pairs = sum(k * (k - 1) / 2.0 for k in z) * pt.iters
+    res = {
+        "workload": "digits stand-in: N=60000, D=30, 10 anisotropic components; 120 threads, "
+                    "2 layers (z=1000), perplexity 400, momentum 0.8",
+        "iterations_per_epoch": pt.iters,
+        "epochs_per_round": math.isqrt(n),
+        "epochs_timed": epochs,
+        "ms_per_epoch": ms,
+        "round_s": ms * math.isqrt(n) * 1e-3,
+        "partial_pair_interactions_per_s": pairs * 1e3 / ms,
+        "monitors_last_epoch": {"mean_partial_cnorm": float(mon[0]),
+                                "mean_layer_size": float(mon[1])},
+        "status": pt.status(),
+    }
+    log(f"[ptsne] {res}")
+    return res
+
+
 def precision_report(n=262144, d=128, perp=50.0):
     """Errors of every distance mode against the FP64 oracle on the 10-D subspace
     mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
@@ -422,13 +470,22 @@ def main():
                     help="skip the per-distance-mode affinity timing and error leg")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-problem batched leg")
+    ap.add_argument("--no-ptsne", action="store_true",
+                    help="skip the parallel-scheme (ptSNE) leg")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate training / inference / evaluation leg")
+    ap.add_argument("--ptsne-only", action="store_true",
+                    help="only run the parallel-scheme leg (prints its JSON object)")
+    ap.add_argument("--ptsne-epochs", type=int, default=10,
+                    help="timed epochs of the parallel-scheme leg")
     ap.add_argument("--precision-report", action="store_true",
                     help="only run the per-mode error report at N=262,144, D=128")
     args = ap.parse_args()
     if args.precision_report:
         precision_report()
+        return
+    if args.ptsne_only:
+        print(json.dumps(ptsne_leg(args.ptsne_epochs)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -551,11 +608,14 @@ def main():
     if not args.no_surrogate:
         y_exact = y.clone()
         out["surrogate"] = surrogate_leg(x, y_exact, perp)
-    if not args.no_precision or not args.no_batched:
+    if not args.no_precision or not args.no_batched or not args.no_ptsne:
         del ws
         torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_leg()
+        torch.cuda.empty_cache()
+    if not args.no_ptsne:
+        out["ptsne"] = ptsne_leg(args.ptsne_epochs)
         torch.cuda.empty_cache()
     if not args.no_precision:
         torch.cuda.empty_cache()
