@@ -48,6 +48,9 @@ def _load():
         "orc_calibrate": (None, [_f64p, _i64, _i32, _d, ctypes.c_void_p, _i64, ctypes.c_int, _d,
                                  _f64p, _f64p, _f64p, _f64p, _i32p]),
         "orc_joint_p": (None, [_f64p, _i64, _i32, _f64p, _f64p, _f64p, _f64p]),
+        "orc_calibrate_dissim": (None, [_f64p, _i64, _d, ctypes.c_int, _d, _f64p, _f64p, _f64p,
+                                        _f64p, _i32p]),
+        "orc_joint_p_dissim": (None, [_f64p, _i64, _f64p, _f64p, _f64p, _f64p]),
         "orc_p_entries": (None, [_f64p, _i64, _i32, _i64p, _i64p, _i64, _f64p, _f64p, _f64p,
                                  _f64p, _f64p, _f64p, _f64p]),
         "orc_p_entropy_term": (_d, [_f64p, _i64]),
@@ -146,6 +149,28 @@ def joint_p(x, st: RowStats) -> np.ndarray:
     n, d = x.shape
     out = np.empty((n, n), dtype=np.float64)
     _load().orc_joint_p(x, n, d, _f64(st.beta), _f64(st.m), _f64(st.S), out)
+    return out
+
+
+def calibrate_dissim(dis, perplexity: float, max_iter: int = DEFAULT_MAX_ITER,
+                     tol: float = DEFAULT_TOL) -> RowStats:
+    """Row calibration (Eqs. 1-2) from a given n x n dissimilarity matrix; the
+    dissimilarity stands for ||x_i - x_j||, so its square enters Eq. 1."""
+    dis = _f64(dis)
+    n = dis.shape[0]
+    beta, m, S, H = (np.empty(n) for _ in range(4))
+    iters = np.empty(n, dtype=np.int32)
+    _load().orc_calibrate_dissim(dis, n, float(perplexity), int(max_iter), float(tol), beta, m, S,
+                                 H, iters)
+    return RowStats(beta, m, S, H, iters)
+
+
+def joint_p_dissim(dis, st: RowStats) -> np.ndarray:
+    """Full square P of Eq. 3 from a dissimilarity matrix and its row statistics."""
+    dis = _f64(dis)
+    n = dis.shape[0]
+    out = np.empty((n, n), dtype=np.float64)
+    _load().orc_joint_p_dissim(dis, n, _f64(st.beta), _f64(st.m), _f64(st.S), out)
     return out
 
 

@@ -192,6 +192,44 @@ ORC_API void orc_joint_p(const double *X, int64_t n, int32_t d, const double *be
   }
 }
 
+/*
+ * Affinities from given dissimilarities (section "ptSNE: parallelized t-SNE":
+ * any measure of similarity may enter; the dwt1005 set gives shortest-path
+ * distances). The dissimilarity delta_ij takes the place of ||x_i - x_j||, so
+ * Eq. 1 uses delta_ij^2. Dl is the n x n matrix (row-major, symmetric; the
+ * diagonal is ignored). Row i is calibrated from its own row of delta^2.
+ */
+ORC_API void orc_calibrate_dissim(const double *Dl, int64_t n, double perplexity, int max_iter,
+                                  double tol, double *beta, double *m, double *S, double *H,
+                                  int32_t *iters) {
+  const double logu = log(perplexity);
+#pragma omp parallel
+  {
+    double *drow = (double *)malloc((size_t)n * sizeof(double));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+      for (int64_t j = 0; j < n; ++j) drow[j] = (j == i) ? 0.0 : Dl[i * n + j] * Dl[i * n + j];
+      iters[i] = calibrate_row(drow, n, i, logu, max_iter, tol, beta + i, m + i, S + i, H + i);
+    }
+    free(drow);
+  }
+}
+
+/* Full square P of Eq. 3 from given dissimilarities: p_{j|i} from row i's
+ * delta_ij^2 and p_{i|j} from row j's delta_ji^2. */
+ORC_API void orc_joint_p_dissim(const double *Dl, int64_t n, const double *beta, const double *m,
+                                const double *S, double *P) {
+  const double inv2n = 1.0 / (2.0 * (double)n);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < n; ++j) {
+      if (i == j) { P[i * n + j] = 0.0; continue; }
+      const double dij = Dl[i * n + j] * Dl[i * n + j], dji = Dl[j * n + i] * Dl[j * n + i];
+      P[i * n + j] = (cond_p(dij, beta[i], m[i], S[i]) + cond_p(dji, beta[j], m[j], S[j])) * inv2n;
+    }
+  }
+}
+
 /* Single entries P_{i_k j_k} from the statistics of rows i_k and j_k. */
 ORC_API void orc_p_entries(const double *X, int64_t n, int32_t d, const int64_t *ii,
                            const int64_t *jj, int64_t cnt, const double *beta_i,

@@ -417,3 +417,35 @@ def test_knn_overlap_brute_force():
     # a map that keeps the first two coordinates of 2-D data keeps every neighbour
     x2 = rng.standard_normal((60, 2))
     assert oracle.knn_overlap(x2, x2, rows, k) == 1.0
+
+
+# ---------------------------------------------------------------------------
+# Given dissimilarities instead of points (section "ptSNE: parallelized t-SNE")
+# ---------------------------------------------------------------------------
+
+def test_dissimilarity_input_equals_point_input_for_euclidean_distances():
+    """Euclidean distances of X given as dissimilarities reproduce the
+    affinities of X itself (the squared dissimilarity enters Eq. 1)."""
+    x = _rng(61).standard_normal((45, 6)) * 2.0
+    dis = np.sqrt(cdist(x, x, "sqeuclidean"))
+    st_x = oracle.calibrate(x, 9.0)
+    st_d = oracle.calibrate_dissim(dis, 9.0)
+    np.testing.assert_allclose(st_d.beta, st_x.beta, rtol=1e-9)
+    P = oracle.joint_p_dissim(dis, st_d)
+    np.testing.assert_allclose(P, oracle.joint_p(x, st_x), rtol=1e-9, atol=1e-15)
+
+
+def test_dissimilarity_path_graph():
+    """Shortest-path distances of a 4-node path graph (1-2-3-4): node 1 has
+    neighbours at distances 1, 2, 3, so with squared distances 1, 4, 9 its
+    entropy at the returned beta is that of the weights e^{-beta}, e^{-4 beta},
+    e^{-9 beta} (brute force), and P is symmetric with unit sum (Eq. 3)."""
+    dis = np.abs(np.subtract.outer(np.arange(4.0), np.arange(4.0)))
+    st = oracle.calibrate_dissim(dis, 2.0)
+    b = st.beta[0]
+    w = np.exp(-b * np.array([1.0, 4.0, 9.0]))
+    p = w / w.sum()
+    assert -(p * np.log(p)).sum() == pytest.approx(math.log(2.0), abs=1e-10)
+    P = oracle.joint_p_dissim(dis, st)
+    np.testing.assert_allclose(P, P.T, rtol=0, atol=1e-17)
+    assert P.sum() == pytest.approx(1.0, abs=1e-14)
