@@ -124,6 +124,23 @@ TSNE_API int tsne_affinities(const float *x, int64_t n, int32_t d, double perple
                     const tsne_aff_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Input affinities from given dissimilarities instead of points (any measure
+ * of similarity may enter the method, section "ptSNE: parallelized t-SNE";
+ * the paper's dwt1005 set gives shortest-path distances). dis: n x n FP32
+ * (device, row-major), symmetric and non-negative; the diagonal is ignored.
+ * The dissimilarity takes the place of ||x_i - x_j||, so Eq. 1 uses its
+ * square; everything after that is tsne_affinities. The workspace is that of
+ * tsne_workspace_bytes(n, 1, TSNE_DIST_FP64). opts->dist_mode and
+ * opts->reorder are ignored (no coordinates: the caller's order is kept).
+ * P takes the upper-triangle value dis[i][j], i < j, for both orders of a
+ * pair. Errors as tsne_affinities; a negative or non-finite off-diagonal
+ * entry sets TSNE_E_NONFINITE on the device.
+ */
+TSNE_API int tsne_affinities_dissim(const float *dis, int64_t n, double perplexity,
+                                    const tsne_aff_opts *opts, void *ws, size_t ws_bytes,
+                                    void *stream);
+
+/*
  * One iteration of the exact gradient descent from state (y, u, g), each
  * n x 2 FP32 on the device, updated in place:
  *   grad_i = 4 sum_j (alpha p_ij - q_ij) w_ij (y_i - y_j),

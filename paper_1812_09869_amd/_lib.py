@@ -32,6 +32,7 @@ DIST_MODES = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fp16": 4, "fp16x3":
 EXPORTED = [
     "tsne_workspace_bytes",
     "tsne_affinities",
+    "tsne_affinities_dissim",
     "tsne_step",
     "tsne_forces",
     "tsne_update",
@@ -112,6 +113,9 @@ def load(path: str = LIB_PATH):
         "tsne_workspace_bytes": (ctypes.c_size_t, [_i64, _i32, _i32]),
         "tsne_affinities": (ctypes.c_int, [_vp, _i64, _i32, ctypes.c_double,
                                            ctypes.POINTER(AffOpts), _vp, ctypes.c_size_t, _vp]),
+        "tsne_affinities_dissim": (ctypes.c_int, [_vp, _i64, ctypes.c_double,
+                                                  ctypes.POINTER(AffOpts), _vp, ctypes.c_size_t,
+                                                  _vp]),
         "tsne_step": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, ctypes.POINTER(StepParams), _vp,
                                      _vp, _vp]),
         "tsne_forces": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
@@ -211,6 +215,16 @@ LR_RULES = {"gains": 0, "range": 1}
 def _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule):
     rule = LR_RULES[lr_rule] if isinstance(lr_rule, str) else int(lr_rule)
     return StepParams(exaggeration, momentum, learning_rate, min_gain, 1 if recentre else 0, rule)
+
+
+def affinities_dissim(dis: torch.Tensor, perplexity: float, ws: torch.Tensor,
+                      max_bisect: int = 200, tol_h: float = 1e-6):
+    """Affinities from an n x n dissimilarity matrix (its square enters Eq. 1)."""
+    n = dis.shape[0]
+    opts = AffOpts(DIST_MODES["fp64"], max_bisect, tol_h, 0, 0)
+    _check(load().tsne_affinities_dissim(_ptr(dis, shape=(n, n), name="dis"), n,
+                                         float(perplexity), ctypes.byref(opts),
+                                         _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()))
 
 
 def step(ws, n, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01, recentre=True,

@@ -671,6 +671,28 @@ constexpr int kTreePowerIters = 4;
 constexpr int kTreeTargetGroups = 1024;  // workgroups per level at the shallow levels
 constexpr int kSortBlock = 4096;         // keys per workgroup in the LDS sorting stages
 
+// Given dissimilarities (any measure may enter, section "ptSNE: parallelized
+// t-SNE"): the squares of rows b*T .. b*T + T - 1 of the n x n matrix into the
+// distance block, in place of the contraction. Grid (npad / 256, T / 16):
+// workgroup (c, g) covers columns 256 c .. 256 c + 255 of rows 16 g .. 16 g + 15.
+__global__ __launch_bounds__(256) void k_dissim_block(const float *__restrict__ dis, int64_t n,
+                                                      int64_t npad, int32_t b,
+                                                      float *__restrict__ dblock, Hdr *h) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  bool bad = false;
+  for (int r = 16 * blockIdx.y; r < 16 * (blockIdx.y + 1); ++r) {
+    const int64_t i = (int64_t)b * T + r;
+    float v = 0.f;
+    if (i < n && j < n) {
+      const float dv = dis[i * n + j];
+      bad |= !(dv >= 0.f && dv < INFINITY) && j != i;
+      v = dv * dv;
+    }
+    dblock[(int64_t)r * npad + j] = v;
+  }
+  if (bad) flag_error(h, kErrNonFinite);
+}
+
 __global__ void k_reorder_init(int64_t n, int64_t npad, int32_t *__restrict__ perm,
                                int32_t *__restrict__ inv) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1338,8 +1360,9 @@ __global__ __launch_bounds__(1024) void k_small_lists(const SmallEntry *__restri
 // ----------------------------------------------------------------------------
 // Host-side sequencing
 // ----------------------------------------------------------------------------
-hipError_t launch_affinities(const Layout &L, const float *x, double perplexity, int max_bisect,
-                             double tol_h, int reorder, void *ws, hipStream_t st) {
+hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
+                             int max_bisect, double tol_h, int reorder, void *ws,
+                             hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(64), 0, st, h, L.n, L.d, L.mode, perplexity);
   double *mean = at<double>(ws, L.xmean);
@@ -1349,9 +1372,11 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
   float4 *P = at<float4>(ws, L.P);
   int32_t *perm = at<int32_t>(ws, L.perm), *inv = at<int32_t>(ws, L.inv);
   const unsigned pgrid = (unsigned)((L.npad + 255) / 256);
-  hipLaunchKernelGGL(k_colmean, dim3(L.d), dim3(256), 0, st, x, L.n, L.d, mean);
-  hipLaunchKernelGGL(k_centre, dim3(pgrid), dim3(256), 0, st, x, L.n, L.d, L.npad, L.dpad, mean,
-                     xcT, norms, h);
+  if (!dis) {
+    hipLaunchKernelGGL(k_colmean, dim3(L.d), dim3(256), 0, st, x, L.n, L.d, mean);
+    hipLaunchKernelGGL(k_centre, dim3(pgrid), dim3(256), 0, st, x, L.n, L.d, L.npad, L.dpad,
+                       mean, xcT, norms, h);
+  }
   hipLaunchKernelGGL(k_reorder_init, dim3(pgrid), dim3(256), 0, st, L.n, L.npad, perm, inv);
   CalOut co{at<double>(ws, L.beta), at<double>(ws, L.S), at<double>(ws, L.H),
             at<float>(ws, L.m),     at<float>(ws, L.a),  at<float>(ws, L.r),
@@ -1455,6 +1480,18 @@ hipError_t launch_affinities(const Layout &L, const float *x, double perplexity,
                        at<int32_t>(ws, L.tlist), at<int32_t>(ws, L.tcount));
   };
 
+  if (dis) {
+    // given dissimilarities: no coordinates, so no ordering tree; the squared
+    // rows take the place of the contraction
+    for (int b = 0; b < L.nb; ++b) {
+      hipLaunchKernelGGL(k_dissim_block, dim3((unsigned)(L.npad / 256), T / 16), dim3(256), 0, st,
+                         dis, L.n, L.npad, b, dblock, h);
+      calibrate(b);
+      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
+    }
+    pack();
+    return hipGetLastError();
+  }
   const double *xc = xcT, *nrm = norms;
   if (reorder && L.nb >= 2 && L.d <= kTreeMaxD) {
     // Internal order: bisection tree over the centred X, then X in that order.

@@ -137,9 +137,33 @@ int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
   if (ws_bytes < L.total)
     return fail(TSNE_E_WORKSPACE, "tsne_affinities: workspace %zu bytes, need %zu", ws_bytes,
                 L.total);
-  return hip_check(tsne::launch_affinities(L, x, perplexity, o.max_bisect, o.tol_h,
+  return hip_check(tsne::launch_affinities(L, x, nullptr, perplexity, o.max_bisect, o.tol_h,
                                            o.reorder != 0, ws, (hipStream_t)stream),
                    "tsne_affinities");
+}
+
+int tsne_affinities_dissim(const float *dis, int64_t n, double perplexity,
+                           const tsne_aff_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  tsne_aff_opts o = {TSNE_DIST_FP64, 200, 1e-6, 0, 0};
+  if (opts) o = *opts;
+  if (!dis || !ws) return fail(TSNE_E_ARG, "tsne_affinities_dissim: null pointer");
+  if (!valid_n(n))
+    return fail(TSNE_E_ARG, "tsne_affinities_dissim: n = %lld out of range", (long long)n);
+  if (o.max_bisect < 1 || !(o.tol_h > 0.0) || o.reserved != 0)
+    return fail(TSNE_E_ARG,
+                "tsne_affinities_dissim: max_bisect >= 1, tol_h > 0, reserved = 0 required");
+  if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))
+    return fail(TSNE_E_PERPLEXITY, "tsne_affinities_dissim: perplexity %g not in (1, n-1 = %lld)",
+                perplexity, (long long)(n - 1));
+  if (!aligned(ws, 256))
+    return fail(TSNE_E_WORKSPACE, "tsne_affinities_dissim: ws not 256-byte aligned");
+  const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
+  if (ws_bytes < L.total)
+    return fail(TSNE_E_WORKSPACE, "tsne_affinities_dissim: workspace %zu bytes, need %zu",
+                ws_bytes, L.total);
+  return hip_check(tsne::launch_affinities(L, nullptr, dis, perplexity, o.max_bisect, o.tol_h, 0,
+                                           ws, (hipStream_t)stream),
+                   "tsne_affinities_dissim");
 }
 
 static int check_params(const char *fn, const tsne_step_params *prm) {

@@ -155,8 +155,10 @@ inline P *at(void *ws, size_t off) {
 // ---------------------------------------------------------------------------
 // Launch wrappers (all asynchronous on `stream`)
 // ---------------------------------------------------------------------------
-hipError_t launch_affinities(const Layout &L, const float *x, double perplexity, int max_bisect,
-                             double tol_h, int reorder, void *ws, hipStream_t stream);
+// Exactly one of x (n x d points) and dis (n x n dissimilarities) is non-null.
+hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
+                             int max_bisect, double tol_h, int reorder, void *ws,
+                             hipStream_t stream);
 // Fills the table entry of a problem whose workspace has layout L.
 void small_entry(const Layout &L, void *ws, const float *x, double perplexity, SmallEntry &e);
 // tab: device copy of `count` entries with prefix offsets filled in; wgs,

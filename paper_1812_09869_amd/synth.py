@@ -27,6 +27,9 @@ Workloads (sizes and recipes):
   (section "Parallelized implementation").
 * ``epoch_orders``: one random permutation of the points per epoch (the
   master's mixing draw of the parallel scheme).
+* ``mesh_graph_distances``: stand-in for the paper's dwt1005 set (a 3-D mesh
+  given as shortest-path distances between its 1,005 nodes): a closed
+  cylinder mesh of 15 x 67 nodes with grid edges, hop-count shortest paths.
 * ``digits_like``: stand-in for the whitened 30-D digits set of the paper's
   rounds figure: N=60,000, D=30, 10 anisotropic components (Dirichlet(5)
   weights, means ~ N(0, 25 I), covariance log-uniform in [0.1, 10] along Haar
@@ -50,6 +53,7 @@ __all__ = [
     "disk_init",
     "epoch_orders",
     "digits_like",
+    "mesh_graph_distances",
     "SEEDS",
 ]
 
@@ -220,3 +224,16 @@ def digits_like(n: int = 60000, seed: int = SEEDS["digits_like"], k: int = 10, d
         factors[c] = q * np.sqrt(lam)
     x, lab = Mixture(w, means, factors).sample(rng, n)
     return x.astype(np.float32), lab
+
+
+def mesh_graph_distances(around: int = 15, along: int = 67) -> np.ndarray:
+    """Shortest-path (hop) distances on a cylinder mesh of around x along nodes
+    (edges to the grid neighbours, wrapping around); FP32, n x n, n = 1,005."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import shortest_path
+    n = around * along
+    idx = np.arange(n).reshape(along, around)
+    rows = np.concatenate([idx.ravel(), idx[:-1].ravel()])
+    cols = np.concatenate([np.roll(idx, -1, axis=1).ravel(), idx[1:].ravel()])
+    g = coo_matrix((np.ones(rows.shape[0]), (rows, cols)), shape=(n, n))
+    return shortest_path(g, directed=False, unweighted=True).astype(np.float32)

@@ -58,6 +58,20 @@ class ExactTSNE:
         self._z = torch.zeros(1, dtype=torch.float64, device=x.device)
         self._cost = torch.zeros(2, dtype=torch.float64, device=x.device)
 
+    @classmethod
+    def from_dissimilarities(cls, dis: torch.Tensor, perplexity: float, max_bisect: int = 200,
+                             tol_h: float = 1e-6):
+        """Affinities from an n x n dissimilarity matrix (device FP32) instead
+        of points; the iteration is the same."""
+        self = cls.__new__(cls)
+        self.n, self.d = dis.shape[0], 1
+        self.perplexity = float(perplexity)
+        self.ws = _lib.new_workspace(self.n, 1, "fp64", device=dis.device)
+        _lib.affinities_dissim(dis.contiguous(), perplexity, self.ws, max_bisect, tol_h)
+        self._z = torch.zeros(1, dtype=torch.float64, device=dis.device)
+        self._cost = torch.zeros(2, dtype=torch.float64, device=dis.device)
+        return self
+
     def init_state(self, y0: torch.Tensor):
         y = y0.detach().to(dtype=torch.float32).contiguous().clone()
         return y, torch.zeros_like(y), torch.ones_like(y)
