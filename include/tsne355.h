@@ -318,6 +318,41 @@ TSNE_API int tsne_pt_partial(int64_t n, int32_t d, const tsne_pt_opts *opts, voi
 TSNE_API const char *tsne_pt_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Perplexity-adaptive kernel density estimate of a 2-D map (paKDE, section
+ * "Perplexity-adaptive Kernel Density Estimation"). Each map point j gets the
+ * precision beta_j of the same perplexity search as the input affinities
+ * (Eqs. 1-2 on the squared map distances |y_j - y_k|^2); the density is the
+ * sample smoothing estimator with bivariate Gaussian kernels of bandwidth
+ * h_j^2 = 2 sigma_j^2 = 1 / beta_j:
+ *   f(c) = (S / n) sum_j (beta_j / pi) exp(-beta_j |c - y_j|^2),
+ * at the centre c of every cell of a regular raster with cells of area S
+ * (the probability mass of the cell; a raster covering the map sums to ~1).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  float x0, y0;    /* corner of the raster: cell (v, u) spans [x0 + u cx, x0 + (u+1) cx] x ... */
+  float cx, cy;    /* cell sizes (> 0); S = cx cy */
+  int32_t gx, gy;  /* cells along x and y; the output is gy x gx, row v = y index */
+} tsne_raster;
+
+/* Bytes of the workspace of tsne_kde_bandwidths for n map points (0 if n < 3).
+ * Host-only. It holds the row statistics and one 256 x n distance block. */
+TSNE_API size_t tsne_kde_workspace_bytes(int64_t n);
+
+/* beta (device double[n]) of every point of the map y (device n x 2 FP32),
+ * for the given perplexity (1 < perplexity < n - 1). Device conditions (a row
+ * that did not converge, non-finite input) are read with tsne_sync_status on
+ * this workspace. */
+TSNE_API int tsne_kde_bandwidths(const float *y, int64_t n, double perplexity, double *beta,
+                                 void *ws, size_t ws_bytes, void *stream);
+
+/* f(c) of every raster cell into out (device FP32, gy x gx, row-major), from
+ * the map y (n x 2 FP32) and its precisions beta (n FP64), all on the device.
+ * The sum over points is FP32 within chunks of 256 points and FP64 across
+ * chunks. Errors: TSNE_E_ARG for null pointers or an invalid raster. */
+TSNE_API int tsne_kde_raster(const float *y, int64_t n, const double *beta,
+                             const tsne_raster *grid, float *out, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned surrogate (not in the paper): an MLP d_in -> H -> H -> 2 with ReLU
  * that maps input points to their embedding, trained on (x, y) pairs that
  * the exact path produced. Exact t-SNE (tsne_step) stays the fallback: a

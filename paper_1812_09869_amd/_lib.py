@@ -60,6 +60,9 @@ EXPORTED = [
     "tsne_pt_sync_status",
     "tsne_pt_last_error",
     "tsne_pt_partial",
+    "tsne_kde_workspace_bytes",
+    "tsne_kde_bandwidths",
+    "tsne_kde_raster",
 ]
 
 
@@ -84,6 +87,11 @@ class StepParams(ctypes.Structure):
     _fields_ = [("exaggeration", ctypes.c_float), ("momentum", ctypes.c_float),
                 ("learning_rate", ctypes.c_float), ("min_gain", ctypes.c_float),
                 ("recentre", ctypes.c_int32), ("lr_rule", ctypes.c_int32)]
+
+
+class Raster(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_float), ("y0", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("gx", ctypes.c_int32), ("gy", ctypes.c_int32)]
 
 
 class PtOpts(ctypes.Structure):
@@ -152,6 +160,10 @@ def load(path: str = LIB_PATH):
         "tsne_pt_sync_status": (ctypes.c_int, [_i64, _i32, ctypes.POINTER(PtOpts), _vp,
                                                ctypes.c_size_t, _vp]),
         "tsne_pt_last_error": (ctypes.c_char_p, []),
+        "tsne_kde_workspace_bytes": (ctypes.c_size_t, [_i64]),
+        "tsne_kde_bandwidths": (ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp,
+                                               ctypes.c_size_t, _vp]),
+        "tsne_kde_raster": (ctypes.c_int, [_vp, _i64, _vp, ctypes.POINTER(Raster), _vp, _vp]),
         "tsne_pt_partial": (ctypes.c_int, [_i64, _i32, ctypes.POINTER(PtOpts), _vp,
                                            ctypes.c_size_t, _i32, ctypes.POINTER(_vp),
                                            ctypes.POINTER(_i64)]),
@@ -442,3 +454,30 @@ def pt_partial(n: int, d: int, opts: PtOpts, ws, k: int):
                                      ws.numel(), k, ctypes.byref(ptr), ctypes.byref(nk)))
     off = ptr.value - ws.data_ptr()
     return ws[off:off + workspace_bytes(nk.value, d, opts.dist_mode)], nk.value
+
+
+# --------------------------------------------------------------------------
+# Perplexity-adaptive KDE of a map (paKDE)
+# --------------------------------------------------------------------------
+
+def kde_new_workspace(n: int, device="cuda") -> torch.Tensor:
+    nbytes = int(load().tsne_kde_workspace_bytes(n))
+    if nbytes == 0:
+        raise TsneError(1, f"no KDE workspace size for n={n}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def kde_bandwidths(y, perplexity: float, ws, beta):
+    n = y.shape[0]
+    _check(load().tsne_kde_bandwidths(_ptr(y, shape=(n, 2), name="y"), n, float(perplexity),
+                                      _ptr(beta, torch.float64, shape=(n,), name="beta"),
+                                      _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()))
+
+
+def kde_raster(y, beta, x0, y0, cx, cy, gx, gy, out):
+    n = y.shape[0]
+    g = Raster(float(x0), float(y0), float(cx), float(cy), int(gx), int(gy))
+    _check(load().tsne_kde_raster(_ptr(y, shape=(n, 2), name="y"), n,
+                                  _ptr(beta, torch.float64, shape=(n,), name="beta"),
+                                  ctypes.byref(g), _ptr(out, shape=(gy, gx), name="out"),
+                                  _stream()))

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["tsne_api.hip", "tsne_affinity.hip", "tsne_iterate.hip", "tsne_mlp.hip", "tsne_pt.hip"]
+SOURCES = ["tsne_api.hip", "tsne_affinity.hip", "tsne_iterate.hip", "tsne_mlp.hip", "tsne_pt.hip", "tsne_kde.hip"]
 LIB = os.path.join(HERE, "libtsne355.so")
 ARCH = "gfx950"
 

@@ -1361,8 +1361,8 @@ __global__ __launch_bounds__(1024) void k_small_lists(const SmallEntry *__restri
 // Host-side sequencing
 // ----------------------------------------------------------------------------
 hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
-                             int max_bisect, double tol_h, int reorder, void *ws,
-                             hipStream_t st) {
+                             int max_bisect, double tol_h, int reorder, void *ws, hipStream_t st,
+                             bool stats_only) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(64), 0, st, h, L.n, L.d, L.mode, perplexity);
   double *mean = at<double>(ws, L.xmean);
@@ -1493,7 +1493,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
     return hipGetLastError();
   }
   const double *xc = xcT, *nrm = norms;
-  if (reorder && L.nb >= 2 && L.d <= kTreeMaxD) {
+  if (reorder && !stats_only && L.nb >= 2 && L.d <= kTreeMaxD) {
     // Internal order: bisection tree over the centred X, then X in that order.
     uint64_t *keys = at<uint64_t>(ws, L.keys);
     int32_t *vals = at<int32_t>(ws, L.vals);
@@ -1551,9 +1551,10 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   for (int b = 0; b < L.nb; ++b) {
     dist(b, xc, nrm);
     calibrate(b);
-    hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
+    if (!stats_only)
+      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
   }
-  pack();
+  if (!stats_only) pack();
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ namespace tsne {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-Layout make_layout(int64_t n, int32_t d, int32_t mode) {
+Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only) {
   Layout L;
   L.n = n;
   L.d = d;
@@ -29,6 +29,9 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
     o = align_up(o + bytes, 256);
     return at;
   };
+  // stats_only: the row statistics and the distance stage only (no P, no
+  // iteration state, no ordering tree)
+  const size_t sz = stats_only ? 0 : 1;
   const size_t np = (size_t)L.npad;
   L.hdr = take(256);
   L.beta = take(np * 8);
@@ -38,22 +41,22 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.a = take(np * 4);
   L.r = take(np * 4);
   L.evals = take(np * 4);
-  L.P = take((size_t)L.nt * T * T * 4);
-  L.part = take((size_t)L.nb * L.nb * T * 16);
-  L.zpart = take((size_t)L.nt * 8);
-  L.cpart = take((size_t)L.nt * 16);
-  L.ppart = take((size_t)L.nt * 16);
-  L.meanpart = take((size_t)L.nb * kMeanPartsPerBlock * 16);
-  L.nz = take((size_t)L.nt);
-  L.tmap = take((size_t)L.nt * 8);
-  L.tlist = take((size_t)L.nt * 4);
+  L.P = take(sz * (size_t)L.nt * T * T * 4);
+  L.part = take(sz * (size_t)L.nb * L.nb * T * 16);
+  L.zpart = take(sz * (size_t)L.nt * 8);
+  L.cpart = take(sz * (size_t)L.nt * 16);
+  L.ppart = take(sz * (size_t)L.nt * 16);
+  L.meanpart = take(sz * (size_t)L.nb * kMeanPartsPerBlock * 16);
+  L.nz = take(sz * (size_t)L.nt);
+  L.tmap = take(sz * (size_t)L.nt * 8);
+  L.tlist = take(sz * (size_t)L.nt * 4);
   L.tcount = take(8);
-  L.slots = take((size_t)L.nb * L.nb * 4);
-  L.nslots = take((size_t)L.nb * 4);
+  L.slots = take(sz * (size_t)L.nb * L.nb * 4);
+  L.nslots = take(sz * (size_t)L.nb * 4);
   L.perm = take(np * 4);
   L.inv = take(np * 4);
-  L.yp = take(np * 8);
-  L.extent = take((size_t)L.nb * 16);
+  L.yp = take(sz * np * 8);
+  L.extent = take(sz * (size_t)L.nb * 16);
   L.iter_end = o;
   // affinity-stage scratch (only needed inside tsne_affinities)
   L.xmean = take((size_t)L.dpad * 8);
@@ -62,10 +65,10 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode) {
   L.dblock = take((size_t)T * np * 4);
   L.npow2 = 1;
   while (L.npow2 < n) L.npow2 <<= 1;
-  L.xcT2 = take((size_t)L.dpad * np * 8);
-  L.norms2 = take(np * 8);
-  L.keys = take((size_t)L.npow2 * 8);
-  L.vals = take((size_t)L.npow2 * 4);
+  L.xcT2 = take(sz * (size_t)L.dpad * np * 8);
+  L.norms2 = take(sz * np * 8);
+  L.keys = take(sz * (size_t)L.npow2 * 8);
+  L.vals = take(sz * (size_t)L.npow2 * 4);
   if (mode == TSNE_DIST_FP32) {
     L.xfT = take((size_t)L.dpad * np * 4);
     L.norms32 = take(np * 4);
@@ -397,6 +400,46 @@ int tsne_batch_cost(const tsne_batch_problem *problems, int32_t count, const voi
   return hip_check(tsne::launch_batch_cost(batch_ws, count, tiles, blocks, out,
                                            (hipStream_t)stream),
                    "tsne_batch_cost");
+}
+
+size_t tsne_kde_workspace_bytes(int64_t n) {
+  if (n < 3 || n > ((int64_t)1 << 30)) return 0;
+  return tsne::make_layout(n, 2, TSNE_DIST_FP64, true).total;
+}
+
+int tsne_kde_bandwidths(const float *y, int64_t n, double perplexity, double *beta, void *ws,
+                        size_t ws_bytes, void *stream) {
+  if (!y || !ws || !beta) return fail(TSNE_E_ARG, "tsne_kde_bandwidths: null pointer");
+  if (n < 3 || n > ((int64_t)1 << 30))
+    return fail(TSNE_E_ARG, "tsne_kde_bandwidths: n = %lld out of range", (long long)n);
+  if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))
+    return fail(TSNE_E_PERPLEXITY, "tsne_kde_bandwidths: perplexity %g not in (1, n-1 = %lld)",
+                perplexity, (long long)(n - 1));
+  if (!aligned(ws, 256)) return fail(TSNE_E_WORKSPACE, "tsne_kde_bandwidths: ws not aligned");
+  const Layout L = tsne::make_layout(n, 2, TSNE_DIST_FP64, true);
+  if (ws_bytes < L.total)
+    return fail(TSNE_E_WORKSPACE, "tsne_kde_bandwidths: workspace %zu bytes, need %zu",
+                ws_bytes, L.total);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = tsne::launch_affinities(L, y, nullptr, perplexity, 200, 1e-6, 0, ws, st, true);
+  // no reordering: the row statistics are in the caller's order
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(beta, tsne::at<double>(ws, L.beta), (size_t)n * sizeof(double),
+                       hipMemcpyDeviceToDevice, st);
+  return hip_check(e, "tsne_kde_bandwidths");
+}
+
+int tsne_kde_raster(const float *y, int64_t n, const double *beta, const tsne_raster *grid,
+                    float *out, void *stream) {
+  if (!y || !beta || !grid || !out) return fail(TSNE_E_ARG, "tsne_kde_raster: null pointer");
+  if (n < 1 || n > ((int64_t)1 << 30))
+    return fail(TSNE_E_ARG, "tsne_kde_raster: n = %lld out of range", (long long)n);
+  const tsne_raster g = *grid;
+  if (g.gx < 1 || g.gy < 1 || (int64_t)g.gx * g.gy > ((int64_t)1 << 30) || !(g.cx > 0.f) ||
+      !(g.cy > 0.f) || !isfinite(g.x0) || !isfinite(g.y0) || !isfinite(g.cx) || !isfinite(g.cy))
+    return fail(TSNE_E_ARG, "tsne_kde_raster: invalid raster");
+  return hip_check(tsne::launch_kde_raster(y, n, beta, g, out, (hipStream_t)stream),
+                   "tsne_kde_raster");
 }
 
 static bool mlp_dims_ok(int32_t d_in, int32_t hidden) {

@@ -76,7 +76,9 @@ struct Layout {
   size_t total = 0;
 };
 
-Layout make_layout(int64_t n, int32_t d, int32_t mode);
+// stats_only: a layout holding only what the per-row search needs (header,
+// row statistics, order, centred X and the distance block).
+Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only = false);
 
 // Upper-triangle tile enumeration: row I holds tiles (I, I..nb-1).
 __host__ __device__ inline int64_t tile_start(int64_t I, int64_t nb) {
@@ -158,7 +160,7 @@ inline P *at(void *ws, size_t off) {
 // Exactly one of x (n x d points) and dis (n x n dissimilarities) is non-null.
 hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
                              int max_bisect, double tol_h, int reorder, void *ws,
-                             hipStream_t stream);
+                             hipStream_t stream, bool stats_only = false);
 // Fills the table entry of a problem whose workspace has layout L.
 void small_entry(const Layout &L, void *ws, const float *x, double perplexity, SmallEntry &e);
 // tab: device copy of `count` entries with prefix offsets filled in; wgs,
@@ -166,6 +168,8 @@ void small_entry(const Layout &L, void *ws, const float *x, double perplexity, S
 hipError_t launch_affinities_small(const SmallEntry *tab, int count, int64_t wgs, int64_t tiles,
                                    int64_t blocks, int64_t nmax, int32_t dmax, int max_bisect,
                                    double tol_h, hipStream_t stream);
+hipError_t launch_kde_raster(const float *y, int64_t n, const double *beta, const tsne_raster &g,
+                             float *out, hipStream_t stream);
 hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t stream);
 hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
                          float mu, float eta, float min_gain, int recentre, int lr_rule,

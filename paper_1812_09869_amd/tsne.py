@@ -180,3 +180,19 @@ class PTSNE:
 
     def status(self) -> int:
         return _lib.pt_sync_status(self.n, self.d, self.opts, self.ws)
+
+
+def pakde(y: torch.Tensor, perplexity: float, x0: float, y0: float, cx: float, cy: float,
+          gx: int, gy: int):
+    """Perplexity-adaptive KDE of a map (n x 2 device FP32): returns (beta, f),
+    f the gy x gx raster of cell masses. Both steps run on the device."""
+    n = y.shape[0]
+    y = y.contiguous()
+    ws = _lib.kde_new_workspace(n, device=y.device)
+    beta = torch.empty(n, dtype=torch.float64, device=y.device)
+    _lib.kde_bandwidths(y, perplexity, ws, beta)
+    f = torch.empty((gy, gx), dtype=torch.float32, device=y.device)
+    _lib.kde_raster(y, beta, x0, y0, cx, cy, gx, gy, f)
+    if _lib.sync_status(ws) != 0:
+        raise _lib.TsneError(_lib.sync_status(ws), "paKDE bandwidth search flagged a device condition")
+    return beta, f
