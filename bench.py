@@ -377,6 +377,55 @@ def ptsne_leg(epochs=10):
     return res
 
 
+def pakde_leg(y, perp=100.0, grid=512, reps=5):
+    """paKDE of the benchmark's final map: bandwidths by the perplexity search
+    on the map (perplexity 100, the paper's paKDE setting for its 7-D mixture),
+    then the raster estimator on a grid x grid raster over the map's box plus
+    a margin of 5% on each side. Each step timed with HIP events (mean of
+    `reps`). The raster's unit of work is one (cell, point) kernel term: a
+    squared distance (2 sub, 1 FMA), the scaled exponent (1 mul, 1 exp2) and
+    the weighted sum (1 FMA)."""
+    import torch
+
+    from paper_1812_09869_amd import _lib
+
+    n = y.shape[0]
+    y = y.contiguous()
+    lo = y.min(dim=0).values.double().cpu().numpy()
+    hi = y.max(dim=0).values.double().cpu().numpy()
+    pad = 0.05 * (hi - lo)
+    lo, hi = lo - pad, hi + pad
+    cx, cy = (hi[0] - lo[0]) / grid, (hi[1] - lo[1]) / grid
+    ws = _lib.kde_new_workspace(n, device=y.device)
+    beta = torch.empty(n, dtype=torch.float64, device=y.device)
+    f = torch.empty((grid, grid), dtype=torch.float32, device=y.device)
+    _lib.kde_bandwidths(y, perp, ws, beta)
+    _lib.kde_raster(y, beta, lo[0], lo[1], cx, cy, grid, grid, f)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        _lib.kde_bandwidths(y, perp, ws, beta)
+    ev[1].record()
+    for _ in range(reps):
+        _lib.kde_raster(y, beta, lo[0], lo[1], cx, cy, grid, grid, f)
+    ev[2].record()
+    torch.cuda.synchronize()
+    bw_ms = ev[0].elapsed_time(ev[1]) / reps
+    r_ms = ev[1].elapsed_time(ev[2]) / reps
+    terms = float(n) * grid * grid
+    res = {
+        "n": n, "perplexity": perp, "raster": [grid, grid],
+        "bandwidths_ms": bw_ms, "raster_ms": r_ms,
+        "raster_terms_per_s": terms * 1e3 / r_ms,
+        "raster_fp32_tflops": 7.0 * terms / (r_ms * 1e-3) / 1e12,
+        "mass": float(f.double().sum()),
+        "status": _lib.sync_status(ws),
+    }
+    log(f"[pakde] {res}")
+    return res
+
+
 def precision_report(n=262144, d=128, perp=50.0):
     """Errors of every distance mode against the FP64 oracle on the 10-D subspace
     mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
@@ -470,6 +519,8 @@ def main():
                     help="skip the per-distance-mode affinity timing and error leg")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-problem batched leg")
+    ap.add_argument("--no-pakde", action="store_true",
+                    help="skip the paKDE leg (bandwidths and raster of the final map)")
     ap.add_argument("--no-ptsne", action="store_true",
                     help="skip the parallel-scheme (ptSNE) leg")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -605,6 +656,8 @@ def main():
         "final_kl": kl,
         "final_cnorm": cnorm,
     }
+    if not args.no_pakde:
+        out["pakde"] = pakde_leg(y.clone())
     if not args.no_surrogate:
         y_exact = y.clone()
         out["surrogate"] = surrogate_leg(x, y_exact, perp)
