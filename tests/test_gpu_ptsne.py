@@ -113,3 +113,46 @@ def test_partial_affinities_match_oracle(n, threads, layers, perp):
         assert np.abs(H - math.log(perp)).max() <= 1e-5
         passes.append(ev.mean())
     print(f"\n  P ok for {threads} partial problems; mean search passes {np.mean(passes):.1f}")
+
+
+def test_benchmark_configuration():
+    """The configuration the benchmark times (the digits stand-in: 60,000
+    points in D = 30, 120 threads x 2 layers, z = 1,000, perplexity 400, 32
+    iterations): the first epoch against the full FP64 ptSNE oracle (all 120
+    partial problems, about 10 s on the host) -- both layers within 1e-4
+    relative, the mean partial C_norm within 1e-6 and the mean layer size
+    within 1e-5 relative -- then, after a second epoch, the P of three
+    sampled partial problems against the oracle's P of the same points
+    (single-problem gates)."""
+    import math
+
+    import oracle
+    from paper_1812_09869_amd import _lib
+    n, threads, layers, perp = 60000, 120, 2, 400.0
+    x, _ = synth.digits_like(n)
+    y0 = synth.disk_init(n, synth.SEEDS["pt_init"])
+    orders = synth.epoch_orders(n, 2, synth.SEEDS["pt_orders"])
+    pt = PTSNE(torch.from_numpy(x).cuda(), threads, layers, perp, momentum=0.8)
+    assert pt.iters == 32
+    pt.init_maps(torch.from_numpy(y0).cuda())
+    mon = pt.epoch(torch.from_numpy(orders[0]).cuda()).cpu().numpy()
+    g = pt.maps.cpu().numpy().astype(np.float64)
+    maps0 = np.repeat(y0.astype(np.float64)[None], layers, axis=0)
+    ref, c, s, _ = ptsne.epoch(x, maps0, orders[0], threads, layers, perp, 32, 0.8)
+    rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    print(f"\n  epoch 0: maps rel {rel:.2e}; cost {mon[0]:.9f} vs {c:.9f}; size {mon[1]:.7f} vs {s:.7f}")
+    assert rel <= 1e-4 and abs(mon[0] - c) <= 1e-6 and abs(mon[1] - s) <= 1e-5 * s
+    pt.epoch(torch.from_numpy(orders[1]).cuda())
+    assert pt.status() == 0
+    for k in (0, 57, 119):
+        idx, _ = ptsne.thread_members(orders[1], threads, layers, k)
+        xk = x[idx]
+        P_ref = oracle.joint_p(xk, oracle.calibrate(xk, perp))
+        ws_k, z = _lib.pt_partial(n, x.shape[1], pt.opts, pt.ws, k)
+        pg = _lib.export_p_rows(ws_k, z, 0, z).cpu().numpy().astype(np.float64)
+        fro = np.linalg.norm(pg - P_ref) / np.linalg.norm(P_ref)
+        mx = np.abs(pg - P_ref).max() / np.abs(P_ref).max()
+        _, _, _, H, ev = (t.cpu().numpy() for t in _lib.export_rowstats(ws_k, z))
+        print(f"  partial {k}: z={z} P rel-Frobenius {fro:.2e} max-rel {mx:.2e}")
+        assert fro <= 1e-5 and mx <= 1e-5 and np.all(ev > 0)
+        assert np.abs(H - math.log(perp)).max() <= 1e-5
