@@ -426,6 +426,47 @@ def pakde_leg(y, perp=100.0, grid=512, reps=5):
     return res
 
 
+def dissim_leg(x, perp=50.0, n=16384, reps=3):
+    """Affinities from a given dissimilarity matrix against the same affinities
+    from the points: the first n points of the benchmark mixture, their
+    Euclidean distances as an n x n FP32 matrix (1 GiB at n = 16,384, built on
+    the device by torch before timing), each path timed with HIP events (mean
+    of `reps` after one untimed call). The dissimilarity path reads the
+    matrix once (4 n^2 bytes) in place of the MFMA contraction."""
+    import torch
+
+    from paper_1812_09869_amd import _lib
+
+    xs = x[:n].contiguous()
+    dis = torch.cdist(xs.double(), xs.double()).float().contiguous()
+    ws = _lib.new_workspace(n, xs.shape[1], device=xs.device)
+    wsd = _lib.new_workspace(n, 1, device=xs.device)
+    _lib.affinities(xs, perp, ws, reorder=False)
+    _lib.affinities_dissim(dis, perp, wsd)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        _lib.affinities(xs, perp, ws, reorder=False)
+    ev[1].record()
+    for _ in range(reps):
+        _lib.affinities_dissim(dis, perp, wsd)
+    ev[2].record()
+    torch.cuda.synchronize()
+    pts_ms = ev[0].elapsed_time(ev[1]) / reps
+    dis_ms = ev[1].elapsed_time(ev[2]) / reps
+    a = _lib.export_p_rows(ws, n, 0, 256)
+    b = _lib.export_p_rows(wsd, n, 0, 256)
+    res = {"n": n, "d": int(xs.shape[1]), "perplexity": perp,
+           "points_affinities_ms": pts_ms, "dissimilarity_affinities_ms": dis_ms,
+           "p_rows_rel_diff": float((a - b).norm() / a.norm()),
+           "status": max(_lib.sync_status(ws), _lib.sync_status(wsd))}
+    log(f"[dissim] {res}")
+    del dis, ws, wsd
+    torch.cuda.empty_cache()
+    return res
+
+
 def precision_report(n=262144, d=128, perp=50.0):
     """Errors of every distance mode against the FP64 oracle on the 10-D subspace
     mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
@@ -521,6 +562,8 @@ def main():
                     help="skip the 64-problem batched leg")
     ap.add_argument("--no-pakde", action="store_true",
                     help="skip the paKDE leg (bandwidths and raster of the final map)")
+    ap.add_argument("--no-dissim", action="store_true",
+                    help="skip the given-dissimilarity affinity leg")
     ap.add_argument("--no-ptsne", action="store_true",
                     help="skip the parallel-scheme (ptSNE) leg")
     ap.add_argument("--no-surrogate", action="store_true",
@@ -670,6 +713,8 @@ def main():
     if not args.no_ptsne:
         out["ptsne"] = ptsne_leg(args.ptsne_epochs)
         torch.cuda.empty_cache()
+    if not args.no_dissim:
+        out["dissim"] = dissim_leg(x)
     if not args.no_precision:
         torch.cuda.empty_cache()
         out["dist_modes"] = precision_leg(x, lab_np, n, d, perp, args.iters, steady_ms)
