@@ -467,6 +467,41 @@ def dissim_leg(x, perp=50.0, n=16384, reps=3):
     return res
 
 
+def implicit_leg(x, perp=50.0, iters=10):
+    """Implicit P on the benchmark workload (N = 65,536, D = 50, perplexity
+    50): workspace size against the stored-P one, and the time of one
+    iteration (every pass recomputes P block row by block row: FP64 MFMA
+    distances, stage, pack, force), mean of `iters` after one untimed."""
+    import torch
+
+    from paper_1812_09869_amd import _lib, synth
+    from paper_1812_09869_amd.tsne import ExactTSNE
+
+    n, d = x.shape
+    model = ExactTSNE(x, perp, implicit=True)
+    y0 = torch.from_numpy(synth.embedding_init(n, seed=17)).to(x.device)
+    state = model.init_state(y0)
+    model.run(state, 1, start=300)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    model.run(state, iters, start=301)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / iters
+    res = {"n": n, "d": d,
+           "workspace_gb": float(model.ws.numel()) / 1e9,
+           "stored_workspace_gb": _lib.workspace_bytes(n, d) / 1e9,
+           "ms_per_iteration": ms,
+           "pair_interactions_per_s": n * (n - 1) / 2.0 * 1e3 / ms,
+           "fp64_mfma_tflops_distances": 2.0 * n * n * d / (ms * 1e-3) / 1e12,
+           "status": model.status()}
+    log(f"[implicit] {res}")
+    del model
+    torch.cuda.empty_cache()
+    return res
+
+
 def precision_report(n=262144, d=128, perp=50.0):
     """Errors of every distance mode against the FP64 oracle on the 10-D subspace
     mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
@@ -562,6 +597,8 @@ def main():
                     help="skip the 64-problem batched leg")
     ap.add_argument("--no-pakde", action="store_true",
                     help="skip the paKDE leg (bandwidths and raster of the final map)")
+    ap.add_argument("--no-implicit", action="store_true",
+                    help="skip the implicit-P leg")
     ap.add_argument("--no-dissim", action="store_true",
                     help="skip the given-dissimilarity affinity leg")
     ap.add_argument("--no-ptsne", action="store_true",
@@ -715,6 +752,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_dissim:
         out["dissim"] = dissim_leg(x)
+    if not args.no_implicit:
+        out["implicit"] = implicit_leg(x, perp)
     if not args.no_precision:
         torch.cuda.empty_cache()
         out["dist_modes"] = precision_leg(x, lab_np, n, d, perp, args.iters, steady_ms)

@@ -63,6 +63,10 @@ EXPORTED = [
     "tsne_kde_workspace_bytes",
     "tsne_kde_bandwidths",
     "tsne_kde_raster",
+    "tsne_workspace_bytes_implicit",
+    "tsne_step_implicit",
+    "tsne_gradient_implicit",
+    "tsne_cost_implicit",
 ]
 
 
@@ -98,7 +102,7 @@ class PtOpts(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("layers", ctypes.c_int32),
                 ("perplexity", ctypes.c_double), ("momentum", ctypes.c_float),
                 ("iters", ctypes.c_int32), ("dist_mode", ctypes.c_int32),
-                ("reorder", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("reorder", ctypes.c_int32), ("implicit_p", ctypes.c_int32)]
 
 
 _lib = None
@@ -161,6 +165,12 @@ def load(path: str = LIB_PATH):
                                                ctypes.c_size_t, _vp]),
         "tsne_pt_last_error": (ctypes.c_char_p, []),
         "tsne_kde_workspace_bytes": (ctypes.c_size_t, [_i64]),
+        "tsne_workspace_bytes_implicit": (ctypes.c_size_t, [_i64, _i32]),
+        "tsne_step_implicit": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp,
+                                              ctypes.POINTER(StepParams), _vp, _vp, _vp]),
+        "tsne_gradient_implicit": (ctypes.c_int, [_vp, _i64, _i32, _vp, ctypes.c_float, _vp, _vp,
+                                                  _vp]),
+        "tsne_cost_implicit": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp]),
         "tsne_kde_bandwidths": (ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp,
                                                ctypes.c_size_t, _vp]),
         "tsne_kde_raster": (ctypes.c_int, [_vp, _i64, _vp, ctypes.POINTER(Raster), _vp, _vp]),
@@ -212,10 +222,11 @@ def new_workspace(n: int, d: int, dist_mode: str | int = "fp64", device="cuda") 
 
 
 def affinities(x: torch.Tensor, perplexity: float, ws: torch.Tensor, dist_mode="fp64",
-               max_bisect: int = 200, tol_h: float = 1e-6, reorder: bool = True):
+               max_bisect: int = 200, tol_h: float = 1e-6, reorder: bool = True,
+               implicit: bool = False):
     n, d = x.shape
     mode = DIST_MODES[dist_mode] if isinstance(dist_mode, str) else int(dist_mode)
-    opts = AffOpts(mode, max_bisect, tol_h, 1 if reorder else 0, 0)
+    opts = AffOpts(mode, max_bisect, tol_h, 1 if reorder else 0, 1 if implicit else 0)
     _check(load().tsne_affinities(_ptr(x, name="x"), n, d, float(perplexity),
                                   ctypes.byref(opts), _ptr(ws, torch.uint8, name="ws"),
                                   ws.numel(), _stream()))
@@ -481,3 +492,39 @@ def kde_raster(y, beta, x0, y0, cx, cy, gx, gy, out):
                                   _ptr(beta, torch.float64, shape=(n,), name="beta"),
                                   ctypes.byref(g), _ptr(out, shape=(gy, gx), name="out"),
                                   _stream()))
+
+
+# --------------------------------------------------------------------------
+# Implicit P (recomputed in every pass)
+# --------------------------------------------------------------------------
+
+def new_workspace_implicit(n: int, d: int, device="cuda") -> torch.Tensor:
+    nbytes = int(load().tsne_workspace_bytes_implicit(n, d))
+    if nbytes == 0:
+        raise TsneError(1, f"no implicit workspace size for n={n}, d={d}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def step_implicit(ws, n, d, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01,
+                  recentre=True, grad_out=None, z_out=None, lr_rule="gains"):
+    prm = _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule)
+    sh = (n, 2)
+    _check(load().tsne_step_implicit(_ptr(ws, torch.uint8, name="ws"), n, d,
+                                     _ptr(y, shape=sh, name="y"), _ptr(u, shape=sh, name="u"),
+                                     _ptr(g, shape=sh, name="g"), ctypes.byref(prm),
+                                     _ptr(grad_out, shape=sh, name="grad_out"),
+                                     _ptr(z_out, torch.float64, name="z_out"), _stream()))
+
+
+def gradient_implicit(ws, n, d, y, alpha, grad_out, z_out=None):
+    sh = (n, 2)
+    _check(load().tsne_gradient_implicit(_ptr(ws, torch.uint8, name="ws"), n, d,
+                                         _ptr(y, shape=sh, name="y"), float(alpha),
+                                         _ptr(grad_out, shape=sh, name="grad_out"),
+                                         _ptr(z_out, torch.float64, name="z_out"), _stream()))
+
+
+def cost_implicit(ws, n, d, y, out):
+    _check(load().tsne_cost_implicit(_ptr(ws, torch.uint8, name="ws"), n, d,
+                                     _ptr(y, shape=(n, 2), name="y"),
+                                     _ptr(out, torch.float64, shape=(2,), name="out"), _stream()))

@@ -24,6 +24,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ inline void flag_error(Hdr *h, uint32_t bit) { atomicOr(&h->err, bit); }
 
+// Implicit P: the kernels of a pass run only on a workspace whose header
+// records implicit affinities for the same n and d (its layout, hence every
+// offset these kernels use, depends on both).
+__device__ inline bool implicit_ready(const Hdr *h, int64_t n, int32_t d) {
+  return h->magic == kMagic && h->n == n && h->d == d && h->ready == 2;
+}
+
 // ----------------------------------------------------------------------------
 // Wave / block reductions (fixed order, hence deterministic)
 // ----------------------------------------------------------------------------
@@ -116,10 +123,13 @@ __global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int
 // ----------------------------------------------------------------------------
 constexpr int kDistCT = 2;  // 16-column MFMA tiles per wave (a wave covers 64 x 16 kDistCT)
 
+// guard (implicit P passes only, else null): the workspace header, n and d.
 __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
                                                   const double *__restrict__ norms, int64_t npad,
                                                   int32_t dpad, int32_t b,
-                                                  float *__restrict__ dblock) {
+                                                  float *__restrict__ dblock,
+                                                  const Hdr *guard, int64_t gn, int32_t gd) {
+  if (guard && !implicit_ready(guard, gn, gd)) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t col0 = (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
   const int row0_loc = blockIdx.y * 64;
@@ -494,12 +504,17 @@ __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restri
 // The diagonal tile holds both orders of each pair; both take the distance
 // of the upper element so that the stored P is exactly symmetric.
 // ----------------------------------------------------------------------------
+// tile_base: the P store's first tile (0; tile_start(b) for the one-block-row
+// buffer of implicit P).
 __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock, int64_t npad,
-                                               int32_t nb, int32_t b, float4 *__restrict__ P) {
+                                               int32_t nb, int32_t b, float4 *__restrict__ P,
+                                               int64_t tile_base, const Hdr *guard, int64_t gn,
+                                               int32_t gd) {
+  if (guard && !implicit_ready(guard, gn, gd)) return;
   const int J = b + blockIdx.x;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
-  float4 *dst = P + (size_t)tile_start(b, nb) * TT4 + (size_t)blockIdx.x * TT4;
+  float4 *dst = P + (size_t)(tile_start(b, nb) - tile_base) * TT4 + (size_t)blockIdx.x * TT4;
   const float *src = dblock + (int64_t)J * T;
   if (J != b) {
 #pragma unroll 4
@@ -535,7 +550,7 @@ __device__ __forceinline__ void pack_tile(float4 *__restrict__ P, const float *_
                                           const float *__restrict__ r, int64_t n, int32_t nb,
                                           double2 *__restrict__ ppart,
                                           uint8_t *__restrict__ nzflag, int2 *__restrict__ tmap,
-                                          int64_t tile) {
+                                          int64_t tile, int64_t pslot) {
   __shared__ double red[2][4];
   int I, J;
   tile_coords(tile, nb, I, J);
@@ -560,7 +575,7 @@ __device__ __forceinline__ void pack_tile(float4 *__restrict__ P, const float *_
     mc[k] = ok ? m[j] : 0.f;
     rc[k] = ok ? r[j] : 0.f;
   }
-  float4 *tp = P + (size_t)tile * TT4;
+  float4 *tp = P + (size_t)pslot * TT4;
   float psum = 0.f, plp = 0.f;
   bool any = false;
 #pragma unroll 2
@@ -614,11 +629,11 @@ __global__ __launch_bounds__(256) void k_pack(float4 *__restrict__ P, const floa
                                               double2 *__restrict__ ppart,
                                               uint8_t *__restrict__ nzflag,
                                               int2 *__restrict__ tmap) {
-  pack_tile(P, a, m, r, n, nb, ppart, nzflag, tmap, blockIdx.x);
+  pack_tile(P, a, m, r, n, nb, ppart, nzflag, tmap, blockIdx.x, blockIdx.x);
 }
 
 __device__ __forceinline__ void pack_reduce_wg(const double2 *__restrict__ ppart, int64_t nt,
-                                               Hdr *h) {
+                                               Hdr *h, int32_t ready = 1) {
   __shared__ double red[2][16];
   double s = 0.0, lg = 0.0;
   for (int64_t q = threadIdx.x; q < nt; q += 1024) {
@@ -641,7 +656,7 @@ __device__ __forceinline__ void pack_reduce_wg(const double2 *__restrict__ ppart
     h->p_sum = S;
     h->c_p = Lg;
     if (!isfinite(S) || !isfinite(Lg)) atomicOr(&h->err, kErrNonFinite);
-    h->ready = 1;
+    h->ready = ready;
   }
 }
 
@@ -1001,7 +1016,8 @@ __global__ void k_export_stats(int64_t n, const double *__restrict__ beta,
                                const double *__restrict__ H, const int32_t *__restrict__ ev,
                                const int32_t *__restrict__ inv, double *ob, float *om, double *oS,
                                double *oH, int32_t *oe, Hdr *h) {
-  if (!(h->magic == kMagic && h->n == n)) {
+  // affinities for this n complete (stored or implicit P): the order exists
+  if (!(h->magic == kMagic && h->n == n && (h->ready == 1 || h->ready == 2))) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
@@ -1013,6 +1029,23 @@ __global__ void k_export_stats(int64_t n, const double *__restrict__ beta,
   if (oS) oS[i] = S[r];
   if (oH) oH[i] = H[r];
   if (oe) oe[i] = ev[r];
+}
+
+// The internal order and the zero-tile flags, after checking that the
+// workspace holds affinities for this n.
+__global__ __launch_bounds__(256) void k_export_order(const Hdr *h, int64_t n, int64_t nt,
+                                                      const int32_t *__restrict__ perm,
+                                                      const uint8_t *__restrict__ nz,
+                                                      int32_t *__restrict__ operm,
+                                                      uint8_t *__restrict__ oflags) {
+  if (!(h->magic == kMagic && h->n == n && (h->ready == 1 || h->ready == 2))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(const_cast<Hdr *>(h), kErrState);
+    return;
+  }
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (operm && i < n) operm[i] = perm[i];
+  // the flags exist only where P is stored
+  if (oflags && h->ready == 1 && i < nt) oflags[i] = nz[i];
 }
 
 __global__ void k_export_scalars(int64_t n, const Hdr *h, double *out) {
@@ -1334,7 +1367,7 @@ __global__ __launch_bounds__(256) void k_small_pack(const SmallEntry *__restrict
   const SmallEntry &e = tab[p];
   const int64_t tile = (int64_t)blockIdx.x - e.tile0;
   if (tile < 0 || tile >= e.nt) return;
-  pack_tile(e.P, e.a, e.m, e.r, e.n, e.nb, e.ppart, e.nz, e.tmap, tile);
+  pack_tile(e.P, e.a, e.m, e.r, e.n, e.nb, e.ppart, e.nz, e.tmap, tile, tile);
 }
 
 __global__ __launch_bounds__(256) void k_small_slots(const SmallEntry *__restrict__ tab,
@@ -1355,6 +1388,50 @@ __global__ __launch_bounds__(1024) void k_small_lists(const SmallEntry *__restri
   tile_lists_wg(e.nz, e.nt, e.tlist, e.tcount);
 }
 
+// ----------------------------------------------------------------------------
+// 6. Implicit P: the workspace keeps one block row of tiles; every pass
+// recomputes the distances of block b (the same MFMA kernel as the affinity
+// stage, from the centred X in the internal order), stages them and packs the
+// block's tiles (b, b .. nb - 1) into the buffer, slot x holding tile
+// tile_start(b) + x. The arithmetic is that of the stored P, so the values
+// are bitwise the same.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack_range(float4 *__restrict__ Pb,
+                                                    const float *__restrict__ a,
+                                                    const float *__restrict__ m,
+                                                    const float *__restrict__ r, int64_t n,
+                                                    int32_t nb, double2 *__restrict__ ppart,
+                                                    uint8_t *__restrict__ nzflag,
+                                                    int2 *__restrict__ tmap, int64_t tile0,
+                                                    const Hdr *guard, int32_t gd) {
+  if (!implicit_ready(guard, n, gd)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(const_cast<Hdr *>(guard), kErrState);
+    return;
+  }
+  pack_tile(Pb, a, m, r, n, nb, ppart, nzflag, tmap, tile0 + blockIdx.x, blockIdx.x);
+}
+
+// After all blocks of a pass: sums of P (the header keeps ready = 2).
+__global__ __launch_bounds__(1024) void k_implicit_sums(const double2 *__restrict__ ppart,
+                                                        int64_t nt, int64_t n, int32_t d, Hdr *h) {
+  if (!implicit_ready(h, n, d)) return;
+  pack_reduce_wg(ppart, nt, h, 2);
+}
+
+// End of an implicit affinity stage: no tile flagged nonzero and empty slot
+// lists until the first pass builds them, then the mode in the header.
+__global__ __launch_bounds__(256) void k_implicit_init(uint8_t *__restrict__ nz, int64_t nt,
+                                                       int32_t *__restrict__ nslots, int32_t nb,
+                                                       Hdr *h) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nt) nz[i] = 0;
+  if (i < nb) nslots[i] = 0;
+}
+
+__global__ void k_set_ready(Hdr *h, int32_t ready) {
+  if (threadIdx.x == 0) h->ready = ready;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -1362,7 +1439,7 @@ __global__ __launch_bounds__(1024) void k_small_lists(const SmallEntry *__restri
 // ----------------------------------------------------------------------------
 hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
                              int max_bisect, double tol_h, int reorder, void *ws, hipStream_t st,
-                             bool stats_only) {
+                             bool stats_only, bool implicit) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(64), 0, st, h, L.n, L.d, L.mode, perplexity);
   double *mean = at<double>(ws, L.xmean);
@@ -1439,7 +1516,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
         break;
       default:
         hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64),
-                           dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b, dblock);
+                           dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b, dblock,
+                           (const Hdr *)nullptr, (int64_t)0, 0);
     }
   };
   auto calibrate = [&](int b) {
@@ -1487,7 +1565,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
       hipLaunchKernelGGL(k_dissim_block, dim3((unsigned)(L.npad / 256), T / 16), dim3(256), 0, st,
                          dis, L.n, L.npad, b, dblock, h);
       calibrate(b);
-      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
+      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P,
+                         (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
     }
     pack();
     return hipGetLastError();
@@ -1551,10 +1630,47 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   for (int b = 0; b < L.nb; ++b) {
     dist(b, xc, nrm);
     calibrate(b);
-    if (!stats_only)
-      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P);
+    if (!stats_only && !implicit)
+      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P,
+                         (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
   }
-  if (!stats_only) pack();
+  if (implicit) {
+    // every pass rebuilds P from the centred X in the internal order: make
+    // sure it sits in the second buffer (the identity order copies it)
+    if (xc != at<double>(ws, L.xcT2))
+      hipLaunchKernelGGL(k_permute_x, dim3(pgrid), dim3(256), 0, st, xcT, norms, perm, L.n,
+                         L.npad, L.dpad, at<double>(ws, L.xcT2), at<double>(ws, L.norms2));
+    const int64_t m = L.nt > L.nb ? L.nt : L.nb;
+    hipLaunchKernelGGL(k_implicit_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                       at<uint8_t>(ws, L.nz), L.nt, at<int32_t>(ws, L.nslots), L.nb, h);
+    hipLaunchKernelGGL(k_set_ready, dim3(1), dim3(64), 0, st, h, 2);
+  } else if (!stats_only) {
+    pack();
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_implicit_block(const Layout &L, void *ws, int b, hipStream_t st) {
+  float *dblock = at<float>(ws, L.dblock);
+  const int64_t t0 = tile_start(b, L.nb);
+  const Hdr *h = at<const Hdr>(ws, L.hdr);
+  hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64), dim3(256), 0,
+                     st, at<const double>(ws, L.xcT2), at<const double>(ws, L.norms2), L.npad,
+                     L.dpad, b, dblock, h, L.n, L.d);
+  hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b,
+                     at<float4>(ws, L.P), t0, h, L.n, L.d);
+  hipLaunchKernelGGL(k_pack_range, dim3(L.nb - b), dim3(256), 0, st, at<float4>(ws, L.P),
+                     at<const float>(ws, L.a), at<const float>(ws, L.m), at<const float>(ws, L.r),
+                     L.n, L.nb, at<double2>(ws, L.ppart), at<uint8_t>(ws, L.nz),
+                     at<int2>(ws, L.tmap), t0, h, L.d);
+  return hipGetLastError();
+}
+
+hipError_t launch_implicit_sums(const Layout &L, void *ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_implicit_sums, dim3(1), dim3(1024), 0, st, at<const double2>(ws, L.ppart),
+                     L.nt, L.n, L.d, at<Hdr>(ws, L.hdr));
+  hipLaunchKernelGGL(k_slot_lists, dim3(L.nb), dim3(256), 0, st, at<const uint8_t>(ws, L.nz),
+                     L.nb, at<int32_t>(ws, L.slots), at<int32_t>(ws, L.nslots));
   return hipGetLastError();
 }
 
@@ -1630,6 +1746,15 @@ hipError_t launch_export_rowstats(const Layout &L, void *ws, double *beta, float
                      at<const double>(ws, L.S), at<const double>(ws, L.H),
                      at<const int32_t>(ws, L.evals), at<const int32_t>(ws, L.inv), beta, m, S, H,
                      evals, at<Hdr>(ws, L.hdr));
+  return hipGetLastError();
+}
+
+hipError_t launch_export_order(const Layout &L, void *ws, int32_t *perm, uint8_t *flags,
+                               hipStream_t st) {
+  const int64_t m = L.n > L.nt ? L.n : L.nt;
+  hipLaunchKernelGGL(k_export_order, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                     at<const Hdr>(ws, L.hdr), L.n, L.nt, at<const int32_t>(ws, L.perm),
+                     at<const uint8_t>(ws, L.nz), perm, flags);
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ namespace tsne {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only) {
+Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only, bool implicit) {
   Layout L;
   L.n = n;
   L.d = d;
@@ -41,7 +41,6 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only) {
   L.a = take(np * 4);
   L.r = take(np * 4);
   L.evals = take(np * 4);
-  L.P = take(sz * (size_t)L.nt * T * T * 4);
   L.part = take(sz * (size_t)L.nb * L.nb * T * 16);
   L.zpart = take(sz * (size_t)L.nt * 8);
   L.cpart = take(sz * (size_t)L.nt * 16);
@@ -57,6 +56,11 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only) {
   L.inv = take(np * 4);
   L.yp = take(sz * np * 8);
   L.extent = take(sz * (size_t)L.nb * 16);
+  // P last: every array above has the same offset whether P is stored (nt
+  // tiles) or recomputed per pass (one block row of nb tiles), so the entry
+  // points of either mode stay inside the other's workspace and find its
+  // header, order and statistics
+  L.P = take(sz * (size_t)(implicit ? L.nb : L.nt) * T * T * 4);
   L.iter_end = o;
   // affinity-stage scratch (only needed inside tsne_affinities)
   L.xmean = take((size_t)L.dpad * 8);
@@ -130,18 +134,21 @@ int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
   if (d < 1 || d > 65536) return fail(TSNE_E_ARG, "tsne_affinities: d = %d out of range", d);
   if (o.dist_mode < TSNE_DIST_FP64 || o.dist_mode > TSNE_DIST_FP16X3)
     return fail(TSNE_E_ARG, "tsne_affinities: unknown distance mode %d", o.dist_mode);
-  if (o.max_bisect < 1 || !(o.tol_h > 0.0) || o.reserved != 0)
-    return fail(TSNE_E_ARG, "tsne_affinities: max_bisect >= 1, tol_h > 0, reserved = 0 required");
+  if (o.max_bisect < 1 || !(o.tol_h > 0.0) || (o.implicit_p != 0 && o.implicit_p != 1))
+    return fail(TSNE_E_ARG, "tsne_affinities: max_bisect >= 1, tol_h > 0, implicit_p 0 or 1 required");
+  if (o.implicit_p && o.dist_mode != TSNE_DIST_FP64)
+    return fail(TSNE_E_ARG, "tsne_affinities: implicit P needs the FP64 distance mode");
   if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))
     return fail(TSNE_E_PERPLEXITY, "tsne_affinities: perplexity %g not in (1, n-1 = %lld)",
                 perplexity, (long long)(n - 1));
   if (!aligned(ws, 256)) return fail(TSNE_E_WORKSPACE, "tsne_affinities: ws not 256-byte aligned");
-  const Layout L = tsne::make_layout(n, d, o.dist_mode);
+  const Layout L = tsne::make_layout(n, d, o.dist_mode, false, o.implicit_p != 0);
   if (ws_bytes < L.total)
     return fail(TSNE_E_WORKSPACE, "tsne_affinities: workspace %zu bytes, need %zu", ws_bytes,
                 L.total);
   return hip_check(tsne::launch_affinities(L, x, nullptr, perplexity, o.max_bisect, o.tol_h,
-                                           o.reorder != 0, ws, (hipStream_t)stream),
+                                           o.reorder != 0, ws, (hipStream_t)stream, false,
+                                           o.implicit_p != 0),
                    "tsne_affinities");
 }
 
@@ -152,9 +159,9 @@ int tsne_affinities_dissim(const float *dis, int64_t n, double perplexity,
   if (!dis || !ws) return fail(TSNE_E_ARG, "tsne_affinities_dissim: null pointer");
   if (!valid_n(n))
     return fail(TSNE_E_ARG, "tsne_affinities_dissim: n = %lld out of range", (long long)n);
-  if (o.max_bisect < 1 || !(o.tol_h > 0.0) || o.reserved != 0)
+  if (o.max_bisect < 1 || !(o.tol_h > 0.0) || o.implicit_p != 0)
     return fail(TSNE_E_ARG,
-                "tsne_affinities_dissim: max_bisect >= 1, tol_h > 0, reserved = 0 required");
+                "tsne_affinities_dissim: max_bisect >= 1, tol_h > 0, implicit_p = 0 required");
   if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))
     return fail(TSNE_E_PERPLEXITY, "tsne_affinities_dissim: perplexity %g not in (1, n-1 = %lld)",
                 perplexity, (long long)(n - 1));
@@ -239,6 +246,57 @@ int tsne_cost(void *ws, int64_t n, const float *y, double *out, void *stream) {
   return hip_check(tsne::launch_cost(L, ws, y, out, (hipStream_t)stream), "tsne_cost");
 }
 
+size_t tsne_workspace_bytes_implicit(int64_t n, int32_t d) {
+  if (!valid_n(n) || d < 1 || d > 65536) return 0;
+  return tsne::make_layout(n, d, TSNE_DIST_FP64, false, true).total;
+}
+
+// The iteration entry points on a workspace whose P is recomputed per pass
+// (the layout of tsne_workspace_bytes_implicit, filled by tsne_affinities
+// with implicit_p = 1).
+static int check_implicit(const char *fn, void *ws, int64_t n, int32_t d) {
+  if (int rc = check_iter_args(fn, ws, n)) return rc;
+  if (d < 1 || d > 65536) return fail(TSNE_E_ARG, "%s: d = %d out of range", fn, d);
+  return TSNE_OK;
+}
+
+int tsne_step_implicit(void *ws, int64_t n, int32_t d, float *y, float *u, float *g,
+                       const tsne_step_params *prm, float *grad_out, double *z_out,
+                       void *stream) {
+  if (int rc = check_implicit("tsne_step_implicit", ws, n, d)) return rc;
+  if (!y || !u || !prm || (!g && prm->lr_rule != TSNE_LR_RANGE))
+    return fail(TSNE_E_ARG, "tsne_step_implicit: null pointer");
+  if (int rc = check_params("tsne_step_implicit", prm)) return rc;
+  const Layout L = tsne::make_layout(n, d, TSNE_DIST_FP64, false, true);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = tsne::launch_force_implicit(L, ws, y, st);
+  if (e == hipSuccess)
+    e = tsne::launch_update(L, ws, y, u, g, prm->exaggeration, prm->momentum, prm->learning_rate,
+                            prm->min_gain, prm->recentre, prm->lr_rule, grad_out, z_out, st);
+  return hip_check(e, "tsne_step_implicit");
+}
+
+int tsne_gradient_implicit(void *ws, int64_t n, int32_t d, const float *y, float alpha,
+                           float *grad_out, double *z_out, void *stream) {
+  if (int rc = check_implicit("tsne_gradient_implicit", ws, n, d)) return rc;
+  if (!y || !grad_out) return fail(TSNE_E_ARG, "tsne_gradient_implicit: null pointer");
+  if (!isfinite(alpha)) return fail(TSNE_E_ARG, "tsne_gradient_implicit: non-finite alpha");
+  const Layout L = tsne::make_layout(n, d, TSNE_DIST_FP64, false, true);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = tsne::launch_force_implicit(L, ws, y, st);
+  if (e == hipSuccess) e = tsne::launch_gradient_only(L, ws, alpha, grad_out, z_out, st);
+  return hip_check(e, "tsne_gradient_implicit");
+}
+
+int tsne_cost_implicit(void *ws, int64_t n, int32_t d, const float *y, double *out,
+                       void *stream) {
+  if (int rc = check_implicit("tsne_cost_implicit", ws, n, d)) return rc;
+  if (!y || !out) return fail(TSNE_E_ARG, "tsne_cost_implicit: null pointer");
+  const Layout L = tsne::make_layout(n, d, TSNE_DIST_FP64, false, true);
+  return hip_check(tsne::launch_cost_implicit(L, ws, y, out, (hipStream_t)stream),
+                   "tsne_cost_implicit");
+}
+
 int tsne_sync_status(void *ws, void *stream) {
   if (!ws) return fail(TSNE_E_ARG, "tsne_sync_status: null workspace");
   hipStream_t st = (hipStream_t)stream;
@@ -287,15 +345,8 @@ int tsne_export_p_rows(void *ws, int64_t n, int64_t row0, int64_t nrows, float *
 int tsne_export_order(void *ws, int64_t n, int32_t *perm, uint8_t *flags, void *stream) {
   if (int rc = check_iter_args("tsne_export_order", ws, n)) return rc;
   const Layout L = tsne::make_layout(n, 1, TSNE_DIST_FP64);
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipSuccess;
-  if (perm)
-    e = hipMemcpyAsync(perm, tsne::at<const int32_t>(ws, L.perm), (size_t)n * 4,
-                       hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess && flags)
-    e = hipMemcpyAsync(flags, tsne::at<const uint8_t>(ws, L.nz), (size_t)L.nt,
-                       hipMemcpyDeviceToDevice, st);
-  return hip_check(e, "tsne_export_order");
+  return hip_check(tsne::launch_export_order(L, ws, perm, flags, (hipStream_t)stream),
+                   "tsne_export_order");
 }
 
 size_t tsne_batch_workspace_bytes(int32_t count) {

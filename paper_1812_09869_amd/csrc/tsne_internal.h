@@ -78,7 +78,10 @@ struct Layout {
 
 // stats_only: a layout holding only what the per-row search needs (header,
 // row statistics, order, centred X and the distance block).
-Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only = false);
+// implicit: P is not stored; one block row of tiles holds the P that every
+// pass recomputes (FP64 distances only).
+Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only = false,
+                   bool implicit = false);
 
 // Upper-triangle tile enumeration: row I holds tiles (I, I..nb-1).
 __host__ __device__ inline int64_t tile_start(int64_t I, int64_t nb) {
@@ -160,7 +163,14 @@ inline P *at(void *ws, size_t off) {
 // Exactly one of x (n x d points) and dis (n x n dissimilarities) is non-null.
 hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
                              int max_bisect, double tol_h, int reorder, void *ws,
-                             hipStream_t stream, bool stats_only = false);
+                             hipStream_t stream, bool stats_only = false, bool implicit = false);
+// Implicit P: recompute block b's distances, stage and pack its tiles into the
+// one-block-row buffer; after all blocks, the P sums and the slot lists.
+hipError_t launch_implicit_block(const Layout &L, void *ws, int b, hipStream_t stream);
+hipError_t launch_implicit_sums(const Layout &L, void *ws, hipStream_t stream);
+hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipStream_t stream);
+hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, double *out,
+                                hipStream_t stream);
 // Fills the table entry of a problem whose workspace has layout L.
 void small_entry(const Layout &L, void *ws, const float *x, double perplexity, SmallEntry &e);
 // tab: device copy of `count` entries with prefix offsets filled in; wgs,
@@ -186,6 +196,8 @@ hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tile
 hipError_t launch_export_p_rows(const Layout &L, void *ws, int64_t row0, int64_t nrows,
                                 float *out, hipStream_t stream);
 hipError_t launch_export_scalars(const Layout &L, void *ws, double *out, hipStream_t stream);
+hipError_t launch_export_order(const Layout &L, void *ws, int32_t *perm, uint8_t *flags,
+                               hipStream_t stream);
 hipError_t launch_export_rowstats(const Layout &L, void *ws, double *beta, float *m, double *S,
                                   double *H, int32_t *evals, hipStream_t stream);
 

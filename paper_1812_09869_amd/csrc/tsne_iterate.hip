@@ -80,8 +80,14 @@ __device__ inline float wave_sum_f(float v) {
 
 // Header check shared by the iteration kernels: the workspace must hold
 // affinities for exactly this n.
+// The workspace holds affinities for n points: ready is 1 when P is stored,
+// 2 when P is recomputed in every pass (implicit P). Kernels that read the
+// stored P accept only 1, those of the implicit pass only 2.
 __device__ inline bool state_ok(Hdr *h, int64_t n) {
-  return h->magic == kMagic && h->n == n && h->ready == 1;
+  return h->magic == kMagic && h->n == n && (h->ready == 1 || h->ready == 2);
+}
+__device__ inline bool ready_is(Hdr *h, int64_t n, int32_t ready) {
+  return h->magic == kMagic && h->n == n && h->ready == ready;
 }
 
 // One row (k) of a thread's 16 x 16 block against its 16 columns.
@@ -291,7 +297,8 @@ __device__ __forceinline__ void gather_rows(const float2 *__restrict__ Y,
 __global__ __launch_bounds__(256) void k_gather_y(const float2 *__restrict__ Y,
                                                   const int32_t *__restrict__ perm, int64_t n,
                                                   float2 *__restrict__ Yp,
-                                                  float4 *__restrict__ extent) {
+                                                  float4 *__restrict__ extent, Hdr *h) {
+  if (!state_ok(h, n)) return;  // the layout of another n: touch nothing
   gather_rows(Y, perm, n, Yp, extent, blockIdx.x);
 }
 
@@ -394,13 +401,13 @@ __device__ __forceinline__ void full_tile_body(const TileCtx &c, const float2 (&
                                                const float4 *__restrict__ P,
                                                float4 *__restrict__ part, int32_t nb,
                                                float *__restrict__ zpart, int64_t tile,
-                                               ForceSmem &sm) {
+                                               int64_t pslot, ForceSmem &sm) {
   float2 *prep = part_rep(part), *patt = part_att(part, nb);
   float z = 0.f;
   float4 *wring = &sm.ring[c.w][0][0][0];
   const uint32_t lane_addr = (uint32_t)(size_t)((lds_void_t *)wring) + (uint32_t)c.l * 16u;
   const uint32_t yrow_addr = (uint32_t)(size_t)((lds_void_t *)(sm.yrow + c.tr));
-  const float4 *tp = P + (size_t)tile * TT4;
+  const float4 *tp = P + (size_t)pslot * TT4;
   float4 myrow = make_float4(0.f, 0.f, 0.f, 0.f);
   float4 colacc[16];
 #pragma unroll
@@ -465,7 +472,7 @@ __global__ __launch_bounds__(256, 4) void k_force_zero(const float2 *__restrict_
   __shared__ ZeroSmem sm;
   // the header check comes first: with a workspace for another n, the lists
   // are not where this layout puts them
-  if (!state_ok(h, n)) {
+  if (!ready_is(h, n, 1)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
@@ -484,7 +491,7 @@ __global__ __launch_bounds__(256, 2) void k_force_full(const float4 *__restrict_
                                                        const int32_t *__restrict__ tcount,
                                                        const int2 *__restrict__ tmap, Hdr *h) {
   __shared__ ForceSmem sm;
-  if (!state_ok(h, n)) {
+  if (!ready_is(h, n, 1)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
@@ -497,8 +504,27 @@ __global__ __launch_bounds__(256, 2) void k_force_full(const float4 *__restrict_
     const int64_t tile = tlist[first + i];
     float2 yc[16];
     const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
-    full_tile_body(c, yc, P, part, nb, zpart, tile, sm);
+    full_tile_body(c, yc, P, part, nb, zpart, tile, tile, sm);
   }
+}
+
+// Implicit P: the tiles (b, b .. nb - 1) of one block row, whose P was just
+// recomputed into the one-block-row buffer Pb (tile tile0 + x at slot x).
+__global__ __launch_bounds__(256, 2) void k_force_range(const float4 *__restrict__ Pb,
+                                                        const float2 *__restrict__ Y, int64_t n,
+                                                        int32_t nb, float4 *__restrict__ part,
+                                                        float *__restrict__ zpart,
+                                                        const int2 *__restrict__ tmap,
+                                                        int64_t tile0, int32_t d, Hdr *h) {
+  __shared__ ForceSmem sm;
+  if (!ready_is(h, n, 2) || h->d != d) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
+    return;
+  }
+  const int64_t tile = tile0 + blockIdx.x;
+  float2 yc[16];
+  const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
+  full_tile_body(c, yc, Pb, part, nb, zpart, tile, blockIdx.x, sm);
 }
 
 // ----------------------------------------------------------------------------
@@ -556,8 +582,10 @@ __device__ inline double4 row_sums(const float4 *__restrict__ part,
                                    const int32_t *__restrict__ slots,
                                    const int32_t *__restrict__ nslots, int32_t nb, int b, int r,
                                    int q, UpdSmem &sm) {
-  // the block's list of slots with nonzero P (attractive sums exist only there)
-  const int cnt = nslots[b];
+  // the block's list of slots with nonzero P (attractive sums exist only
+  // there); count and entries are clamped to the block's nb slots, so a list
+  // that was never built cannot send the reads outside the partial sums
+  const int cnt = min(max(nslots[b], 0), (int)nb);
   const int32_t *gl = slots + (int64_t)b * nb;
   for (int m = threadIdx.x; m < cnt && m < kSlotLds; m += kUpd) sm.slots[m] = gl[m];
   __syncthreads();
@@ -571,6 +599,7 @@ __device__ inline double4 row_sums(const float4 *__restrict__ part,
   }
   for (int m = q; m < cnt; m += kUpdSplit) {
     const int s = m < kSlotLds ? sm.slots[m] : gl[m];
+    if (s < 0 || s >= nb) continue;
     const float2 a = pa[(size_t)s * T];
     ax += a.x;
     ay += a.y;
@@ -788,7 +817,7 @@ __global__ __launch_bounds__(256, 4) void k_force_zero_batched(const BatchHdr *_
   const BatchEntry &e = tab[p];
   const int64_t i = (int64_t)blockIdx.x - e.tile0;
   if (i < 0 || i >= e.nt) return;
-  if (!state_ok(e.h, e.n)) {
+  if (!ready_is(e.h, e.n, 1)) {
     if (i == 0 && threadIdx.x == 0) flag_error(e.h, kErrState);
     return;
   }
@@ -809,12 +838,12 @@ __global__ __launch_bounds__(256, 2) void k_force_full_batched(const BatchHdr *_
   const BatchEntry &e = tab[p];
   const int64_t i = (int64_t)blockIdx.x - e.tile0;
   if (i < 0 || i >= e.nt) return;
-  if (!state_ok(e.h, e.n)) return;
+  if (!ready_is(e.h, e.n, 1)) return;
   if (i >= e.tcount[1]) return;
   const int64_t tile = e.tlist[e.tcount[0] + i];
   float2 yc[16];
   const TileCtx c = tile_begin(e.yp, e.n, e.nb, e.tmap, tile, yc, sm);
-  full_tile_body(c, yc, e.P, e.part, e.nb, e.zpart, tile, sm);
+  full_tile_body(c, yc, e.P, e.part, e.nb, e.zpart, tile, tile, sm);
 }
 
 __global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restrict__ bh,
@@ -826,6 +855,7 @@ __global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restri
   const BatchEntry &e = tab[p];
   const int64_t b = (int64_t)blockIdx.x - e.blk0;
   if (b < 0 || b >= e.nb) return;
+  if (!state_ok(e.h, e.n)) return;
   gather_rows(e.Y, e.perm, e.n, e.yp, e.extent, b);
 }
 
@@ -919,9 +949,10 @@ __device__ __forceinline__ void cost_tile(const float4 *__restrict__ tp,
 __device__ __forceinline__ void cost_wg(const float4 *__restrict__ P,
                                         const float2 *__restrict__ Y, int64_t n, int32_t nb,
                                         double2 *__restrict__ cpart,
-                                        const uint8_t *__restrict__ nz, Hdr *h, int64_t tile) {
+                                        const uint8_t *__restrict__ nz, Hdr *h, int64_t tile,
+                                        int64_t pslot, int32_t ready) {
   __shared__ double red[2][4];
-  if (!state_ok(h, n)) {
+  if (!ready_is(h, n, ready)) {
     if (tile == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
@@ -936,7 +967,7 @@ __device__ __forceinline__ void cost_wg(const float4 *__restrict__ P,
   for (int k = 0; k < 16; ++k) yc[k] = Y[(int64_t)J * T + tc + 16 * k];
   const float2 *yrow = Y + (int64_t)I * T + tr;
   const bool edge = ((int64_t)(J + 1) * T > n);
-  const float4 *tp = P + (size_t)tile * TT4;
+  const float4 *tp = P + (size_t)pslot * TT4;
   float plq = 0.f, z = 0.f;
   if (!nz[tile]) {
     // no p_ij in this tile: only Z
@@ -980,7 +1011,16 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
                                                  const float2 *__restrict__ Y, int64_t n,
                                                  int32_t nb, double2 *__restrict__ cpart,
                                                  const uint8_t *__restrict__ nz, Hdr *h) {
-  cost_wg(P, Y, n, nb, cpart, nz, h, blockIdx.x);
+  cost_wg(P, Y, n, nb, cpart, nz, h, blockIdx.x, blockIdx.x, 1);
+}
+
+// Implicit P: the cost terms of the tiles of one block row (see k_force_range).
+__global__ __launch_bounds__(256, 2) void k_cost_range(const float4 *__restrict__ Pb,
+                                                       const float2 *__restrict__ Y, int64_t n,
+                                                       int32_t nb, double2 *__restrict__ cpart,
+                                                       const uint8_t *__restrict__ nz, Hdr *h,
+                                                       int64_t tile0) {
+  cost_wg(Pb, Y, n, nb, cpart, nz, h, tile0 + blockIdx.x, blockIdx.x, 2);
 }
 
 __device__ __forceinline__ void cost_reduce_wg(const double2 *__restrict__ cpart, int64_t nt,
@@ -1029,7 +1069,7 @@ __global__ __launch_bounds__(256, 2) void k_cost_batched(const BatchHdr *__restr
   const BatchEntry &e = tab[p];
   const int64_t i = (int64_t)blockIdx.x - e.tile0;
   if (i < 0 || i >= e.nt) return;
-  cost_wg(e.P, e.yp, e.n, e.nb, e.cpart, e.nz, e.h, i);
+  cost_wg(e.P, e.yp, e.n, e.nb, e.cpart, e.nz, e.h, i, i, 1);
 }
 
 __global__ __launch_bounds__(1024) void k_cost_reduce_batched(const BatchHdr *__restrict__ bh,
@@ -1079,7 +1119,7 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
   Hdr *h = at<Hdr>(ws, L.hdr);
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
-                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent));
+                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent), h);
   const int32_t *tl = at<const int32_t>(ws, L.tlist), *tc = at<const int32_t>(ws, L.tcount);
   const int2 *tm = at<const int2>(ws, L.tmap);
   float4 *part = at<float4>(ws, L.part);
@@ -1099,6 +1139,46 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
   return hipStreamWaitEvent(st, ss->join, 0);
+}
+
+// Implicit P: per block row, recompute its tiles' P into the buffer (the
+// affinity kernels) and run the full tile body on them; then the P sums and
+// the slot lists of the update. Every tile takes the full body (the all-zero
+// split needs the tile lists of a stored P).
+hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipStream_t st) {
+  Hdr *h = at<Hdr>(ws, L.hdr);
+  float2 *yp = at<float2>(ws, L.yp);
+  hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
+                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent), h);
+  for (int b = 0; b < L.nb; ++b) {
+    hipError_t e = launch_implicit_block(L, ws, b, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_force_range, dim3((unsigned)(L.nb - b)), dim3(256), 0, st,
+                       at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb,
+                       at<float4>(ws, L.part), at<float>(ws, L.zpart), at<const int2>(ws, L.tmap),
+                       tile_start(b, L.nb), L.d, h);
+  }
+  return launch_implicit_sums(L, ws, st);
+}
+
+hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, double *out,
+                                hipStream_t st) {
+  Hdr *h = at<Hdr>(ws, L.hdr);
+  double2 *cp = at<double2>(ws, L.cpart);
+  float2 *yp = at<float2>(ws, L.yp);
+  hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
+                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent), h);
+  for (int b = 0; b < L.nb; ++b) {
+    hipError_t e = launch_implicit_block(L, ws, b, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cost_range, dim3((unsigned)(L.nb - b)), dim3(256), 0, st,
+                       at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb, cp,
+                       at<const uint8_t>(ws, L.nz), h, tile_start(b, L.nb));
+  }
+  hipError_t e = launch_implicit_sums(L, ws, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_update(const Layout &L, void *ws, float *y, float *u, float *g, float alpha,
@@ -1135,7 +1215,7 @@ hipError_t launch_cost(const Layout &L, void *ws, const float *y, double *out, h
   double2 *cp = at<double2>(ws, L.cpart);
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
-                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent));
+                     at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent), h);
   hipLaunchKernelGGL(k_cost, dim3((unsigned)L.nt), dim3(256), 0, st, at<const float4>(ws, L.P), yp,
                      L.n, L.nb, cp, at<const uint8_t>(ws, L.nz), h);
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);

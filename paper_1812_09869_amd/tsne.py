@@ -47,14 +47,19 @@ class Schedule:
 
 class ExactTSNE:
     def __init__(self, x: torch.Tensor, perplexity: float, dist_mode="fp64", max_bisect: int = 200,
-                 tol_h: float = 1e-6, ws: torch.Tensor | None = None, reorder: bool = True):
+                 tol_h: float = 1e-6, ws: torch.Tensor | None = None, reorder: bool = True,
+                 implicit: bool = False):
+        """implicit: keep no P and recompute it in every pass (FP64 mode)."""
         if x.dim() != 2:
             raise ValueError("x must be n x d")
         self.n, self.d = x.shape
         self.perplexity = float(perplexity)
-        self.ws = ws if ws is not None else _lib.new_workspace(self.n, self.d, dist_mode,
-                                                               device=x.device)
-        _lib.affinities(x, perplexity, self.ws, dist_mode, max_bisect, tol_h, reorder)
+        self.implicit = bool(implicit)
+        if ws is None:
+            ws = (_lib.new_workspace_implicit(self.n, self.d, device=x.device) if implicit else
+                  _lib.new_workspace(self.n, self.d, dist_mode, device=x.device))
+        self.ws = ws
+        _lib.affinities(x, perplexity, self.ws, dist_mode, max_bisect, tol_h, reorder, implicit)
         self._z = torch.zeros(1, dtype=torch.float64, device=x.device)
         self._cost = torch.zeros(2, dtype=torch.float64, device=x.device)
 
@@ -65,6 +70,7 @@ class ExactTSNE:
         of points; the iteration is the same."""
         self = cls.__new__(cls)
         self.n, self.d = dis.shape[0], 1
+        self.implicit = False
         self.perplexity = float(perplexity)
         self.ws = _lib.new_workspace(self.n, 1, "fp64", device=dis.device)
         _lib.affinities_dissim(dis.contiguous(), perplexity, self.ws, max_bisect, tol_h)
@@ -79,8 +85,12 @@ class ExactTSNE:
     def step(self, t: int, state, sched: Schedule, grad_out=None, z_out=None):
         y, u, g = state
         alpha, mu, eta = sched(t)
-        _lib.step(self.ws, self.n, y, u, g, alpha, mu, eta, sched.min_gain, True, grad_out, z_out,
-                  lr_rule=sched.lr_rule)
+        if self.implicit:
+            _lib.step_implicit(self.ws, self.n, self.d, y, u, g, alpha, mu, eta, sched.min_gain,
+                               True, grad_out, z_out, lr_rule=sched.lr_rule)
+        else:
+            _lib.step(self.ws, self.n, y, u, g, alpha, mu, eta, sched.min_gain, True, grad_out,
+                      z_out, lr_rule=sched.lr_rule)
 
     def run(self, state, iters: int, start: int = 0, sched: Schedule | None = None):
         sched = sched or Schedule()
@@ -90,12 +100,18 @@ class ExactTSNE:
 
     def gradient(self, y: torch.Tensor, alpha: float = 1.0):
         g = torch.empty_like(y)
-        _lib.gradient(self.ws, self.n, y, alpha, g, self._z)
+        if self.implicit:
+            _lib.gradient_implicit(self.ws, self.n, self.d, y, alpha, g, self._z)
+        else:
+            _lib.gradient(self.ws, self.n, y, alpha, g, self._z)
         return g, self._z
 
     def cost(self, y: torch.Tensor):
         """Device tensor [KL, C_norm]."""
-        _lib.cost(self.ws, self.n, y, self._cost)
+        if self.implicit:
+            _lib.cost_implicit(self.ws, self.n, self.d, y, self._cost)
+        else:
+            _lib.cost(self.ws, self.n, y, self._cost)
         return self._cost
 
     def status(self) -> int:

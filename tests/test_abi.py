@@ -68,3 +68,15 @@ def test_pt_host_logic_matches_the_paper_examples():
                 _lib.pt_opts(5, 2, 799.5),       # perplexity >= z - 1
                 _lib.pt_opts(5, 2, 1.0)):        # perplexity <= 1
         assert lib.tsne_pt_workspace_bytes(2000, 10, ctypes.byref(bad)) == 0
+
+
+def test_implicit_workspace_is_small():
+    """An implicit-P workspace holds one block row of P instead of the triangle."""
+    from paper_1812_09869_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libtsne355.so not built")
+    lib = _lib.load()
+    full = _lib.workspace_bytes(65536, 50)
+    imp = lib.tsne_workspace_bytes_implicit(65536, 50)
+    assert 0 < imp < full / 10
+    assert lib.tsne_workspace_bytes_implicit(1, 50) == 0
