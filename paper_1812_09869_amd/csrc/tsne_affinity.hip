@@ -504,8 +504,9 @@ __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restri
 // The diagonal tile holds both orders of each pair; both take the distance
 // of the upper element so that the stored P is exactly symmetric.
 // ----------------------------------------------------------------------------
-// tile_base: the P store's first tile (0; tile_start(b) for the one-block-row
-// buffer of implicit P).
+// tile_base: the P store's first tile (0, or the first tile of the buffer of
+// implicit P). Grid (nb - b, kStageSplit).
+constexpr int kStageSplit = 4;
 __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock, int64_t npad,
                                                int32_t nb, int32_t b, float4 *__restrict__ P,
                                                int64_t tile_base, const Hdr *guard, int64_t gn,
@@ -516,15 +517,17 @@ __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock,
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
   float4 *dst = P + (size_t)(tile_start(b, nb) - tile_base) * TT4 + (size_t)blockIdx.x * TT4;
   const float *src = dblock + (int64_t)J * T;
+  // workgroup y of the tile copies float4 rows s0 .. s1 - 1 of its 64
+  const int s0 = blockIdx.y * (64 / kStageSplit), s1 = s0 + 64 / kStageSplit;
   if (J != b) {
 #pragma unroll 4
-    for (int s = 0; s < 64; ++s) {
+    for (int s = s0; s < s1; ++s) {
       const int k = s >> 2, mq = s & 3;
       const float *rp = src + (int64_t)(tr + 16 * k) * npad + tc + 64 * mq;
       dst[s * 256 + t] = make_float4(rp[0], rp[16], rp[32], rp[48]);
     }
   } else {
-    for (int s = 0; s < 64; ++s) {
+    for (int s = s0; s < s1; ++s) {
       const int k = s >> 2, mq = s & 3;
       const int il = tr + 16 * k;
       float v[4];
@@ -1403,12 +1406,14 @@ __global__ __launch_bounds__(256) void k_pack_range(float4 *__restrict__ Pb,
                                                     int32_t nb, double2 *__restrict__ ppart,
                                                     uint8_t *__restrict__ nzflag,
                                                     int2 *__restrict__ tmap, int64_t tile0,
-                                                    const Hdr *guard, int32_t gd) {
+                                                    int64_t tile_base, const Hdr *guard,
+                                                    int32_t gd) {
   if (!implicit_ready(guard, n, gd)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(const_cast<Hdr *>(guard), kErrState);
     return;
   }
-  pack_tile(Pb, a, m, r, n, nb, ppart, nzflag, tmap, tile0 + blockIdx.x, blockIdx.x);
+  const int64_t tile = tile0 + blockIdx.x;
+  pack_tile(Pb, a, m, r, n, nb, ppart, nzflag, tmap, tile, tile - tile_base);
 }
 
 // After all blocks of a pass: sums of P (the header keeps ready = 2).
@@ -1565,8 +1570,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
       hipLaunchKernelGGL(k_dissim_block, dim3((unsigned)(L.npad / 256), T / 16), dim3(256), 0, st,
                          dis, L.n, L.npad, b, dblock, h);
       calibrate(b);
-      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P,
-                         (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
+      hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
+                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
     }
     pack();
     return hipGetLastError();
@@ -1631,8 +1636,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
     dist(b, xc, nrm);
     calibrate(b);
     if (!stats_only && !implicit)
-      hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b, P,
-                         (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
+      hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
+                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
   }
   if (implicit) {
     // every pass rebuilds P from the centred X in the internal order: make
@@ -1650,19 +1655,25 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   return hipGetLastError();
 }
 
-hipError_t launch_implicit_block(const Layout &L, void *ws, int b, hipStream_t st) {
+hipError_t launch_implicit_block(const Layout &L, void *ws, int b, int64_t tile_base,
+                                 hipStream_t st) {
   float *dblock = at<float>(ws, L.dblock);
   const int64_t t0 = tile_start(b, L.nb);
   const Hdr *h = at<const Hdr>(ws, L.hdr);
   hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64), dim3(256), 0,
                      st, at<const double>(ws, L.xcT2), at<const double>(ws, L.norms2), L.npad,
                      L.dpad, b, dblock, h, L.n, L.d);
-  hipLaunchKernelGGL(k_stage, dim3(L.nb - b), dim3(256), 0, st, dblock, L.npad, L.nb, b,
-                     at<float4>(ws, L.P), t0, h, L.n, L.d);
-  hipLaunchKernelGGL(k_pack_range, dim3(L.nb - b), dim3(256), 0, st, at<float4>(ws, L.P),
+  hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
+                     L.nb, b, at<float4>(ws, L.P), tile_base, h, L.n, L.d);
+  return hipGetLastError();
+}
+
+hipError_t launch_implicit_pack(const Layout &L, void *ws, int64_t tile0, int64_t count,
+                                int64_t tile_base, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_range, dim3((unsigned)count), dim3(256), 0, st, at<float4>(ws, L.P),
                      at<const float>(ws, L.a), at<const float>(ws, L.m), at<const float>(ws, L.r),
                      L.n, L.nb, at<double2>(ws, L.ppart), at<uint8_t>(ws, L.nz),
-                     at<int2>(ws, L.tmap), t0, h, L.d);
+                     at<int2>(ws, L.tmap), tile0, tile_base, at<const Hdr>(ws, L.hdr), L.d);
   return hipGetLastError();
 }
 

@@ -60,7 +60,11 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only, bool imp
   // tiles) or recomputed per pass (one block row of nb tiles), so the entry
   // points of either mode stay inside the other's workspace and find its
   // header, order and statistics
-  L.P = take(sz * (size_t)(implicit ? L.nb : L.nt) * T * T * 4);
+  {
+    const int64_t cap = L.nb > kImplicitTiles ? L.nb : kImplicitTiles;
+    const int64_t tiles = implicit ? (cap < L.nt ? cap : L.nt) : L.nt;
+    L.P = take(sz * (size_t)tiles * T * T * 4);
+  }
   L.iter_end = o;
   // affinity-stage scratch (only needed inside tsne_affinities)
   L.xmean = take((size_t)L.dpad * 8);

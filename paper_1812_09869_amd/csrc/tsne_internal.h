@@ -23,6 +23,7 @@ namespace tsne {
 // e = 0..3, so every wave-wide float4 load is one contiguous 1 KiB segment.
 // ---------------------------------------------------------------------------
 constexpr int kMeanPartsPerBlock = 2;  // re-centring partial sums per row block
+constexpr int64_t kImplicitTiles = 2048;  // implicit P: tiles recomputed per force launch (at least)
 constexpr int T = 256;             // tile edge
 constexpr int TT4 = T * T / 4;     // float4 per tile
 constexpr int kThreads = 256;      // threads per tile workgroup
@@ -164,9 +165,22 @@ inline P *at(void *ws, size_t off) {
 hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
                              int max_bisect, double tol_h, int reorder, void *ws,
                              hipStream_t stream, bool stats_only = false, bool implicit = false);
-// Implicit P: recompute block b's distances, stage and pack its tiles into the
-// one-block-row buffer; after all blocks, the P sums and the slot lists.
-hipError_t launch_implicit_block(const Layout &L, void *ws, int b, hipStream_t stream);
+// Implicit P: recompute block b's distances and stage its tiles into the
+// buffer; pack a range of staged tiles; after all blocks, the P sums and the
+// slot lists.
+// Implicit P buffer capacity in tiles: at least one block row, at most the
+// whole triangle.
+inline int64_t implicit_capacity(const Layout &L) {
+  const int64_t c = L.nb > kImplicitTiles ? L.nb : kImplicitTiles;
+  return c < L.nt ? c : L.nt;
+}
+// Block rows [b0, b1) fill the buffer: tile t of them sits at slot
+// t - tile_start(b0).
+hipError_t launch_implicit_block(const Layout &L, void *ws, int b, int64_t tile_base,
+                                 hipStream_t stream);
+// Pack (Eq. 3) the staged tiles tile0 .. tile0 + count - 1 of the buffer.
+hipError_t launch_implicit_pack(const Layout &L, void *ws, int64_t tile0, int64_t count,
+                                int64_t tile_base, hipStream_t stream);
 hipError_t launch_implicit_sums(const Layout &L, void *ws, hipStream_t stream);
 hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipStream_t stream);
 hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, double *out,

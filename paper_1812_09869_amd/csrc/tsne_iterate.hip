@@ -1150,13 +1150,25 @@ hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipS
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
                      at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent), h);
-  for (int b = 0; b < L.nb; ++b) {
-    hipError_t e = launch_implicit_block(L, ws, b, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_force_range, dim3((unsigned)(L.nb - b)), dim3(256), 0, st,
+  const int64_t cap = implicit_capacity(L);
+  for (int b0 = 0; b0 < L.nb;) {
+    // the block rows whose tiles fill the buffer (at least one)
+    int b1 = b0 + 1;
+    while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
+    const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
+    for (int b = b0; b < b1; ++b) {
+      hipError_t e = launch_implicit_block(L, ws, b, base, st);
+      if (e != hipSuccess) return e;
+    }
+    {
+      hipError_t e = launch_implicit_pack(L, ws, base, count, base, st);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_force_range, dim3((unsigned)count), dim3(256), 0, st,
                        at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb,
                        at<float4>(ws, L.part), at<float>(ws, L.zpart), at<const int2>(ws, L.tmap),
-                       tile_start(b, L.nb), L.d, h);
+                       base, L.d, h);
+    b0 = b1;
   }
   return launch_implicit_sums(L, ws, st);
 }
@@ -1168,12 +1180,23 @@ hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, doubl
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
                      at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent), h);
-  for (int b = 0; b < L.nb; ++b) {
-    hipError_t e = launch_implicit_block(L, ws, b, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cost_range, dim3((unsigned)(L.nb - b)), dim3(256), 0, st,
+  const int64_t cap = implicit_capacity(L);
+  for (int b0 = 0; b0 < L.nb;) {
+    int b1 = b0 + 1;
+    while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
+    const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
+    for (int b = b0; b < b1; ++b) {
+      hipError_t e = launch_implicit_block(L, ws, b, base, st);
+      if (e != hipSuccess) return e;
+    }
+    {
+      hipError_t e = launch_implicit_pack(L, ws, base, count, base, st);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_cost_range, dim3((unsigned)count), dim3(256), 0, st,
                        at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb, cp,
-                       at<const uint8_t>(ws, L.nz), h, tile_start(b, L.nb));
+                       at<const uint8_t>(ws, L.nz), h, base);
+    b0 = b1;
   }
   hipError_t e = launch_implicit_sums(L, ws, st);
   if (e != hipSuccess) return e;
