@@ -184,7 +184,7 @@ TSNE_API int tsne_cost(void *ws, int64_t n, const float *y, double *out, void *s
 /* ------------------------------------------------------------------------
  * Implicit P. For n beyond what a stored P fits (the packed FP32 triangle
  * takes 2 n^2 bytes), tsne_affinities with implicit_p = 1 keeps only the row
- * statistics, the centred input in the internal order and one block row of
+ * statistics, the centred input in the internal order and a buffer of
  * tiles; every force pass and cost evaluation then recomputes P block row by
  * block row (the FP64 distances on MFMA, Eq. 1 with the stored beta, m and S,
  * Eq. 3) and consumes it at once. The values of P are bitwise those of the

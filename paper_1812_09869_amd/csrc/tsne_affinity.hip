@@ -1392,11 +1392,12 @@ __global__ __launch_bounds__(1024) void k_small_lists(const SmallEntry *__restri
 }
 
 // ----------------------------------------------------------------------------
-// 6. Implicit P: the workspace keeps one block row of tiles; every pass
-// recomputes the distances of block b (the same MFMA kernel as the affinity
-// stage, from the centred X in the internal order), stages them and packs the
-// block's tiles (b, b .. nb - 1) into the buffer, slot x holding tile
-// tile_start(b) + x. The arithmetic is that of the stored P, so the values
+// 6. Implicit P: the workspace keeps a buffer of whole block rows of tiles
+// (at most 2,048 tiles, at least one block row); every pass recomputes the
+// distances of each block b of the rows in the buffer (the same MFMA kernel as
+// the affinity stage, from the centred X in the internal order) and stages
+// its tiles (b, b .. nb - 1), then packs the buffer, slot x holding tile
+// base + x. The arithmetic is that of the stored P, so the values
 // are bitwise the same.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pack_range(float4 *__restrict__ Pb,

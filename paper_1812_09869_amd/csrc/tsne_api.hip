@@ -57,7 +57,7 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only, bool imp
   L.yp = take(sz * np * 8);
   L.extent = take(sz * (size_t)L.nb * 16);
   // P last: every array above has the same offset whether P is stored (nt
-  // tiles) or recomputed per pass (one block row of nb tiles), so the entry
+  // tiles) or recomputed per pass (a buffer of whole block rows), so the entry
   // points of either mode stay inside the other's workspace and find its
   // header, order and statistics
   {

@@ -79,7 +79,7 @@ struct Layout {
 
 // stats_only: a layout holding only what the per-row search needs (header,
 // row statistics, order, centred X and the distance block).
-// implicit: P is not stored; one block row of tiles holds the P that every
+// implicit: P is not stored; a buffer of whole block rows holds the P that every
 // pass recomputes (FP64 distances only).
 Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only = false,
                    bool implicit = false);

@@ -508,8 +508,8 @@ __global__ __launch_bounds__(256, 2) void k_force_full(const float4 *__restrict_
   }
 }
 
-// Implicit P: the tiles (b, b .. nb - 1) of one block row, whose P was just
-// recomputed into the one-block-row buffer Pb (tile tile0 + x at slot x).
+// Implicit P: the tiles tile0 .. tile0 + gridDim.x - 1 (whole block rows),
+// whose P was just recomputed into the buffer Pb (tile tile0 + x at slot x).
 __global__ __launch_bounds__(256, 2) void k_force_range(const float4 *__restrict__ Pb,
                                                         const float2 *__restrict__ Y, int64_t n,
                                                         int32_t nb, float4 *__restrict__ part,
@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(256, 2) void k_cost(const float4 *__restrict__ P,
   cost_wg(P, Y, n, nb, cpart, nz, h, blockIdx.x, blockIdx.x, 1);
 }
 
-// Implicit P: the cost terms of the tiles of one block row (see k_force_range).
+// Implicit P: the cost terms of the tiles in the buffer (see k_force_range).
 __global__ __launch_bounds__(256, 2) void k_cost_range(const float4 *__restrict__ Pb,
                                                        const float2 *__restrict__ Y, int64_t n,
                                                        int32_t nb, double2 *__restrict__ cpart,
