@@ -112,21 +112,25 @@ __global__ __launch_bounds__(64 * KW) void k_gemm_bf16(const __bf16 *__restrict_
 // registers and runs tiles of kInferRows rows through the whole network:
 //
 //   wave w owns hidden units [H/W w, H/W (w + 1)) of both wide layers: its
-//   slice of W1 (as the A operand of the transposed first layer) and its
-//   column slice of W2 (as the B operand of the second) stay in registers
-//   for the life of the workgroup;
+//   row slices of W1 and W2 (the A operands of the two transposed layers)
+//   stay in registers for the life of the workgroup;
 //   the standardised BF16 input tile and the BF16 first-layer output tile
 //   live in LDS, shared by the W waves;
 //   the output layer's partial sums of the W waves meet in LDS.
 //
-// Layer 1 is computed transposed, H1^T = W1 X^T (M = hidden, N = rows), so
-// lane l = 16g + c receives H1^T[16t + 4g + r][16a + c]: four consecutive
-// hidden units of one row, stored to LDS as one 8-byte write. Layer 2 (M =
-// rows, N = its hidden slice) reads its A operand for the K step s in a
-// permuted order, slot (g, j) holding hidden unit 32s + 4g + j for j < 4 and
-// 32s + 16 + 4g + (j - 4) otherwise (two 8-byte LDS reads); the W2 slice in
-// registers is held in the same permuted order, so every dot product is the
-// same sum of the same BF16 products.
+// Both wide layers are computed transposed, H1^T = W1 X^T and H2^T = W2 H1^T
+// (M = hidden, N = rows). The B operand of either is one 16-byte LDS read of
+// eight consecutive inputs of one row, and lane l = 16g + c receives
+// H^T[h0 + 16i + 4g + r][16a + c]: four consecutive hidden units of row
+// 16a + c. The first layer's four go to LDS as one 8-byte write; the second
+// layer's are summed into the output layer in place, so the sum over a wave's
+// hidden units needs only the four lanes of a column (two cross-lane steps).
+//
+// The next tile's inputs are loaded into registers at the start of a tile and
+// written to LDS after its second layer, so the loads have most of a tile's
+// time to arrive; the second layer's LDS reads run one K step ahead of its
+// MFMAs (explicit double buffer plus scheduling groups of one read per TW
+// MFMAs).
 // ----------------------------------------------------------------------------
 constexpr int kInferRows = 64;   // rows per tile
 constexpr int kXPitch = kK1 + 8;  // BF16 elements per LDS row of the input tile
@@ -159,59 +163,63 @@ __global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int c = l & 15, g = l >> 4;
   const int h0 = w * HW;  // first hidden unit of this wave
-  // weights of this wave, in registers
   v8bf wa[TW][2];  // W1 rows h0 + 16i + c, inputs 32s + 8g .. + 7
 #pragma unroll
   for (int i = 0; i < TW; ++i)
 #pragma unroll
     for (int st = 0; st < 2; ++st)
       wa[i][st] = *reinterpret_cast<const v8bf *>(w1b + (h0 + 16 * i + c) * kK1 + 32 * st + 8 * g);
-  v8bf wb[TW][KS];  // W2 rows h0 + 16e + c, hidden units of step s in the permuted order
+  v8bf wb[TW][KS];  // W2 rows h0 + 16e + c, inputs 32s + 8g .. + 7
 #pragma unroll
   for (int e = 0; e < TW; ++e)
 #pragma unroll
-    for (int st = 0; st < KS; ++st) {
-      const __bf16 *wr = w2b + (int64_t)(h0 + 16 * e + c) * H + 32 * st + 4 * g;
-      const v4bf lo = *reinterpret_cast<const v4bf *>(wr);
-      const v4bf hi = *reinterpret_cast<const v4bf *>(wr + 16);
-      wb[e][st] = (v8bf){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    for (int st = 0; st < KS; ++st)
+      wb[e][st] = *reinterpret_cast<const v8bf *>(w2b + (int64_t)(h0 + 16 * e + c) * H + 32 * st + 8 * g);
+  float bias1[TW][4], bias2[TW][4], u0[TW][4], u1[TW][4];
+#pragma unroll
+  for (int i = 0; i < TW; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = h0 + 16 * i + 4 * g + r;
+      bias1[i][r] = b1[j];
+      bias2[i][r] = b2[j];
+      u0[i][r] = w3[j];
+      u1[i][r] = w3[H + j];
     }
-  float bias1[TW][4], bias2[TW], u0[TW], u1[TW];
-#pragma unroll
-  for (int i = 0; i < TW; ++i) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bias1[i][r] = b1[h0 + 16 * i + 4 * g + r];
-    bias2[i] = b2[h0 + 16 * i + c];
-    u0[i] = w3[h0 + 16 * i + c];
-    u1[i] = w3[H + h0 + 16 * i + c];
-  }
   const float c0 = b3[0], c1 = b3[1];
   const int64_t ntiles = (n + kInferRows - 1) / kInferRows;
-  // input staging: thread t always handles input k = t % 64 of rows t / 64 + W m
   constexpr int XM = kInferRows * kK1 / NT;
   const int xk = t & (kK1 - 1), xr = t / kK1;
   const bool kin = xk < d_in;
+  const int xkc = kin ? xk : d_in - 1;  // padding lanes load a real element and store 0
   const float xmean = kin ? mean[xk] : 0.f, xinv = kin ? invstd[xk] : 0.f;
   float xv[XM];
   auto load_x = [&](int64_t tl) {
+    if (tl >= ntiles) return;
+    const float *xt = x + tl * kInferRows * d_in;  // uniform tile base
+    const int64_t lim = n - tl * kInferRows;       // rows of this tile that exist
+    if (lim >= kInferRows) {
 #pragma unroll
-    for (int m = 0; m < XM; ++m) {
-      const int64_t row = tl * kInferRows + xr + W * m;
-      xv[m] = (kin && tl < ntiles && row < n) ? x[row * d_in + xk] : 0.f;
+      for (int m = 0; m < XM; ++m) xv[m] = xt[(xr + W * m) * d_in + xkc];
+    } else {
+#pragma unroll
+      for (int m = 0; m < XM; ++m) {
+        const int rl = xr + W * m;
+        xv[m] = rl < lim ? xt[rl * d_in + xkc] : 0.f;
+      }
     }
   };
   auto store_x = [&]() {
 #pragma unroll
     for (int m = 0; m < XM; ++m)
-      xs[xr + W * m][xk] = (__bf16)(kin ? (xv[m] - xmean) * xinv : 0.f);
+      xs[xr + W * m][xk] = (__bf16)((xv[m] - xmean) * xinv);  // 0 in padding lanes
   };
   load_x(blockIdx.x);
   store_x();
   __syncthreads();
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row0 = tile * kInferRows;
-    load_x(tile + gridDim.x);  // next tile's inputs, in flight during this tile
-    // layer 1, transposed: acc1[i][a] = H1^T[h0 + 16i + 4g + r][16a + c]
+    load_x(tile + gridDim.x);
     v4f acc1[TW][RA];
 #pragma unroll
     for (int i = 0; i < TW; ++i)
@@ -226,7 +234,6 @@ __global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
         for (int i = 0; i < TW; ++i)
           acc1[i][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[i][st], xb, acc1[i][a], 0, 0, 0);
       }
-    // bias, ReLU, BF16 into the shared hidden tile
 #pragma unroll
     for (int i = 0; i < TW; ++i)
 #pragma unroll
@@ -237,44 +244,56 @@ __global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
         *reinterpret_cast<v4bf *>(&hs[16 * a + c][h0 + 16 * i + 4 * g]) = hv;
       }
     __syncthreads();
-    store_x();  // every wave is past layer 1: the input tile may be replaced
-    // layer 2: acc2[a][e] = H2[16a + 4g + r][h0 + 16e + c]
-    v4f acc2[RA][TW];
+    // layer 2, transposed: acc2[e][a] = H2^T[h0 + 16e + 4g + r][16a + c]
+    v4f acc2[TW][RA];
 #pragma unroll
-    for (int a = 0; a < RA; ++a)
+    for (int e = 0; e < TW; ++e)
 #pragma unroll
-      for (int e = 0; e < TW; ++e) acc2[a][e] = (v4f){0.f, 0.f, 0.f, 0.f};
+      for (int a = 0; a < RA; ++a) acc2[e][a] = (v4f){0.f, 0.f, 0.f, 0.f};
+    v8bf hb[2][RA];
 #pragma unroll
-    for (int st = 0; st < KS; ++st)
+    for (int a = 0; a < RA; ++a) hb[0][a] = *reinterpret_cast<const v8bf *>(&hs[16 * a + c][8 * g]);
 #pragma unroll
-      for (int a = 0; a < RA; ++a) {
-        const __bf16 *hr = &hs[16 * a + c][32 * st + 4 * g];
-        const v4bf lo = *reinterpret_cast<const v4bf *>(hr);
-        const v4bf hi = *reinterpret_cast<const v4bf *>(hr + 16);
-        const v8bf av = (v8bf){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    for (int st = 0; st < KS; ++st) {
+      if (st + 1 < KS) {
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+          hb[(st + 1) & 1][a] = *reinterpret_cast<const v8bf *>(&hs[16 * a + c][32 * (st + 1) + 8 * g]);
+      }
+#pragma unroll
+      for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int e = 0; e < TW; ++e)
-          acc2[a][e] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wb[e][st], acc2[a][e], 0, 0, 0);
-      }
-    // output layer: this wave's share of every row, reduced over the 16 lanes
+          acc2[e][a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[e][st], hb[st & 1][a], acc2[e][a], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, RA, 0);
 #pragma unroll
-    for (int a = 0; a < RA; ++a)
+    for (int q = 0; q < (KS - 1) * RA; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, TW, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, TW * RA, 0);
+    // output layer: lane (c, g) holds 4 TW hidden units of row 16a + c
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float s0 = 0.f, s1 = 0.f;
+    for (int a = 0; a < RA; ++a) {
+      float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-        for (int e = 0; e < TW; ++e) {
-          const float hh = fmaxf(acc2[a][e][r] + bias2[e], 0.f);
-          s0 = fmaf(u0[e], hh, s0);
-          s1 = fmaf(u1[e], hh, s1);
+      for (int e = 0; e < TW; ++e)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float hh = fmaxf(acc2[e][a][r] + bias2[e][r], 0.f);
+          s0 = fmaf(u0[e][r], hh, s0);
+          s1 = fmaf(u1[e][r], hh, s1);
         }
-        s0 = row16_sum_f(s0);
-        s1 = row16_sum_f(s1);
-        if (c == 0) {
-          po[w][16 * a + 4 * g + r][0] = s0;
-          po[w][16 * a + 4 * g + r][1] = s1;
-        }
-      }
+      s0 += __shfl_xor(s0, 32);
+      s1 += __shfl_xor(s1, 32);
+      s0 += __shfl_xor(s0, 16);
+      s1 += __shfl_xor(s1, 16);
+      po[w][16 * a + c][0] = s0;  // the four lanes of a column hold the same sums
+      po[w][16 * a + c][1] = s1;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    store_x();
     __syncthreads();
     if (t < kInferRows * 2) {
       const int rr = t >> 1, o = t & 1;
@@ -284,10 +303,9 @@ __global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
       for (int q = 0; q < W; ++q) sum += po[q][rr][o];
       if (row < n) out[2 * row + o] = sum + (o ? c1 : c0);
     }
-    // hs and po are rewritten in the next tile only after its first barrier,
-    // which every wave reaches after this tile's last LDS read
   }
 }
+
 
 // BF16 copies of W1 (zero-padded to [H][kK1]), W2 and W2 transposed.
 __global__ void k_mlp_cast(const float *__restrict__ p, int d_in, int H, __bf16 *__restrict__ w1b,
