@@ -123,15 +123,18 @@ __global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int
 // ----------------------------------------------------------------------------
 constexpr int kDistCT = 2;  // 16-column MFMA tiles per wave (a wave covers 64 x 16 kDistCT)
 
-// guard (implicit P passes only, else null): the workspace header, n and d.
+// Columns from col_base (a multiple of 64 kDistCT) to npad: all of them for
+// the calibration, only those of the block row's own tiles (col_base = b T)
+// in an implicit pass. guard (implicit P passes only, else null): the
+// workspace header, n and d.
 __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
                                                   const double *__restrict__ norms, int64_t npad,
-                                                  int32_t dpad, int32_t b,
+                                                  int32_t dpad, int32_t b, int64_t col_base,
                                                   float *__restrict__ dblock,
                                                   const Hdr *guard, int64_t gn, int32_t gd) {
   if (guard && !implicit_ready(guard, gn, gd)) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
+  const int64_t col0 = col_base + (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -1522,7 +1525,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
         break;
       default:
         hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64),
-                           dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b, dblock,
+                           dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b, (int64_t)0, dblock,
                            (const Hdr *)nullptr, (int64_t)0, 0);
     }
   };
@@ -1661,9 +1664,12 @@ hipError_t launch_implicit_block(const Layout &L, void *ws, int b, int64_t tile_
   float *dblock = at<float>(ws, L.dblock);
   const int64_t t0 = tile_start(b, L.nb);
   const Hdr *h = at<const Hdr>(ws, L.hdr);
-  hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64), dim3(256), 0,
-                     st, at<const double>(ws, L.xcT2), at<const double>(ws, L.norms2), L.npad,
-                     L.dpad, b, dblock, h, L.n, L.d);
+  // only the columns of the block row's own tiles (s >= b) are staged
+  const int64_t col_base = (int64_t)b * T;
+  hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)((L.npad - col_base) / (64 * kDistCT)), T / 64),
+                     dim3(256), 0, st, at<const double>(ws, L.xcT2),
+                     at<const double>(ws, L.norms2), L.npad, L.dpad, b, col_base, dblock, h, L.n,
+                     L.d);
   hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
                      L.nb, b, at<float4>(ws, L.P), tile_base, h, L.n, L.d);
   return hipGetLastError();
