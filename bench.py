@@ -468,38 +468,42 @@ def dissim_leg(x, perp=50.0, n=16384, reps=3):
     return res
 
 
-def implicit_leg(x, perp=50.0, iters=10):
+def implicit_leg(x, perp=50.0, iters=10, modes=("fp64", "fp32", "bf16")):
     """Implicit P on the benchmark workload (N = 65,536, D = 50, perplexity
-    50): workspace size against the stored-P one, and the time of one
-    iteration (every pass recomputes P block row by block row: FP64 MFMA
-    distances, stage, pack, force), mean of `iters` after one untimed."""
+    50) in each distance mode: workspace size against the stored-P one, and
+    the time of one iteration (every pass recomputes P block row by block
+    row: MFMA distances of the mode against the block row's own columns,
+    stage, pack, force), mean of `iters` after one untimed. Here the mode
+    sets the iteration rate, unlike the stored path."""
     import torch
 
     from paper_1812_09869_amd import _lib, synth
     from paper_1812_09869_amd.tsne import ExactTSNE
 
     n, d = x.shape
-    model = ExactTSNE(x, perp, implicit=True)
+    nb = (n + 255) // 256
+    flop = float(d) * 256 * 256 * nb * (nb + 1)  # 2 d per (row, column) pair of the block rows
+    res = {"n": n, "d": d, "stored_workspace_gb": _lib.workspace_bytes(n, d) / 1e9,
+           "distance_flop_per_pass": flop, "modes": {}}
     y0 = torch.from_numpy(synth.embedding_init(n, seed=17)).to(x.device)
-    state = model.init_state(y0)
-    model.run(state, 1, start=300)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    torch.cuda.synchronize()
-    ev[0].record()
-    model.run(state, iters, start=301)
-    ev[1].record()
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / iters
-    res = {"n": n, "d": d,
-           "workspace_gb": float(model.ws.numel()) / 1e9,
-           "stored_workspace_gb": _lib.workspace_bytes(n, d) / 1e9,
-           "ms_per_iteration": ms,
-           "pair_interactions_per_s": n * (n - 1) / 2.0 * 1e3 / ms,
-           "fp64_mfma_tflops_distances": 2.0 * n * n * d / (ms * 1e-3) / 1e12,
-           "status": model.status()}
-    log(f"[implicit] {res}")
-    del model
-    torch.cuda.empty_cache()
+    for mode in modes:
+        model = ExactTSNE(x, perp, dist_mode=mode, implicit=True)
+        state = model.init_state(y0)
+        model.run(state, 1, start=300)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        model.run(state, iters, start=301)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / iters
+        res["modes"][mode] = {"workspace_gb": float(model.ws.numel()) / 1e9,
+                              "ms_per_iteration": ms, "iters_per_s": 1e3 / ms,
+                              "distance_tflops_over_pass": flop / (ms * 1e-3) / 1e12,
+                              "status": model.status()}
+        log(f"[implicit] {mode}: {res['modes'][mode]}")
+        del model
+        torch.cuda.empty_cache()
     return res
 
 

@@ -81,7 +81,7 @@ typedef struct {
   double tol_h;       /* stop when |H_i - ln(perplexity)| <= tol_h (nats), > 0 */
   int32_t reorder;    /* 1: group points by affinity components (default); 0: keep order */
   int32_t implicit_p; /* 0: store P (default); 1: store only what rebuilds it, and recompute
-                         P in every pass (tsne_*_implicit; FP64 mode only) */
+                         P in every pass (tsne_*_implicit, any distance mode) */
 } tsne_aff_opts;
 
 /* Learning-rate rules of an update. */
@@ -184,31 +184,36 @@ TSNE_API int tsne_cost(void *ws, int64_t n, const float *y, double *out, void *s
 /* ------------------------------------------------------------------------
  * Implicit P. For n beyond what a stored P fits (the packed FP32 triangle
  * takes 2 n^2 bytes), tsne_affinities with implicit_p = 1 keeps only the row
- * statistics, the centred input in the internal order and a buffer of
- * tiles; every force pass and cost evaluation then recomputes P block row by
- * block row (the FP64 distances on MFMA, Eq. 1 with the stored beta, m and S,
- * Eq. 3) and consumes it at once. The values of P are bitwise those of the
- * stored path; the iteration does about N^2 D more FP64 MFMA work per pass.
+ * statistics, the contraction operands in the internal order (the centred
+ * input in FP64, or the FP32 / 16-bit operands of a reduced distance mode)
+ * and a buffer of tiles; every force pass and cost evaluation then recomputes
+ * P block row by block row (each block row's distances against the columns
+ * of its own tiles on MFMA, in the workspace's distance mode; Eq. 1 with the
+ * stored beta, m and S; Eq. 3) and consumes it at once. The values of P are
+ * bitwise those of the stored path in the same mode; a pass does about
+ * N^2 D / 2 more multiply-adds of the mode's contraction.
  * The stored-P entry points (tsne_step, tsne_forces, tsne_gradient,
  * tsne_cost, tsne_export_p_rows, the batched launch) reject such a workspace
  * on the device (TSNE_E_STATE), and these reject a stored-P workspace.
  * ---------------------------------------------------------------------- */
 
-/* Bytes of an implicit-P workspace for n points in d dimensions (0 if out of
- * range). Host-only. */
-TSNE_API size_t tsne_workspace_bytes_implicit(int64_t n, int32_t d);
+/* Bytes of an implicit-P workspace for n points in d dimensions with the
+ * given distance mode (tsne_dist_mode; 0 if out of range). Host-only. */
+TSNE_API size_t tsne_workspace_bytes_implicit(int64_t n, int32_t d, int32_t dist_mode);
 
-/* tsne_step, tsne_gradient and tsne_cost on an implicit-P workspace. d is
- * the input dimension the affinities were computed with (the workspace keeps
- * the centred input; a workspace prepared for another n or d is refused on
- * the device with TSNE_E_STATE, before any of its buffers is touched). */
-TSNE_API int tsne_step_implicit(void *ws, int64_t n, int32_t d, float *y, float *u, float *g,
-                                const tsne_step_params *prm, float *grad_out, double *z_out,
-                                void *stream);
-TSNE_API int tsne_gradient_implicit(void *ws, int64_t n, int32_t d, const float *y, float alpha,
-                                    float *grad_out, double *z_out, void *stream);
-TSNE_API int tsne_cost_implicit(void *ws, int64_t n, int32_t d, const float *y, double *out,
-                                void *stream);
+/* tsne_step, tsne_gradient and tsne_cost on an implicit-P workspace. d and
+ * dist_mode are those the affinities were computed with (the workspace keeps
+ * the contraction operands of that mode; a workspace prepared for another n,
+ * d or mode is refused on the device with TSNE_E_STATE, before any of its
+ * buffers is touched; a mode outside tsne_dist_mode is TSNE_E_ARG). */
+TSNE_API int tsne_step_implicit(void *ws, int64_t n, int32_t d, int32_t dist_mode, float *y,
+                                float *u, float *g, const tsne_step_params *prm, float *grad_out,
+                                double *z_out, void *stream);
+TSNE_API int tsne_gradient_implicit(void *ws, int64_t n, int32_t d, int32_t dist_mode,
+                                    const float *y, float alpha, float *grad_out, double *z_out,
+                                    void *stream);
+TSNE_API int tsne_cost_implicit(void *ws, int64_t n, int32_t d, int32_t dist_mode,
+                                const float *y, double *out, void *stream);
 
 /* Synchronises the stream and returns the first device-side condition
  * recorded in the workspace (TSNE_OK if none). Clears nothing. */

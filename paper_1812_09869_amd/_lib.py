@@ -165,12 +165,12 @@ def load(path: str = LIB_PATH):
                                                ctypes.c_size_t, _vp]),
         "tsne_pt_last_error": (ctypes.c_char_p, []),
         "tsne_kde_workspace_bytes": (ctypes.c_size_t, [_i64]),
-        "tsne_workspace_bytes_implicit": (ctypes.c_size_t, [_i64, _i32]),
-        "tsne_step_implicit": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp,
+        "tsne_workspace_bytes_implicit": (ctypes.c_size_t, [_i64, _i32, _i32]),
+        "tsne_step_implicit": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp,
                                               ctypes.POINTER(StepParams), _vp, _vp, _vp]),
-        "tsne_gradient_implicit": (ctypes.c_int, [_vp, _i64, _i32, _vp, ctypes.c_float, _vp, _vp,
-                                                  _vp]),
-        "tsne_cost_implicit": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp]),
+        "tsne_gradient_implicit": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, ctypes.c_float,
+                                                  _vp, _vp, _vp]),
+        "tsne_cost_implicit": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp]),
         "tsne_kde_bandwidths": (ctypes.c_int, [_vp, _i64, ctypes.c_double, _vp, _vp,
                                                ctypes.c_size_t, _vp]),
         "tsne_kde_raster": (ctypes.c_int, [_vp, _i64, _vp, ctypes.POINTER(Raster), _vp, _vp]),
@@ -498,33 +498,42 @@ def kde_raster(y, beta, x0, y0, cx, cy, gx, gy, out):
 # Implicit P (recomputed in every pass)
 # --------------------------------------------------------------------------
 
-def new_workspace_implicit(n: int, d: int, device="cuda") -> torch.Tensor:
-    nbytes = int(load().tsne_workspace_bytes_implicit(n, d))
+def _mode(dist_mode) -> int:
+    return DIST_MODES[dist_mode] if isinstance(dist_mode, str) else int(dist_mode)
+
+
+def workspace_bytes_implicit(n: int, d: int, dist_mode: str | int = "fp64") -> int:
+    return int(load().tsne_workspace_bytes_implicit(n, d, _mode(dist_mode)))
+
+
+def new_workspace_implicit(n: int, d: int, device="cuda", dist_mode: str | int = "fp64"):
+    nbytes = workspace_bytes_implicit(n, d, dist_mode)
     if nbytes == 0:
-        raise TsneError(1, f"no implicit workspace size for n={n}, d={d}")
+        raise TsneError(1, f"no implicit workspace size for n={n}, d={d}, mode={dist_mode}")
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
 def step_implicit(ws, n, d, y, u, g, exaggeration, momentum, learning_rate, min_gain=0.01,
-                  recentre=True, grad_out=None, z_out=None, lr_rule="gains"):
+                  recentre=True, grad_out=None, z_out=None, lr_rule="gains", dist_mode="fp64"):
     prm = _params(exaggeration, momentum, learning_rate, min_gain, recentre, lr_rule)
     sh = (n, 2)
-    _check(load().tsne_step_implicit(_ptr(ws, torch.uint8, name="ws"), n, d,
+    _check(load().tsne_step_implicit(_ptr(ws, torch.uint8, name="ws"), n, d, _mode(dist_mode),
                                      _ptr(y, shape=sh, name="y"), _ptr(u, shape=sh, name="u"),
                                      _ptr(g, shape=sh, name="g"), ctypes.byref(prm),
                                      _ptr(grad_out, shape=sh, name="grad_out"),
                                      _ptr(z_out, torch.float64, name="z_out"), _stream()))
 
 
-def gradient_implicit(ws, n, d, y, alpha, grad_out, z_out=None):
+def gradient_implicit(ws, n, d, y, alpha, grad_out, z_out=None, dist_mode="fp64"):
     sh = (n, 2)
     _check(load().tsne_gradient_implicit(_ptr(ws, torch.uint8, name="ws"), n, d,
+                                         _mode(dist_mode),
                                          _ptr(y, shape=sh, name="y"), float(alpha),
                                          _ptr(grad_out, shape=sh, name="grad_out"),
                                          _ptr(z_out, torch.float64, name="z_out"), _stream()))
 
 
-def cost_implicit(ws, n, d, y, out):
-    _check(load().tsne_cost_implicit(_ptr(ws, torch.uint8, name="ws"), n, d,
+def cost_implicit(ws, n, d, y, out, dist_mode="fp64"):
+    _check(load().tsne_cost_implicit(_ptr(ws, torch.uint8, name="ws"), n, d, _mode(dist_mode),
                                      _ptr(y, shape=(n, 2), name="y"),
                                      _ptr(out, torch.float64, shape=(2,), name="out"), _stream()))

@@ -25,10 +25,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 __device__ inline void flag_error(Hdr *h, uint32_t bit) { atomicOr(&h->err, bit); }
 
 // Implicit P: the kernels of a pass run only on a workspace whose header
-// records implicit affinities for the same n and d (its layout, hence every
-// offset these kernels use, depends on both).
-__device__ inline bool implicit_ready(const Hdr *h, int64_t n, int32_t d) {
-  return h->magic == kMagic && h->n == n && h->d == d && h->ready == 2;
+// records implicit affinities for the same n, d and distance mode (its layout,
+// hence every offset these kernels use, depends on all three); key is
+// implicit_key(d, mode).
+__device__ inline bool implicit_ready(const Hdr *h, int64_t n, int32_t key) {
+  return h->magic == kMagic && h->n == n && implicit_key(h->d, h->mode) == key && h->ready == 2;
 }
 
 // ----------------------------------------------------------------------------
@@ -126,13 +127,21 @@ constexpr int kDistCT = 2;  // 16-column MFMA tiles per wave (a wave covers 64 x
 // Columns from col_base (a multiple of 64 kDistCT) to npad: all of them for
 // the calibration, only those of the block row's own tiles (col_base = b T)
 // in an implicit pass. guard (implicit P passes only, else null): the
-// workspace header, n and d.
+// workspace header, n and implicit_key(d, mode). nzskip (implicit passes
+// after the zero tiles are known, else null): per-tile nonzero flags; a
+// workgroup whose tile (b, J) is all zero returns at once.
 __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
                                                   const double *__restrict__ norms, int64_t npad,
                                                   int32_t dpad, int32_t b, int64_t col_base,
                                                   float *__restrict__ dblock,
-                                                  const Hdr *guard, int64_t gn, int32_t gd) {
-  if (guard && !implicit_ready(guard, gn, gd)) return;
+                                                  const Hdr *guard, int64_t gn, int32_t gkey,
+                                                  const uint8_t *__restrict__ nzskip,
+                                                  int32_t nb) {
+  if (guard && !implicit_ready(guard, gn, gkey)) return;
+  if (nzskip) {  // zero tiles known: the workgroup's tile needs no distances
+    const int64_t J = (col_base + (int64_t)blockIdx.x * (64 * kDistCT)) / T;
+    if (!nzskip[tile_start(b, nb) + J - b]) return;
+  }
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t col0 = col_base + (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
   const int row0_loc = blockIdx.y * 64;
@@ -249,12 +258,18 @@ __global__ __launch_bounds__(256) void k_prep_lp(const double *__restrict__ xcT,
   norms32[i] = (float)nrm;
 }
 
+// Columns col_base .. npad - 1 (col_base a multiple of 256); guard and
+// nzskip as for k_dist_f64 (a workgroup covers one tile's columns).
 __global__ __launch_bounds__(256) void k_dist_f32(const float *__restrict__ xfT,
                                                   const float *__restrict__ norms, int64_t npad,
-                                                  int32_t dpad, int32_t b,
-                                                  float *__restrict__ dblock) {
+                                                  int32_t dpad, int32_t b, int64_t col_base,
+                                                  float *__restrict__ dblock, const Hdr *guard,
+                                                  int64_t gn, int32_t gkey,
+                                                  const uint8_t *__restrict__ nzskip, int32_t nb) {
+  if (guard && !implicit_ready(guard, gn, gkey)) return;
+  if (nzskip && !nzskip[tile_start(b, nb) + col_base / T + blockIdx.x - b]) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  const int64_t col0 = col_base + (int64_t)blockIdx.x * 256 + w * 64;
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -295,10 +310,14 @@ __global__ __launch_bounds__(256) void k_dist_f32(const float *__restrict__ xfT,
 template <typename H, typename V8, bool SCALE>
 __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa, const H *__restrict__ xb,
                                                  const float *__restrict__ norms, int64_t npad,
-                                                 int32_t kk, int32_t b, float *__restrict__ dblock,
-                                                 const Hdr *h) {
+                                                 int32_t kk, int32_t b, int64_t col_base,
+                                                 float *__restrict__ dblock, const Hdr *h,
+                                                 bool guarded, int64_t gn, int32_t gkey,
+                                                 const uint8_t *__restrict__ nzskip, int32_t nb) {
+  if (guarded && !implicit_ready(h, gn, gkey)) return;
+  if (nzskip && !nzskip[tile_start(b, nb) + col_base / T + blockIdx.x - b]) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  const int64_t col0 = col_base + (int64_t)blockIdx.x * 256 + w * 64;
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -513,8 +532,9 @@ constexpr int kStageSplit = 4;
 __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock, int64_t npad,
                                                int32_t nb, int32_t b, float4 *__restrict__ P,
                                                int64_t tile_base, const Hdr *guard, int64_t gn,
-                                               int32_t gd) {
-  if (guard && !implicit_ready(guard, gn, gd)) return;
+                                               int32_t gkey, const uint8_t *__restrict__ nzskip) {
+  if (guard && !implicit_ready(guard, gn, gkey)) return;
+  if (nzskip && !nzskip[tile_start(b, nb) + blockIdx.x]) return;  // all-zero tile: not staged
   const int J = b + blockIdx.x;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
@@ -1411,19 +1431,22 @@ __global__ __launch_bounds__(256) void k_pack_range(float4 *__restrict__ Pb,
                                                     uint8_t *__restrict__ nzflag,
                                                     int2 *__restrict__ tmap, int64_t tile0,
                                                     int64_t tile_base, const Hdr *guard,
-                                                    int32_t gd) {
-  if (!implicit_ready(guard, n, gd)) {
+                                                    int32_t gkey, bool skip_zero) {
+  if (!implicit_ready(guard, n, gkey)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(const_cast<Hdr *>(guard), kErrState);
     return;
   }
   const int64_t tile = tile0 + blockIdx.x;
+  // zero tiles known: theirs flag, sums (0) and coordinates stay as found
+  if (skip_zero && !nzflag[tile]) return;
   pack_tile(Pb, a, m, r, n, nb, ppart, nzflag, tmap, tile, tile - tile_base);
 }
 
 // After all blocks of a pass: sums of P (the header keeps ready = 2).
 __global__ __launch_bounds__(1024) void k_implicit_sums(const double2 *__restrict__ ppart,
-                                                        int64_t nt, int64_t n, int32_t d, Hdr *h) {
-  if (!implicit_ready(h, n, d)) return;
+                                                        int64_t nt, int64_t n, int32_t key,
+                                                        Hdr *h) {
+  if (!implicit_ready(h, n, key)) return;
   pack_reduce_wg(ppart, nt, h, 2);
 }
 
@@ -1446,6 +1469,48 @@ __global__ void k_set_ready(Hdr *h, int32_t ready) {
 // ----------------------------------------------------------------------------
 // Host-side sequencing
 // ----------------------------------------------------------------------------
+
+// Distances of row block b against columns col_base .. npad - 1 into the
+// block scratch, in the workspace's distance mode. xc, nrm: the centred X and
+// its norms for the FP64 mode (the reduced modes read their prepared
+// operands). guard: null in the affinity stage, the header in an implicit
+// pass (the kernels then check the mode key). nzskip: null, or the tile flags
+// whose zero tiles are skipped.
+static void launch_dist(const Layout &L, void *ws, int b, const double *xc, const double *nrm,
+                        int64_t col_base, const Hdr *guard, const uint8_t *nzskip,
+                        hipStream_t st) {
+  const Hdr *h = at<const Hdr>(ws, L.hdr);
+  const int32_t key = implicit_key(L.d, L.mode);
+  float *dblock = at<float>(ws, L.dblock);
+  const float *norms32 = at<const float>(ws, L.norms32);
+  const dim3 dgrid((unsigned)((L.npad - col_base) / 256), T / 64);
+  switch (L.mode) {
+    case TSNE_DIST_FP32:
+      hipLaunchKernelGGL(k_dist_f32, dgrid, dim3(256), 0, st, at<const float>(ws, L.xfT), norms32,
+                         L.npad, L.dpad, b, col_base, dblock, guard, L.n, key, nzskip, L.nb);
+      break;
+    case TSNE_DIST_BF16:
+    case TSNE_DIST_BF16X3:
+      hipLaunchKernelGGL((k_dist_lp<__bf16, v8bf, false>), dgrid, dim3(256), 0, st,
+                         at<const __bf16>(ws, L.xa), at<const __bf16>(ws, L.xb), norms32, L.npad,
+                         L.kk, b, col_base, dblock, h, guard != nullptr, L.n, key, nzskip,
+                         L.nb);
+      break;
+    case TSNE_DIST_FP16:
+    case TSNE_DIST_FP16X3:
+      hipLaunchKernelGGL((k_dist_lp<_Float16, v8h, true>), dgrid, dim3(256), 0, st,
+                         at<const _Float16>(ws, L.xa), at<const _Float16>(ws, L.xb), norms32,
+                         L.npad, L.kk, b, col_base, dblock, h, guard != nullptr, L.n, key,
+                         nzskip, L.nb);
+      break;
+    default:
+      hipLaunchKernelGGL(k_dist_f64,
+                         dim3((unsigned)((L.npad - col_base) / (64 * kDistCT)), T / 64), dim3(256),
+                         0, st, xc, nrm, L.npad, L.dpad, b, col_base, dblock, guard, L.n, key,
+                         nzskip, L.nb);
+  }
+}
+
 hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
                              int max_bisect, double tol_h, int reorder, void *ws, hipStream_t st,
                              bool stats_only, bool implicit) {
@@ -1474,7 +1539,6 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   float *xfT = at<float>(ws, L.xfT);
   __bf16 *xa_b = at<__bf16>(ws, L.xa), *xb_b = at<__bf16>(ws, L.xb);
   _Float16 *xa_h = at<_Float16>(ws, L.xa), *xb_h = at<_Float16>(ws, L.xb);
-  const dim3 dgrid((unsigned)(L.npad / 256), T / 64);
   double2 *ppart = at<double2>(ws, L.ppart);
   uint8_t *nz = at<uint8_t>(ws, L.nz);
 
@@ -1506,28 +1570,9 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
         break;
     }
   };
-  // Distances of row block b (into the block scratch).
+  // Distances of row block b (into the block scratch), all columns.
   auto dist = [&](int b, const double *xc, const double *nrm) {
-    switch (L.mode) {
-      case TSNE_DIST_FP32:
-        hipLaunchKernelGGL(k_dist_f32, dgrid, dim3(256), 0, st, xfT, norms32, L.npad, L.dpad, b,
-                           dblock);
-        break;
-      case TSNE_DIST_BF16:
-      case TSNE_DIST_BF16X3:
-        hipLaunchKernelGGL((k_dist_lp<__bf16, v8bf, false>), dgrid, dim3(256), 0, st, xa_b, xb_b,
-                           norms32, L.npad, L.kk, b, dblock, h);
-        break;
-      case TSNE_DIST_FP16:
-      case TSNE_DIST_FP16X3:
-        hipLaunchKernelGGL((k_dist_lp<_Float16, v8h, true>), dgrid, dim3(256), 0, st, xa_h, xb_h,
-                           norms32, L.npad, L.kk, b, dblock, h);
-        break;
-      default:
-        hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64),
-                           dim3(256), 0, st, xc, nrm, L.npad, L.dpad, b, (int64_t)0, dblock,
-                           (const Hdr *)nullptr, (int64_t)0, 0);
-    }
+    launch_dist(L, ws, b, xc, nrm, 0, nullptr, nullptr, st);
   };
   auto calibrate = [&](int b) {
     const int rows = (int)((L.n - (int64_t)b * T) < T ? (L.n - (int64_t)b * T) : T);
@@ -1575,7 +1620,8 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
                          dis, L.n, L.npad, b, dblock, h);
       calibrate(b);
       hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
-                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
+                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0,
+                         (const uint8_t *)nullptr);
     }
     pack();
     return hipGetLastError();
@@ -1641,18 +1687,23 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
     calibrate(b);
     if (!stats_only && !implicit)
       hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
-                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0);
+                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0,
+                         (const uint8_t *)nullptr);
   }
   if (implicit) {
-    // every pass rebuilds P from the centred X in the internal order: make
-    // sure it sits in the second buffer (the identity order copies it)
-    if (xc != at<double>(ws, L.xcT2))
+    // every pass rebuilds P from the contraction operands in the internal
+    // order: the prepared ones of a reduced mode stay where prep() wrote
+    // them; the FP64 mode reads the centred X from the second buffer (the
+    // identity order copies it there)
+    if (L.mode == TSNE_DIST_FP64 && xc != at<double>(ws, L.xcT2))
       hipLaunchKernelGGL(k_permute_x, dim3(pgrid), dim3(256), 0, st, xcT, norms, perm, L.n,
                          L.npad, L.dpad, at<double>(ws, L.xcT2), at<double>(ws, L.norms2));
     const int64_t m = L.nt > L.nb ? L.nt : L.nb;
     hipLaunchKernelGGL(k_implicit_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
                        at<uint8_t>(ws, L.nz), L.nt, at<int32_t>(ws, L.nslots), L.nb, h);
     hipLaunchKernelGGL(k_set_ready, dim3(1), dim3(64), 0, st, h, 2);
+    hipError_t e = launch_implicit_discover(L, ws, st);
+    if (e != hipSuccess) return e;
   } else if (!stats_only) {
     pack();
   }
@@ -1660,35 +1711,54 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
 }
 
 hipError_t launch_implicit_block(const Layout &L, void *ws, int b, int64_t tile_base,
-                                 hipStream_t st) {
-  float *dblock = at<float>(ws, L.dblock);
-  const int64_t t0 = tile_start(b, L.nb);
+                                 bool skip_zero, hipStream_t st) {
   const Hdr *h = at<const Hdr>(ws, L.hdr);
+  const uint8_t *nzskip = skip_zero ? at<const uint8_t>(ws, L.nz) : nullptr;
   // only the columns of the block row's own tiles (s >= b) are staged
-  const int64_t col_base = (int64_t)b * T;
-  hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)((L.npad - col_base) / (64 * kDistCT)), T / 64),
-                     dim3(256), 0, st, at<const double>(ws, L.xcT2),
-                     at<const double>(ws, L.norms2), L.npad, L.dpad, b, col_base, dblock, h, L.n,
-                     L.d);
-  hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
-                     L.nb, b, at<float4>(ws, L.P), tile_base, h, L.n, L.d);
+  launch_dist(L, ws, b, at<const double>(ws, L.xcT2), at<const double>(ws, L.norms2),
+              (int64_t)b * T, h, nzskip, st);
+  hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st,
+                     at<const float>(ws, L.dblock), L.npad, L.nb, b, at<float4>(ws, L.P),
+                     tile_base, h, L.n, implicit_key(L.d, L.mode), nzskip);
   return hipGetLastError();
 }
 
 hipError_t launch_implicit_pack(const Layout &L, void *ws, int64_t tile0, int64_t count,
-                                int64_t tile_base, hipStream_t st) {
+                                int64_t tile_base, bool skip_zero, hipStream_t st) {
   hipLaunchKernelGGL(k_pack_range, dim3((unsigned)count), dim3(256), 0, st, at<float4>(ws, L.P),
                      at<const float>(ws, L.a), at<const float>(ws, L.m), at<const float>(ws, L.r),
                      L.n, L.nb, at<double2>(ws, L.ppart), at<uint8_t>(ws, L.nz),
-                     at<int2>(ws, L.tmap), tile0, tile_base, at<const Hdr>(ws, L.hdr), L.d);
+                     at<int2>(ws, L.tmap), tile0, tile_base, at<const Hdr>(ws, L.hdr),
+                     implicit_key(L.d, L.mode), skip_zero);
   return hipGetLastError();
 }
 
-hipError_t launch_implicit_sums(const Layout &L, void *ws, hipStream_t st) {
+// The end of the affinity stage of implicit P: one pass over every tile
+// (distances, stage, pack) finds the zero tiles, the sums of P and the tile
+// coordinates; P is the same in every later pass, so those passes recompute
+// only the nonzero tiles and take the all-zero ones with the repulsion-only
+// body, as the stored path does.
+hipError_t launch_implicit_discover(const Layout &L, void *ws, hipStream_t st) {
+  const int64_t cap = implicit_capacity(L);
+  for (int b0 = 0; b0 < L.nb;) {
+    int b1 = b0 + 1;
+    while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
+    const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
+    for (int b = b0; b < b1; ++b) {
+      hipError_t e = launch_implicit_block(L, ws, b, base, false, st);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_implicit_pack(L, ws, base, count, base, false, st);
+    if (e != hipSuccess) return e;
+    b0 = b1;
+  }
+  uint8_t *nz = at<uint8_t>(ws, L.nz);
   hipLaunchKernelGGL(k_implicit_sums, dim3(1), dim3(1024), 0, st, at<const double2>(ws, L.ppart),
-                     L.nt, L.n, L.d, at<Hdr>(ws, L.hdr));
-  hipLaunchKernelGGL(k_slot_lists, dim3(L.nb), dim3(256), 0, st, at<const uint8_t>(ws, L.nz),
-                     L.nb, at<int32_t>(ws, L.slots), at<int32_t>(ws, L.nslots));
+                     L.nt, L.n, implicit_key(L.d, L.mode), at<Hdr>(ws, L.hdr));
+  hipLaunchKernelGGL(k_slot_lists, dim3(L.nb), dim3(256), 0, st, nz, L.nb,
+                     at<int32_t>(ws, L.slots), at<int32_t>(ws, L.nslots));
+  hipLaunchKernelGGL(k_tile_lists, dim3(1), dim3(1024), 0, st, nz, L.nt,
+                     at<int32_t>(ws, L.tlist), at<int32_t>(ws, L.tcount));
   return hipGetLastError();
 }
 

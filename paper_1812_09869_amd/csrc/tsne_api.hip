@@ -140,8 +140,6 @@ int tsne_affinities(const float *x, int64_t n, int32_t d, double perplexity,
     return fail(TSNE_E_ARG, "tsne_affinities: unknown distance mode %d", o.dist_mode);
   if (o.max_bisect < 1 || !(o.tol_h > 0.0) || (o.implicit_p != 0 && o.implicit_p != 1))
     return fail(TSNE_E_ARG, "tsne_affinities: max_bisect >= 1, tol_h > 0, implicit_p 0 or 1 required");
-  if (o.implicit_p && o.dist_mode != TSNE_DIST_FP64)
-    return fail(TSNE_E_ARG, "tsne_affinities: implicit P needs the FP64 distance mode");
   if (!(perplexity > 1.0) || !(perplexity < (double)(n - 1)))
     return fail(TSNE_E_PERPLEXITY, "tsne_affinities: perplexity %g not in (1, n-1 = %lld)",
                 perplexity, (long long)(n - 1));
@@ -250,28 +248,32 @@ int tsne_cost(void *ws, int64_t n, const float *y, double *out, void *stream) {
   return hip_check(tsne::launch_cost(L, ws, y, out, (hipStream_t)stream), "tsne_cost");
 }
 
-size_t tsne_workspace_bytes_implicit(int64_t n, int32_t d) {
-  if (!valid_n(n) || d < 1 || d > 65536) return 0;
-  return tsne::make_layout(n, d, TSNE_DIST_FP64, false, true).total;
+size_t tsne_workspace_bytes_implicit(int64_t n, int32_t d, int32_t dist_mode) {
+  if (!valid_n(n) || d < 1 || d > 65536 || dist_mode < TSNE_DIST_FP64 ||
+      dist_mode > TSNE_DIST_FP16X3)
+    return 0;
+  return tsne::make_layout(n, d, dist_mode, false, true).total;
 }
 
 // The iteration entry points on a workspace whose P is recomputed per pass
 // (the layout of tsne_workspace_bytes_implicit, filled by tsne_affinities
 // with implicit_p = 1).
-static int check_implicit(const char *fn, void *ws, int64_t n, int32_t d) {
+static int check_implicit(const char *fn, void *ws, int64_t n, int32_t d, int32_t mode) {
   if (int rc = check_iter_args(fn, ws, n)) return rc;
   if (d < 1 || d > 65536) return fail(TSNE_E_ARG, "%s: d = %d out of range", fn, d);
+  if (mode < TSNE_DIST_FP64 || mode > TSNE_DIST_FP16X3)
+    return fail(TSNE_E_ARG, "%s: unknown distance mode %d", fn, mode);
   return TSNE_OK;
 }
 
-int tsne_step_implicit(void *ws, int64_t n, int32_t d, float *y, float *u, float *g,
-                       const tsne_step_params *prm, float *grad_out, double *z_out,
+int tsne_step_implicit(void *ws, int64_t n, int32_t d, int32_t dist_mode, float *y, float *u,
+                       float *g, const tsne_step_params *prm, float *grad_out, double *z_out,
                        void *stream) {
-  if (int rc = check_implicit("tsne_step_implicit", ws, n, d)) return rc;
+  if (int rc = check_implicit("tsne_step_implicit", ws, n, d, dist_mode)) return rc;
   if (!y || !u || !prm || (!g && prm->lr_rule != TSNE_LR_RANGE))
     return fail(TSNE_E_ARG, "tsne_step_implicit: null pointer");
   if (int rc = check_params("tsne_step_implicit", prm)) return rc;
-  const Layout L = tsne::make_layout(n, d, TSNE_DIST_FP64, false, true);
+  const Layout L = tsne::make_layout(n, d, dist_mode, false, true);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = tsne::launch_force_implicit(L, ws, y, st);
   if (e == hipSuccess)
@@ -280,23 +282,23 @@ int tsne_step_implicit(void *ws, int64_t n, int32_t d, float *y, float *u, float
   return hip_check(e, "tsne_step_implicit");
 }
 
-int tsne_gradient_implicit(void *ws, int64_t n, int32_t d, const float *y, float alpha,
-                           float *grad_out, double *z_out, void *stream) {
-  if (int rc = check_implicit("tsne_gradient_implicit", ws, n, d)) return rc;
+int tsne_gradient_implicit(void *ws, int64_t n, int32_t d, int32_t dist_mode, const float *y,
+                           float alpha, float *grad_out, double *z_out, void *stream) {
+  if (int rc = check_implicit("tsne_gradient_implicit", ws, n, d, dist_mode)) return rc;
   if (!y || !grad_out) return fail(TSNE_E_ARG, "tsne_gradient_implicit: null pointer");
   if (!isfinite(alpha)) return fail(TSNE_E_ARG, "tsne_gradient_implicit: non-finite alpha");
-  const Layout L = tsne::make_layout(n, d, TSNE_DIST_FP64, false, true);
+  const Layout L = tsne::make_layout(n, d, dist_mode, false, true);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = tsne::launch_force_implicit(L, ws, y, st);
   if (e == hipSuccess) e = tsne::launch_gradient_only(L, ws, alpha, grad_out, z_out, st);
   return hip_check(e, "tsne_gradient_implicit");
 }
 
-int tsne_cost_implicit(void *ws, int64_t n, int32_t d, const float *y, double *out,
-                       void *stream) {
-  if (int rc = check_implicit("tsne_cost_implicit", ws, n, d)) return rc;
+int tsne_cost_implicit(void *ws, int64_t n, int32_t d, int32_t dist_mode, const float *y,
+                       double *out, void *stream) {
+  if (int rc = check_implicit("tsne_cost_implicit", ws, n, d, dist_mode)) return rc;
   if (!y || !out) return fail(TSNE_E_ARG, "tsne_cost_implicit: null pointer");
-  const Layout L = tsne::make_layout(n, d, TSNE_DIST_FP64, false, true);
+  const Layout L = tsne::make_layout(n, d, dist_mode, false, true);
   return hip_check(tsne::launch_cost_implicit(L, ws, y, out, (hipStream_t)stream),
                    "tsne_cost_implicit");
 }

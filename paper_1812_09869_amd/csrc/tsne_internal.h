@@ -168,6 +168,12 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
 // Implicit P: recompute block b's distances and stage its tiles into the
 // buffer; pack a range of staged tiles; after all blocks, the P sums and the
 // slot lists.
+// Implicit P: the passes check the workspace header against the shape their
+// layout was computed for, n and one word holding d (below 2^20) and the
+// distance mode (the mode decides which contraction operands exist).
+inline __host__ __device__ int32_t implicit_key(int32_t d, int32_t mode) {
+  return d | (mode << 20);
+}
 // Implicit P buffer capacity in tiles: at least one block row, at most the
 // whole triangle.
 inline int64_t implicit_capacity(const Layout &L) {
@@ -175,13 +181,16 @@ inline int64_t implicit_capacity(const Layout &L) {
   return c < L.nt ? c : L.nt;
 }
 // Block rows [b0, b1) fill the buffer: tile t of them sits at slot
-// t - tile_start(b0).
+// t - tile_start(b0). skip_zero: the zero tiles are known (every pass after
+// the affinity stage) and are neither computed nor staged.
 hipError_t launch_implicit_block(const Layout &L, void *ws, int b, int64_t tile_base,
-                                 hipStream_t stream);
+                                 bool skip_zero, hipStream_t stream);
 // Pack (Eq. 3) the staged tiles tile0 .. tile0 + count - 1 of the buffer.
 hipError_t launch_implicit_pack(const Layout &L, void *ws, int64_t tile0, int64_t count,
-                                int64_t tile_base, hipStream_t stream);
-hipError_t launch_implicit_sums(const Layout &L, void *ws, hipStream_t stream);
+                                int64_t tile_base, bool skip_zero, hipStream_t stream);
+// The affinity stage's pass over every tile: zero flags, tile coordinates,
+// the sums of P, slot and tile lists.
+hipError_t launch_implicit_discover(const Layout &L, void *ws, hipStream_t stream);
 hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipStream_t stream);
 hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, double *out,
                                 hipStream_t stream);

@@ -468,11 +468,14 @@ __global__ __launch_bounds__(256, 4) void k_force_zero(const float2 *__restrict_
                                                        float *__restrict__ zpart,
                                                        const int32_t *__restrict__ tlist,
                                                        const int32_t *__restrict__ tcount,
-                                                       const int2 *__restrict__ tmap, Hdr *h) {
+                                                       const int2 *__restrict__ tmap, Hdr *h,
+                                                       int32_t ready) {
   __shared__ ZeroSmem sm;
   // the header check comes first: with a workspace for another n, the lists
-  // are not where this layout puts them
-  if (!ready_is(h, n, 1)) {
+  // are not where this layout puts them. ready: 1 stored P, 2 implicit P
+  // (the lists and tile coordinates of its affinity stage; nothing here
+  // depends on d or the distance mode)
+  if (!ready_is(h, n, ready)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
@@ -508,20 +511,23 @@ __global__ __launch_bounds__(256, 2) void k_force_full(const float4 *__restrict_
   }
 }
 
-// Implicit P: the tiles tile0 .. tile0 + gridDim.x - 1 (whole block rows),
-// whose P was just recomputed into the buffer Pb (tile tile0 + x at slot x).
+// Implicit P: the nonzero tiles among tile0 .. tile0 + gridDim.x - 1 (whole
+// block rows), whose P was just recomputed into the buffer Pb (tile
+// tile0 + x at slot x); the all-zero ones are k_force_zero's.
 __global__ __launch_bounds__(256, 2) void k_force_range(const float4 *__restrict__ Pb,
                                                         const float2 *__restrict__ Y, int64_t n,
                                                         int32_t nb, float4 *__restrict__ part,
                                                         float *__restrict__ zpart,
                                                         const int2 *__restrict__ tmap,
-                                                        int64_t tile0, int32_t d, Hdr *h) {
+                                                        const uint8_t *__restrict__ nz,
+                                                        int64_t tile0, int32_t key, Hdr *h) {
   __shared__ ForceSmem sm;
-  if (!ready_is(h, n, 2) || h->d != d) {
+  if (!ready_is(h, n, 2) || implicit_key(h->d, h->mode) != key) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(h, kErrState);
     return;
   }
   const int64_t tile = tile0 + blockIdx.x;
+  if (!nz[tile]) return;
   float2 yc[16];
   const TileCtx c = tile_begin(Y, n, nb, tmap, tile, yc, sm);
   full_tile_body(c, yc, Pb, part, nb, zpart, tile, blockIdx.x, sm);
@@ -1135,21 +1141,28 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_force_zero, dim3((unsigned)L.nt), dim3(256), 0, ss->s, (const float2 *)yp,
-                     L.n, L.nb, part, zp, tl, tc, tm, h);
+                     L.n, L.nb, part, zp, tl, tc, tm, h, 1);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
   return hipStreamWaitEvent(st, ss->join, 0);
 }
 
-// Implicit P: per block row, recompute its tiles' P into the buffer (the
-// affinity kernels) and run the full tile body on them; then the P sums and
-// the slot lists of the update. Every tile takes the full body (the all-zero
-// split needs the tile lists of a stored P).
+// Implicit P: the all-zero tiles (known since the affinity stage) in one
+// repulsion-only launch, as in the stored path; then per buffer of block
+// rows, the nonzero tiles' P recomputed (the affinity kernels, zero tiles
+// skipped) and the full tile body on them. The slot lists and the sums of P
+// are those of the affinity stage.
 hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   float2 *yp = at<float2>(ws, L.yp);
   hipLaunchKernelGGL(k_gather_y, dim3(L.nb), dim3(256), 0, st, reinterpret_cast<const float2 *>(y),
                      at<const int32_t>(ws, L.perm), L.n, yp, at<float4>(ws, L.extent), h);
+  float4 *part = at<float4>(ws, L.part);
+  float *zp = at<float>(ws, L.zpart);
+  const int2 *tm = at<const int2>(ws, L.tmap);
+  hipLaunchKernelGGL(k_force_zero, dim3((unsigned)L.nt), dim3(256), 0, st, (const float2 *)yp,
+                     L.n, L.nb, part, zp, at<const int32_t>(ws, L.tlist),
+                     at<const int32_t>(ws, L.tcount), tm, h, 2);
   const int64_t cap = implicit_capacity(L);
   for (int b0 = 0; b0 < L.nb;) {
     // the block rows whose tiles fill the buffer (at least one)
@@ -1157,20 +1170,19 @@ hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipS
     while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
     const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
     for (int b = b0; b < b1; ++b) {
-      hipError_t e = launch_implicit_block(L, ws, b, base, st);
+      hipError_t e = launch_implicit_block(L, ws, b, base, true, st);
       if (e != hipSuccess) return e;
     }
     {
-      hipError_t e = launch_implicit_pack(L, ws, base, count, base, st);
+      hipError_t e = launch_implicit_pack(L, ws, base, count, base, true, st);
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_force_range, dim3((unsigned)count), dim3(256), 0, st,
-                       at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb,
-                       at<float4>(ws, L.part), at<float>(ws, L.zpart), at<const int2>(ws, L.tmap),
-                       base, L.d, h);
+                       at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb, part, zp, tm,
+                       at<const uint8_t>(ws, L.nz), base, implicit_key(L.d, L.mode), h);
     b0 = b1;
   }
-  return launch_implicit_sums(L, ws, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, double *out,
@@ -1186,20 +1198,19 @@ hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, doubl
     while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
     const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
     for (int b = b0; b < b1; ++b) {
-      hipError_t e = launch_implicit_block(L, ws, b, base, st);
+      hipError_t e = launch_implicit_block(L, ws, b, base, true, st);
       if (e != hipSuccess) return e;
     }
     {
-      hipError_t e = launch_implicit_pack(L, ws, base, count, base, st);
+      hipError_t e = launch_implicit_pack(L, ws, base, count, base, true, st);
       if (e != hipSuccess) return e;
     }
+    // every tile: the all-zero ones add to Z without reading P
     hipLaunchKernelGGL(k_cost_range, dim3((unsigned)count), dim3(256), 0, st,
                        at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb, cp,
                        at<const uint8_t>(ws, L.nz), h, base);
     b0 = b1;
   }
-  hipError_t e = launch_implicit_sums(L, ws, st);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(1024), 0, st, cp, L.nt, L.n, h, out);
   return hipGetLastError();
 }

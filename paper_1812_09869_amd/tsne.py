@@ -49,15 +49,16 @@ class ExactTSNE:
     def __init__(self, x: torch.Tensor, perplexity: float, dist_mode="fp64", max_bisect: int = 200,
                  tol_h: float = 1e-6, ws: torch.Tensor | None = None, reorder: bool = True,
                  implicit: bool = False):
-        """implicit: keep no P and recompute it in every pass (FP64 mode)."""
+        """implicit: keep no P and recompute it in every pass (in dist_mode)."""
         if x.dim() != 2:
             raise ValueError("x must be n x d")
         self.n, self.d = x.shape
         self.perplexity = float(perplexity)
         self.implicit = bool(implicit)
+        self.dist_mode = dist_mode
         if ws is None:
-            ws = (_lib.new_workspace_implicit(self.n, self.d, device=x.device) if implicit else
-                  _lib.new_workspace(self.n, self.d, dist_mode, device=x.device))
+            ws = (_lib.new_workspace_implicit(self.n, self.d, device=x.device, dist_mode=dist_mode)
+                  if implicit else _lib.new_workspace(self.n, self.d, dist_mode, device=x.device))
         self.ws = ws
         _lib.affinities(x, perplexity, self.ws, dist_mode, max_bisect, tol_h, reorder, implicit)
         self._z = torch.zeros(1, dtype=torch.float64, device=x.device)
@@ -71,6 +72,7 @@ class ExactTSNE:
         self = cls.__new__(cls)
         self.n, self.d = dis.shape[0], 1
         self.implicit = False
+        self.dist_mode = "fp64"
         self.perplexity = float(perplexity)
         self.ws = _lib.new_workspace(self.n, 1, "fp64", device=dis.device)
         _lib.affinities_dissim(dis.contiguous(), perplexity, self.ws, max_bisect, tol_h)
@@ -87,7 +89,8 @@ class ExactTSNE:
         alpha, mu, eta = sched(t)
         if self.implicit:
             _lib.step_implicit(self.ws, self.n, self.d, y, u, g, alpha, mu, eta, sched.min_gain,
-                               True, grad_out, z_out, lr_rule=sched.lr_rule)
+                               True, grad_out, z_out, lr_rule=sched.lr_rule,
+                               dist_mode=self.dist_mode)
         else:
             _lib.step(self.ws, self.n, y, u, g, alpha, mu, eta, sched.min_gain, True, grad_out,
                       z_out, lr_rule=sched.lr_rule)
@@ -101,7 +104,8 @@ class ExactTSNE:
     def gradient(self, y: torch.Tensor, alpha: float = 1.0):
         g = torch.empty_like(y)
         if self.implicit:
-            _lib.gradient_implicit(self.ws, self.n, self.d, y, alpha, g, self._z)
+            _lib.gradient_implicit(self.ws, self.n, self.d, y, alpha, g, self._z,
+                                   dist_mode=self.dist_mode)
         else:
             _lib.gradient(self.ws, self.n, y, alpha, g, self._z)
         return g, self._z
@@ -109,7 +113,7 @@ class ExactTSNE:
     def cost(self, y: torch.Tensor):
         """Device tensor [KL, C_norm]."""
         if self.implicit:
-            _lib.cost_implicit(self.ws, self.n, self.d, y, self._cost)
+            _lib.cost_implicit(self.ws, self.n, self.d, y, self._cost, dist_mode=self.dist_mode)
         else:
             _lib.cost(self.ws, self.n, y, self._cost)
         return self._cost

@@ -77,6 +77,11 @@ def test_implicit_workspace_is_small():
         pytest.skip("libtsne355.so not built")
     lib = _lib.load()
     full = _lib.workspace_bytes(65536, 50)
-    imp = lib.tsne_workspace_bytes_implicit(65536, 50)
+    imp = lib.tsne_workspace_bytes_implicit(65536, 50, 0)
     assert 0 < imp < full / 5
-    assert lib.tsne_workspace_bytes_implicit(1, 50) == 0
+    assert lib.tsne_workspace_bytes_implicit(1, 50, 0) == 0
+    # a reduced distance mode keeps its contraction operands as well
+    for mode in range(1, 6):
+        assert imp < lib.tsne_workspace_bytes_implicit(65536, 50, mode) < full / 5
+    assert lib.tsne_workspace_bytes_implicit(65536, 50, 6) == 0
+    assert lib.tsne_workspace_bytes_implicit(65536, 50, -1) == 0

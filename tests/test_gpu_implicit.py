@@ -1,11 +1,13 @@
 """Implicit P (recomputed block row by block row in every pass) on the GPU.
 
-The recomputation runs the same kernels as the stored path (FP64 MFMA
-distances, stage, pack), so P itself is bitwise the same; the force pass
-takes the full tile body on every tile (the stored path splits off the
-all-zero tiles), so gradients agree with the stored path to rounding. Gates
-against the oracle are those of the stored path: gradient relative L2 <= 1e-4,
-Z relative <= 1e-6, KL relative <= 1e-5, map after three steps <= 1e-4.
+The recomputation runs the same kernels as the stored path (MFMA distances
+in the workspace's mode, stage, pack), so P itself is bitwise the same; the
+force pass takes the full tile body on every tile (the stored path splits off
+the all-zero tiles), so gradients agree with the stored path to rounding.
+Gates against the oracle (FP64 mode) are those of the stored path: gradient
+relative L2 <= 1e-4, Z relative <= 1e-6, KL relative <= 1e-5, map after three
+steps <= 1e-4. The reduced distance modes are checked against the stored path
+of the same mode (their distance to the oracle is the precision report's).
 """
 import numpy as np
 import pytest
@@ -83,3 +85,57 @@ def test_modes_are_not_mixed():
     imp2 = ExactTSNE(xt, 20.0, implicit=True)
     _lib.gradient_implicit(imp2.ws, 600, 11, y, 1.0, g)
     assert _lib.sync_status(imp2.ws) == 7
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16", "fp16x3"])
+def test_reduced_modes_match_stored(mode):
+    """Implicit P in a reduced distance mode: the same row statistics as the
+    stored path of that mode, gradient and Z within rounding of it, the same
+    cost, and the same map after three steps."""
+    n, perp = 1300, 30.0
+    x, lab = synth.gmm_aniso(n, sample_seed=77)
+    print(f"\n[implicit] mode={mode} n={n} d={x.shape[1]}", flush=True)
+    xt = torch.from_numpy(x).cuda()
+    imp = ExactTSNE(xt, perp, dist_mode=mode, implicit=True)
+    sto = ExactTSNE(xt, perp, dist_mode=mode)
+    for a, b in zip(imp.rowstats(), sto.rowstats()):
+        assert torch.equal(a, b)
+    yt = torch.from_numpy(synth.clustered_state(lab, seed=9)).cuda()
+    gi, zi = imp.gradient(yt, 1.0)
+    gi, zi = gi.clone(), float(zi.cpu()[0])
+    gs, zs = sto.gradient(yt, 1.0)
+    zs = float(zs.cpu()[0])
+    rel = (torch.linalg.norm(gi - gs) / torch.linalg.norm(gs)).item()
+    print(f"  gradient rel vs stored {rel:.2e}, Z rel {abs(zi - zs) / zs:.2e}")
+    assert rel <= 1e-5 and abs(zi - zs) <= 1e-6 * zs
+    ci = imp.cost(yt).cpu().numpy().copy()
+    cs = sto.cost(yt).cpu().numpy()
+    assert abs(ci[0] - cs[0]) <= 1e-6 * abs(cs[0]) and abs(ci[1] - cs[1]) <= 1e-6
+    y0 = torch.from_numpy(synth.embedding_init(n, seed=11)).cuda()
+    si, ss = imp.init_state(y0), sto.init_state(y0)
+    imp.run(si, 3)
+    sto.run(ss, 3)
+    rel = (torch.linalg.norm(si[0] - ss[0]) / torch.linalg.norm(ss[0])).item()
+    print(f"  map after 3 steps rel vs stored {rel:.2e}")
+    assert rel <= 1e-5
+    assert imp.status() == 0 and sto.status() == 0
+
+
+def test_wrong_mode_is_refused():
+    """An implicit workspace used with another distance mode is refused on the
+    device before its buffers are read (the reduced modes' operands sit past
+    the end of an FP64 workspace)."""
+    x, _ = synth.plain_small(600, seed=5)
+    xt = torch.from_numpy(x).cuda()
+    y = torch.from_numpy(synth.embedding_init(600, seed=6)).cuda()
+    g = torch.empty_like(y)
+    f64 = ExactTSNE(xt, 20.0, implicit=True)
+    _lib.gradient_implicit(f64.ws, 600, 10, y, 1.0, g, dist_mode="bf16")
+    assert _lib.sync_status(f64.ws) == 7
+    b16 = ExactTSNE(xt, 20.0, dist_mode="bf16", implicit=True)
+    _lib.gradient_implicit(b16.ws, 600, 10, y, 1.0, g, dist_mode="fp64")
+    assert _lib.sync_status(b16.ws) == 7
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    b16b = ExactTSNE(xt, 20.0, dist_mode="bf16", implicit=True)
+    _lib.cost_implicit(b16b.ws, 600, 10, y, out, dist_mode="fp32")
+    assert _lib.sync_status(b16b.ws) == 7
