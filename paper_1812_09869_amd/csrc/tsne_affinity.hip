@@ -124,26 +124,12 @@ __global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int
 // ----------------------------------------------------------------------------
 constexpr int kDistCT = 2;  // 16-column MFMA tiles per wave (a wave covers 64 x 16 kDistCT)
 
-// Columns from col_base (a multiple of 64 kDistCT) to npad: all of them for
-// the calibration, only those of the block row's own tiles (col_base = b T)
-// in an implicit pass. guard (implicit P passes only, else null): the
-// workspace header, n and implicit_key(d, mode). nzskip (implicit passes
-// after the zero tiles are known, else null): per-tile nonzero flags; a
-// workgroup whose tile (b, J) is all zero returns at once.
 __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
                                                   const double *__restrict__ norms, int64_t npad,
-                                                  int32_t dpad, int32_t b, int64_t col_base,
-                                                  float *__restrict__ dblock,
-                                                  const Hdr *guard, int64_t gn, int32_t gkey,
-                                                  const uint8_t *__restrict__ nzskip,
-                                                  int32_t nb) {
-  if (guard && !implicit_ready(guard, gn, gkey)) return;
-  if (nzskip) {  // zero tiles known: the workgroup's tile needs no distances
-    const int64_t J = (col_base + (int64_t)blockIdx.x * (64 * kDistCT)) / T;
-    if (!nzskip[tile_start(b, nb) + J - b]) return;
-  }
+                                                  int32_t dpad, int32_t b,
+                                                  float *__restrict__ dblock) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = col_base + (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
+  const int64_t col0 = (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -258,18 +244,12 @@ __global__ __launch_bounds__(256) void k_prep_lp(const double *__restrict__ xcT,
   norms32[i] = (float)nrm;
 }
 
-// Columns col_base .. npad - 1 (col_base a multiple of 256); guard and
-// nzskip as for k_dist_f64 (a workgroup covers one tile's columns).
 __global__ __launch_bounds__(256) void k_dist_f32(const float *__restrict__ xfT,
                                                   const float *__restrict__ norms, int64_t npad,
-                                                  int32_t dpad, int32_t b, int64_t col_base,
-                                                  float *__restrict__ dblock, const Hdr *guard,
-                                                  int64_t gn, int32_t gkey,
-                                                  const uint8_t *__restrict__ nzskip, int32_t nb) {
-  if (guard && !implicit_ready(guard, gn, gkey)) return;
-  if (nzskip && !nzskip[tile_start(b, nb) + col_base / T + blockIdx.x - b]) return;
+                                                  int32_t dpad, int32_t b,
+                                                  float *__restrict__ dblock) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = col_base + (int64_t)blockIdx.x * 256 + w * 64;
+  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -310,14 +290,10 @@ __global__ __launch_bounds__(256) void k_dist_f32(const float *__restrict__ xfT,
 template <typename H, typename V8, bool SCALE>
 __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa, const H *__restrict__ xb,
                                                  const float *__restrict__ norms, int64_t npad,
-                                                 int32_t kk, int32_t b, int64_t col_base,
-                                                 float *__restrict__ dblock, const Hdr *h,
-                                                 bool guarded, int64_t gn, int32_t gkey,
-                                                 const uint8_t *__restrict__ nzskip, int32_t nb) {
-  if (guarded && !implicit_ready(h, gn, gkey)) return;
-  if (nzskip && !nzskip[tile_start(b, nb) + col_base / T + blockIdx.x - b]) return;
+                                                 int32_t kk, int32_t b, float *__restrict__ dblock,
+                                                 const Hdr *h) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = col_base + (int64_t)blockIdx.x * 256 + w * 64;
+  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -526,19 +502,14 @@ __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restri
 // The diagonal tile holds both orders of each pair; both take the distance
 // of the upper element so that the stored P is exactly symmetric.
 // ----------------------------------------------------------------------------
-// tile_base: the P store's first tile (0, or the first tile of the buffer of
-// implicit P). Grid (nb - b, kStageSplit).
+// Grid (nb - b, kStageSplit).
 constexpr int kStageSplit = 4;
 __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock, int64_t npad,
-                                               int32_t nb, int32_t b, float4 *__restrict__ P,
-                                               int64_t tile_base, const Hdr *guard, int64_t gn,
-                                               int32_t gkey, const uint8_t *__restrict__ nzskip) {
-  if (guard && !implicit_ready(guard, gn, gkey)) return;
-  if (nzskip && !nzskip[tile_start(b, nb) + blockIdx.x]) return;  // all-zero tile: not staged
+                                               int32_t nb, int32_t b, float4 *__restrict__ P) {
   const int J = b + blockIdx.x;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
-  float4 *dst = P + (size_t)(tile_start(b, nb) - tile_base) * TT4 + (size_t)blockIdx.x * TT4;
+  float4 *dst = P + (size_t)tile_start(b, nb) * TT4 + (size_t)blockIdx.x * TT4;
   const float *src = dblock + (int64_t)J * T;
   // workgroup y of the tile copies float4 rows s0 .. s1 - 1 of its 64
   const int s0 = blockIdx.y * (64 / kStageSplit), s1 = s0 + 64 / kStageSplit;
@@ -561,6 +532,319 @@ __global__ __launch_bounds__(256) void k_stage(const float *__restrict__ dblock,
         v[e] = src[(int64_t)lo * npad + hi];
       }
       dst[s * 256 + t] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 2d. Implicit P: distances straight into the tile buffer. One launch covers
+// the tiles tile0 .. tile0 + gridDim.x - 1 (whole block rows) and writes each
+// tile's distances in the layout k_stage produces (float4 s * 256 + t of a
+// tile holds rows tr + 16 (s / 4), columns tc + 64 (s % 4) + 16 e), so the
+// pack and force kernels read them as before. The contraction of an element
+// is the one the per-block-row kernels form for it (same operands, same
+// MFMA sequence); a diagonal tile takes the upper element for both orders of
+// a pair, as k_stage does, so P stays bitwise symmetric and bitwise that of
+// the stored path. skip: the zero tiles are known and are left alone.
+// ----------------------------------------------------------------------------
+// p_ij of Eq. 3 from the distance and both rows' statistics (a = beta
+// log2(e), m = row minimum, r = 1 / (2 n S)). No contraction into an FMA, so
+// that the two orders of a pair give bitwise equal sums.
+__device__ __forceinline__ float pair_p(float d, float ai, float mi, float ri, float aj, float mj,
+                                        float rj) {
+#pragma clang fp contract(off)
+  const float pi = __builtin_amdgcn_exp2f(-ai * (d - mi)) * ri;
+  const float pj = __builtin_amdgcn_exp2f(-aj * (d - mj)) * rj;
+  return pi + pj;
+}
+
+__device__ __forceinline__ int64_t tile_pos(int il, int jl) {
+  const int tr = il & 15, k = il >> 4, tc = jl & 15, mq = jl >> 6, e = (jl >> 4) & 3;
+  const int t = 64 * (tr >> 2) + 16 * (tr & 3) + tc;
+  return ((int64_t)(4 * k + mq) * 256 + t) * 4 + e;
+}
+
+__device__ __forceinline__ void put_d(float *__restrict__ tp, bool diag, int il, int jl,
+                                      float v) {
+  if (!diag) {
+    tp[tile_pos(il, jl)] = v;
+  } else if (il < jl) {
+    tp[tile_pos(il, jl)] = v;
+    tp[tile_pos(jl, il)] = v;
+  } else if (il == jl) {
+    tp[tile_pos(il, il)] = v;
+  }
+}
+
+// Statistics (a, m, r) of one point for the PACK epilogue; ok = false for a
+// padding point (its pairs are stored as 0).
+struct PtStat {
+  float a, m, r;
+  bool ok;
+};
+
+template <bool PACK>
+__device__ __forceinline__ PtStat pt_stat(int64_t g, int64_t n, const float *__restrict__ a,
+                                          const float *__restrict__ m,
+                                          const float *__restrict__ r) {
+  PtStat p{0.f, 0.f, 0.f, false};
+  if (PACK && g < n) p = PtStat{a[g], m[g], r[g], true};
+  return p;
+}
+
+// The stored value of one element: the distance, or with PACK its p_ij (the
+// packed value k_pack would write: zero on the diagonal, for padding points
+// and below FP32's normal range).
+template <bool PACK>
+__device__ __forceinline__ float tile_value(float d, bool diag, int il, int jl, const PtStat &si,
+                                            const PtStat &sj) {
+  if (!PACK) return d;
+  if ((diag && il == jl) || !si.ok || !sj.ok) return 0.f;
+  const float v = pair_p(d, si.a, si.m, si.r, sj.a, sj.m, sj.r);
+  return v < FLT_MIN ? 0.f : v;
+}
+
+// Common start: header check (a workspace prepared for another n, d or mode
+// is flagged and left alone), zero-tile skip, tile coordinates. Returns false
+// if the workgroup has nothing to do.
+__device__ __forceinline__ bool tdist_begin(const Hdr *guard, int64_t gn, int32_t gkey,
+                                            const uint8_t *__restrict__ nz, bool skip,
+                                            int64_t tile, int32_t nb, int &I, int &J) {
+  if (!implicit_ready(guard, gn, gkey)) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+      flag_error(const_cast<Hdr *>(guard), kErrState);
+    return false;
+  }
+  if (skip && !nz[tile]) return false;
+  tile_coords(tile, nb, I, J);
+  return true;
+}
+
+// FP64 mode: a workgroup covers 64 rows x 128 columns of a tile (grid y: 4
+// row groups x 2 column groups), as k_dist_f64. a, m, r: the row statistics
+// (read with PACK only).
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_tdist_f64(const double *__restrict__ xcT,
+                                                   const double *__restrict__ norms, int64_t npad,
+                                                   int32_t dpad, int32_t nb, int64_t tile0,
+                                                   int64_t tile_base, float *__restrict__ Pb,
+                                                   const Hdr *guard, int64_t gn, int32_t gkey,
+                                                   const uint8_t *__restrict__ nz, bool skip,
+                                                   const float *__restrict__ ra,
+                                                   const float *__restrict__ rm,
+                                                   const float *__restrict__ rr) {
+  const int64_t tile = tile0 + blockIdx.x;
+  int I, J;
+  if (!tdist_begin(guard, gn, gkey, nz, skip, tile, nb, I, J)) return;
+  const int ry = blockIdx.y & 3, cx = blockIdx.y >> 2;
+  const bool diag = (I == J);
+  if (diag && 64 * ry >= 64 * kDistCT * (cx + 1)) return;  // wholly below the diagonal
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int cl0 = 64 * kDistCT * cx + w * (16 * kDistCT);  // first column in the tile
+  const int64_t col0 = (int64_t)J * T + cl0;
+  const int row0_loc = 64 * ry;
+  const int64_t row0 = (int64_t)I * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  v4d acc[4][kDistCT];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < kDistCT; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < dpad; k0 += 4) {
+    const double *xk = xcT + (int64_t)(k0 + lk) * npad;
+    double av[4], bv[kDistCT];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = xk[row0 + a * 16 + li];
+#pragma unroll
+    for (int c = 0; c < kDistCT; ++c) bv[c] = xk[col0 + c * 16 + li];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < kDistCT; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
+  }
+  float *tp = Pb + (size_t)(tile - tile_base) * T * T;
+  PtStat sc[kDistCT];
+#pragma unroll
+  for (int c = 0; c < kDistCT; ++c)
+    sc[c] = pt_stat<PACK>((int64_t)J * T + cl0 + c * 16 + li, gn, ra, rm, rr);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + a * 16 + lk + 4 * r;
+      const double ni = norms[(int64_t)I * T + il];
+      const PtStat si = pt_stat<PACK>((int64_t)I * T + il, gn, ra, rm, rr);
+      float v[kDistCT];
+#pragma unroll
+      for (int c = 0; c < kDistCT; ++c) {
+        const int jl = cl0 + c * 16 + li;
+        const double dd = ni + norms[(int64_t)J * T + jl] - 2.0 * acc[a][c][r];
+        v[c] = tile_value<PACK>((float)fmax(dd, 0.0), diag, il, jl, si, sc[c]);
+      }
+      // the lane's columns are consecutive elements (e, e + 1) of one float4
+      // slot of the tile layout: one 8-byte store off the diagonal
+      static_assert(kDistCT == 2, "two columns per lane");
+      if (!diag) {
+        *reinterpret_cast<float2 *>(tp + tile_pos(il, cl0 + li)) = make_float2(v[0], v[1]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < kDistCT; ++c) put_d(tp, true, il, cl0 + c * 16 + li, v[c]);
+      }
+    }
+  }
+}
+
+// FP32 mode: a workgroup covers 64 rows x 256 columns (grid y: 4 row groups),
+// as k_dist_f32.
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_tdist_f32(const float *__restrict__ xfT,
+                                                   const float *__restrict__ norms, int64_t npad,
+                                                   int32_t dpad, int32_t nb, int64_t tile0,
+                                                   int64_t tile_base, float *__restrict__ Pb,
+                                                   const Hdr *guard, int64_t gn, int32_t gkey,
+                                                   const uint8_t *__restrict__ nz, bool skip,
+                                                   const float *__restrict__ ra,
+                                                   const float *__restrict__ rm,
+                                                   const float *__restrict__ rr) {
+  const int64_t tile = tile0 + blockIdx.x;
+  int I, J;
+  if (!tdist_begin(guard, gn, gkey, nz, skip, tile, nb, I, J)) return;
+  const bool diag = (I == J);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int cl0 = w * 64;
+  const int64_t col0 = (int64_t)J * T + cl0;
+  const int row0_loc = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)I * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < dpad; k0 += 4) {
+    const float *xk = xfT + (int64_t)(k0 + lk) * npad;
+    float av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = xk[row0 + a * 16 + li];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bv[c] = xk[col0 + c * 16 + li];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[c], acc[a][c], 0, 0, 0);
+  }
+  float *tp = Pb + (size_t)(tile - tile_base) * T * T;
+  PtStat sc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    sc[c] = pt_stat<PACK>((int64_t)J * T + cl0 + c * 16 + li, gn, ra, rm, rr);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + a * 16 + 4 * lk + r;
+      const float ni = norms[(int64_t)I * T + il];
+      const PtStat si = pt_stat<PACK>((int64_t)I * T + il, gn, ra, rm, rr);
+      float v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int jl = cl0 + c * 16 + li;
+        const float dd = (ni + norms[(int64_t)J * T + jl]) - 2.f * acc[a][c][r];
+        v[c] = tile_value<PACK>(fmaxf(dd, 0.f), diag, il, jl, si, sc[c]);
+      }
+      // the lane's four columns are the four elements of one float4 slot of
+      // the tile layout: one 16-byte store off the diagonal
+      if (!diag) {
+        *reinterpret_cast<float4 *>(tp + tile_pos(il, cl0 + li)) =
+            make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) put_d(tp, true, il, cl0 + c * 16 + li, v[c]);
+      }
+    }
+  }
+}
+
+// 16-bit modes: as k_dist_lp, a workgroup covers 64 rows x 256 columns.
+template <typename H, typename V8, bool SCALE, bool PACK>
+__global__ __launch_bounds__(256) void k_tdist_lp(const H *__restrict__ xa,
+                                                  const H *__restrict__ xb,
+                                                  const float *__restrict__ norms, int32_t kk,
+                                                  int32_t nb, int64_t tile0, int64_t tile_base,
+                                                  float *__restrict__ Pb, const Hdr *guard,
+                                                  int64_t gn, int32_t gkey,
+                                                  const uint8_t *__restrict__ nz, bool skip,
+                                                  const float *__restrict__ ra,
+                                                  const float *__restrict__ rm,
+                                                  const float *__restrict__ rr) {
+  const int64_t tile = tile0 + blockIdx.x;
+  int I, J;
+  if (!tdist_begin(guard, gn, gkey, nz, skip, tile, nb, I, J)) return;
+  const bool diag = (I == J);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int cl0 = w * 64;
+  const int64_t col0 = (int64_t)J * T + cl0;
+  const int row0_loc = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)I * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  float inv_s2 = 1.f;
+  if (SCALE) {
+    const float s = fp16_scale(guard);
+    inv_s2 = 1.f / (s * s);
+  }
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < kk; k0 += 32) {
+    V8 av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      av[a] = *reinterpret_cast<const V8 *>(xa + (row0 + a * 16 + li) * kk + k0 + 8 * lk);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      bv[c] = *reinterpret_cast<const V8 *>(xb + (col0 + c * 16 + li) * kk + k0 + 8 * lk);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if constexpr (sizeof(H) == 2 && __is_same(H, __bf16))
+          acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[c], acc[a][c], 0, 0, 0);
+        else
+          acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv[c], acc[a][c], 0, 0, 0);
+      }
+  }
+  float *tp = Pb + (size_t)(tile - tile_base) * T * T;
+  PtStat sc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    sc[c] = pt_stat<PACK>((int64_t)J * T + cl0 + c * 16 + li, gn, ra, rm, rr);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + a * 16 + 4 * lk + r;
+      const float ni = norms[(int64_t)I * T + il];
+      const PtStat si = pt_stat<PACK>((int64_t)I * T + il, gn, ra, rm, rr);
+      float v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int jl = cl0 + c * 16 + li;
+        const float dd = (ni + norms[(int64_t)J * T + jl]) - 2.f * (acc[a][c][r] * inv_s2);
+        v[c] = tile_value<PACK>(fmaxf(dd, 0.f), diag, il, jl, si, sc[c]);
+      }
+      // the lane's four columns are the four elements of one float4 slot of
+      // the tile layout: one 16-byte store off the diagonal
+      if (!diag) {
+        *reinterpret_cast<float4 *>(tp + tile_pos(il, cl0 + li)) =
+            make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) put_d(tp, true, il, cl0 + c * 16 + li, v[c]);
+      }
     }
   }
 }
@@ -612,13 +896,8 @@ __device__ __forceinline__ void pack_tile(float4 *__restrict__ P, const float *_
     float pv[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-#pragma clang fp contract(off)
       const int mm = 4 * mq + e;
-      // no contraction into an FMA here (pragma above), so that the two
-      // orders of a pair in a diagonal tile give bitwise equal sums
-      float pi = __builtin_amdgcn_exp2f(-ar[k] * (dd[e] - mr[k])) * rr[k];
-      float pj = __builtin_amdgcn_exp2f(-ac[mm] * (dd[e] - mc[mm])) * rc[mm];
-      float p = pi + pj;
+      float p = pair_p(dd[e], ar[k], mr[k], rr[k], ac[mm], mc[mm], rc[mm]);
       if (diag && tr == tc && k == mm) p = 0.f;
       if (!((rvalid >> k) & (cvalid >> mm) & 1u)) p = 0.f;
       // values below the normal FP32 range are stored as 0 (they change no
@@ -1431,14 +1710,12 @@ __global__ __launch_bounds__(256) void k_pack_range(float4 *__restrict__ Pb,
                                                     uint8_t *__restrict__ nzflag,
                                                     int2 *__restrict__ tmap, int64_t tile0,
                                                     int64_t tile_base, const Hdr *guard,
-                                                    int32_t gkey, bool skip_zero) {
+                                                    int32_t gkey) {
   if (!implicit_ready(guard, n, gkey)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) flag_error(const_cast<Hdr *>(guard), kErrState);
     return;
   }
   const int64_t tile = tile0 + blockIdx.x;
-  // zero tiles known: theirs flag, sums (0) and coordinates stay as found
-  if (skip_zero && !nzflag[tile]) return;
   pack_tile(Pb, a, m, r, n, nb, ppart, nzflag, tmap, tile, tile - tile_base);
 }
 
@@ -1470,44 +1747,35 @@ __global__ void k_set_ready(Hdr *h, int32_t ready) {
 // Host-side sequencing
 // ----------------------------------------------------------------------------
 
-// Distances of row block b against columns col_base .. npad - 1 into the
-// block scratch, in the workspace's distance mode. xc, nrm: the centred X and
-// its norms for the FP64 mode (the reduced modes read their prepared
-// operands). guard: null in the affinity stage, the header in an implicit
-// pass (the kernels then check the mode key). nzskip: null, or the tile flags
-// whose zero tiles are skipped.
+// Distances of row block b against all columns into the block scratch, in
+// the workspace's distance mode. xc, nrm: the centred X and its norms for the
+// FP64 mode (the reduced modes read their prepared operands).
 static void launch_dist(const Layout &L, void *ws, int b, const double *xc, const double *nrm,
-                        int64_t col_base, const Hdr *guard, const uint8_t *nzskip,
                         hipStream_t st) {
   const Hdr *h = at<const Hdr>(ws, L.hdr);
-  const int32_t key = implicit_key(L.d, L.mode);
   float *dblock = at<float>(ws, L.dblock);
   const float *norms32 = at<const float>(ws, L.norms32);
-  const dim3 dgrid((unsigned)((L.npad - col_base) / 256), T / 64);
+  const dim3 dgrid((unsigned)(L.npad / 256), T / 64);
   switch (L.mode) {
     case TSNE_DIST_FP32:
       hipLaunchKernelGGL(k_dist_f32, dgrid, dim3(256), 0, st, at<const float>(ws, L.xfT), norms32,
-                         L.npad, L.dpad, b, col_base, dblock, guard, L.n, key, nzskip, L.nb);
+                         L.npad, L.dpad, b, dblock);
       break;
     case TSNE_DIST_BF16:
     case TSNE_DIST_BF16X3:
       hipLaunchKernelGGL((k_dist_lp<__bf16, v8bf, false>), dgrid, dim3(256), 0, st,
                          at<const __bf16>(ws, L.xa), at<const __bf16>(ws, L.xb), norms32, L.npad,
-                         L.kk, b, col_base, dblock, h, guard != nullptr, L.n, key, nzskip,
-                         L.nb);
+                         L.kk, b, dblock, h);
       break;
     case TSNE_DIST_FP16:
     case TSNE_DIST_FP16X3:
       hipLaunchKernelGGL((k_dist_lp<_Float16, v8h, true>), dgrid, dim3(256), 0, st,
                          at<const _Float16>(ws, L.xa), at<const _Float16>(ws, L.xb), norms32,
-                         L.npad, L.kk, b, col_base, dblock, h, guard != nullptr, L.n, key,
-                         nzskip, L.nb);
+                         L.npad, L.kk, b, dblock, h);
       break;
     default:
-      hipLaunchKernelGGL(k_dist_f64,
-                         dim3((unsigned)((L.npad - col_base) / (64 * kDistCT)), T / 64), dim3(256),
-                         0, st, xc, nrm, L.npad, L.dpad, b, col_base, dblock, guard, L.n, key,
-                         nzskip, L.nb);
+      hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64), dim3(256),
+                         0, st, xc, nrm, L.npad, L.dpad, b, dblock);
   }
 }
 
@@ -1572,7 +1840,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   };
   // Distances of row block b (into the block scratch), all columns.
   auto dist = [&](int b, const double *xc, const double *nrm) {
-    launch_dist(L, ws, b, xc, nrm, 0, nullptr, nullptr, st);
+    launch_dist(L, ws, b, xc, nrm, st);
   };
   auto calibrate = [&](int b) {
     const int rows = (int)((L.n - (int64_t)b * T) < T ? (L.n - (int64_t)b * T) : T);
@@ -1620,8 +1888,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
                          dis, L.n, L.npad, b, dblock, h);
       calibrate(b);
       hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
-                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0,
-                         (const uint8_t *)nullptr);
+                         L.nb, b, P);
     }
     pack();
     return hipGetLastError();
@@ -1687,8 +1954,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
     calibrate(b);
     if (!stats_only && !implicit)
       hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
-                         L.nb, b, P, (int64_t)0, (const Hdr *)nullptr, (int64_t)0, 0,
-                         (const uint8_t *)nullptr);
+                         L.nb, b, P);
   }
   if (implicit) {
     // every pass rebuilds P from the contraction operands in the internal
@@ -1710,26 +1976,62 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   return hipGetLastError();
 }
 
-hipError_t launch_implicit_block(const Layout &L, void *ws, int b, int64_t tile_base,
-                                 bool skip_zero, hipStream_t st) {
+template <bool PACK>
+static void launch_tdist(const Layout &L, void *ws, int64_t tile0, int64_t count,
+                         int64_t tile_base, bool skip_zero, hipStream_t st) {
   const Hdr *h = at<const Hdr>(ws, L.hdr);
-  const uint8_t *nzskip = skip_zero ? at<const uint8_t>(ws, L.nz) : nullptr;
-  // only the columns of the block row's own tiles (s >= b) are staged
-  launch_dist(L, ws, b, at<const double>(ws, L.xcT2), at<const double>(ws, L.norms2),
-              (int64_t)b * T, h, nzskip, st);
-  hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st,
-                     at<const float>(ws, L.dblock), L.npad, L.nb, b, at<float4>(ws, L.P),
-                     tile_base, h, L.n, implicit_key(L.d, L.mode), nzskip);
+  const int32_t key = implicit_key(L.d, L.mode);
+  const uint8_t *nz = at<const uint8_t>(ws, L.nz);
+  float *Pb = at<float>(ws, L.P);
+  const float *norms32 = at<const float>(ws, L.norms32);
+  const float *ra = at<const float>(ws, L.a), *rm = at<const float>(ws, L.m),
+              *rr = at<const float>(ws, L.r);
+  const dim3 g4((unsigned)count, T / 64);
+  switch (L.mode) {
+    case TSNE_DIST_FP32:
+      hipLaunchKernelGGL(k_tdist_f32<PACK>, g4, dim3(256), 0, st, at<const float>(ws, L.xfT),
+                         norms32, L.npad, L.dpad, L.nb, tile0, tile_base, Pb, h, L.n, key, nz,
+                         skip_zero, ra, rm, rr);
+      break;
+    case TSNE_DIST_BF16:
+    case TSNE_DIST_BF16X3:
+      hipLaunchKernelGGL((k_tdist_lp<__bf16, v8bf, false, PACK>), g4, dim3(256), 0, st,
+                         at<const __bf16>(ws, L.xa), at<const __bf16>(ws, L.xb), norms32, L.kk,
+                         L.nb, tile0, tile_base, Pb, h, L.n, key, nz, skip_zero, ra, rm, rr);
+      break;
+    case TSNE_DIST_FP16:
+    case TSNE_DIST_FP16X3:
+      hipLaunchKernelGGL((k_tdist_lp<_Float16, v8h, true, PACK>), g4, dim3(256), 0, st,
+                         at<const _Float16>(ws, L.xa), at<const _Float16>(ws, L.xb), norms32,
+                         L.kk, L.nb, tile0, tile_base, Pb, h, L.n, key, nz, skip_zero, ra, rm, rr);
+      break;
+    default:
+      hipLaunchKernelGGL(k_tdist_f64<PACK>,
+                         dim3((unsigned)count, (T / 64) * (T / (64 * kDistCT))), dim3(256), 0, st,
+                         at<const double>(ws, L.xcT2), at<const double>(ws, L.norms2), L.npad,
+                         L.dpad, L.nb, tile0, tile_base, Pb, h, L.n, key, nz, skip_zero, ra, rm,
+                         rr);
+  }
+}
+
+hipError_t launch_implicit_tiles(const Layout &L, void *ws, int64_t tile0, int64_t count,
+                                 int64_t tile_base, bool skip_zero, bool pack, hipStream_t st) {
+  if (pack)
+    launch_tdist<true>(L, ws, tile0, count, tile_base, skip_zero, st);
+  else
+    launch_tdist<false>(L, ws, tile0, count, tile_base, skip_zero, st);
   return hipGetLastError();
 }
 
-hipError_t launch_implicit_pack(const Layout &L, void *ws, int64_t tile0, int64_t count,
-                                int64_t tile_base, bool skip_zero, hipStream_t st) {
+// Pack (Eq. 3) the tiles tile0 .. tile0 + count - 1 of the buffer, with their
+// sums, flags and coordinates.
+static hipError_t launch_implicit_pack(const Layout &L, void *ws, int64_t tile0, int64_t count,
+                                       int64_t tile_base, hipStream_t st) {
   hipLaunchKernelGGL(k_pack_range, dim3((unsigned)count), dim3(256), 0, st, at<float4>(ws, L.P),
                      at<const float>(ws, L.a), at<const float>(ws, L.m), at<const float>(ws, L.r),
                      L.n, L.nb, at<double2>(ws, L.ppart), at<uint8_t>(ws, L.nz),
                      at<int2>(ws, L.tmap), tile0, tile_base, at<const Hdr>(ws, L.hdr),
-                     implicit_key(L.d, L.mode), skip_zero);
+                     implicit_key(L.d, L.mode));
   return hipGetLastError();
 }
 
@@ -1744,11 +2046,9 @@ hipError_t launch_implicit_discover(const Layout &L, void *ws, hipStream_t st) {
     int b1 = b0 + 1;
     while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
     const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
-    for (int b = b0; b < b1; ++b) {
-      hipError_t e = launch_implicit_block(L, ws, b, base, false, st);
-      if (e != hipSuccess) return e;
-    }
-    hipError_t e = launch_implicit_pack(L, ws, base, count, base, false, st);
+    hipError_t e = launch_implicit_tiles(L, ws, base, count, base, false, false, st);
+    if (e != hipSuccess) return e;
+    e = launch_implicit_pack(L, ws, base, count, base, st);
     if (e != hipSuccess) return e;
     b0 = b1;
   }

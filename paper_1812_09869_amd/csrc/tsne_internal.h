@@ -181,13 +181,13 @@ inline int64_t implicit_capacity(const Layout &L) {
   return c < L.nt ? c : L.nt;
 }
 // Block rows [b0, b1) fill the buffer: tile t of them sits at slot
-// t - tile_start(b0). skip_zero: the zero tiles are known (every pass after
-// the affinity stage) and are neither computed nor staged.
-hipError_t launch_implicit_block(const Layout &L, void *ws, int b, int64_t tile_base,
-                                 bool skip_zero, hipStream_t stream);
-// Pack (Eq. 3) the staged tiles tile0 .. tile0 + count - 1 of the buffer.
-hipError_t launch_implicit_pack(const Layout &L, void *ws, int64_t tile0, int64_t count,
-                                int64_t tile_base, bool skip_zero, hipStream_t stream);
+// t - tile_start(b0). The distances of the tiles tile0 .. tile0 + count - 1,
+// written into the buffer in the staged layout, or with pack their packed
+// P (Eq. 3, the values launch_implicit_pack would leave). skip_zero: the zero
+// tiles are known (every pass after the affinity stage) and are left alone.
+hipError_t launch_implicit_tiles(const Layout &L, void *ws, int64_t tile0, int64_t count,
+                                 int64_t tile_base, bool skip_zero, bool pack,
+                                 hipStream_t stream);
 // The affinity stage's pass over every tile: zero flags, tile coordinates,
 // the sums of P, slot and tile lists.
 hipError_t launch_implicit_discover(const Layout &L, void *ws, hipStream_t stream);

@@ -1169,12 +1169,9 @@ hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipS
     int b1 = b0 + 1;
     while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
     const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
-    for (int b = b0; b < b1; ++b) {
-      hipError_t e = launch_implicit_block(L, ws, b, base, true, st);
-      if (e != hipSuccess) return e;
-    }
     {
-      hipError_t e = launch_implicit_pack(L, ws, base, count, base, true, st);
+      // the nonzero tiles' P, packed as the distances are formed
+      hipError_t e = launch_implicit_tiles(L, ws, base, count, base, true, true, st);
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_force_range, dim3((unsigned)count), dim3(256), 0, st,
@@ -1197,12 +1194,9 @@ hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, doubl
     int b1 = b0 + 1;
     while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
     const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
-    for (int b = b0; b < b1; ++b) {
-      hipError_t e = launch_implicit_block(L, ws, b, base, true, st);
-      if (e != hipSuccess) return e;
-    }
     {
-      hipError_t e = launch_implicit_pack(L, ws, base, count, base, true, st);
+      // the nonzero tiles' P, packed as the distances are formed
+      hipError_t e = launch_implicit_tiles(L, ws, base, count, base, true, true, st);
       if (e != hipSuccess) return e;
     }
     // every tile: the all-zero ones add to Z without reading P
