@@ -21,7 +21,10 @@ from paper_1812_09869_amd.tsne import ExactTSNE
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(255, 3, 10.0, "gauss"), (600, 50, 30.0, "aniso"), (1300, 10, 30.0, "small")]
+# n = 3: one tile, nearly all padding; n = 257: two block rows, the second
+# holding one point (a ragged tail in both the row and the column direction)
+CASES = [(3, 2, 1.5, "gauss"), (255, 3, 10.0, "gauss"), (257, 5, 20.0, "gauss"),
+         (600, 50, 30.0, "aniso"), (1300, 10, 30.0, "small")]
 
 
 def _data(n, d, gen, seed):
