@@ -123,6 +123,9 @@ __global__ __launch_bounds__(256) void k_centre(const float *__restrict__ x, int
 // per SIMD); a workgroup of 4 waves covers 64 rows x 64 kDistCT columns.
 // ----------------------------------------------------------------------------
 constexpr int kDistCT = 2;  // 16-column MFMA tiles per wave (a wave covers 64 x 16 kDistCT)
+// the implicit tile kernel's width: two 16-column tiles per wave, so that a
+// lane's two columns are neighbours in the tile layout
+constexpr int kTileCT = 2;
 
 __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
                                                   const double *__restrict__ norms, int64_t npad,
@@ -638,35 +641,35 @@ __global__ __launch_bounds__(256) void k_tdist_f64(const double *__restrict__ xc
   if (!tdist_begin(guard, gn, gkey, nz, skip, tile, nb, I, J)) return;
   const int ry = blockIdx.y & 3, cx = blockIdx.y >> 2;
   const bool diag = (I == J);
-  if (diag && 64 * ry >= 64 * kDistCT * (cx + 1)) return;  // wholly below the diagonal
+  if (diag && 64 * ry >= 64 * kTileCT * (cx + 1)) return;  // wholly below the diagonal
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int cl0 = 64 * kDistCT * cx + w * (16 * kDistCT);  // first column in the tile
+  const int cl0 = 64 * kTileCT * cx + w * (16 * kTileCT);  // first column in the tile
   const int64_t col0 = (int64_t)J * T + cl0;
   const int row0_loc = 64 * ry;
   const int64_t row0 = (int64_t)I * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
-  v4d acc[4][kDistCT];
+  v4d acc[4][kTileCT];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < kDistCT; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < kTileCT; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < dpad; k0 += 4) {
     const double *xk = xcT + (int64_t)(k0 + lk) * npad;
-    double av[4], bv[kDistCT];
+    double av[4], bv[kTileCT];
 #pragma unroll
     for (int a = 0; a < 4; ++a) av[a] = xk[row0 + a * 16 + li];
 #pragma unroll
-    for (int c = 0; c < kDistCT; ++c) bv[c] = xk[col0 + c * 16 + li];
+    for (int c = 0; c < kTileCT; ++c) bv[c] = xk[col0 + c * 16 + li];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int c = 0; c < kDistCT; ++c)
+      for (int c = 0; c < kTileCT; ++c)
         acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
   }
   float *tp = Pb + (size_t)(tile - tile_base) * T * T;
-  PtStat sc[kDistCT];
+  PtStat sc[kTileCT];
 #pragma unroll
-  for (int c = 0; c < kDistCT; ++c)
+  for (int c = 0; c < kTileCT; ++c)
     sc[c] = pt_stat<PACK>((int64_t)J * T + cl0 + c * 16 + li, gn, ra, rm, rr);
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -675,21 +678,21 @@ __global__ __launch_bounds__(256) void k_tdist_f64(const double *__restrict__ xc
       const int il = row0_loc + a * 16 + lk + 4 * r;
       const double ni = norms[(int64_t)I * T + il];
       const PtStat si = pt_stat<PACK>((int64_t)I * T + il, gn, ra, rm, rr);
-      float v[kDistCT];
+      float v[kTileCT];
 #pragma unroll
-      for (int c = 0; c < kDistCT; ++c) {
+      for (int c = 0; c < kTileCT; ++c) {
         const int jl = cl0 + c * 16 + li;
         const double dd = ni + norms[(int64_t)J * T + jl] - 2.0 * acc[a][c][r];
         v[c] = tile_value<PACK>((float)fmax(dd, 0.0), diag, il, jl, si, sc[c]);
       }
       // the lane's columns are consecutive elements (e, e + 1) of one float4
       // slot of the tile layout: one 8-byte store off the diagonal
-      static_assert(kDistCT == 2, "two columns per lane");
+      static_assert(kTileCT == 2, "two columns per lane");
       if (!diag) {
         *reinterpret_cast<float2 *>(tp + tile_pos(il, cl0 + li)) = make_float2(v[0], v[1]);
       } else {
 #pragma unroll
-        for (int c = 0; c < kDistCT; ++c) put_d(tp, true, il, cl0 + c * 16 + li, v[c]);
+        for (int c = 0; c < kTileCT; ++c) put_d(tp, true, il, cl0 + c * 16 + li, v[c]);
       }
     }
   }
@@ -2007,7 +2010,7 @@ static void launch_tdist(const Layout &L, void *ws, int64_t tile0, int64_t count
       break;
     default:
       hipLaunchKernelGGL(k_tdist_f64<PACK>,
-                         dim3((unsigned)count, (T / 64) * (T / (64 * kDistCT))), dim3(256), 0, st,
+                         dim3((unsigned)count, (T / 64) * (T / (64 * kTileCT))), dim3(256), 0, st,
                          at<const double>(ws, L.xcT2), at<const double>(ws, L.norms2), L.npad,
                          L.dpad, L.nb, tile0, tile_base, Pb, h, L.n, key, nz, skip_zero, ra, rm,
                          rr);
