@@ -616,9 +616,21 @@ def main():
                     help="timed epochs of the parallel-scheme leg")
     ap.add_argument("--precision-report", action="store_true",
                     help="only run the per-mode error report at N=262,144, D=128")
+    ap.add_argument("--implicit-large", action="store_true",
+                    help="only run the implicit-P leg at N=262,144, D=128 (the 10-D subspace "
+                         "mixture), where a stored P would take 142 GB")
     args = ap.parse_args()
     if args.precision_report:
         precision_report()
+        return
+    if args.implicit_large:
+        import torch
+
+        from paper_1812_09869_amd import synth
+        xl, _ = synth.subspace(262144, d=128)
+        res = implicit_leg(torch.from_numpy(xl).cuda(), 50.0, iters=5, modes=("fp64", "bf16"))
+        res["workload"] = "10-D subspace mixture, N=262144, D=128, perplexity 50"
+        print(json.dumps(res), flush=True)
         return
     if args.ptsne_only:
         print(json.dumps(ptsne_leg(args.ptsne_epochs)), flush=True)
