@@ -186,12 +186,14 @@ TSNE_API int tsne_cost(void *ws, int64_t n, const float *y, double *out, void *s
  * takes 2 n^2 bytes), tsne_affinities with implicit_p = 1 keeps only the row
  * statistics, the contraction operands in the internal order (the centred
  * input in FP64, or the FP32 / 16-bit operands of a reduced distance mode)
- * and a buffer of tiles; every force pass and cost evaluation then recomputes
- * P block row by block row (each block row's distances against the columns
- * of its own tiles on MFMA, in the workspace's distance mode; Eq. 1 with the
- * stored beta, m and S; Eq. 3) and consumes it at once. The values of P are
- * bitwise those of the stored path in the same mode; a pass does about
- * N^2 D / 2 more multiply-adds of the mode's contraction.
+ * and a buffer of tiles. The affinity stage ends with one pass over every
+ * tile that finds the all-zero tiles of P; every force pass and cost
+ * evaluation then recomputes the nonzero tiles buffer by buffer (their
+ * distances on MFMA in the workspace's distance mode, Eq. 1 with the stored
+ * beta, m and S, Eq. 3) and consumes them at once, and gives the zero tiles
+ * the repulsion-only body. P, gradients, costs and maps are bitwise those of
+ * the stored path in the same mode; a pass does up to N^2 D / 2 more
+ * multiply-adds of the mode's contraction (fewer by the zero tiles' share).
  * The stored-P entry points (tsne_step, tsne_forces, tsne_gradient,
  * tsne_cost, tsne_export_p_rows, the batched launch) reject such a workspace
  * on the device (TSNE_E_STATE), and these reject a stored-P workspace.

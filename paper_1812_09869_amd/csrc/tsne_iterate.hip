@@ -1149,9 +1149,9 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
 
 // Implicit P: the all-zero tiles (known since the affinity stage) in one
 // repulsion-only launch, as in the stored path; then per buffer of block
-// rows, the nonzero tiles' P recomputed (the affinity kernels, zero tiles
-// skipped) and the full tile body on them. The slot lists and the sums of P
-// are those of the affinity stage.
+// rows, the nonzero tiles' packed P recomputed by one tile-distance launch
+// (zero tiles skipped) and the full tile body on them. The slot lists and
+// the sums of P are those of the affinity stage.
 hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   float2 *yp = at<float2>(ws, L.yp);
