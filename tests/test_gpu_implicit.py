@@ -179,3 +179,29 @@ def test_benchmark_size_matches_stored(mode):
     print(f"  map after 10 steps rel vs stored {rel:.2e}", flush=True)
     assert all(torch.equal(a, b) for a, b in zip(si, ss))
     assert imp.status() == 0 and sto.status() == 0
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16"])
+def test_no_reorder_matches_stored(mode):
+    """Implicit P without the locality order (the caller's order is the
+    internal one; the FP64 operands are the identity copy of the centred X),
+    over three block rows: bitwise the stored path of the same mode."""
+    n = 600
+    x, lab = synth.gmm_aniso(n, sample_seed=91)
+    print(f"\n[implicit] no reorder, mode={mode}, n={n}", flush=True)
+    xt = torch.from_numpy(x).cuda()
+    imp = ExactTSNE(xt, 30.0, dist_mode=mode, implicit=True, reorder=False)
+    sto = ExactTSNE(xt, 30.0, dist_mode=mode, reorder=False)
+    for a, b in zip(imp.rowstats(), sto.rowstats()):
+        assert torch.equal(a, b)
+    yt = torch.from_numpy(synth.clustered_state(lab, seed=9)).cuda()
+    gi, zi = imp.gradient(yt, 1.0)
+    gi, zi = gi.clone(), float(zi.cpu()[0])
+    gs, zs = sto.gradient(yt, 1.0)
+    assert torch.equal(gi, gs) and zi == float(zs.cpu()[0])
+    y0 = torch.from_numpy(synth.embedding_init(n, seed=12)).cuda()
+    si, ss = imp.init_state(y0), sto.init_state(y0)
+    imp.run(si, 3)
+    sto.run(ss, 3)
+    assert all(torch.equal(a, b) for a, b in zip(si, ss))
+    assert imp.status() == 0 and sto.status() == 0
