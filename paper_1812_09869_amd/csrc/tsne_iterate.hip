@@ -1148,10 +1148,11 @@ hipError_t launch_force(const Layout &L, void *ws, const float *y, hipStream_t s
 }
 
 // Implicit P: the all-zero tiles (known since the affinity stage) in one
-// repulsion-only launch, as in the stored path; then per buffer of block
-// rows, the nonzero tiles' packed P recomputed by one tile-distance launch
-// (zero tiles skipped) and the full tile body on them. The slot lists and
-// the sums of P are those of the affinity stage.
+// repulsion-only launch on the side stream, as in the stored path; beside it,
+// per buffer of block rows, the nonzero tiles' packed P recomputed by one
+// tile-distance launch (zero tiles skipped) and the full tile body on them.
+// The two write disjoint partial-sum slots. The slot lists and the sums of P
+// are those of the affinity stage.
 hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipStream_t st) {
   Hdr *h = at<Hdr>(ws, L.hdr);
   float2 *yp = at<float2>(ws, L.yp);
@@ -1160,26 +1161,33 @@ hipError_t launch_force_implicit(const Layout &L, void *ws, const float *y, hipS
   float4 *part = at<float4>(ws, L.part);
   float *zp = at<float>(ws, L.zpart);
   const int2 *tm = at<const int2>(ws, L.tmap);
-  hipLaunchKernelGGL(k_force_zero, dim3((unsigned)L.nt), dim3(256), 0, st, (const float2 *)yp,
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStream *ss = nullptr;
+  hipError_t e = side_stream(ss);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(ss->fork, st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_force_zero, dim3((unsigned)L.nt), dim3(256), 0, ss->s, (const float2 *)yp,
                      L.n, L.nb, part, zp, at<const int32_t>(ws, L.tlist),
                      at<const int32_t>(ws, L.tcount), tm, h, 2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
   const int64_t cap = implicit_capacity(L);
   for (int b0 = 0; b0 < L.nb;) {
     // the block rows whose tiles fill the buffer (at least one)
     int b1 = b0 + 1;
     while (b1 < L.nb && tile_start(b1 + 1, L.nb) - tile_start(b0, L.nb) <= cap) ++b1;
     const int64_t base = tile_start(b0, L.nb), count = tile_start(b1, L.nb) - base;
-    {
-      // the nonzero tiles' P, packed as the distances are formed
-      hipError_t e = launch_implicit_tiles(L, ws, base, count, base, true, true, st);
-      if (e != hipSuccess) return e;
-    }
+    // the nonzero tiles' P, packed as the distances are formed
+    if ((e = launch_implicit_tiles(L, ws, base, count, base, true, true, st)) != hipSuccess)
+      return e;
     hipLaunchKernelGGL(k_force_range, dim3((unsigned)count), dim3(256), 0, st,
                        at<const float4>(ws, L.P), (const float2 *)yp, L.n, L.nb, part, zp, tm,
                        at<const uint8_t>(ws, L.nz), base, implicit_key(L.d, L.mode), h);
     b0 = b1;
   }
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipStreamWaitEvent(st, ss->join, 0);
 }
 
 hipError_t launch_cost_implicit(const Layout &L, void *ws, const float *y, double *out,
