@@ -70,7 +70,7 @@ def test_gradient_parity(B):
 
 @pytest.mark.parametrize("hidden", [256, 128])
 def test_forward_parity(hidden):
-    """n = 1000 rows (31 full 32-row wave tiles and a ragged one) through the fused inference
+    """n = 1000 rows (15 full 64-row tiles and a ragged one of 40) through the fused inference
     kernel, against the oracle with the GPU's BF16 rounding."""
     n = 1000
     rng = np.random.Generator(np.random.PCG64(5))
@@ -85,6 +85,31 @@ def test_forward_parity(hidden):
     rel = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
     print(f"\n  H={hidden} forward rel-L2 vs bf16-emulating oracle {rel:.2e}")
     assert rel <= 1e-4
+
+
+def test_forward_parity_full_size():
+    """The benchmark's inference workload, 1,048,576 new points of the mixture (plus 37 more,
+    so that the last 64-row tile is ragged), in the launch the benchmark times (one persistent
+    workgroup per compute unit, 64 tiles each): 2,000 sampled rows and the whole ragged tail
+    against the oracle with the GPU's BF16 rounding, row by row."""
+    n = (1 << 20) + 37
+    rng = np.random.Generator(np.random.PCG64(7))
+    p = (rng.standard_normal(oracle.mlp_param_count(D, H)) * 0.08).astype(np.float32)
+    x, _ = synth.gmm_aniso(n, sample_seed=synth.SEEDS["surrogate_new"])
+    mean = x[:65536].mean(axis=0).astype(np.float32)
+    invstd = (1.0 / x[:65536].std(axis=0)).astype(np.float32)
+    ws = _lib.mlp_new_workspace(D, H, 256, False)
+    out = torch.empty((n, 2), device="cuda")
+    print(f"\n  full-size forward, n={n}", flush=True)
+    _lib.mlp_forward(_t(p), D, H, _t(mean), _t(invstd), _t(x), out, ws)
+    rows = np.concatenate([rng.choice(n - 37, 2000, replace=False), np.arange(n - 37, n)])
+    ref = oracle.mlp_forward(p, x[rows], mean, invstd, H, emulate=True)
+    got = out.cpu().numpy()[rows]
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    worst = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"  sampled rows rel-L2 {rel:.2e}, max abs / max |ref| {worst:.2e}")
+    assert rel <= 1e-4 and worst <= 1e-3
+    assert np.all(np.isfinite(out.cpu().numpy()))
 
 
 def test_adam_parity():
