@@ -2,7 +2,8 @@
 
 * Every problem's state after batched steps is bitwise equal to running
   tsne_step on it alone (same kernels, same reduction order), so the batched
-  path inherits the single-problem parity with the oracle.
+  path inherits the single-problem parity with the oracle; checked on small
+  problems and on sampled problems of the full 64-problem workload.
 * On the four smallest problems of the 64-problem workload: the gradient at
   oracle states of iterations 0, 249 and 499 (oracle FP64 trajectories cast to
   FP32) matches the oracle to 1e-4, and the batched 500-iteration run ends
@@ -47,6 +48,32 @@ def test_batched_bitwise_equals_single(rule):
     _lib.batch_cost(batched._arr, batched._bws, out)
     for k, m in enumerate(batched.models):
         assert torch.equal(out[k], m.cost(batched.states[k][0])), k
+
+
+def test_full_workload_bitwise_on_sampled_problems():
+    """The benchmark's 64-problem workload (636,092 points) in the launch the benchmark
+    times: after six batched sweeps of the benchmark schedule (the exaggeration phase),
+    the smallest and the largest problem and two others are bitwise the state of a
+    separate single-problem run, and every problem's status is clean."""
+    data = [synth.batch_problem(p) for p in range(64)]
+    print(f"\n[batched] 64 problems, {sum(x.shape[0] for x, _, _ in data)} points", flush=True)
+    y0s = [synth.embedding_init(x.shape[0], seed=4100 + p) for p, (x, _, _) in enumerate(data)]
+    batched = BatchedTSNE([(_t(x), perp) for x, _, perp in data])
+    batched.init_states([_t(y) for y in y0s])
+    batched.run(6)
+    assert max(m.status() for m in batched.models) == 0
+    sizes = [x.shape[0] for x, _, _ in data]
+    chosen = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 42})
+    for k in chosen:
+        x, _, perp = data[k]
+        single = ExactTSNE(_t(x), perp)
+        st = single.init_state(_t(y0s[k]))
+        single.run(st, 6)
+        for a, b in zip(batched.states[k], st):
+            assert torch.equal(a, b), k
+        print(f"  problem {k} (n={sizes[k]}): bitwise equal", flush=True)
+        del single, st
+        torch.cuda.empty_cache()
 
 
 def test_batched_matches_oracle_on_smallest_problems():
