@@ -64,3 +64,41 @@ def test_raster_argument_errors():
     out = torch.empty((4, 4), device="cuda")
     with pytest.raises(_lib.TsneError):
         _lib.kde_raster(y, beta, 0.0, 0.0, -1.0, 1.0, 4, 4, out)
+
+
+def test_benchmark_configuration():
+    """The benchmark's paKDE workload: a clustered 65,536-point map, perplexity 100, a
+    512 x 512 raster over the map box plus 5% margins. Bandwidths of 64 sampled points
+    against the oracle's search (relative <= 1e-4); 256 sampled cells (corners included)
+    against the oracle's estimator given the GPU's bandwidths (relative <= 1e-5 of the
+    raster's maximum); the mass within 1e-3 of 1."""
+    import oracle
+    n, perp, grid = 65536, 100.0, 512
+    lab = np.random.Generator(np.random.PCG64(65)).integers(0, 32, n)
+    y = synth.clustered_state(lab, seed=66, spread=30.0)
+    lo = y.min(axis=0).astype(np.float64)
+    hi = y.max(axis=0).astype(np.float64)
+    pad = 0.05 * (hi - lo)
+    lo, hi = lo - pad, hi + pad
+    cx, cy = (hi[0] - lo[0]) / grid, (hi[1] - lo[1]) / grid
+    print(f"\n[pakde] benchmark configuration n={n} raster {grid}x{grid}", flush=True)
+    yt = torch.from_numpy(y).cuda()
+    beta, f = pakde(yt, perp, lo[0], lo[1], cx, cy, grid, grid)
+    beta = beta.cpu().numpy()
+    f = f.cpu().numpy().astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(67))
+    rows = rng.choice(n, 64, replace=False)
+    ref = oracle.calibrate(y.astype(np.float64), perp, rows=rows).beta
+    rb = np.abs(beta[rows] - ref) / ref
+    print(f"  beta (64 sampled points) max-rel {rb.max():.2e}", flush=True)
+    assert rb.max() <= 1e-4
+    cells = np.concatenate([np.stack([rng.integers(0, grid, 252), rng.integers(0, grid, 252)], 1),
+                            [[0, 0], [grid - 1, grid - 1], [0, grid - 1], [grid - 1, 0]]])
+    # the densest cell too, where the estimator's sums are largest
+    cells = np.concatenate([cells, [np.unravel_index(np.argmax(f), f.shape)]])
+    fr = opk.raster_at(y.astype(np.float64), beta, lo[0], lo[1], cx, cy, cells)
+    got = f[cells[:, 0], cells[:, 1]]
+    err = np.abs(got - fr).max() / f.max()
+    print(f"  raster (257 sampled cells) max |df| / max f {err:.2e}; mass {f.sum():.6f}", flush=True)
+    assert err <= 1e-5
+    assert abs(f.sum() - 1.0) <= 1e-3

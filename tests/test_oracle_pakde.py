@@ -72,3 +72,16 @@ def test_mirrored_map_mirrors_the_raster():
     f = pakde.raster(y, beta, -20.0, -20.0, 0.8, 0.8, 50, 50)
     g = pakde.raster(y * [-1.0, 1.0], beta, -20.0, -20.0, 0.8, 0.8, 50, 50)
     np.testing.assert_allclose(g, f[:, ::-1], rtol=1e-10, atol=1e-18)
+
+
+def test_spot_cells_equal_the_raster():
+    """raster_at (spot checks on rasters too large to form) gives the raster's values at
+    the chosen cells, corners and ragged last row and column included."""
+    y = _map(70, 11)
+    beta = pakde.bandwidths(y, 9.0)
+    f = pakde.raster(y, beta, -18.0, -21.0, 0.7, 0.6, 53, 47)
+    rng = np.random.Generator(np.random.PCG64(4))
+    cells = np.concatenate([np.stack([rng.integers(0, 47, 40), rng.integers(0, 53, 40)], 1),
+                            [[0, 0], [46, 52], [0, 52], [46, 0]]])
+    got = pakde.raster_at(y, beta, -18.0, -21.0, 0.7, 0.6, cells)
+    np.testing.assert_allclose(got, f[cells[:, 0], cells[:, 1]], rtol=1e-12, atol=1e-300)
