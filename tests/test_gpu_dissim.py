@@ -59,3 +59,34 @@ def test_negative_dissimilarity_is_flagged():
     dis[3, 7] = -1.0
     model = ExactTSNE.from_dissimilarities(torch.from_numpy(dis).cuda(), 5.0)
     assert model.status() == 5  # TSNE_E_NONFINITE
+
+
+def test_benchmark_size_euclidean():
+    """The benchmark's dissimilarity leg: Euclidean distances of the first 16,384 points
+    of the benchmark mixture (D = 50) given as a 1 GiB FP32 matrix. The bandwidths of 64
+    sampled points against the oracle's search on the points (relative <= 1e-5), and
+    eight sampled rows of P against the path from the points (max |dP| / max P <= 1e-5)."""
+    n = 16384
+    x, _ = synth.gmm_aniso(n)
+    xt = torch.from_numpy(x).cuda()
+    dis = torch.cdist(xt.double(), xt.double()).float().contiguous()  # FP64, then rounded
+    print(f"\n[dissim] n={n}, matrix {dis.numel() * 4 / 2**30:.2f} GiB", flush=True)
+    m_d = ExactTSNE.from_dissimilarities(dis, 50.0)
+    del dis
+    torch.cuda.empty_cache()
+    m_x = ExactTSNE(xt, 50.0)
+    rng = np.random.Generator(np.random.PCG64(16))
+    rows = rng.choice(n, 64, replace=False)
+    ref = oracle.calibrate(x.astype(np.float64), 50.0, rows=rows).beta
+    beta = m_d.rowstats()[0].cpu().numpy()[rows]
+    rb = np.abs(beta - ref) / ref
+    print(f"  beta (64 sampled points) max-rel {rb.max():.2e}", flush=True)
+    assert rb.max() <= 1e-5
+    worst = 0.0
+    for r in rng.choice(n - 1, 8, replace=False):
+        pd = m_d.p_rows(int(r), 1).cpu().numpy()
+        px = m_x.p_rows(int(r), 1).cpu().numpy()
+        worst = max(worst, float(np.abs(pd - px).max() / px.max()))
+    print(f"  P rows (8 sampled) max |dP| / max P {worst:.2e}", flush=True)
+    assert worst <= 1e-5
+    assert m_d.status() == 0 and m_x.status() == 0
