@@ -42,9 +42,6 @@ def _load():
     lib = ctypes.CDLL(path)
     sig = {
         "orc_sqdist": (None, [_f64p, _i64, _i32, _f64p]),
-        "orc_calibrate_drow": (ctypes.c_int, [_f64p, _i64, _i64, _d, ctypes.c_int, _d,
-                                              ctypes.POINTER(_d), ctypes.POINTER(_d),
-                                              ctypes.POINTER(_d), ctypes.POINTER(_d)]),
         "orc_calibrate": (None, [_f64p, _i64, _i32, _d, ctypes.c_void_p, _i64, ctypes.c_int, _d,
                                  _f64p, _f64p, _f64p, _f64p, _i32p]),
         "orc_joint_p": (None, [_f64p, _i64, _i32, _f64p, _f64p, _f64p, _f64p]),
@@ -53,7 +50,10 @@ def _load():
         "orc_joint_p_dissim": (None, [_f64p, _i64, _f64p, _f64p, _f64p, _f64p]),
         "orc_p_entries": (None, [_f64p, _i64, _i32, _i64p, _i64p, _i64, _f64p, _f64p, _f64p,
                                  _f64p, _f64p, _f64p, _f64p]),
+        "orc_p_rows": (None, [_f64p, _i64, _i32, _i64p, _i64, _f64p, _f64p, _f64p, _f64p]),
         "orc_p_entropy_term": (_d, [_f64p, _i64]),
+        "orc_gradient_rows": (None, [_f64p, _i64, _f64p, _i64p, _i64, _d, _d, _f64p]),
+        "orc_kl_rows": (None, [_f64p, _i64, _f64p, _i64p, _i64, _d, _f64p]),
         "orc_z": (_d, [_f64p, _i64]),
         "orc_gradient": (None, [_f64p, _i64, _f64p, _d, _f64p, ctypes.POINTER(_d)]),
         "orc_repulsion_rows": (None, [_f64p, _i64, _i64p, _i64, _d, _f64p]),
@@ -128,17 +128,6 @@ def calibrate(x, perplexity: float, rows=None, max_iter: int = DEFAULT_MAX_ITER,
     return RowStats(beta, m, S, H, iters)
 
 
-def calibrate_drow(drow, i: int, perplexity: float, max_iter: int = DEFAULT_MAX_ITER,
-                   tol: float = DEFAULT_TOL):
-    """Calibrate one row from a given distance row (drow[i] is ignored)."""
-    drow = _f64(drow)
-    b, m, S, H = _d(), _d(), _d(), _d()
-    it = _load().orc_calibrate_drow(drow, drow.shape[0], int(i), float(perplexity),
-                                    int(max_iter), float(tol), ctypes.byref(b), ctypes.byref(m),
-                                    ctypes.byref(S), ctypes.byref(H))
-    return b.value, m.value, S.value, H.value, it
-
-
 # --------------------------------------------------------------------------
 # Joint P (Eq. 3)
 # --------------------------------------------------------------------------
@@ -186,6 +175,17 @@ def p_entries(x, ii, jj, st_i: RowStats, st_j: RowStats) -> np.ndarray:
     return out
 
 
+def p_rows(x, rows, st: RowStats) -> np.ndarray:
+    """Rows of P (Eq. 3) for the listed points, from the statistics of every
+    row (``st`` indexed by point); (len(rows), n)."""
+    x = _f64(x)
+    n, d = x.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((rows.shape[0], n))
+    _load().orc_p_rows(x, n, d, rows, rows.shape[0], _f64(st.beta), _f64(st.m), _f64(st.S), out)
+    return out
+
+
 def p_entropy_term(P) -> float:
     """sum_{p > 0} p ln p over i != j (the constant part of Eq. 5)."""
     P = _f64(P)
@@ -217,6 +217,25 @@ def repulsion_rows(y, rows, Z: float) -> np.ndarray:
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     out = np.empty((rows.shape[0], 2))
     _load().orc_repulsion_rows(y, y.shape[0], rows, rows.shape[0], float(Z), out)
+    return out
+
+
+def gradient_rows(prows, y, rows, alpha: float, Z: float) -> np.ndarray:
+    """Eq. 6 for the listed rows from their rows of P and the global Z."""
+    prows, y = _f64(prows), _f64(y)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((rows.shape[0], 2))
+    _load().orc_gradient_rows(prows, y.shape[0], y, rows, rows.shape[0], float(alpha), float(Z),
+                              out)
+    return out
+
+
+def kl_rows(prows, y, rows, Z: float) -> np.ndarray:
+    """Per-row shares sum_j p_ij ln(p_ij / q_ij) of the KL (Eq. 5) for the listed rows."""
+    prows, y = _f64(prows), _f64(y)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty(rows.shape[0])
+    _load().orc_kl_rows(prows, y.shape[0], y, rows, rows.shape[0], float(Z), out)
     return out
 
 

@@ -139,13 +139,6 @@ static int calibrate_row(const double *drow, int64_t n, int64_t i, double logu, 
   return ok ? it : -it;
 }
 
-/* Calibrate row i from its distance row drow (length n, drow[i] ignored). */
-ORC_API int orc_calibrate_drow(const double *drow, int64_t n, int64_t i, double perplexity,
-                               int max_iter, double tol, double *beta, double *m, double *S,
-                               double *H) {
-  return calibrate_row(drow, n, i, log(perplexity), max_iter, tol, beta, m, S, H);
-}
-
 /*
  * Calibrate the rows listed in rows[0..nrows) (all rows if rows == NULL, then
  * nrows must equal n). Distances of each row are recomputed from X; nothing
@@ -244,6 +237,28 @@ ORC_API void orc_p_entries(const double *X, int64_t n, int32_t d, const int64_t 
   }
 }
 
+/*
+ * Whole rows of P (Eq. 3) for the listed rows, from the statistics of every
+ * row (beta, m, S indexed by point): out[r*n + j] = p_{rows[r], j}. Needs
+ * O(nrows * n) memory, so rows of P can be formed at sizes where the full
+ * square cannot be stored.
+ */
+ORC_API void orc_p_rows(const double *X, int64_t n, int32_t d, const int64_t *rows,
+                        int64_t nrows, const double *beta, const double *m, const double *S,
+                        double *out) {
+  const double inv2n = 1.0 / (2.0 * (double)n);
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) { out[r * n + j] = 0.0; continue; }
+      double dij = sqdist(X + i * d, X + j * d, d);
+      out[r * n + j] =
+          (cond_p(dij, beta[i], m[i], S[i]) + cond_p(dij, beta[j], m[j], S[j])) * inv2n;
+    }
+  }
+}
+
 /* sum_{i != j, p > 0} p_ij ln p_ij: the constant part of the KL cost. */
 ORC_API double orc_p_entropy_term(const double *P, int64_t n) {
   double *row = (double *)malloc((size_t)n * sizeof(double));
@@ -329,6 +344,53 @@ ORC_API void orc_repulsion_rows(const double *Y, int64_t n, const int64_t *rows,
     }
     out[2 * r] = -4.0 * gx / Z;
     out[2 * r + 1] = -4.0 * gy / Z;
+  }
+}
+
+/*
+ * Eq. 6 for the listed rows only, from their rows of P (Prows[r*n + j] =
+ * p_{rows[r], j}) and a given Z (the sum over all ordered pairs, Eq. 4):
+ *   g_i = 4 sum_{j != i} (alpha p_ij - w_ij / Z) w_ij (y_i - y_j).
+ * The same loop as the whole-map gradient, so rows of P that cannot all be
+ * stored still give exact gradient rows.
+ */
+ORC_API void orc_gradient_rows(const double *Prows, int64_t n, const double *Y,
+                               const int64_t *rows, int64_t nrows, double alpha, double Z,
+                               double *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    double gx = 0.0, gy = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double w = wker(Y, i, j);
+      double c = (alpha * Prows[r * n + j] - w / Z) * w;
+      gx += c * (Y[2 * i] - Y[2 * j]);
+      gy += c * (Y[2 * i + 1] - Y[2 * j + 1]);
+    }
+    out[2 * r] = 4.0 * gx;
+    out[2 * r + 1] = 4.0 * gy;
+  }
+}
+
+/*
+ * The listed rows' share of the KL of Eq. 5, from their rows of P and a
+ * given Z:  kl_i = sum_{j != i, p_ij > 0} p_ij (ln p_ij - ln w_ij + ln Z).
+ * Summed over every row this is the KL itself.
+ */
+ORC_API void orc_kl_rows(const double *Prows, int64_t n, const double *Y, const int64_t *rows,
+                         int64_t nrows, double Z, double *out) {
+  const double lz = log(Z);
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    double s = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      const double p = Prows[r * n + j];
+      if (j == i || !(p > 0.0)) continue;
+      s += p * (log(p) - log(wker(Y, i, j)) + lz);
+    }
+    out[r] = s;
   }
 }
 

@@ -1,0 +1,23 @@
+"""The final-KL gate of every full-run parity test.
+
+The paper's iteration is chaotic: exact FP64 runs whose initial maps differ by
+one FP32 ulp in one coordinate end with final KLs that differ by far more than
+the 1e-3 tolerance (the oracle ensembles stored under tests/golden show up to
+2% at 500 iterations). So a run with another rounding order is held to the
+spread of that ensemble, not to 1e-3 alone:
+
+    |KL_gpu - KL_ref| <= max(1.5 * band, 1e-3 * KL_ref),
+    band = max_k |KL_k - KL_ref|
+
+with KL_ref the oracle's run from the unperturbed map and KL_k the runs from
+the perturbed maps. One rule for every test (single problem, batched, the
+benchmark size); the KL at early iterations, before the trajectories
+separate, is gated at 1e-4 separately.
+"""
+
+
+def final_kl_gate(kl_gpu: float, kl_ref: float, ensemble):
+    """(passes, band, tolerance) of the rule above."""
+    band = max(abs(k - kl_ref) for k in ensemble)
+    tol = max(1.5 * band, 1e-3 * kl_ref)
+    return abs(kl_gpu - kl_ref) <= tol, band, tol

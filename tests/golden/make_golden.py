@@ -5,7 +5,7 @@ Output: tests/golden/plain_small_oracle.json — the 2,000-point, 10-D,
 momentum 0.5 before iteration 250, then 1 and 0.8, learning rate 200.
 
 Besides the final KL of the run from the stored initial map, it records the
-KL reached from eight initial maps that differ from it by one FP32 ulp in one
+KL reached from sixteen initial maps that differ from it by one FP32 ulp in one
 coordinate. Their spread is the chaos floor of the final KL: two exact FP64
 runs whose inputs differ by one rounding already disagree by this much, so no
 implementation with a different rounding order can be held closer than that.
@@ -43,7 +43,7 @@ def main():
         kl, cn = oracle.cost(P, y)
         checkpoints[str(t_end)] = {"kl": kl, "cnorm": cn}
     ens = []
-    for r in range(8):
+    for r in range(16):
         y0b = y0.copy()
         i, c = (r * 331) % x.shape[0], r % 2
         y0b[i, c] = np.nextafter(y0b[i, c], np.float32(1))

@@ -1,12 +1,19 @@
 """Precision path: reduced-precision distance contractions against the FP64 oracle.
 
 Every mode must give a valid P (symmetric, summing to 1, zero diagonal, every
-row calibrated), and its error against the FP64 oracle must sit inside the
-bound that the operand rounding implies. With u the unit roundoff of the
-operands (BF16 2^-9, FP16 2^-12, FP32 2^-24; the split modes about u^2), the
-distance error is of order u |x|^2 / sqrt(D) and the relative error of p_ij
-is beta times that. The bounds below are those estimates for the test data
-times a safety factor of about 10; the measured errors are printed.
+row calibrated), and its error against the FP64 oracle must sit inside its
+bound.
+
+* The plain modes (fp32, fp16, bf16) keep the cancellation of
+  |x|^2 + |y|^2 - 2 x.y: with u the unit roundoff of the operands or of the
+  FP32 accumulator (BF16 2^-9, FP16 2^-12, FP32 2^-24), the distance error is
+  of order u |x|^2 and the relative error of p_ij beta times that. Their
+  bounds are those estimates for the test data times about 10; they do not
+  meet the per-step gates.
+* The x3 modes (three exact-accumulate slices, compensated FP32 combine) are
+  held to the per-step gates themselves: P within 1e-5 (relative Frobenius
+  and largest entry error over the largest entry) and the gradient within
+  1e-4 relative L2.
 """
 import numpy as np
 import pytest
@@ -18,14 +25,15 @@ from paper_1812_09869_amd.tsne import ExactTSNE
 
 pytestmark = pytest.mark.gpu
 
-# (mode, bound on the relative Frobenius error of P, bound on the gradient rel-L2)
+# (mode, bound on the relative Frobenius error of P, bound on the gradient rel-L2,
+#  bound on the largest entry error over the largest entry, or None)
 MODES = [
-    ("fp64", 1e-5, 1e-4),
-    ("fp32", 2e-4, 2e-4),
-    ("fp16x3", 1e-4, 1e-4),
-    ("bf16x3", 1e-3, 1e-3),
-    ("fp16", 2e-2, 2e-2),
-    ("bf16", 2e-1, 2e-1),
+    ("fp64", 1e-5, 1e-4, 1e-5),
+    ("fp16x3", 1e-5, 1e-4, 1e-5),
+    ("bf16x3", 1e-5, 1e-4, 1e-5),
+    ("fp32", 2e-4, 2e-4, None),
+    ("fp16", 2e-2, 2e-2, None),
+    ("bf16", 2e-1, 2e-1, None),
 ]
 
 WORKLOADS = {
@@ -46,8 +54,8 @@ def ref(request):
     return dict(name=request.param, x=x, perp=perp, P=P, y=y, g_ref=g_ref, kl_ref=kl_ref)
 
 
-@pytest.mark.parametrize("mode,p_bound,g_bound", MODES, ids=[m[0] for m in MODES])
-def test_mode_errors(ref, mode, p_bound, g_bound):
+@pytest.mark.parametrize("mode,p_bound,g_bound,max_bound", MODES, ids=[m[0] for m in MODES])
+def test_mode_errors(ref, mode, p_bound, g_bound, max_bound):
     x, P = ref["x"], ref["P"]
     n = x.shape[0]
     model = ExactTSNE(torch.from_numpy(x).cuda(), ref["perp"], dist_mode=mode)
@@ -65,4 +73,6 @@ def test_mode_errors(ref, mode, p_bound, g_bound):
     print(f"  {ref['name']:9s} {mode:7s} P fro {fro:.2e} max {mx:.2e} | grad {grel:.2e} | "
           f"KL {klrel:.2e}")
     assert fro <= p_bound and grel <= g_bound
+    if max_bound is not None:
+        assert mx <= max_bound
     assert klrel <= max(p_bound, 1e-5)

@@ -69,6 +69,49 @@ def test_bf16_emulation_rounds():
     assert 1e-5 < rel < 3e-2
 
 
+def test_bf16_emulated_backward_hand_worked():
+    """One row through a 1 -> 1 -> 1 -> 2 network whose values need few bits, so the
+    emulated BF16 roundings (8 significant bits) can be followed by hand. Each
+    rounding of the backward pass (dh2, h1, w2, dh1, xh) changes a stated entry:
+    dropping one, or rounding a value the GPU keeps in FP32, fails an assertion.
+
+    Forward: xh = 3 + 2^-8 (BF16: 3); h1 = 1 * 3 + b1 = 3 + 2^-8;
+    w2 = 1 + 2^-7 + 2^-11 (BF16: 1 + 2^-7); h2 = bf16(w2) bf16(h1) = (1 + 2^-7) 3;
+    out = (h2, 0).
+    Target y0 = h2 - e with e = 1 + 2^-7 + 2^-10, so dh2 = e (BF16: 1 + 2^-7).
+    Backward: g_b3 = (e, 0), g_w3 = (e h2, 0), g_b2 = dh2 = e,
+    g_w2 = bf16(dh2) bf16(h1) = (1 + 2^-7) 3,
+    dh1 = bf16(dh2) bf16(w2) = (1 + 2^-7)^2 = 1 + 2^-6 + 2^-14 (exact in FP32),
+    g_b1 = dh1, g_w1 = bf16(dh1) bf16(xh) = (1 + 2^-6) 3.
+    """
+    e = 1 + 2.0 ** -7 + 2.0 ** -10
+    h2 = (1 + 2.0 ** -7) * 3
+    # packed: W1 [1][1], b1 [1], W2 [1][1], b2 [1], W3 [2][1], b3 [2]
+    w2 = 1 + 2.0 ** -7 + 2.0 ** -11
+    params = np.array([1.0, 2.0 ** -8, w2, 0.0, 1.0, 0.0, 0.0, 0.0])
+    x = np.array([[3 + 2.0 ** -8]])
+    y = np.array([[h2 - e, 0.0]])
+    mean, invstd = np.zeros(1), np.ones(1)
+    out = oracle.mlp_forward(params, x, mean, invstd, hidden=1, emulate=True)
+    np.testing.assert_array_equal(out, [[h2, 0.0]])
+    loss, g = oracle.mlp_gradient(params, x, y, mean, invstd, hidden=1, emulate=True)
+    assert loss == 0.5 * e * e
+    dh1 = 1 + 2.0 ** -6 + 2.0 ** -14
+    expect = [
+        (1 + 2.0 ** -6) * 3,  # g_w1 = bf16(dh1) bf16(xh)
+        dh1,                  # g_b1
+        (1 + 2.0 ** -7) * 3,  # g_w2 = bf16(dh2) bf16(h1)
+        e,                    # g_b2
+        e * h2, 0.0,          # g_w3
+        e, 0.0,               # g_b3
+    ]
+    np.testing.assert_array_equal(g, expect)
+    # without emulation the same network follows plain double arithmetic
+    _, g_plain = oracle.mlp_gradient(params, x, y, mean, invstd, hidden=1, emulate=False)
+    h1 = 3 + 2.0 ** -8 + 2.0 ** -8
+    assert g_plain[2] == (h1 * w2 - (h2 - e)) * h1
+
+
 def test_adam_hand_worked():
     """Step 1 with m = v = 0: m = 0.1 g, v = 0.001 g^2, bias-corrected to g and g^2,
     so p moves by lr * g / (|g| + eps), i.e. lr * sign(g)."""

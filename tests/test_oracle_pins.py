@@ -143,6 +143,34 @@ def test_joint_p_properties():
     np.testing.assert_allclose(oracle.p_entries(x, ii, jj, si, sj), P[ii, jj], rtol=1e-13)
 
 
+def test_p_rows_equal_rows_of_joint_p():
+    """Rows of P formed from every row's statistics are the rows of the full P."""
+    x, _ = synth.plain_small(300, seed=11)
+    st = oracle.calibrate(x, 30.0)
+    P = oracle.joint_p(x, st)
+    rows = np.array([0, 17, 150, 299])
+    pr = oracle.p_rows(x, rows, st)
+    np.testing.assert_array_equal(pr, P[rows])
+    assert np.all(pr[np.arange(rows.size), rows] == 0.0)
+
+
+def test_p_entropy_term_closed_forms():
+    """sum_{i != j, p > 0} p ln p: -ln 2 for two points (p = 1/2 each way, Eq. 3
+    at n = 2), -ln(n(n - 1)) for the uniform P; zero entries and the diagonal
+    add nothing."""
+    assert abs(oracle.p_entropy_term(np.array([[0.0, 0.5], [0.5, 0.0]])) + math.log(2.0)) <= 1e-15
+    n = 7
+    P = np.full((n, n), 1.0 / (n * (n - 1)))
+    np.fill_diagonal(P, 0.0)
+    assert abs(oracle.p_entropy_term(P) + math.log(n * (n - 1))) <= 1e-14
+    # three points with p_12 = p_21 = 1/2 and the rest zero: still -ln 2, and a
+    # value on the diagonal is ignored
+    P = np.zeros((3, 3))
+    P[0, 1] = P[1, 0] = 0.5
+    P[2, 2] = 0.3
+    assert abs(oracle.p_entropy_term(P) + math.log(2.0)) <= 1e-15
+
+
 def test_two_points():
     """n = 2: p_12 = p_21 = 1/2 for any X; q = 1/2 too, so g = 0 and KL = 0."""
     x = np.array([[0.3, -1.0, 2.0], [5.0, 1.0, 0.0]])
@@ -252,6 +280,31 @@ def test_repulsion_rows(small_problem):
     g0, z0 = oracle.gradient(P, y, 0.0)
     rows = np.array([0, 7, 119])
     np.testing.assert_allclose(oracle.repulsion_rows(y, rows, z0), g0[rows], rtol=1e-12)
+
+
+def test_gradient_rows_equal_gradient(small_problem):
+    """Eq. 6 for listed rows from their rows of P and the global Z is the whole-map gradient."""
+    _, P, y = small_problem
+    rows = np.array([0, 7, 64, 119])
+    for alpha in (1.0, 12.0):
+        g, z0 = oracle.gradient(P, y, alpha)
+        np.testing.assert_array_equal(oracle.gradient_rows(P[rows], y, rows, alpha, z0), g[rows])
+
+
+def test_kl_rows_sum_to_kl(small_problem):
+    """The per-row shares of Eq. 5 sum to the KL; each share is sum_j p ln(p / q)."""
+    _, P, y = small_problem
+    n = P.shape[0]
+    z0 = oracle.z(y)
+    shares = oracle.kl_rows(P, y, np.arange(n), z0)
+    kl, _ = oracle.cost(P, y)
+    assert abs(shares.sum() - kl) <= 1e-12 * kl
+    w = 1.0 / (1.0 + cdist(y, y, "sqeuclidean"))
+    q = w / z0
+    i = 33
+    mask = P[i] > 0
+    mask[i] = False
+    assert abs(shares[i] - np.sum(P[i, mask] * np.log(P[i, mask] / q[i, mask]))) <= 1e-13
 
 
 def test_cost_invariances(small_problem):
