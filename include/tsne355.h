@@ -52,15 +52,29 @@ typedef enum {
 } tsne_status;
 
 /* Precision of the squared-distance contraction d = |x|^2 + |y|^2 - 2 x.y
- * that feeds the affinities. All modes run on MFMA; the bisection and every
- * reduction stay FP64/FP32 as documented below. */
+ * (Eq. 1's ||x_i - x_j||^2 in GEMM form) that feeds the affinities. All modes
+ * run on MFMA; the bisection and every reduction stay FP64/FP32 as documented
+ * below.
+ *
+ * FP32, BF16 and FP16 keep the cancellation of the GEMM form: where |x|^2 is
+ * much larger than d, one rounding of the large terms moves d by
+ * u |x|^2 (u the unit roundoff), and p_ij by beta_i times that.
+ *
+ * The x3 modes remove it. Every centred coordinate is cut on one grid for the
+ * whole input into three integer slices (x = sigma (h1 + 2^-b h2 + 2^-2b h3)
+ * plus a remainder below sigma 2^(-2b-1), with b <= 10 for FP16 and <= 8 for
+ * BF16 and 2b + log2(K) <= 24 for K = d rounded up to 32). Eight MFMA
+ * products per operand pair, summed in FP32, give the leading two slice sums
+ * exactly (integers below 2^24) and the third 2^-2b lower; the norms are FP32
+ * (hi, lo) pairs, and n_i + n_j - 2 x.y is formed with error-free
+ * transformations (TwoSum), so d carries about one FP32 rounding of d itself. */
 typedef enum {
   TSNE_DIST_FP64 = 0,   /* FP64 MFMA on the centred input (default) */
   TSNE_DIST_FP32 = 1,   /* FP32 MFMA */
   TSNE_DIST_BF16 = 2,   /* BF16 operands, FP32 accumulate */
-  TSNE_DIST_BF16X3 = 3, /* BF16 hi/lo split, hi.hi + hi.lo + lo.hi, FP32 accumulate */
+  TSNE_DIST_BF16X3 = 3, /* three BF16 slices, eight products, compensated combine */
   TSNE_DIST_FP16 = 4,   /* FP16 operands, FP32 accumulate */
-  TSNE_DIST_FP16X3 = 5  /* FP16 hi/lo split, three products, FP32 accumulate */
+  TSNE_DIST_FP16X3 = 5  /* three FP16 slices, eight products, compensated combine */
 } tsne_dist_mode;
 
 /* Options of the affinity stage. A NULL pointer selects the defaults

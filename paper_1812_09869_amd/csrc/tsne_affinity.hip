@@ -176,14 +176,15 @@ __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT
 // FP32 mode: the FP64-centred X rounded to FP32, v_mfma_f32_16x16x4f32, norms
 // of the rounded points, d = (n_i + n_j) - 2 x.y in FP32.
 // BF16 / FP16 modes: operands rounded to 16 bits, v_mfma_f32_16x16x32_{bf16,f16}
-// with FP32 accumulation. The single-product modes take the norms of the
-// rounded operands, so that d is the exact squared distance of two slightly
-// moved points (never negative, no cancellation blow-up of the dot-product
-// error). The x3 modes split x = hi + lo (lo = x - hi rounded again) and form
-// hi.hi + hi.lo + lo.hi as one contraction of length 3K over A' = [hi|hi|lo],
-// B' = [hi|lo|hi]; their norms are FP32 norms of the unsplit FP32 values.
-// FP16 operands are scaled by a power of two so that max |x| maps to <= 256
-// (exact, undone after the contraction).
+// with FP32 accumulation, and the norms of the rounded operands, so that d is
+// the exact squared distance of two slightly moved points (never negative, no
+// cancellation blow-up of the dot-product error). FP16 operands are scaled by
+// a power of two so that max |x| maps to <= 256 (exact, undone after the
+// contraction).
+// These three keep the cancellation of |x|^2 + |y|^2 - 2 x.y: near pairs
+// have d ~ 200 against |x|^2 ~ 1,350 on the benchmark data, so an FP32
+// rounding of the large terms moves d by ~1e-4. The x3 modes (2a'' below)
+// remove it.
 // 16x16x32 layout: lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and the
 // matching B column slice, and receives D[4(l/16) + r][l%16] in element r.
 // ----------------------------------------------------------------------------
@@ -214,35 +215,21 @@ __global__ __launch_bounds__(256) void k_prep_f32(const double *__restrict__ xcT
   norms32[i] = (float)nrm;
 }
 
-template <typename H, bool SPLIT, bool SCALE>
+template <typename H, bool SCALE>
 __global__ __launch_bounds__(256) void k_prep_lp(const double *__restrict__ xcT, int64_t npad,
                                                  int32_t d, int32_t k32, H *__restrict__ xa,
-                                                 H *__restrict__ xb, float *__restrict__ norms32,
-                                                 const Hdr *h) {
+                                                 float *__restrict__ norms32, const Hdr *h) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= npad) return;
   const float s = SCALE ? fp16_scale(h) : 1.f;
-  const int kk = SPLIT ? 3 * k32 : k32;
-  H *ra = xa + i * kk;
-  H *rb = xb + i * kk;
+  H *ra = xa + i * k32;
   double nrm = 0.0;
   for (int k = 0; k < k32; ++k) {
     const float v = (k < d) ? (float)xcT[(int64_t)k * npad + i] : 0.f;
     const H hi = (H)(v * s);
-    if (SPLIT) {
-      const H lo = (H)(v * s - (float)hi);
-      ra[k] = hi;
-      ra[k32 + k] = hi;
-      ra[2 * k32 + k] = lo;
-      rb[k] = hi;
-      rb[k32 + k] = lo;
-      rb[2 * k32 + k] = hi;
-      nrm += (double)v * (double)v;
-    } else {
-      ra[k] = hi;
-      const double hv = (double)(float)hi / (double)s;
-      nrm += hv * hv;
-    }
+    ra[k] = hi;
+    const double hv = (double)(float)hi / (double)s;
+    nrm += hv * hv;
   }
   norms32[i] = (float)nrm;
 }
@@ -291,7 +278,7 @@ __global__ __launch_bounds__(256) void k_dist_f32(const float *__restrict__ xfT,
 }
 
 template <typename H, typename V8, bool SCALE>
-__global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa, const H *__restrict__ xb,
+__global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa,
                                                  const float *__restrict__ norms, int64_t npad,
                                                  int32_t kk, int32_t b, float *__restrict__ dblock,
                                                  const Hdr *h) {
@@ -317,7 +304,7 @@ __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa, const
       av[a] = *reinterpret_cast<const V8 *>(xa + (row0 + a * 16 + li) * kk + k0 + 8 * lk);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-      bv[c] = *reinterpret_cast<const V8 *>(xb + (col0 + c * 16 + li) * kk + k0 + 8 * lk);
+      bv[c] = *reinterpret_cast<const V8 *>(xa + (col0 + c * 16 + li) * kk + k0 + 8 * lk);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -339,6 +326,196 @@ __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa, const
         const int64_t j = col0 + c * 16 + li;
         const float dd = (ni + norms[j]) - 2.f * (acc[a][c][r] * inv_s2);
         dblock[(int64_t)il * npad + j] = fmaxf(dd, 0.f);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// 2a''. The x3 modes: exact-accumulate slices and a compensated FP32 combine.
+//
+// Every centred coordinate is cut on one grid for the whole data set,
+//   x = sigma (h1 + 2^-b h2 + 2^-2b h3) + r,  sigma = 2^(E - b), max |x| < 2^E,
+// rounding to the nearest integer at each level (|h1| <= 2^b, |h2|, |h3| <=
+// 2^(b-1), |r| <= sigma 2^(-2b-1)). b is the largest value with
+// 2b + log2(K) <= 24 (K = d rounded up to 32), at most 10 for FP16 and 8 for
+// BF16, so each slice is exact in 16 bits and the sums
+//   A0 = sum_k h1 h1',   A1 = sum_k (h1 h2' + h2 h1')
+// are integers below 2^24: the MFMA's FP32 accumulation adds them exactly,
+// in whatever order it works. The next sum,
+//   A2 = sum_k (h1 h3' + h2 h2' + h3 h1') + 2^-b sum_k (h2 h3' + h3 h2')
+// (the last two through stored copies 2^-b h3), lies 2^-2b lower and may
+// round. Then x.y = sigma^2 (A0 + 2^-b A1 + 2^-2b A2); the products left out
+// (h3 h3' and below) are under sigma^2 2^-4b K 2^2b. Eight MFMA products per
+// operand pair in all.
+// The norms are FP32 pairs (hi, lo) of the FP64 norm of the represented point
+// sigma (h1 + 2^-b h2 + 2^-2b h3). d = n_i + n_j - 2 x.y cancels most of its
+// operands, so it is formed with error-free transformations: TwoSum of the
+// two hi parts, TwoSum of that with -2 sigma^2 A0 (an exact product), then
+// the small terms (both TwoSum errors, the lo parts and
+// 2 sigma^2 (2^-b A1 + 2^-2b A2)) added to the leading difference. d then
+// carries about one FP32 rounding of d itself instead of one of |x|^2.
+// ----------------------------------------------------------------------------
+__host__ __device__ inline int x3_bits(int32_t k32, bool bf16) {
+  int lk = 0;
+  while ((1 << lk) < k32) ++lk;
+  const int b = (24 - lk) / 2;
+  const int bmax = bf16 ? 8 : 10;
+  return b < bmax ? b : bmax;
+}
+
+// E with max |x| < 2^E (0 for an all-zero input)
+__device__ inline int x3_exp(const Hdr *h) {
+  const float xm = h->xmax;
+  if (!(xm > 0.f)) return 0;
+  int e;
+  frexpf(xm, &e);
+  return e;
+}
+
+// Four slice vectors of k32 values per point, [h1 | h2 | h3 | 2^-b h3], and
+// the (hi, lo) norm of the represented point.
+template <typename H>
+__global__ __launch_bounds__(256) void k_prep_x3(const double *__restrict__ xcT, int64_t npad,
+                                                 int32_t d, int32_t k32, int32_t b,
+                                                 H *__restrict__ xs, float2 *__restrict__ nhl,
+                                                 const Hdr *h) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npad) return;
+  const int E = x3_exp(h);
+  H *row = xs + i * (4 * (int64_t)k32);
+  double nrm = 0.0;
+  for (int k = 0; k < k32; ++k) {
+    const double v = (k < d) ? xcT[(int64_t)k * npad + i] : 0.0;
+    const double q = ldexp(v, b - E);
+    const double h1 = rint(q);
+    double r = ldexp(q - h1, b);
+    const double h2 = rint(r);
+    r = ldexp(r - h2, b);
+    const double h3 = rint(r);
+    row[k] = (H)(float)h1;
+    row[k32 + k] = (H)(float)h2;
+    row[2 * k32 + k] = (H)(float)h3;
+    row[3 * k32 + k] = (H)(float)ldexp(h3, -b);
+    const double xr = ldexp(h1 + ldexp(h2 + ldexp(h3, -b), -b), E - b);
+    nrm += xr * xr;
+  }
+  const float hi = (float)nrm;
+  nhl[i] = make_float2(hi, (float)(nrm - (double)hi));
+}
+
+template <typename H, typename V8>
+__device__ __forceinline__ v4f mfma16x32(V8 a, V8 b, v4f c) {
+  if constexpr (__is_same(H, __bf16))
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// The three slice sums of a 64 x 64 block (4 x 4 MFMA tiles): rows ra .. ra+63
+// against columns cb .. cb+63. Stored and recomputed P call this same routine,
+// so their sums agree bit for bit.
+template <typename H, typename V8>
+__device__ __forceinline__ void x3_contract(const H *__restrict__ xs, int32_t k32, int64_t ra,
+                                            int64_t cb, int li, int lk, v4f (&A0)[4][4],
+                                            v4f (&A1)[4][4], v4f (&A2)[4][4]) {
+  const int64_t kk = 4 * (int64_t)k32;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      A0[t][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+      A1[t][c] = A0[t][c];
+      A2[t][c] = A0[t][c];
+    }
+  for (int k0 = 0; k0 < k32; k0 += 32) {
+    V8 a[4][4];  // [slice][row tile]
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        a[q][t] = *reinterpret_cast<const V8 *>(xs + (ra + 16 * t + li) * kk + q * k32 + k0 +
+                                                8 * lk);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      V8 bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        bv[q] = *reinterpret_cast<const V8 *>(xs + (cb + 16 * c + li) * kk + q * k32 + k0 +
+                                              8 * lk);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A0[t][c] = mfma16x32<H, V8>(a[0][t], bv[0], A0[t][c]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A1[t][c] = mfma16x32<H, V8>(a[0][t], bv[1], A1[t][c]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A1[t][c] = mfma16x32<H, V8>(a[1][t], bv[0], A1[t][c]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[0][t], bv[2], A2[t][c]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[1][t], bv[1], A2[t][c]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[2][t], bv[0], A2[t][c]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[1][t], bv[3], A2[t][c]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[3][t], bv[1], A2[t][c]);
+    }
+  }
+}
+
+// 2 sigma^2, 2 sigma^2 2^-b, 2 sigma^2 2^-2b
+struct X3Scale {
+  float s0, s1, s2;
+};
+__device__ inline X3Scale x3_scale(const Hdr *h, int b) {
+  const int e = 2 * (x3_exp(h) - b) + 1;
+  return X3Scale{ldexpf(1.f, e), ldexpf(1.f, e - b), ldexpf(1.f, e - 2 * b)};
+}
+
+// d = n_i + n_j - 2 x.y from (hi, lo) norms and the three slice sums
+__device__ __forceinline__ float x3_combine(float2 ni, float2 nj, float a0, float a1, float a2,
+                                            const X3Scale &sc) {
+  const float s = __fadd_rn(ni.x, nj.x);
+  const float bs = __fsub_rn(s, ni.x);
+  const float e1 = __fadd_rn(__fsub_rn(ni.x, __fsub_rn(s, bs)), __fsub_rn(nj.x, bs));
+  const float big = __fmul_rn(sc.s0, a0);  // exact: an integer below 2^24 times a power of two
+  const float t = __fsub_rn(s, big);
+  const float bt = __fsub_rn(t, s);
+  const float e2 = __fadd_rn(__fsub_rn(s, __fsub_rn(t, bt)), __fsub_rn(-big, bt));
+  const float low = __fsub_rn(__fadd_rn(__fadd_rn(e1, e2), __fadd_rn(ni.y, nj.y)),
+                              __fadd_rn(__fmul_rn(sc.s1, a1), __fmul_rn(sc.s2, a2)));
+  return fmaxf(__fadd_rn(t, low), 0.f);
+}
+
+// Distance block of the x3 modes: a workgroup covers 64 rows x 256 columns,
+// as k_dist_lp.
+template <typename H, typename V8>
+__global__ __launch_bounds__(256) void k_dist_x3(const H *__restrict__ xs,
+                                                 const float2 *__restrict__ nhl, int64_t npad,
+                                                 int32_t k32, int32_t bits, int32_t b,
+                                                 float *__restrict__ dblock, const Hdr *h) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  const int row0_loc = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)b * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  v4f A0[4][4], A1[4][4], A2[4][4];
+  x3_contract<H, V8>(xs, k32, row0, col0, li, lk, A0, A1, A2);
+  const X3Scale sc = x3_scale(h, bits);
+  float2 nj[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) nj[c] = nhl[col0 + c * 16 + li];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + t * 16 + 4 * lk + r;
+      const float2 ni = nhl[(int64_t)b * T + il];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t j = col0 + c * 16 + li;
+        dblock[(int64_t)il * npad + j] =
+            x3_combine(ni, nj[c], A0[t][c][r], A1[t][c][r], A2[t][c][r], sc);
       }
     }
   }
@@ -773,7 +950,6 @@ __global__ __launch_bounds__(256) void k_tdist_f32(const float *__restrict__ xfT
 // 16-bit modes: as k_dist_lp, a workgroup covers 64 rows x 256 columns.
 template <typename H, typename V8, bool SCALE, bool PACK>
 __global__ __launch_bounds__(256) void k_tdist_lp(const H *__restrict__ xa,
-                                                  const H *__restrict__ xb,
                                                   const float *__restrict__ norms, int32_t kk,
                                                   int32_t nb, int64_t tile0, int64_t tile_base,
                                                   float *__restrict__ Pb, const Hdr *guard,
@@ -809,7 +985,7 @@ __global__ __launch_bounds__(256) void k_tdist_lp(const H *__restrict__ xa,
       av[a] = *reinterpret_cast<const V8 *>(xa + (row0 + a * 16 + li) * kk + k0 + 8 * lk);
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-      bv[c] = *reinterpret_cast<const V8 *>(xb + (col0 + c * 16 + li) * kk + k0 + 8 * lk);
+      bv[c] = *reinterpret_cast<const V8 *>(xa + (col0 + c * 16 + li) * kk + k0 + 8 * lk);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -841,6 +1017,64 @@ __global__ __launch_bounds__(256) void k_tdist_lp(const H *__restrict__ xa,
       }
       // the lane's four columns are the four elements of one float4 slot of
       // the tile layout: one 16-byte store off the diagonal
+      if (!diag) {
+        *reinterpret_cast<float4 *>(tp + tile_pos(il, cl0 + li)) =
+            make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) put_d(tp, true, il, cl0 + c * 16 + li, v[c]);
+      }
+    }
+  }
+}
+
+// x3 modes: as k_tdist_lp, a workgroup covers 64 rows x 256 columns of the
+// tile; the sums come from the same routine as the stored path's.
+template <typename H, typename V8, bool PACK>
+__global__ __launch_bounds__(256) void k_tdist_x3(const H *__restrict__ xs,
+                                                  const float2 *__restrict__ nhl, int32_t k32,
+                                                  int32_t bits, int32_t nb, int64_t tile0,
+                                                  int64_t tile_base, float *__restrict__ Pb,
+                                                  const Hdr *guard, int64_t gn, int32_t gkey,
+                                                  const uint8_t *__restrict__ nz, bool skip,
+                                                  const float *__restrict__ ra,
+                                                  const float *__restrict__ rm,
+                                                  const float *__restrict__ rr) {
+  const int64_t tile = tile0 + blockIdx.x;
+  int I, J;
+  if (!tdist_begin(guard, gn, gkey, nz, skip, tile, nb, I, J)) return;
+  const bool diag = (I == J);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int cl0 = w * 64;
+  const int64_t col0 = (int64_t)J * T + cl0;
+  const int row0_loc = blockIdx.y * 64;
+  const int64_t row0 = (int64_t)I * T + row0_loc;
+  const int li = l & 15, lk = l >> 4;
+  v4f A0[4][4], A1[4][4], A2[4][4];
+  x3_contract<H, V8>(xs, k32, row0, col0, li, lk, A0, A1, A2);
+  const X3Scale sc = x3_scale(guard, bits);
+  float *tp = Pb + (size_t)(tile - tile_base) * T * T;
+  PtStat scs[4];
+  float2 nj[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    scs[c] = pt_stat<PACK>(col0 + c * 16 + li, gn, ra, rm, rr);
+    nj[c] = nhl[col0 + c * 16 + li];
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int il = row0_loc + t * 16 + 4 * lk + r;
+      const float2 ni = nhl[(int64_t)I * T + il];
+      const PtStat si = pt_stat<PACK>((int64_t)I * T + il, gn, ra, rm, rr);
+      float v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int jl = cl0 + c * 16 + li;
+        const float dd = x3_combine(ni, nj[c], A0[t][c][r], A1[t][c][r], A2[t][c][r], sc);
+        v[c] = tile_value<PACK>(dd, diag, il, jl, si, scs[c]);
+      }
       if (!diag) {
         *reinterpret_cast<float4 *>(tp + tile_pos(il, cl0 + li)) =
             make_float4(v[0], v[1], v[2], v[3]);
@@ -1765,16 +1999,24 @@ static void launch_dist(const Layout &L, void *ws, int b, const double *xc, cons
                          L.npad, L.dpad, b, dblock);
       break;
     case TSNE_DIST_BF16:
-    case TSNE_DIST_BF16X3:
       hipLaunchKernelGGL((k_dist_lp<__bf16, v8bf, false>), dgrid, dim3(256), 0, st,
-                         at<const __bf16>(ws, L.xa), at<const __bf16>(ws, L.xb), norms32, L.npad,
+                         at<const __bf16>(ws, L.xa), norms32, L.npad,
                          L.kk, b, dblock, h);
       break;
     case TSNE_DIST_FP16:
-    case TSNE_DIST_FP16X3:
       hipLaunchKernelGGL((k_dist_lp<_Float16, v8h, true>), dgrid, dim3(256), 0, st,
-                         at<const _Float16>(ws, L.xa), at<const _Float16>(ws, L.xb), norms32,
+                         at<const _Float16>(ws, L.xa), norms32,
                          L.npad, L.kk, b, dblock, h);
+      break;
+    case TSNE_DIST_BF16X3:
+      hipLaunchKernelGGL((k_dist_x3<__bf16, v8bf>), dgrid, dim3(256), 0, st,
+                         at<const __bf16>(ws, L.xa), at<const float2>(ws, L.norms32), L.npad,
+                         L.kk / 4, x3_bits(L.kk / 4, true), b, dblock, h);
+      break;
+    case TSNE_DIST_FP16X3:
+      hipLaunchKernelGGL((k_dist_x3<_Float16, v8h>), dgrid, dim3(256), 0, st,
+                         at<const _Float16>(ws, L.xa), at<const float2>(ws, L.norms32), L.npad,
+                         L.kk / 4, x3_bits(L.kk / 4, false), b, dblock, h);
       break;
     default:
       hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64), dim3(256),
@@ -1808,8 +2050,9 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   const int32_t k32 = (L.d + 31) / 32 * 32;
   float *norms32 = at<float>(ws, L.norms32);
   float *xfT = at<float>(ws, L.xfT);
-  __bf16 *xa_b = at<__bf16>(ws, L.xa), *xb_b = at<__bf16>(ws, L.xb);
-  _Float16 *xa_h = at<_Float16>(ws, L.xa), *xb_h = at<_Float16>(ws, L.xb);
+  __bf16 *xa_b = at<__bf16>(ws, L.xa);
+  _Float16 *xa_h = at<_Float16>(ws, L.xa);
+  float2 *nhl = at<float2>(ws, L.norms32);
   double2 *ppart = at<double2>(ws, L.ppart);
   uint8_t *nz = at<uint8_t>(ws, L.nz);
 
@@ -1822,20 +2065,20 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
                            norms32);
         break;
       case TSNE_DIST_BF16:
-        hipLaunchKernelGGL((k_prep_lp<__bf16, false, false>), dim3(pgrid), dim3(256), 0, st, xc,
-                           L.npad, L.d, k32, xa_b, xb_b, norms32, h);
+        hipLaunchKernelGGL((k_prep_lp<__bf16, false>), dim3(pgrid), dim3(256), 0, st, xc, L.npad,
+                           L.d, k32, xa_b, norms32, h);
         break;
       case TSNE_DIST_BF16X3:
-        hipLaunchKernelGGL((k_prep_lp<__bf16, true, false>), dim3(pgrid), dim3(256), 0, st, xc,
-                           L.npad, L.d, k32, xa_b, xb_b, norms32, h);
+        hipLaunchKernelGGL(k_prep_x3<__bf16>, dim3(pgrid), dim3(256), 0, st, xc, L.npad, L.d, k32,
+                           x3_bits(k32, true), xa_b, nhl, h);
         break;
       case TSNE_DIST_FP16:
-        hipLaunchKernelGGL((k_prep_lp<_Float16, false, true>), dim3(pgrid), dim3(256), 0, st, xc,
-                           L.npad, L.d, k32, xa_h, xb_h, norms32, h);
+        hipLaunchKernelGGL((k_prep_lp<_Float16, true>), dim3(pgrid), dim3(256), 0, st, xc,
+                           L.npad, L.d, k32, xa_h, norms32, h);
         break;
       case TSNE_DIST_FP16X3:
-        hipLaunchKernelGGL((k_prep_lp<_Float16, true, true>), dim3(pgrid), dim3(256), 0, st, xc,
-                           L.npad, L.d, k32, xa_h, xb_h, norms32, h);
+        hipLaunchKernelGGL(k_prep_x3<_Float16>, dim3(pgrid), dim3(256), 0, st, xc, L.npad, L.d,
+                           k32, x3_bits(k32, false), xa_h, nhl, h);
         break;
       default:
         break;
@@ -1997,16 +2240,26 @@ static void launch_tdist(const Layout &L, void *ws, int64_t tile0, int64_t count
                          skip_zero, ra, rm, rr);
       break;
     case TSNE_DIST_BF16:
-    case TSNE_DIST_BF16X3:
       hipLaunchKernelGGL((k_tdist_lp<__bf16, v8bf, false, PACK>), g4, dim3(256), 0, st,
-                         at<const __bf16>(ws, L.xa), at<const __bf16>(ws, L.xb), norms32, L.kk,
+                         at<const __bf16>(ws, L.xa), norms32, L.kk,
                          L.nb, tile0, tile_base, Pb, h, L.n, key, nz, skip_zero, ra, rm, rr);
       break;
     case TSNE_DIST_FP16:
-    case TSNE_DIST_FP16X3:
       hipLaunchKernelGGL((k_tdist_lp<_Float16, v8h, true, PACK>), g4, dim3(256), 0, st,
-                         at<const _Float16>(ws, L.xa), at<const _Float16>(ws, L.xb), norms32,
+                         at<const _Float16>(ws, L.xa), norms32,
                          L.kk, L.nb, tile0, tile_base, Pb, h, L.n, key, nz, skip_zero, ra, rm, rr);
+      break;
+    case TSNE_DIST_BF16X3:
+      hipLaunchKernelGGL((k_tdist_x3<__bf16, v8bf, PACK>), g4, dim3(256), 0, st,
+                         at<const __bf16>(ws, L.xa), at<const float2>(ws, L.norms32), L.kk / 4,
+                         x3_bits(L.kk / 4, true), L.nb, tile0, tile_base, Pb, h, L.n, key, nz,
+                         skip_zero, ra, rm, rr);
+      break;
+    case TSNE_DIST_FP16X3:
+      hipLaunchKernelGGL((k_tdist_x3<_Float16, v8h, PACK>), g4, dim3(256), 0, st,
+                         at<const _Float16>(ws, L.xa), at<const float2>(ws, L.norms32), L.kk / 4,
+                         x3_bits(L.kk / 4, false), L.nb, tile0, tile_base, Pb, h, L.n, key, nz,
+                         skip_zero, ra, rm, rr);
       break;
     default:
       hipLaunchKernelGGL(k_tdist_f64<PACK>,

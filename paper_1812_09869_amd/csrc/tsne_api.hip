@@ -81,12 +81,13 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only, bool imp
     L.xfT = take((size_t)L.dpad * np * 4);
     L.norms32 = take(np * 4);
   } else if (mode != TSNE_DIST_FP64) {
+    // 16-bit operands; the x3 modes keep four slice vectors per point and
+    // (hi, lo) FP32 norm pairs
     const int32_t k32 = (d + 31) / 32 * 32;
     const bool split = (mode == TSNE_DIST_BF16X3 || mode == TSNE_DIST_FP16X3);
-    L.kk = split ? 3 * k32 : k32;
+    L.kk = split ? 4 * k32 : k32;
     L.xa = take(np * (size_t)L.kk * 2);
-    L.xb = split ? take(np * (size_t)L.kk * 2) : L.xa;
-    L.norms32 = take(np * 4);
+    L.norms32 = take(np * (split ? 8 : 4));
   }
   L.total = o;
   return L;

@@ -69,11 +69,11 @@ struct Layout {
   size_t yp = 0;    // float2 [npad]: the map in the internal order (per force pass)
   size_t extent = 0;  // float4 [nb]: per-block {min x, max x, min y, max y} of that map
   size_t iter_end = 0;  // end of the part that tsne_step needs
-  int32_t kk = 0;  // K of the reduced-precision contraction (d rounded up, x3 for split modes)
+  int32_t kk = 0;  // 16-bit operand values per point (d rounded up to 32; four slices in the x3 modes)
   size_t xmean = 0, xcT = 0, norms = 0, dblock = 0;
   size_t xcT2 = 0, norms2 = 0, keys = 0, vals = 0;  // reordering
   int64_t npow2 = 0;
-  size_t xfT = 0, norms32 = 0, xa = 0, xb = 0;  // reduced-precision operands
+  size_t xfT = 0, norms32 = 0, xa = 0;  // reduced-precision operands and norms
   size_t total = 0;
 };
 
