@@ -431,6 +431,20 @@ TSNE_API int tsne_mlp_forward(const float *params, int32_t d_in, int32_t hidden,
                               const float *mean, const float *invstd, const float *x, int64_t n,
                               float *out, void *ws, size_t ws_bytes, void *stream);
 
+/* tsne_mlp_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results, with the BF16 weight copies kept in a
+ * device-resident scratch array of the library (512 KiB per device, held until
+ * the process ends) instead of a caller workspace. No allocation happens in
+ * the call. The scratch is shared by every call on a device and keeps the
+ * last call's contents, so calls that overlap on one device (different
+ * streams, threads) race. The stream must belong to the current device.
+ * Errors: TSNE_E_ARG as tsne_mlp_forward; TSNE_E_WORKSPACE if the network's
+ * scratch would exceed the array (no supported d_in, hidden does). */
+TSNE_API int tsne_mlp_forward_noalloc(const float *params, int32_t d_in, int32_t hidden,
+                                      const float *mean, const float *invstd, const float *x,
+                                      int64_t n, float *out, void *stream);
+
 /* Gradient of L = (1 / (2B)) sum_b |net(x_b) - y_b|^2 over a batch of B rows,
  * rows idx[0..B) of x and y (idx: device int32, or NULL for rows 0..B-1).
  * grad: packed FP32 like params (fully overwritten); loss: device double. */

@@ -51,6 +51,7 @@ EXPORTED = [
     "tsne_mlp_param_count",
     "tsne_mlp_workspace_bytes",
     "tsne_mlp_forward",
+    "tsne_mlp_forward_noalloc",
     "tsne_mlp_gradient",
     "tsne_mlp_adam",
     "tsne_pt_workspace_bytes",
@@ -151,6 +152,8 @@ def load(path: str = LIB_PATH):
         "tsne_mlp_workspace_bytes": (ctypes.c_size_t, [_i32, _i32, _i64, _i32]),
         "tsne_mlp_forward": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp, _vp,
                                             ctypes.c_size_t, _vp]),
+        "tsne_mlp_forward_noalloc": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i64, _vp,
+                                                     _vp]),
         "tsne_mlp_gradient": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                              _vp, _vp, ctypes.c_size_t, _vp]),
         "tsne_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float,
@@ -357,6 +360,14 @@ def mlp_forward(params, d_in, hidden, mean, invstd, x, out, ws):
                                    _ptr(invstd), _ptr(x, shape=(n, d_in), name="x"), n,
                                    _ptr(out, shape=(n, 2), name="out"),
                                    _ptr(ws, torch.uint8, name="ws"), ws.numel(), _stream()))
+
+
+def mlp_forward_noalloc(params, d_in, hidden, mean, invstd, x, out):
+    """tsne_mlp_forward without a workspace (the library's device scratch)."""
+    n = x.shape[0]
+    _check(load().tsne_mlp_forward_noalloc(_ptr(params, name="params"), d_in, hidden, _ptr(mean),
+                                           _ptr(invstd), _ptr(x, shape=(n, d_in), name="x"), n,
+                                           _ptr(out, shape=(n, 2), name="out"), _stream()))
 
 
 def mlp_gradient(params, d_in, hidden, mean, invstd, x, y, idx, batch, grad, loss, ws):

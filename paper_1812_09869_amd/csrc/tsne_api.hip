@@ -548,6 +548,27 @@ int tsne_mlp_forward(const float *params, int32_t d_in, int32_t hidden, const fl
                    "tsne_mlp_forward");
 }
 
+int tsne_mlp_forward_noalloc(const float *params, int32_t d_in, int32_t hidden,
+                             const float *mean, const float *invstd, const float *x, int64_t n,
+                             float *out, void *stream) {
+  if (!params || !mean || !invstd || !x || !out)
+    return fail(TSNE_E_ARG, "tsne_mlp_forward_noalloc: null pointer");
+  if (!mlp_dims_ok(d_in, hidden) || n < 1)
+    return fail(TSNE_E_ARG, "tsne_mlp_forward_noalloc: unsupported d_in %d / hidden %d / n %lld",
+                d_in, hidden, (long long)n);
+  const tsne::MlpLayout L = tsne::make_mlp_layout(d_in, hidden, 64, false);
+  if (L.total > tsne::kNoAllocScratchBytes)
+    return fail(TSNE_E_WORKSPACE,
+                "tsne_mlp_forward_noalloc: needs %zu bytes of scratch, the library holds %zu",
+                L.total, tsne::kNoAllocScratchBytes);
+  void *scr = nullptr;
+  hipError_t e = tsne::noalloc_scratch(&scr);
+  if (e != hipSuccess) return hip_check(e, "tsne_mlp_forward_noalloc: scratch address");
+  return hip_check(tsne::launch_mlp_forward(L, params, mean, invstd, x, n, out, scr,
+                                            (hipStream_t)stream),
+                   "tsne_mlp_forward_noalloc");
+}
+
 int tsne_mlp_gradient(const float *params, int32_t d_in, int32_t hidden, const float *mean,
                       const float *invstd, const float *x, const float *y, const int32_t *idx,
                       int64_t batch, float *grad, double *loss, void *ws, size_t ws_bytes,

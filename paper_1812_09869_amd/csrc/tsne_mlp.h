@@ -19,6 +19,11 @@ struct MlpLayout {
 
 MlpLayout make_mlp_layout(int d_in, int H, int64_t Bpad, bool train);
 
+// Size of the device-resident scratch of tsne_mlp_forward_noalloc, and its
+// address on the current device (looked up on the first call per device).
+constexpr size_t kNoAllocScratchBytes = 512 * 1024;
+hipError_t noalloc_scratch(void **out);
+
 hipError_t launch_mlp_forward(const MlpLayout &L, const float *params, const float *mean,
                               const float *invstd, const float *x, int64_t n, float *out, void *ws,
                               hipStream_t stream);

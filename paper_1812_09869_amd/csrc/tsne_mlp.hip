@@ -9,6 +9,8 @@
 // are kept in FP32 and rounded to BF16 where they feed a contraction.
 #include <math.h>
 
+#include <mutex>
+
 #include "tsne_internal.h"
 #include "tsne_mlp.h"
 
@@ -579,6 +581,39 @@ hipError_t launch_mlp_forward(const MlpLayout &L, const float *params, const flo
                          invstd, w1b, b1, w2b, b2, w3, b3, out);
   }
   return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Scratch of the allocation-free forward entry point: the BF16 weight copies
+// of a forward pass (the whole 64-row forward layout, under 0.4 MiB for every
+// supported d_in and H). One copy per device, held until the process ends and
+// shared by every call on that device. Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): the
+// device address is looked up once per device, with that device current, and
+// kept here.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_mlp_gradient(const MlpLayout &L, const float *params, const float *mean,
