@@ -30,41 +30,91 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(x_full, perplexity, n_target, iters_target, n_sample=8192, iters_sample=100):
-    """Time the FP64 oracle on a bounded sample of the same workload.
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    The oracle runs the affinities and ``iters_sample`` iterations on the first
-    ``n_sample`` points; both stages are O(n^2) per pass, so the time is scaled
-    by (n_target / n_sample)^2 and to ``iters_target`` iterations.
+
+def _omp_threads(n=None):
+    """Thread count of the OpenMP runtime the oracle runs on (sets it if n is given)."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
+def cpu_baseline(x_full, perplexity, n_target, iters_target, n_sample=8192, iters_sample=100,
+                 n_one=4096, iters_one=20):
+    """Time the FP64 oracle on bounded samples of the same workload.
+
+    On all host threads: the affinities and ``iters_sample`` iterations on the
+    first ``n_sample`` points. On one thread: the affinities and ``iters_one``
+    iterations on the first ``n_one`` points. Both stages are O(n^2) per pass,
+    so each time is scaled by (n_target / n)^2 and to ``iters_target``
+    iterations. Also the whole 2,000-point, 500-iteration workload on all
+    threads, unscaled.
     """
     import numpy as np
 
     import oracle
     from paper_1812_09869_amd import synth
 
-    xs = np.ascontiguousarray(x_full[:n_sample])
-    y0 = synth.embedding_init(n_sample, seed=synth.SEEDS["init_aniso"]).astype(np.float64)
+    def sample(n, iters):
+        xs = np.ascontiguousarray(x_full[:n])
+        y0 = synth.embedding_init(n, seed=synth.SEEDS["init_aniso"]).astype(np.float64)
+        t0 = time.perf_counter()
+        st = oracle.calibrate(xs, perplexity)
+        P = oracle.joint_p(xs, st)
+        t_aff = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.run(P, y0, iters)
+        t_it = (time.perf_counter() - t0) / iters
+        scale = (n_target / n) ** 2
+        return t_aff, t_it, iters_target / ((t_aff + iters_target * t_it) * scale)
+
+    oracle._load()
+    threads = _omp_threads()
+    t_aff, t_it, rate = sample(n_sample, iters_sample)
+    _omp_threads(1)
+    t_aff1, t_it1, rate1 = sample(n_one, iters_one)
+    _omp_threads(threads)
+    xs, _ = synth.plain_small()
     t0 = time.perf_counter()
-    st = oracle.calibrate(xs, perplexity)
-    P = oracle.joint_p(xs, st)
-    t_aff = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.run(P, y0, iters_sample)
-    t_it = (time.perf_counter() - t0) / iters_sample
-    scale = (n_target / n_sample) ** 2
-    total = (t_aff + iters_target * t_it) * scale
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    P = oracle.joint_p(xs, oracle.calibrate(xs, 30.0))
+    oracle.run(P, synth.embedding_init(xs.shape[0], synth.SEEDS["init_small"]), 500)
+    t_small = time.perf_counter() - t0
     return {
-        "value": iters_target / total,
+        "value": rate,
         "unit": "iters/s",
-        "cores": cores,
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"FP64 oracle on the first {n_sample} points of the same mixture: affinities "
                    f"+ {iters_sample} iterations ({t_aff:.2f} s + {iters_sample * t_it:.2f} s), "
                    f"scaled by (N/{n_sample})^2 to N={n_target} and to {iters_target} "
                    f"iterations"),
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
         "iter_s_at_sample": t_it,
         "affinity_s_at_sample": t_aff,
+        "one_thread": {
+            "value": rate1,
+            "unit": "iters/s",
+            "sample": (f"first {n_one} points: affinities + {iters_one} iterations "
+                       f"({t_aff1:.2f} s + {iters_one * t_it1:.2f} s), scaled by "
+                       f"(N/{n_one})^2 and to {iters_target} iterations"),
+        },
+        "plain_small_full_run_s": t_small,
+        "plain_small_full_run": ("the 2,000-point, 10-D, perplexity-30 workload in full "
+                                 "(affinities + 500 iterations), all threads"),
     }
 
 
@@ -155,9 +205,10 @@ def precision_leg(x, lab, n, d, perp, iters, steady_ms):
     """Affinity time and per-step error of every distance mode at the benchmark size.
 
     Errors are taken against the FP64 mode (which the parity tests hold to the
-    FP64 oracle at ~1e-6): P on 32 sampled rows (relative Frobenius), the
+    FP64 oracle at ~1e-7 at this size): P on 32 sampled rows (relative
+    Frobenius, and the largest entry error over the largest entry), the
     gradient (alpha = 1) and the KL at a fixed clustered map. A mode meets the
-    per-step gates if P <= 1e-5 and gradient <= 1e-4.
+    per-step gates if both P errors are <= 1e-5 and the gradient <= 1e-4.
     """
     import numpy as np
     import torch
@@ -191,21 +242,72 @@ def precision_leg(x, lab, n, d, perp, iters, steady_ms):
         if ref is None:
             ref = (prow, g, kl)
         pe = float(torch.linalg.norm(prow - ref[0]) / torch.linalg.norm(ref[0]))
+        pm = float((prow - ref[0]).abs().max() / ref[0].max())
         ge = float(torch.linalg.norm(g - ref[1]) / torch.linalg.norm(ref[1]))
         ke = abs(kl - ref[2]) / ref[2]
         aff = min(times)
         res[mode] = {
             "affinity_ms": aff,
             "p_rel_vs_fp64": pe,
+            "p_maxrel_vs_fp64": pm,
             "grad_rel_vs_fp64": ge,
             "kl_rel_vs_fp64": ke,
             "end_to_end_iters_per_s": iters / ((aff + iters * steady_ms) * 1e-3),
-            "meets_step_gates": bool(pe <= 1e-5 and ge <= 1e-4),
+            "meets_step_gates": bool(pe <= 1e-5 and pm <= 1e-5 and ge <= 1e-4),
         }
-        log(f"[bench] mode {mode:7s} affinities {aff:7.2f} ms  P {pe:.2e}  grad {ge:.2e}  "
-            f"KL {ke:.2e}")
+        log(f"[bench] mode {mode:7s} affinities {aff:7.2f} ms  P {pe:.2e} (max {pm:.2e})  "
+            f"grad {ge:.2e}  KL {ke:.2e}")
     del ws
     return res
+
+
+def monitor_leg(ws, n, y0, iters, sched, every=50):
+    """One more run of the benchmark trajectory, outside the timed steps, with
+    the run log every ``every`` iterations: KL and C_norm (Eqs. 5 and 9, from
+    tsne_cost), Z and the gradient norm of that iteration (from tsne_step),
+    and the diagonal of the map's bounding box (the embedding size monitor)."""
+    import torch
+
+    from paper_1812_09869_amd import _lib
+
+    y = y0.clone()
+    u = torch.zeros_like(y)
+    g = torch.ones_like(y)
+    grad = torch.empty_like(y)
+    z = torch.zeros(1, dtype=torch.float64, device=y.device)
+    cost = torch.zeros(2, dtype=torch.float64, device=y.device)
+    log_rows = []
+    for t in range(iters):
+        alpha, mu, eta = sched(t)
+        want = (t + 1) % every == 0
+        _lib.step(ws, n, y, u, g, alpha, mu, eta, sched.min_gain, True,
+                  grad if want else None, z if want else None)
+        if want:
+            _lib.cost(ws, n, y, cost)
+            ext = (y.max(dim=0).values - y.min(dim=0).values).double()
+            log_rows.append({"t": t + 1, "kl": float(cost[0]), "cnorm": float(cost[1]),
+                             "z": float(z[0]), "grad_norm": float(torch.linalg.norm(grad.double())),
+                             "box_diagonal": float(torch.linalg.norm(ext))})
+    return log_rows
+
+
+def knn_overlap(x, y, rows, k=10):
+    """Mean over the query rows of |kNN_k in x  intersect  kNN_k in y| / k
+    (Euclidean, self excluded): an evaluation metric of a map, in torch on the
+    device (FP64 distances of the query rows to all points)."""
+    import torch
+
+    q = torch.as_tensor(rows, device=x.device, dtype=torch.long)
+
+    def nbrs(a):
+        a = a.double()
+        d = torch.cdist(a[q], a)
+        d[torch.arange(q.numel(), device=a.device), q] = float("inf")
+        return torch.topk(d, k, dim=1, largest=False).indices
+
+    nx, ny = nbrs(x), nbrs(y)
+    common = (nx.unsqueeze(2) == ny.unsqueeze(1)).any(dim=2).sum(dim=1)
+    return float(common.double().mean() / k)
 
 
 def surrogate_leg(x_train, y_train, perp, n_new=1 << 20, n_eval=65536, epochs=100, batch=1024):
@@ -217,7 +319,6 @@ def surrogate_leg(x_train, y_train, perp, n_new=1 << 20, n_eval=65536, epochs=10
     import numpy as np
     import torch
 
-    import oracle
     from paper_1812_09869_amd import synth
     from paper_1812_09869_amd.surrogate import Surrogate
     from paper_1812_09869_amd.tsne import ExactTSNE, Schedule
@@ -261,8 +362,7 @@ def surrogate_leg(x_train, y_train, perp, n_new=1 << 20, n_eval=65536, epochs=10
         t = t_end
         kl_rand[t_end] = float(model.cost(st0[0]).cpu()[0])
     rows = np.arange(0, n_eval, n_eval // 1024)
-    xe_np = xn_np[:n_eval]
-    ov = {k: oracle.knn_overlap(xe_np, v.cpu().numpy(), rows, 10)
+    ov = {k: knn_overlap(xe, v, rows, 10)
           for k, v in (("surrogate", ye), ("refined_100", st[0]), ("exact_1000", st0[0]))}
     reach = next((t for t, v in sorted(kl_rand.items()) if v <= kl_ref), None)
     res = {
@@ -508,44 +608,22 @@ def implicit_leg(x, perp=50.0, iters=10, modes=("fp64", "fp32", "bf16")):
 
 
 def precision_report(n=262144, d=128, perp=50.0):
-    """Errors of every distance mode against the FP64 oracle on the 10-D subspace
-    mixture at N=262,144, D=128 (the oracle cannot form all of P here, so it
-    computes sampled rows: beta of 64 rows, and P at the 30 nearest and 30 random
-    columns of 24 rows), plus gradient and KL at a fixed clustered map against
-    the FP64 mode. Prints one JSON line."""
+    """Time and error of every distance mode at N=262,144, D=128 (the 10-D
+    subspace mixture), against the FP64 mode: beta of every row, P on 24
+    sampled rows (relative Frobenius and largest-entry error), the gradient and
+    the KL at a fixed clustered map. The FP64 mode itself is held to the
+    oracle by the tests (tests/test_gpu_large.py runs every mode against the
+    oracle's statistics of all rows at 98,304 points of the same mixture).
+    Prints one JSON line."""
     import numpy as np
     import torch
 
-    import oracle
     from paper_1812_09869_amd import _lib, synth
 
     x_np, lab = synth.subspace(n, d=d)
     x = torch.from_numpy(x_np).cuda()
     rng = np.random.Generator(np.random.PCG64(5))
-    brow = np.sort(rng.choice(n, 64, replace=False))
     prow = np.sort(rng.choice(n, 24, replace=False))
-    t0 = time.perf_counter()
-    st_b = oracle.calibrate(x_np, perp, rows=brow)
-    ii, jj = [], []
-    xd = x_np.astype(np.float64)
-    for i in prow:
-        dist = ((xd - xd[i]) ** 2).sum(axis=1)
-        dist[i] = np.inf
-        cols = np.unique(np.concatenate([np.argsort(dist)[:30], rng.choice(n, 30, replace=False)]))
-        cols = cols[cols != i]
-        ii.extend([int(i)] * cols.size)
-        jj.extend(cols.tolist())
-    ii, jj = np.array(ii), np.array(jj)
-    need = np.unique(np.concatenate([ii, jj]))
-    st = oracle.calibrate(x_np, perp, rows=need)
-    pos = {r: k for k, r in enumerate(need)}
-
-    def pick(idx):
-        k = np.array([pos[r] for r in idx])
-        return oracle.RowStats(st.beta[k], st.m[k], st.S[k], st.H[k], st.iters[k])
-
-    p_ref = oracle.p_entries(x_np, ii, jj, pick(ii), pick(jj))
-    log(f"[precision] oracle references in {time.perf_counter() - t0:.1f} s")
     ws = _lib.new_workspace(n, d, max(MODES, key=lambda m: _lib.workspace_bytes(n, d, m)))
     y = torch.from_numpy(synth.clustered_state(lab, seed=41, spread=60.0)).cuda()
     gbuf = torch.empty_like(y)
@@ -559,29 +637,26 @@ def precision_report(n=262144, d=128, perp=50.0):
         torch.cuda.synchronize()
         status = _lib.sync_status(ws)
         beta = _lib.export_rowstats(ws, n)[0].cpu().numpy()
-        p_gpu = np.empty_like(p_ref)
-        for i in prow:
-            row = _lib.export_p_rows(ws, n, int(i), 1).cpu().numpy()[0].astype(np.float64)
-            sel = ii == i
-            p_gpu[sel] = row[jj[sel]]
+        p = torch.cat([_lib.export_p_rows(ws, n, int(i), 1) for i in prow]).double().cpu()
         _lib.gradient(ws, n, y, 1.0, gbuf)
         g = gbuf.double().cpu()
         _lib.cost(ws, n, y, cost)
         kl = float(cost[0].cpu())
         if ref is None:
-            ref = (g, kl)
-        big = p_ref >= 1e-3 * p_ref.max()
+            ref = (beta, p, g, kl)
+        pe = float(torch.linalg.norm(p - ref[1]) / torch.linalg.norm(ref[1]))
+        pm = float((p - ref[1]).abs().max() / ref[1].max())
+        ge = float(torch.linalg.norm(g - ref[2]) / torch.linalg.norm(ref[2]))
         out[mode] = {
             "status": status,
             "affinity_ms": e0.elapsed_time(e1),
-            "beta_maxrel_vs_oracle": float((np.abs(beta[brow] - st_b.beta) / st_b.beta).max()),
-            "p_maxrel_large_vs_oracle": float((np.abs(p_gpu - p_ref)[big] / p_ref[big]).max()),
-            "p_maxabs_over_max_vs_oracle": float(np.abs(p_gpu - p_ref).max() / p_ref.max()),
-            "p_rel_l2_sampled_vs_oracle": float(np.linalg.norm(p_gpu - p_ref) /
-                                                np.linalg.norm(p_ref)),
-            "grad_rel_vs_fp64": float(torch.linalg.norm(g - ref[0]) / torch.linalg.norm(ref[0])),
-            "kl_rel_vs_fp64": abs(kl - ref[1]) / ref[1],
+            "beta_maxrel_vs_fp64": float((np.abs(beta - ref[0]) / ref[0]).max()),
+            "p_rel_vs_fp64": pe,
+            "p_maxrel_vs_fp64": pm,
+            "grad_rel_vs_fp64": ge,
+            "kl_rel_vs_fp64": abs(kl - ref[3]) / ref[3],
             "kl": kl,
+            "meets_step_gates": bool(pe <= 1e-5 and pm <= 1e-5 and ge <= 1e-4),
         }
         log(f"[precision] {mode}: {out[mode]}")
     print(json.dumps({"workload": f"10-D subspace mixture, N={n}, D={d}, perplexity {perp:g}",
@@ -753,6 +828,7 @@ def main():
         "final_kl": kl,
         "final_cnorm": cnorm,
     }
+    out["run_log"] = monitor_leg(ws, n, y0, args.iters, sched)
     if not args.no_pakde:
         out["pakde"] = pakde_leg(y.clone())
     if not args.no_surrogate:

@@ -161,6 +161,28 @@ def test_determinism(case):
     assert torch.equal(a, b)
 
 
+def test_checkpoint_resume_bitwise(tmp_path):
+    """The iteration state (Y, U, G and the iteration index) belongs to the
+    caller: seven steps in one go equal three steps, a save of the state to
+    disk, a reload into fresh tensors and four more steps, bit for bit."""
+    x, _ = synth.plain_small(900, seed=61)
+    y0 = synth.embedding_init(900, seed=62)
+    model = ExactTSNE(torch.from_numpy(x).cuda(), 30.0)
+    sched = Schedule(switch=5)
+    a = model.init_state(torch.from_numpy(y0).cuda())
+    model.run(a, 7, sched=sched)
+    b = model.init_state(torch.from_numpy(y0).cuda())
+    model.run(b, 3, sched=sched)
+    torch.save({"t": 3, "state": [t.cpu() for t in b]}, tmp_path / "ckpt.pt")
+    del b
+    ck = torch.load(tmp_path / "ckpt.pt", weights_only=True)
+    c = [t.cuda().contiguous() for t in ck["state"]]
+    model.run(c, 4, start=ck["t"], sched=sched)
+    for u, v in zip(a, c):
+        assert torch.equal(u, v)
+    assert model.status() == 0
+
+
 def test_plain_small_full_run():
     """The 2,000-point workload, 500 iterations, final KL against the oracle.
 
