@@ -339,22 +339,27 @@ __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa,
 // rounding to the nearest integer at each level (|h1| <= 2^b, |h2|, |h3| <=
 // 2^(b-1), |r| <= sigma 2^(-2b-1)). b is the largest value with
 // 2b + log2(K) <= 24 (K = d rounded up to 32), at most 10 for FP16 and 8 for
-// BF16, so each slice is exact in 16 bits and the sums
-//   A0 = sum_k h1 h1',   A1 = sum_k (h1 h2' + h2 h1')
-// are integers below 2^24: the MFMA's FP32 accumulation adds them exactly,
-// in whatever order it works. The next sum,
-//   A2 = sum_k (h1 h3' + h2 h2' + h3 h1') + 2^-b sum_k (h2 h3' + h3 h2')
-// (the last two through stored copies 2^-b h3), lies 2^-2b lower and may
-// round. Then x.y = sigma^2 (A0 + 2^-b A1 + 2^-2b A2); the products left out
-// (h3 h3' and below) are under sigma^2 2^-4b K 2^2b. Eight MFMA products per
-// operand pair in all.
+// BF16, so each slice is exact in 16 bits and
+//   A0 = sum_k h1 h1'
+// is an integer below 2^24: the MFMA's FP32 accumulation adds it exactly, in
+// whatever order it works. The rest of the contraction, scaled by 2^b,
+//   R = sum_k (h1 h2' + h2 h1') + 2^-b (h1 h3' + h2 h2' + h3 h1')
+//       + 2^-2b (h2 h3' + h3 h2'),
+// is 2^-b smaller and is allowed to round. Its operands are stored as four
+// slices per point, [h1 | h2 | 2^-b h2 | 2^-b h3] (all normal numbers in
+// both formats), so R takes seven MFMA products and A0 one. Then
+//   x.y = sigma^2 (A0 + 2^-b R);
+// the product left out (h3 h3') is below sigma^2 2^-4b K 2^2b.
 // The norms are FP32 pairs (hi, lo) of the FP64 norm of the represented point
 // sigma (h1 + 2^-b h2 + 2^-2b h3). d = n_i + n_j - 2 x.y cancels most of its
 // operands, so it is formed with error-free transformations: TwoSum of the
 // two hi parts, TwoSum of that with -2 sigma^2 A0 (an exact product), then
-// the small terms (both TwoSum errors, the lo parts and
-// 2 sigma^2 (2^-b A1 + 2^-2b A2)) added to the leading difference. d then
-// carries about one FP32 rounding of d itself instead of one of |x|^2.
+// the small terms (both TwoSum errors, the lo parts and 2 sigma^2 2^-b R)
+// added to the leading difference. d then carries about one FP32 rounding of
+// d itself instead of one of |x|^2.
+// Operand layout: per point, per block of 32 values of k, the four slices'
+// 32 values in a row ([point][k / 32][slice][32]), so that the four
+// fragments a lane loads for one MFMA step sit in one 256-byte segment.
 // ----------------------------------------------------------------------------
 __host__ __device__ inline int x3_bits(int32_t k32, bool bf16) {
   int lk = 0;
@@ -373,8 +378,6 @@ __device__ inline int x3_exp(const Hdr *h) {
   return e;
 }
 
-// Four slice vectors of k32 values per point, [h1 | h2 | h3 | 2^-b h3], and
-// the (hi, lo) norm of the represented point.
 template <typename H>
 __global__ __launch_bounds__(256) void k_prep_x3(const double *__restrict__ xcT, int64_t npad,
                                                  int32_t d, int32_t k32, int32_t b,
@@ -393,10 +396,11 @@ __global__ __launch_bounds__(256) void k_prep_x3(const double *__restrict__ xcT,
     const double h2 = rint(r);
     r = ldexp(r - h2, b);
     const double h3 = rint(r);
-    row[k] = (H)(float)h1;
-    row[k32 + k] = (H)(float)h2;
-    row[2 * k32 + k] = (H)(float)h3;
-    row[3 * k32 + k] = (H)(float)ldexp(h3, -b);
+    H *blk = row + (k >> 5) * 128 + (k & 31);
+    blk[0] = (H)(float)h1;
+    blk[32] = (H)(float)h2;
+    blk[64] = (H)(float)ldexp(h2, -b);
+    blk[96] = (H)(float)ldexp(h3, -b);
     const double xr = ldexp(h1 + ldexp(h2 + ldexp(h3, -b), -b), E - b);
     nrm += xr * xr;
   }
@@ -412,68 +416,66 @@ __device__ __forceinline__ v4f mfma16x32(V8 a, V8 b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-// The three slice sums of a 64 x 64 block (4 x 4 MFMA tiles): rows ra .. ra+63
+// The two sums A0 and R of a 64 x 64 block (4 x 4 MFMA tiles): rows ra .. ra+63
 // against columns cb .. cb+63. Stored and recomputed P call this same routine,
 // so their sums agree bit for bit.
 template <typename H, typename V8>
 __device__ __forceinline__ void x3_contract(const H *__restrict__ xs, int32_t k32, int64_t ra,
                                             int64_t cb, int li, int lk, v4f (&A0)[4][4],
-                                            v4f (&A1)[4][4], v4f (&A2)[4][4]) {
+                                            v4f (&R)[4][4]) {
   const int64_t kk = 4 * (int64_t)k32;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       A0[t][c] = (v4f){0.f, 0.f, 0.f, 0.f};
-      A1[t][c] = A0[t][c];
-      A2[t][c] = A0[t][c];
+      R[t][c] = A0[t][c];
     }
   for (int k0 = 0; k0 < k32; k0 += 32) {
-    V8 a[4][4];  // [slice][row tile]
+    const int64_t off = (int64_t)(k0 >> 5) * 128 + 8 * lk;
+    V8 a[4][4];  // [slice][row tile]: h1, h2, 2^-b h2, 2^-b h3
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        a[q][t] = *reinterpret_cast<const V8 *>(xs + (ra + 16 * t + li) * kk + q * k32 + k0 +
-                                                8 * lk);
+        a[q][t] = *reinterpret_cast<const V8 *>(xs + (ra + 16 * t + li) * kk + off + 32 * q);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       V8 bv[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        bv[q] = *reinterpret_cast<const V8 *>(xs + (cb + 16 * c + li) * kk + q * k32 + k0 +
-                                              8 * lk);
+        bv[q] = *reinterpret_cast<const V8 *>(xs + (cb + 16 * c + li) * kk + off + 32 * q);
 #pragma unroll
       for (int t = 0; t < 4; ++t) A0[t][c] = mfma16x32<H, V8>(a[0][t], bv[0], A0[t][c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) A1[t][c] = mfma16x32<H, V8>(a[0][t], bv[1], A1[t][c]);
+      for (int t = 0; t < 4; ++t) R[t][c] = mfma16x32<H, V8>(a[0][t], bv[1], R[t][c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) A1[t][c] = mfma16x32<H, V8>(a[1][t], bv[0], A1[t][c]);
+      for (int t = 0; t < 4; ++t) R[t][c] = mfma16x32<H, V8>(a[1][t], bv[0], R[t][c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[0][t], bv[2], A2[t][c]);
+      for (int t = 0; t < 4; ++t) R[t][c] = mfma16x32<H, V8>(a[0][t], bv[3], R[t][c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[1][t], bv[1], A2[t][c]);
+      for (int t = 0; t < 4; ++t) R[t][c] = mfma16x32<H, V8>(a[1][t], bv[2], R[t][c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[2][t], bv[0], A2[t][c]);
+      for (int t = 0; t < 4; ++t) R[t][c] = mfma16x32<H, V8>(a[3][t], bv[0], R[t][c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[1][t], bv[3], A2[t][c]);
+      for (int t = 0; t < 4; ++t) R[t][c] = mfma16x32<H, V8>(a[2][t], bv[3], R[t][c]);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) A2[t][c] = mfma16x32<H, V8>(a[3][t], bv[1], A2[t][c]);
+      for (int t = 0; t < 4; ++t) R[t][c] = mfma16x32<H, V8>(a[3][t], bv[2], R[t][c]);
     }
   }
 }
 
-// 2 sigma^2, 2 sigma^2 2^-b, 2 sigma^2 2^-2b
+// 2 sigma^2 and 2 sigma^2 2^-b
 struct X3Scale {
-  float s0, s1, s2;
+  float s0, s1;
 };
 __device__ inline X3Scale x3_scale(const Hdr *h, int b) {
   const int e = 2 * (x3_exp(h) - b) + 1;
-  return X3Scale{ldexpf(1.f, e), ldexpf(1.f, e - b), ldexpf(1.f, e - 2 * b)};
+  return X3Scale{ldexpf(1.f, e), ldexpf(1.f, e - b)};
 }
 
-// d = n_i + n_j - 2 x.y from (hi, lo) norms and the three slice sums
-__device__ __forceinline__ float x3_combine(float2 ni, float2 nj, float a0, float a1, float a2,
+// d = n_i + n_j - 2 x.y from (hi, lo) norms and the two sums
+__device__ __forceinline__ float x3_combine(float2 ni, float2 nj, float a0, float r,
                                             const X3Scale &sc) {
   const float s = __fadd_rn(ni.x, nj.x);
   const float bs = __fsub_rn(s, ni.x);
@@ -483,14 +485,14 @@ __device__ __forceinline__ float x3_combine(float2 ni, float2 nj, float a0, floa
   const float bt = __fsub_rn(t, s);
   const float e2 = __fadd_rn(__fsub_rn(s, __fsub_rn(t, bt)), __fsub_rn(-big, bt));
   const float low = __fsub_rn(__fadd_rn(__fadd_rn(e1, e2), __fadd_rn(ni.y, nj.y)),
-                              __fadd_rn(__fmul_rn(sc.s1, a1), __fmul_rn(sc.s2, a2)));
+                              __fmul_rn(sc.s1, r));
   return fmaxf(__fadd_rn(t, low), 0.f);
 }
 
 // Distance block of the x3 modes: a workgroup covers 64 rows x 256 columns,
 // as k_dist_lp.
 template <typename H, typename V8>
-__global__ __launch_bounds__(256) void k_dist_x3(const H *__restrict__ xs,
+__global__ __launch_bounds__(256, 2) void k_dist_x3(const H *__restrict__ xs,
                                                  const float2 *__restrict__ nhl, int64_t npad,
                                                  int32_t k32, int32_t bits, int32_t b,
                                                  float *__restrict__ dblock, const Hdr *h) {
@@ -499,8 +501,8 @@ __global__ __launch_bounds__(256) void k_dist_x3(const H *__restrict__ xs,
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
-  v4f A0[4][4], A1[4][4], A2[4][4];
-  x3_contract<H, V8>(xs, k32, row0, col0, li, lk, A0, A1, A2);
+  v4f A0[4][4], R[4][4];
+  x3_contract<H, V8>(xs, k32, row0, col0, li, lk, A0, R);
   const X3Scale sc = x3_scale(h, bits);
   float2 nj[4];
 #pragma unroll
@@ -514,8 +516,7 @@ __global__ __launch_bounds__(256) void k_dist_x3(const H *__restrict__ xs,
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t j = col0 + c * 16 + li;
-        dblock[(int64_t)il * npad + j] =
-            x3_combine(ni, nj[c], A0[t][c][r], A1[t][c][r], A2[t][c][r], sc);
+        dblock[(int64_t)il * npad + j] = x3_combine(ni, nj[c], A0[t][c][r], R[t][c][r], sc);
       }
     }
   }
@@ -1031,7 +1032,7 @@ __global__ __launch_bounds__(256) void k_tdist_lp(const H *__restrict__ xa,
 // x3 modes: as k_tdist_lp, a workgroup covers 64 rows x 256 columns of the
 // tile; the sums come from the same routine as the stored path's.
 template <typename H, typename V8, bool PACK>
-__global__ __launch_bounds__(256) void k_tdist_x3(const H *__restrict__ xs,
+__global__ __launch_bounds__(256, 2) void k_tdist_x3(const H *__restrict__ xs,
                                                   const float2 *__restrict__ nhl, int32_t k32,
                                                   int32_t bits, int32_t nb, int64_t tile0,
                                                   int64_t tile_base, float *__restrict__ Pb,
@@ -1050,8 +1051,8 @@ __global__ __launch_bounds__(256) void k_tdist_x3(const H *__restrict__ xs,
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)I * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
-  v4f A0[4][4], A1[4][4], A2[4][4];
-  x3_contract<H, V8>(xs, k32, row0, col0, li, lk, A0, A1, A2);
+  v4f A0[4][4], R[4][4];
+  x3_contract<H, V8>(xs, k32, row0, col0, li, lk, A0, R);
   const X3Scale sc = x3_scale(guard, bits);
   float *tp = Pb + (size_t)(tile - tile_base) * T * T;
   PtStat scs[4];
@@ -1072,7 +1073,7 @@ __global__ __launch_bounds__(256) void k_tdist_x3(const H *__restrict__ xs,
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int jl = cl0 + c * 16 + li;
-        const float dd = x3_combine(ni, nj[c], A0[t][c][r], A1[t][c][r], A2[t][c][r], sc);
+        const float dd = x3_combine(ni, nj[c], A0[t][c][r], R[t][c][r], sc);
         v[c] = tile_value<PACK>(dd, diag, il, jl, si, scs[c]);
       }
       if (!diag) {
