@@ -525,9 +525,13 @@ __global__ __launch_bounds__(256, 2) void k_dist_x3(const H *__restrict__ xs,
 // ----------------------------------------------------------------------------
 // 2b. Per-row search for beta (Eqs. 1-2).
 //
-// One workgroup of 1024 threads per row. The row's distances, shifted by the
-// row minimum m, are held in registers (VPT per thread) when they fit, else
-// re-read from the block scratch on every pass. Each pass forms, with FP32
+// One workgroup of 1024 threads per row, one launch for the rows of a group
+// of consecutive row blocks (their distances side by side in the scratch;
+// b is the group's first block), so that rows needing more passes than
+// others are spread over the compute units instead of setting the length of
+// every block's launch. The row's distances, shifted by the row minimum m,
+// are held in registers (VPT per thread) when they fit, else re-read from
+// the scratch on every pass. Each pass forms, with FP32
 // exponentials and FP32 per-thread partial sums combined in FP64,
 //   S = sum_j exp(-beta (d_j - m)),  T = sum_j (d_j - m) exp(-beta (d_j - m)),
 //   Q = sum_j (d_j - m)^2 exp(-beta (d_j - m)),
@@ -535,11 +539,17 @@ __global__ __launch_bounds__(256, 2) void k_dist_x3(const H *__restrict__ xs,
 // where beta is the FP32-rounded precision actually applied. The paper
 // leaves the search to a supplement it does not include; H decreases in
 // beta, so any bracketed search that reaches the tolerance finds the same
-// root. Bracket logic: start at beta = 1 with [0, inf); each pass moves one
-// end of the bracket to beta, then takes the Newton step if it lands inside
-// the bracket, else doubles beta (no upper end yet) or bisects. Stops at
-// |H - ln u| <= tol_h, at a bracket narrower than FP32 resolution, or after
-// max_bisect passes (then the row is flagged as not converged).
+// root. Bracket logic: start with [0, inf) at the beta of the same position
+// in the row block before the group (a nearby point in the locality order;
+// 1 for the first group); each pass moves one end of the bracket to beta, then takes
+// the Newton step if it lands inside the bracket, else doubles beta (no
+// upper end yet) or bisects. Stops at |H - ln u| <= tol_h, at a bracket
+// narrower than FP32 resolution, or after max_bisect passes (then the row is
+// flagged as not converged).
+// The per-wave FP64 partial sums meet in LDS (double-buffered by pass
+// parity); every wave then reduces them in the same fixed order and takes
+// the same step, so one barrier per pass suffices and no thread waits for
+// another's serial arithmetic.
 // ----------------------------------------------------------------------------
 constexpr int kCalThreads = 1024;
 
@@ -549,15 +559,23 @@ struct CalOut {
   int32_t *evals;
 };
 
+// sum over the 16 lanes of each DPP row group, the same in every lane of the
+// group (xor butterfly of exactly commutative additions)
+__device__ inline double sum16_d(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <int VPT>
 __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restrict__ dblock,
                                                            int64_t n, int64_t npad, int32_t b,
                                                            double logu, int max_bisect,
                                                            double tol_h, CalOut out, Hdr *h) {
-  __shared__ double sred[3][kCalThreads / 64];
-  __shared__ float smin[kCalThreads / 64];
-  __shared__ double sbeta;
-  __shared__ int sdone;
+  constexpr int NW = kCalThreads / 64;
+  static_assert(NW == 16, "one partial per lane of a 16-lane group");
+  __shared__ double sred[2][3][NW];
+  __shared__ float smin[NW];
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
   const int64_t i = (int64_t)b * T + blockIdx.x;
   if (i >= n) return;
@@ -583,89 +601,93 @@ __global__ __launch_bounds__(kCalThreads) void k_calibrate(const float *__restri
   __syncthreads();
   float m = smin[0];
 #pragma unroll
-  for (int q = 1; q < kCalThreads / 64; ++q) m = fminf(m, smin[q]);
+  for (int q = 1; q < NW; ++q) m = fminf(m, smin[q]);
   if constexpr (VPT > 0) {
 #pragma unroll
     for (int q = 0; q < VPT; ++q) v[q] = (v[q] == INFINITY) ? kBig : v[q] - m;
   }
 
-  double beta = 1.0, lo = 0.0, hi = INFINITY, S = 0.0, H = 0.0;
+  double beta = 1.0;
+  if (b > 0) {
+    const double bp = out.beta[(int64_t)(b - 1) * T + (blockIdx.x & (T - 1))];
+    if (bp > 0.0 && isfinite(bp)) beta = bp;
+  }
+  double lo = 0.0, hi = INFINITY, S = 0.0, H = 0.0;
   float a = 0.f;
-  int it = 0;
-  bool ok = false;
+  int it = 0, done = 0;
   for (;;) {
     ++it;
     a = fmaxf((float)(beta * kLog2e), 1e-30f);
-    float s = 0.f, tt = 0.f, qq = 0.f;
+    float s0 = 0.f, s1 = 0.f, t0 = 0.f, t1 = 0.f, q0 = 0.f, q1 = 0.f;
     if constexpr (VPT > 0) {
 #pragma unroll
-      for (int q = 0; q < VPT; ++q) {
-        const float e = __builtin_amdgcn_exp2f(-a * v[q]);
-        const float ve = v[q] * e;  // 0 for an excluded entry (e = 0)
-        s += e;
-        tt += ve;
-        qq = fmaf(v[q], ve, qq);
+      for (int q = 0; q < VPT; q += 2) {
+        const float e0 = __builtin_amdgcn_exp2f(-a * v[q]);
+        const float ve0 = v[q] * e0;  // 0 for an excluded entry (e = 0)
+        s0 += e0;
+        t0 += ve0;
+        q0 = fmaf(v[q], ve0, q0);
+        if (q + 1 < VPT) {
+          const float e1 = __builtin_amdgcn_exp2f(-a * v[q + 1]);
+          const float ve1 = v[q + 1] * e1;
+          s1 += e1;
+          t1 += ve1;
+          q1 = fmaf(v[q + 1], ve1, q1);
+        }
       }
     } else {
       for (int64_t j = tid; j < n; j += kCalThreads) {
         const float dm = (j == i) ? kBig : row[j] - m;
         const float e = __builtin_amdgcn_exp2f(-a * dm);
         const float ve = dm * e;
-        s += e;
-        tt += ve;
-        qq = fmaf(dm, ve, qq);
+        s0 += e;
+        t0 += ve;
+        q0 = fmaf(dm, ve, q0);
       }
     }
-    double ds = wave_sum_d((double)s), dt = wave_sum_d((double)tt), dq = wave_sum_d((double)qq);
+    const int par = it & 1;
+    const double ds = wave_sum_d((double)(s0 + s1)), dt = wave_sum_d((double)(t0 + t1)),
+                 dq = wave_sum_d((double)(q0 + q1));
     if (ln == 0) {
-      sred[0][wv] = ds;
-      sred[1][wv] = dt;
-      sred[2][wv] = dq;
+      sred[par][0][wv] = ds;
+      sred[par][1][wv] = dt;
+      sred[par][2][wv] = dq;
     }
     __syncthreads();
-    if (tid == 0) {
-      double SS = 0.0, TT = 0.0, QQ = 0.0;
-      for (int q = 0; q < kCalThreads / 64; ++q) {
-        SS += sred[0][q];
-        TT += sred[1][q];
-        QQ += sred[2][q];
-      }
-      const double beff = (double)a * kLn2;
-      S = SS;
-      const double mean = TT / SS;
-      H = log(SS) + beff * mean;
-      int done = 0;
-      if (fabs(H - logu) <= tol_h) {
-        done = 1;
-      } else if (isfinite(hi) && (hi - lo) <= hi * 0x1p-24) {
-        done = 1;
-      } else if (it >= max_bisect) {
-        done = 2;
-      } else {
-        // H falls with beta (dH/dbeta = -beta Var(d)): shrink the bracket of
-        // FP64 iterates, then take the Newton step if it lands inside it,
-        // else bisect (H was taken at beff, within 2^-24 of beta)
-        if (H > logu)
-          lo = beta;
-        else
-          hi = beta;
-        const double var = QQ / SS - mean * mean;
-        const double nb = beta + (H - logu) / (beff * var);
-        if (var > 0.0 && nb > lo && nb < hi && isfinite(nb))
-          beta = nb;
-        else
-          beta = isinf(hi) ? 2.0 * beta : 0.5 * (lo + hi);
-      }
-      sbeta = beta;
-      sdone = done;
-      ok = (done == 1);
+    // every wave: the 16 wave partials, summed in one fixed order
+    const int k16 = ln & 15;
+    const double SS = sum16_d(sred[par][0][k16]), TT = sum16_d(sred[par][1][k16]),
+                 QQ = sum16_d(sred[par][2][k16]);
+    const double beff = (double)a * kLn2;
+    S = SS;
+    const double mean = TT / SS;
+    H = log(SS) + beff * mean;
+    if (fabs(H - logu) <= tol_h) {
+      done = 1;
+    } else if (isfinite(hi) && (hi - lo) <= hi * 0x1p-24) {
+      done = 1;
+    } else if (it >= max_bisect) {
+      done = 2;
+    } else {
+      // H falls with beta (dH/dbeta = -beta Var(d)): shrink the bracket of
+      // FP64 iterates, then take the Newton step if it lands inside it,
+      // else bisect (H was taken at beff, within 2^-24 of beta)
+      if (H > logu)
+        lo = beta;
+      else
+        hi = beta;
+      const double var = QQ / SS - mean * mean;
+      const double nb = beta + (H - logu) / (beff * var);
+      if (var > 0.0 && nb > lo && nb < hi && isfinite(nb))
+        beta = nb;
+      else
+        beta = isinf(hi) ? 2.0 * beta : 0.5 * (lo + hi);
     }
-    __syncthreads();
-    if (sdone) break;
-    beta = sbeta;
+    if (done) break;
   }
   if (tid == 0) {
     const double beff = (double)a * kLn2;
+    const bool ok = (done == 1);
     out.beta[i] = beff;
     out.S[i] = S;
     out.H[i] = H;
@@ -1985,13 +2007,12 @@ __global__ void k_set_ready(Hdr *h, int32_t ready) {
 // Host-side sequencing
 // ----------------------------------------------------------------------------
 
-// Distances of row block b against all columns into the block scratch, in
-// the workspace's distance mode. xc, nrm: the centred X and its norms for the
+// Distances of row block b against all columns into dblock (its slot of the
+// group scratch), in the workspace's distance mode. xc, nrm: the centred X and its norms for the
 // FP64 mode (the reduced modes read their prepared operands).
 static void launch_dist(const Layout &L, void *ws, int b, const double *xc, const double *nrm,
-                        hipStream_t st) {
+                        float *dblock, hipStream_t st) {
   const Hdr *h = at<const Hdr>(ws, L.hdr);
-  float *dblock = at<float>(ws, L.dblock);
   const float *norms32 = at<const float>(ws, L.norms32);
   const dim3 dgrid((unsigned)(L.npad / 256), T / 64);
   switch (L.mode) {
@@ -2085,12 +2106,18 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
         break;
     }
   };
-  // Distances of row block b (into the block scratch), all columns.
+  // Row blocks are handled in groups of L.cal_group: block b's distances go
+  // to slot b - b0 of the scratch (b0 the group's first block).
+  auto slot = [&](int b) { return dblock + (size_t)(b % L.cal_group) * T * L.npad; };
+  auto group_end = [&](int b0) { return b0 + L.cal_group < L.nb ? b0 + L.cal_group : L.nb; };
+  // Distances of row block b (into its slot), all columns.
   auto dist = [&](int b, const double *xc, const double *nrm) {
-    launch_dist(L, ws, b, xc, nrm, st);
+    launch_dist(L, ws, b, xc, nrm, slot(b), st);
   };
+  // The search over every row of the group starting at block b.
   auto calibrate = [&](int b) {
-    const int rows = (int)((L.n - (int64_t)b * T) < T ? (L.n - (int64_t)b * T) : T);
+    const int64_t left = L.n - (int64_t)b * T, span = (int64_t)L.cal_group * T;
+    const int rows = (int)(left < span ? left : span);
     dim3 g(rows), blk(kCalThreads);
     if (vpt_need <= 1)
       hipLaunchKernelGGL(k_calibrate<1>, g, blk, 0, st, dblock, L.n, L.npad, b, logu, max_bisect,
@@ -2130,12 +2157,14 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   if (dis) {
     // given dissimilarities: no coordinates, so no ordering tree; the squared
     // rows take the place of the contraction
-    for (int b = 0; b < L.nb; ++b) {
-      hipLaunchKernelGGL(k_dissim_block, dim3((unsigned)(L.npad / 256), T / 16), dim3(256), 0, st,
-                         dis, L.n, L.npad, b, dblock, h);
-      calibrate(b);
-      hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
-                         L.nb, b, P);
+    for (int b0 = 0; b0 < L.nb; b0 += L.cal_group) {
+      for (int b = b0; b < group_end(b0); ++b)
+        hipLaunchKernelGGL(k_dissim_block, dim3((unsigned)(L.npad / 256), T / 16), dim3(256), 0,
+                           st, dis, L.n, L.npad, b, slot(b), h);
+      calibrate(b0);
+      for (int b = b0; b < group_end(b0); ++b)
+        hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, slot(b),
+                           L.npad, L.nb, b, P);
     }
     pack();
     return hipGetLastError();
@@ -2196,12 +2225,13 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   }
   // Distances, calibration and staging block by block, then P.
   prep(xc);
-  for (int b = 0; b < L.nb; ++b) {
-    dist(b, xc, nrm);
-    calibrate(b);
+  for (int b0 = 0; b0 < L.nb; b0 += L.cal_group) {
+    for (int b = b0; b < group_end(b0); ++b) dist(b, xc, nrm);
+    calibrate(b0);
     if (!stats_only && !implicit)
-      hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, dblock, L.npad,
-                         L.nb, b, P);
+      for (int b = b0; b < group_end(b0); ++b)
+        hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, slot(b),
+                           L.npad, L.nb, b, P);
   }
   if (implicit) {
     // every pass rebuilds P from the contraction operands in the internal

@@ -70,7 +70,8 @@ Layout make_layout(int64_t n, int32_t d, int32_t mode, bool stats_only, bool imp
   L.xmean = take((size_t)L.dpad * 8);
   L.xcT = take((size_t)L.dpad * np * 8);
   L.norms = take(np * 8);
-  L.dblock = take((size_t)T * np * 4);
+  L.cal_group = L.nb < kCalGroup ? L.nb : kCalGroup;
+  L.dblock = take((size_t)L.cal_group * T * np * 4);
   L.npow2 = 1;
   while (L.npow2 < n) L.npow2 <<= 1;
   L.xcT2 = take(sz * (size_t)L.dpad * np * 8);

@@ -27,6 +27,7 @@ constexpr int64_t kImplicitTiles = 2048;  // implicit P: tiles recomputed per fo
 constexpr int T = 256;             // tile edge
 constexpr int TT4 = T * T / 4;     // float4 per tile
 constexpr int kThreads = 256;      // threads per tile workgroup
+constexpr int kCalGroup = 4;       // row blocks per launch of the per-row search
 constexpr uint64_t kMagic = 0x74534E4533353501ull;
 
 // Error bits of the device flag word.
@@ -70,6 +71,7 @@ struct Layout {
   size_t extent = 0;  // float4 [nb]: per-block {min x, max x, min y, max y} of that map
   size_t iter_end = 0;  // end of the part that tsne_step needs
   int32_t kk = 0;  // 16-bit operand values per point (d rounded up to 32; four slices in the x3 modes)
+  int32_t cal_group = 1;  // row blocks per search launch (their distance blocks side by side)
   size_t xmean = 0, xcT = 0, norms = 0, dblock = 0;
   size_t xcT2 = 0, norms2 = 0, keys = 0, vals = 0;  // reordering
   int64_t npow2 = 0;
