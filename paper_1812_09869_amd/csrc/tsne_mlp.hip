@@ -147,6 +147,21 @@ __device__ inline float row16_sum_f(float v) {
   return v;
 }
 
+// v + (v of lane l ^ 32) and v + (v of lane l ^ 16) in every lane, with the
+// gfx950 lane-swap instructions (VALU, no LDS crossbar): permlane32_swap(v, v)
+// leaves the two halves of the wave in its two results, permlane16_swap(v, v)
+// the even and odd rows of 16.
+__device__ inline float add_xor32(float v) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ inline float add_xor16(float v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
 template <int H, int W>
 __global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
     const float *__restrict__ x, int64_t n, int d_in, const float *__restrict__ mean,
@@ -190,31 +205,44 @@ __global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
     }
   const float c0 = b3[0], c1 = b3[1];
   const int64_t ntiles = (n + kInferRows - 1) / kInferRows;
-  constexpr int XM = kInferRows * kK1 / NT;
-  const int xk = t & (kK1 - 1), xr = t / kK1;
-  const bool kin = xk < d_in;
-  const int xkc = kin ? xk : d_in - 1;  // padding lanes load a real element and store 0
-  const float xmean = kin ? mean[xk] : 0.f, xinv = kin ? invstd[xk] : 0.f;
-  float xv[XM];
+  // the input tile: each thread loads two adjacent columns (xk, xk + 1) of
+  // XM rows and stores them as one 32-bit LDS write
+  constexpr int XM = kInferRows * kK1 / NT / 2;
+  constexpr int RS = NT / (kK1 / 2);  // rows covered per step
+  const int xk = 2 * (t & (kK1 / 2 - 1)), xr = t / (kK1 / 2);
+  const bool kin0 = xk < d_in, kin1 = xk + 1 < d_in;
+  const int xkc0 = kin0 ? xk : d_in - 1, xkc1 = kin1 ? xk + 1 : d_in - 1;  // padding lanes load a real element and store 0
+  const float xmean0 = kin0 ? mean[xk] : 0.f, xinv0 = kin0 ? invstd[xk] : 0.f;
+  const float xmean1 = kin1 ? mean[xk + 1] : 0.f, xinv1 = kin1 ? invstd[xk + 1] : 0.f;
+  float xv[XM][2];
   auto load_x = [&](int64_t tl) {
     if (tl >= ntiles) return;
     const float *xt = x + tl * kInferRows * d_in;  // uniform tile base
     const int64_t lim = n - tl * kInferRows;       // rows of this tile that exist
     if (lim >= kInferRows) {
 #pragma unroll
-      for (int m = 0; m < XM; ++m) xv[m] = xt[(xr + W * m) * d_in + xkc];
+      for (int m = 0; m < XM; ++m) {
+        xv[m][0] = xt[(xr + RS * m) * d_in + xkc0];
+        xv[m][1] = xt[(xr + RS * m) * d_in + xkc1];
+      }
     } else {
 #pragma unroll
       for (int m = 0; m < XM; ++m) {
-        const int rl = xr + W * m;
-        xv[m] = rl < lim ? xt[rl * d_in + xkc] : 0.f;
+        const int rl = xr + RS * m;
+        xv[m][0] = rl < lim ? xt[rl * d_in + xkc0] : 0.f;
+        xv[m][1] = rl < lim ? xt[rl * d_in + xkc1] : 0.f;
       }
     }
   };
   auto store_x = [&]() {
 #pragma unroll
-    for (int m = 0; m < XM; ++m)
-      xs[xr + W * m][xk] = (__bf16)((xv[m] - xmean) * xinv);  // 0 in padding lanes
+    for (int m = 0; m < XM; ++m) {
+      typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+      v2bf pr;
+      pr[0] = (__bf16)((xv[m][0] - xmean0) * xinv0);  // 0 in padding lanes
+      pr[1] = (__bf16)((xv[m][1] - xmean1) * xinv1);
+      *reinterpret_cast<v2bf *>(&xs[xr + RS * m][xk]) = pr;
+    }
   };
   load_x(blockIdx.x);
   store_x();
@@ -287,10 +315,10 @@ __global__ __launch_bounds__(64 * W, 1) void k_mlp_infer(
           s0 = fmaf(u0[e][r], hh, s0);
           s1 = fmaf(u1[e][r], hh, s1);
         }
-      s0 += __shfl_xor(s0, 32);
-      s1 += __shfl_xor(s1, 32);
-      s0 += __shfl_xor(s0, 16);
-      s1 += __shfl_xor(s1, 16);
+      s0 = add_xor32(s0);
+      s1 = add_xor32(s1);
+      s0 = add_xor16(s0);
+      s1 = add_xor16(s1);
       po[w][16 * a + c][0] = s0;  // the four lanes of a column hold the same sums
       po[w][16 * a + c][1] = s1;
     }

@@ -4,9 +4,11 @@ Kernel parity compares with the oracle run with the same BF16 operand
 rounding (so the remaining difference is FP32 accumulation order), and reports
 the distance to the plain FP64 network as well. The quality of the learned
 map itself is parity unpinned (the surrogate is not in the paper); the gain
-test shows what it buys: at an equal budget of 100 exact iterations,
-refining the surrogate's map reaches a lower KL than exact t-SNE from a random
-start.
+test shows what it buys: at an equal schedule and budget of 100 exact
+iterations, refining the surrogate's map reaches a lower KL than exact t-SNE
+from a random start, and a random start with the standard schedule needs at
+least 300 iterations to get there; the learned map's KL and 10-NN overlap are
+bounded against exact t-SNE.
 """
 import numpy as np
 import pytest
@@ -130,7 +132,22 @@ def test_adam_parity():
 
 
 def test_training_gain():
-    """Scaled-down surrogate experiment (N = 8,192 in D = 50)."""
+    """Scaled-down surrogate experiment (N = 8,192 in D = 50): what the trained
+    network buys over exact t-SNE alone, on new points from the same mixture.
+
+    * At the same schedule and budget (100 iterations at exaggeration 1,
+      momentum 0.8, learning rate 200), refining the network's map ends at a
+      lower KL than starting from a random map.
+    * With the standard schedule (exaggeration for 250 iterations), a random
+      start needs at least 300 iterations to reach the KL of the 100-iteration
+      refinement.
+    * The quality of the learned map itself is bounded against exact t-SNE
+      (1,000 iterations from a random start): its KL within 2x, and after
+      refinement within 15%, and the 10-NN overlap of the refined map at least
+      half of exact t-SNE's (measured at this size: 1.69x, 1.10x and 0.77).
+      The network is not in the paper, so these bounds are this test's, not
+      the paper's.
+    """
     n = 8192
     x, lab = synth.gmm_aniso(n, sample_seed=71)
     model = ExactTSNE(_t(x), 50.0)
@@ -151,13 +168,27 @@ def test_training_gain():
     st = new.init_state(ynet)
     new.run(st, 100, sched=refine)
     kl_ref = float(new.cost(st[0]).cpu()[0])
-    st0 = new.init_state(_t(synth.embedding_init(n, seed=74)))
-    new.run(st0, 100)
-    kl_rand = float(new.cost(st0[0]).cpu()[0])
+    y_rand = _t(synth.embedding_init(n, seed=74))
+    st_same = new.init_state(y_rand)
+    new.run(st_same, 100, sched=refine)
+    kl_same = float(new.cost(st_same[0]).cpu()[0])
+    st0 = new.init_state(y_rand)
+    kl_exact, t = {}, 0
+    for t_end in range(50, 1001, 50):
+        new.run(st0, t_end - t, start=t)
+        t = t_end
+        kl_exact[t_end] = float(new.cost(st0[0]).cpu()[0])
+    reach = next((t for t, v in sorted(kl_exact.items()) if v <= kl_ref), None)
     rows = np.arange(0, n, 16)
     ov_net = oracle.knn_overlap(xn, ynet.cpu().numpy(), rows, 10)
     ov_ref = oracle.knn_overlap(xn, st[0].cpu().numpy(), rows, 10)
-    print(f"  KL: surrogate {kl_net:.4f}, refined (100 it) {kl_ref:.4f}, random start (100 it) "
-          f"{kl_rand:.4f}; 10-NN overlap surrogate {ov_net:.3f}, refined {ov_ref:.3f}")
+    ov_exact = oracle.knn_overlap(xn, st0[0].cpu().numpy(), rows, 10)
+    print(f"  KL: surrogate {kl_net:.4f}, refined (100 it) {kl_ref:.4f}, random start with the "
+          f"refinement schedule (100 it) {kl_same:.4f}, exact (1,000 it) {kl_exact[1000]:.4f}; "
+          f"a random start reaches the refined KL after {reach} iterations")
+    print(f"  10-NN overlap: surrogate {ov_net:.3f}, refined {ov_ref:.3f}, exact {ov_exact:.3f}")
     assert new.status() == 0
-    assert kl_ref < kl_rand
+    assert kl_ref < kl_same
+    assert reach is None or reach >= 300
+    assert kl_net <= 2.0 * kl_exact[1000] and kl_ref <= 1.15 * kl_exact[1000]
+    assert ov_ref >= 0.5 * ov_exact
