@@ -21,8 +21,16 @@
  *     flag word inside the workspace, returned by tsne_sync_status().
  *   - Return values are tsne_status codes; tsne_last_error() gives a message
  *     for the last failing call of the calling thread.
- *   - Calls that share a workspace must be ordered on one stream; the
- *     library keeps no other state.
+ *   - Calls that share a workspace must be ordered on one stream.
+ *   - State kept by the library between calls, per device, created on first
+ *     use and held until the process ends: one non-blocking side stream and
+ *     two events on which the all-zero tiles of a force or cost pass run
+ *     beside the rest of the pass (forked from `stream` and joined back into
+ *     it, so a caller sees plain stream order; passes on one device are
+ *     serialised by a mutex while they are enqueued); four side streams and
+ *     their events for the per-thread affinities of tsne_pt_epoch; the
+ *     scratch array of tsne_mlp_forward_noalloc. All streams have the
+ *     default priority. Beyond that, only the thread-local error message.
  */
 #ifndef TSNE355_H
 #define TSNE355_H
@@ -122,7 +130,10 @@ typedef struct {
 } tsne_step_params;
 
 /* Bytes of workspace for n points in d dimensions with the given distance
- * mode; 0 if the arguments are out of range. Host-only, no device work. */
+ * mode; 0 if the arguments are out of range. Host-only, no device work.
+ * (The distance mode is the only option the size depends on, so it is
+ * passed alone rather than as a tsne_aff_opts; an implicit-P workspace has
+ * its own size function below.) */
 TSNE_API size_t tsne_workspace_bytes(int64_t n, int32_t d, int32_t dist_mode);
 
 /*

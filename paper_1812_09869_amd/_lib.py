@@ -80,7 +80,7 @@ class TsneError(RuntimeError):
 class AffOpts(ctypes.Structure):
     _fields_ = [("dist_mode", ctypes.c_int32), ("max_bisect", ctypes.c_int32),
                 ("tol_h", ctypes.c_double), ("reorder", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("implicit_p", ctypes.c_int32)]
 
 
 class BatchProblem(ctypes.Structure):
@@ -103,7 +103,7 @@ class PtOpts(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("layers", ctypes.c_int32),
                 ("perplexity", ctypes.c_double), ("momentum", ctypes.c_float),
                 ("iters", ctypes.c_int32), ("dist_mode", ctypes.c_int32),
-                ("reorder", ctypes.c_int32), ("implicit_p", ctypes.c_int32)]
+                ("reorder", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
