@@ -7,9 +7,11 @@ mixture (synthetic stand-in for the paper's GMM data sets), perplexity 50,
 0.5 before iteration 250, then 1 and 0.8, learning rate 200.
 
 One timed step is one complete pass of the hot path over that input, with X
-already resident in HBM: input affinities (centring, FP64-MFMA distances,
-per-row bisection, symmetric packed P), the 1,000 exact-gradient iterations
-(force pass + FP64 reduction + update), and the final KL cost. ``value`` is
+already resident in HBM: input affinities (centring, the locality order,
+MFMA distances in the chosen mode -- by default the compensated BF16 mode,
+which holds P to the FP64 oracle within the per-step gates -- per-row search
+for beta, symmetric packed P), the 1,000 exact-gradient iterations (force
+pass + FP64 reduction + update), and the final KL cost. ``value`` is
 end-to-end iterations per second over the timed steps.
 
 Prints one JSON line (stdout). Diagnostics go to stderr.
@@ -670,6 +672,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--iters", type=int, default=1000)
+    ap.add_argument("--dist-mode", default="bf16x3",
+                    help="distance mode of the timed affinities (default: the compensated BF16 "
+                         "mode, which meets the per-step parity gates)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the per-distance-mode affinity timing and error leg")
@@ -685,6 +690,10 @@ def main():
                     help="skip the parallel-scheme (ptSNE) leg")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate training / inference / evaluation leg")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 64-problem batched leg (prints its JSON object)")
+    ap.add_argument("--batched-sweeps", type=int, default=500,
+                    help="sweeps of the batched leg")
     ap.add_argument("--ptsne-only", action="store_true",
                     help="only run the parallel-scheme leg (prints its JSON object)")
     ap.add_argument("--ptsne-epochs", type=int, default=10,
@@ -710,6 +719,9 @@ def main():
     if args.ptsne_only:
         print(json.dumps(ptsne_leg(args.ptsne_epochs)), flush=True)
         return
+    if args.batched_only:
+        print(json.dumps(batched_leg(args.batched_sweeps)), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -728,7 +740,7 @@ def main():
     dev = torch.device("cuda:0")
     x = torch.from_numpy(x_np).to(dev)
     y0 = torch.from_numpy(y0_np).to(dev)
-    ws = _lib.new_workspace(n, d)
+    ws = _lib.new_workspace(n, d, args.dist_mode)
     y = torch.empty_like(y0)
     u = torch.empty_like(y0)
     g = torch.empty_like(y0)
@@ -745,7 +757,7 @@ def main():
             events["aff"].append((torch.cuda.Event(enable_timing=True),
                                   torch.cuda.Event(enable_timing=True)))
             events["aff"][-1][0].record()
-        _lib.affinities(x, perp, ws)
+        _lib.affinities(x, perp, ws, dist_mode=args.dist_mode)
         if events is not None:
             events["aff"][-1][1].record()
         for t in range(args.iters):
@@ -818,7 +830,7 @@ def main():
             "d": d,
             "perplexity": perp,
             "iterations_per_step": args.iters,
-            "dist_mode": "fp64",
+            "dist_mode": args.dist_mode,
         },
         "roofline": rl,
         "steady_iters_per_s": 1e3 / steady_ms,
@@ -838,7 +850,7 @@ def main():
         del ws
         torch.cuda.empty_cache()
     if not args.no_batched:
-        out["batched"] = batched_leg()
+        out["batched"] = batched_leg(args.batched_sweeps)
         torch.cuda.empty_cache()
     if not args.no_ptsne:
         out["ptsne"] = ptsne_leg(args.ptsne_epochs)

@@ -71,11 +71,12 @@ typedef enum {
  * The x3 modes remove it. Every centred coordinate is cut on one grid for the
  * whole input into three integer slices (x = sigma (h1 + 2^-b h2 + 2^-2b h3)
  * plus a remainder below sigma 2^(-2b-1), with b <= 10 for FP16 and <= 8 for
- * BF16 and 2b + log2(K) <= 24 for K = d rounded up to 32). Eight MFMA
- * products per operand pair, summed in FP32, give the leading two slice sums
- * exactly (integers below 2^24) and the third 2^-2b lower; the norms are FP32
- * (hi, lo) pairs, and n_i + n_j - 2 x.y is formed with error-free
- * transformations (TwoSum), so d carries about one FP32 rounding of d itself. */
+ * BF16 and 2b + log2(K) <= 24 for K = d rounded up to 32). One MFMA product
+ * per operand pair gives the leading slice sum, an integer below 2^24 that
+ * the FP32 accumulation adds exactly; seven more give the rest, 2^-b lower.
+ * The norms are FP32 (hi, lo) pairs, and n_i + n_j - 2 x.y is formed with an
+ * error-free sum of the hi parts (TwoSum) and an exact leading difference
+ * (Sterbenz), so d carries about one FP32 rounding of d itself. */
 typedef enum {
   TSNE_DIST_FP64 = 0,   /* FP64 MFMA on the centred input (default) */
   TSNE_DIST_FP32 = 1,   /* FP32 MFMA */

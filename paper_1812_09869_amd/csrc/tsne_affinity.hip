@@ -353,10 +353,10 @@ __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa,
 // The norms are FP32 pairs (hi, lo) of the FP64 norm of the represented point
 // sigma (h1 + 2^-b h2 + 2^-2b h3). d = n_i + n_j - 2 x.y cancels most of its
 // operands, so it is formed with error-free transformations: TwoSum of the
-// two hi parts, TwoSum of that with -2 sigma^2 A0 (an exact product), then
-// the small terms (both TwoSum errors, the lo parts and 2 sigma^2 2^-b R)
-// added to the leading difference. d then carries about one FP32 rounding of
-// d itself instead of one of |x|^2.
+// two hi parts, the exact difference of that sum and 2 sigma^2 A0, then the
+// small terms (the TwoSum error, the lo parts and 2 sigma^2 2^-b R) added to
+// the leading difference. d then carries about one FP32 rounding of d
+// itself instead of one of |x|^2.
 // Operand layout: per point, per block of 32 values of k, the four slices'
 // 32 values in a row ([point][k / 32][slice][32]), so that the four
 // fragments a lane loads for one MFMA step sit in one 256-byte segment.
@@ -474,18 +474,19 @@ __device__ inline X3Scale x3_scale(const Hdr *h, int b) {
   return X3Scale{ldexpf(1.f, e), ldexpf(1.f, e - b)};
 }
 
-// d = n_i + n_j - 2 x.y from (hi, lo) norms and the two sums
+// d = n_i + n_j - 2 x.y from (hi, lo) norms and the two sums. The sum of the
+// hi parts is taken with TwoSum (its rounding error e is kept); the leading
+// difference t = s - 2 sigma^2 A0 needs no correction: the product is exact,
+// and where the operands cancel (2 sigma^2 A0 >= s / 2, i.e. d below about
+// s / 2) the subtraction is exact by Sterbenz's lemma, while elsewhere its
+// rounding is below one FP32 ulp of d itself.
 __device__ __forceinline__ float x3_combine(float2 ni, float2 nj, float a0, float r,
                                             const X3Scale &sc) {
   const float s = __fadd_rn(ni.x, nj.x);
   const float bs = __fsub_rn(s, ni.x);
-  const float e1 = __fadd_rn(__fsub_rn(ni.x, __fsub_rn(s, bs)), __fsub_rn(nj.x, bs));
-  const float big = __fmul_rn(sc.s0, a0);  // exact: an integer below 2^24 times a power of two
-  const float t = __fsub_rn(s, big);
-  const float bt = __fsub_rn(t, s);
-  const float e2 = __fadd_rn(__fsub_rn(s, __fsub_rn(t, bt)), __fsub_rn(-big, bt));
-  const float low = __fsub_rn(__fadd_rn(__fadd_rn(e1, e2), __fadd_rn(ni.y, nj.y)),
-                              __fmul_rn(sc.s1, r));
+  const float e = __fadd_rn(__fsub_rn(ni.x, __fsub_rn(s, bs)), __fsub_rn(nj.x, bs));
+  const float t = __fsub_rn(s, __fmul_rn(sc.s0, a0));  // a0: an integer below 2^24
+  const float low = __fsub_rn(__fadd_rn(e, __fadd_rn(ni.y, nj.y)), __fmul_rn(sc.s1, r));
   return fmaxf(__fadd_rn(t, low), 0.f);
 }
 
