@@ -18,6 +18,6 @@ separate, is gated at 1e-4 separately.
 
 def final_kl_gate(kl_gpu: float, kl_ref: float, ensemble):
     """(passes, band, tolerance) of the rule above."""
-    band = max(abs(k - kl_ref) for k in ensemble)
+    band = max((abs(k - kl_ref) for k in ensemble), default=0.0)
     tol = max(1.5 * band, 1e-3 * kl_ref)
     return abs(kl_gpu - kl_ref) <= tol, band, tol

@@ -11,22 +11,36 @@ any size:
   * sum P = 1 and sum_j P_ij > 1/(2N) (Eq. 3);
   * Z over all ordered pairs (oracle, O(N^2) on the map alone);
   * the repulsive gradient (alpha = 0) of sampled rows (needs only the map);
+  * the full gradient (attraction and repulsion, alpha = 1 and 12) of 200
+    sampled rows against Eq. 6 with the oracle's rows of P, formed from the
+    oracle's statistics of all 65,536 rows (stored by
+    tests/golden/make_c2_reference.py), at a clustered map and at the oracle's
+    own maps after 249 and 999 iterations; the x3 distance modes against the
+    same rows;
+  * the whole 1,000-iteration run from the benchmark's initial map against the
+    oracle's run (KL after 1 and 10 iterations within 1e-4, the final KL
+    under the shared chaos gate);
   * zero-sum and linearity in alpha of the full gradient;
   * pseudo-normalised cost ~ 1 at the random initial map (Eq. 9).
 """
+import json
 import math
+import os
+import time
 
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from chaos_gate import final_kl_gate
 from paper_1812_09869_amd import _lib, synth
 from paper_1812_09869_amd.tsne import ExactTSNE
 
 pytestmark = pytest.mark.gpu
 
 PERP = 50.0
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def test_mid_size_full_parity():
@@ -165,3 +179,113 @@ def test_full_cost_at_init(full):
     # at a map of radius ~0.01 every q is within ~1e-3 of 1/(n(n-1))
     assert abs(kl - (c_p + math.log(n * (n - 1.0)))) <= 1e-2
     assert kl > 0
+
+
+def _oracle_rowstats(x):
+    """The oracle's (beta, m, S) of every row, stored by make_c2_reference.py;
+    a few rows are recalibrated here so that a stale file cannot pass."""
+    z = np.load(os.path.join(GOLD, "c2_rowstats.npz"))
+    st = oracle.RowStats(z["beta"], z["m"], z["S"], z["H"], z["iters"])
+    rows = np.array([0, 1234, 65535])
+    fresh = oracle.calibrate(x, PERP, rows=rows)
+    np.testing.assert_array_equal(fresh.beta, st.beta[rows])
+    np.testing.assert_array_equal(fresh.S, st.S[rows])
+    return st
+
+
+@pytest.fixture(scope="module")
+def oracle_rows(full):
+    n, x = full["n"], full["x"]
+    st = _oracle_rowstats(x)
+    rows = _sample_rows(n, 200, 5)
+    t0 = time.time()
+    prow = oracle.p_rows(x, rows, st)
+    print(f"\n  oracle P rows: {rows.size} x {n} in {time.time() - t0:.1f} s; row sums "
+          f"{prow.sum(axis=1).min():.3e}..{prow.sum(axis=1).max():.3e}", flush=True)
+    return rows, prow
+
+
+def _maps(lab):
+    maps = {"clustered": synth.clustered_state(lab, seed=93, spread=30.0)}
+    st = np.load(os.path.join(GOLD, "c2_states.npz"))
+    for k in ("y249", "y999"):
+        maps[k] = st[k]
+    return maps
+
+
+def test_full_gradient_rows_against_oracle(full, oracle_rows):
+    n, lab, model = full["n"], full["lab"], full["model"]
+    rows, prow = oracle_rows
+    for name, y_np in _maps(lab).items():
+        y64 = y_np.astype(np.float64)
+        z_ref = oracle.z(y64)
+        y = torch.from_numpy(y_np).cuda()
+        for alpha in (1.0, 12.0):
+            g_ref = oracle.gradient_rows(prow, y64, rows, alpha, z_ref)
+            g, z = model.gradient(y, alpha)
+            g = g.cpu().numpy().astype(np.float64)[rows]
+            rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+            zr = abs(float(z.cpu()[0]) - z_ref) / z_ref
+            print(f"  map {name}, alpha {alpha}: gradient rel-L2 on {rows.size} rows {rel:.2e}, "
+                  f"Z rel {zr:.2e}", flush=True)
+            assert rel <= 1e-4 and zr <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["fp16x3", "bf16x3"])
+def test_full_x3_modes_against_oracle(full, oracle_rows, mode):
+    """The compensated x3 distance modes at the benchmark size meet the per-step
+    gates against the oracle: P rows (relative Frobenius and largest-entry error
+    over the sampled rows) within 1e-5, gradient rows within 1e-4."""
+    n, x, lab = full["n"], full["x"], full["lab"]
+    rows, prow = oracle_rows
+    model = ExactTSNE(torch.from_numpy(x).cuda(), PERP, dist_mode=mode)
+    assert model.status() == 0
+    pg = np.stack([model.p_rows(int(r), 1).cpu().numpy()[0] for r in rows]).astype(np.float64)
+    fro = np.linalg.norm(pg - prow) / np.linalg.norm(prow)
+    mx = np.abs(pg - prow).max() / prow.max()
+    y_np = synth.clustered_state(lab, seed=93, spread=30.0)
+    y64 = y_np.astype(np.float64)
+    z_ref = oracle.z(y64)
+    g_ref = oracle.gradient_rows(prow, y64, rows, 1.0, z_ref)
+    g = model.gradient(torch.from_numpy(y_np).cuda(), 1.0)[0].cpu().numpy().astype(np.float64)
+    grel = np.linalg.norm(g[rows] - g_ref) / np.linalg.norm(g_ref)
+    print(f"  {mode}: P rel-Frobenius {fro:.2e}, max-rel {mx:.2e}; gradient rel-L2 {grel:.2e}",
+          flush=True)
+    assert fro <= 1e-5 and mx <= 1e-5 and grel <= 1e-4
+    del model
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_full_run_against_oracle_run(full, mode):
+    """1,000 iterations of the benchmark schedule from the benchmark's initial
+    map, against the oracle's FP64 run of the same (stored with two runs from
+    maps one FP32 ulp apart); with FP64 distances and with the compensated
+    BF16 distances the benchmark times."""
+    n = full["n"]
+    model = full["model"] if mode == "fp64" else ExactTSNE(torch.from_numpy(full["x"]).cuda(), PERP,
+                                                            dist_mode=mode)
+    gold = json.load(open(os.path.join(GOLD, "c2_oracle.json")))
+    y0 = synth.embedding_init(n, synth.SEEDS["init_aniso"])
+    state = model.init_state(torch.from_numpy(y0).cuda())
+    kls = {}
+    t = 0
+    for t_end in sorted(int(k) for k in gold["checkpoints"]):
+        model.run(state, t_end - t, start=t)
+        t = t_end
+        kls[t_end] = float(model.cost(state[0]).cpu()[0])
+    assert model.status() == 0
+    ref = {int(k): v["kl"] for k, v in gold["checkpoints"].items()}
+    for t_end in sorted(kls):
+        ens = [e["checkpoints"][str(t_end)]["kl"] for e in gold["perturbed"]
+               if str(t_end) in e["checkpoints"]]
+        print(f"  t={t_end}: KL gpu {kls[t_end]:.6f} oracle {ref[t_end]:.6f} (ulp-perturbed "
+              f"{', '.join(f'{k:.6f}' for k in ens)})", flush=True)
+    for t_end in (1, 10):
+        assert abs(kls[t_end] - ref[t_end]) <= 1e-4 * ref[t_end]
+    ens = [e["checkpoints"]["1000"]["kl"] for e in gold["perturbed"]]
+    assert len(ens) >= 2, "the stored oracle ensemble is incomplete"
+    ok, band, tol = final_kl_gate(kls[1000], ref[1000], ens)
+    print(f"  {mode}: final KL rel diff {abs(kls[1000] - ref[1000]) / ref[1000]:.2e}; oracle "
+          f"band {band / ref[1000]:.2e}, tolerance {tol / ref[1000]:.2e}")
+    assert ok
