@@ -547,6 +547,7 @@ constexpr int kUpdPerBlock = T / kUpdRows;    // workgroups per row block
 static_assert(kUpdPerBlock == kMeanPartsPerBlock, "one re-centring partial per update workgroup");
 constexpr int kUpdSplit = kUpd / kUpdRows;    // threads per row
 constexpr int kSlotLds = 4096;                // nonzero-slot list entries staged in LDS
+constexpr int kUpdBatch = 8;                  // repulsive-slot loads in flight per thread
 
 struct UpdSmem {
   double4 part[kUpdSplit - 1][kUpdRows];
@@ -562,6 +563,19 @@ struct UpdSmem {
 __device__ inline double z_total(const float *__restrict__ zpart, int64_t nt, UpdSmem &sm) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int64_t q = threadIdx.x;
+  for (; q + 7 * kUpd < nt; q += 8 * kUpd) {  // two rounds of four, loads first
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = zpart[q + u * kUpd];
+    s0 += v[0];
+    s1 += v[1];
+    s2 += v[2];
+    s3 += v[3];
+    s0 += v[4];
+    s1 += v[5];
+    s2 += v[6];
+    s3 += v[7];
+  }
   for (; q + 3 * kUpd < nt; q += 4 * kUpd) {
     s0 += zpart[q];
     s1 += zpart[q + kUpd];
@@ -598,15 +612,47 @@ __device__ inline double4 row_sums(const float4 *__restrict__ part,
   double ax = 0.0, ay = 0.0, rx = 0.0, ry = 0.0;
   const float2 *pr = part_rep(part) + (size_t)b * nb * T + r;
   const float2 *pa = part_att(part, nb) + (size_t)b * nb * T + r;
-  for (int s = q; s < nb; s += kUpdSplit) {
+  // batches of kUpdBatch slots: all loads of a batch are issued before the
+  // first add, and the adds keep ascending slot order
+  int s = q;
+  for (; s + (kUpdBatch - 1) * kUpdSplit < nb; s += kUpdBatch * kUpdSplit) {
+    float2 v[kUpdBatch];
+#pragma unroll
+    for (int u = 0; u < kUpdBatch; ++u) v[u] = pr[(size_t)(s + u * kUpdSplit) * T];
+#pragma unroll
+    for (int u = 0; u < kUpdBatch; ++u) {
+      rx += v[u].x;
+      ry += v[u].y;
+    }
+  }
+  for (; s < nb; s += kUpdSplit) {
     const float2 v = pr[(size_t)s * T];
     rx += v.x;
     ry += v.y;
   }
-  for (int m = q; m < cnt; m += kUpdSplit) {
-    const int s = m < kSlotLds ? sm.slots[m] : gl[m];
-    if (s < 0 || s >= nb) continue;
-    const float2 a = pa[(size_t)s * T];
+  int m = q;
+  for (; m + 3 * kUpdSplit < cnt; m += 4 * kUpdSplit) {
+    float2 a[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int mu = m + u * kUpdSplit;
+      const int su = mu < kSlotLds ? sm.slots[mu] : gl[mu];
+      ok[u] = su >= 0 && su < nb;
+      a[u] = ok[u] ? pa[(size_t)su * T] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (ok[u]) {
+        ax += a[u].x;
+        ay += a[u].y;
+      }
+    }
+  }
+  for (; m < cnt; m += kUpdSplit) {
+    const int su = m < kSlotLds ? sm.slots[m] : gl[m];
+    if (su < 0 || su >= nb) continue;
+    const float2 a = pa[(size_t)su * T];
     ax += a.x;
     ay += a.y;
   }
@@ -783,8 +829,9 @@ __global__ __launch_bounds__(256) void k_recentre(const double2 *__restrict__ me
 // Batched iteration: many independent problems (each with its own workspace
 // and map) in one launch per phase. A device table lists the problems in
 // order with prefix sums of their tile and row-block counts; workgroup w
-// finds its problem by binary search and runs the single-problem code on it,
-// so every problem's result is bitwise the same as a separate launch.
+// finds its problem by binary search and runs the single-problem code on it
+// (the nonzero-tile kernel is persistent and walks the problems' lists in
+// turn), so every problem's result is bitwise the same as a separate launch.
 // ----------------------------------------------------------------------------
 __device__ inline int find_entry(const BatchEntry *tab, int count, int64_t key, bool by_tile) {
   int lo = 0, hi = count - 1;
@@ -810,9 +857,10 @@ __device__ inline const BatchEntry *batch_table(const BatchHdr *bh) {
                                               kBatchHdrBytes);
 }
 
-// Force kernels of the batch: launched over every tile of every problem
+// All-zero tiles of the batch: launched over every tile of every problem
 // (the problem found by binary search on its first tile); a workgroup whose
-// position within its problem is past the count of its kind exits at once.
+// position within its problem is past the count of all-zero tiles exits at
+// once.
 __global__ __launch_bounds__(256, 4) void k_force_zero_batched(const BatchHdr *__restrict__ bh,
                                                                int count, int64_t tiles,
                                                                int64_t blocks) {
@@ -834,22 +882,51 @@ __global__ __launch_bounds__(256, 4) void k_force_zero_batched(const BatchHdr *_
   zero_tile_body(c, yc, e.part, e.zpart, tile, sm);
 }
 
+// The nonzero tiles of every problem form one list (problem by problem, each
+// in the order of its own list), dealt round-robin to a persistent grid as in
+// the single-problem kernel: position g of the list goes to workgroup
+// g % active. A problem whose workspace is not ready is skipped here (the
+// all-zero kernel flags it). Counts are clamped to the problem's tile list.
+__device__ inline void full_range(const BatchEntry &e, int64_t &first, int64_t &cnt) {
+  first = min(max((int64_t)e.tcount[0], (int64_t)0), e.nt);
+  cnt = min(max((int64_t)e.tcount[1], (int64_t)0), e.nt - first);
+}
+
 __global__ __launch_bounds__(256, 2) void k_force_full_batched(const BatchHdr *__restrict__ bh,
                                                                int count, int64_t tiles,
                                                                int64_t blocks) {
   __shared__ ForceSmem sm;
   if (!batch_ok(bh, count, tiles, blocks)) return;
   const BatchEntry *tab = batch_table(bh);
-  const int p = find_entry(tab, count, blockIdx.x, true);
-  const BatchEntry &e = tab[p];
-  const int64_t i = (int64_t)blockIdx.x - e.tile0;
-  if (i < 0 || i >= e.nt) return;
-  if (!ready_is(e.h, e.n, 1)) return;
-  if (i >= e.tcount[1]) return;
-  const int64_t tile = e.tlist[e.tcount[0] + i];
-  float2 yc[16];
-  const TileCtx c = tile_begin(e.yp, e.n, e.nb, e.tmap, tile, yc, sm);
-  full_tile_body(c, yc, e.P, e.part, e.nb, e.zpart, tile, tile, sm);
+  int64_t nfull = 0, nzero = 0;
+  for (int p = 0; p < count; ++p) {
+    const BatchEntry &e = tab[p];
+    if (!ready_is(e.h, e.n, 1)) continue;
+    int64_t first, cnt;
+    full_range(e, first, cnt);
+    nzero += first;
+    nfull += cnt;
+  }
+  // one workgroup per CU beside the all-zero kernel; two when most tiles
+  // hold P
+  const int64_t active = min((int64_t)gridDim.x, nfull > nzero ? kFullGrid : kFullGrid / 2);
+  if ((int64_t)blockIdx.x >= active) return;
+  int64_t base = 0;  // list position of the problem's first nonzero tile
+  for (int p = 0; p < count; ++p) {
+    const BatchEntry &e = tab[p];
+    if (!ready_is(e.h, e.n, 1)) continue;
+    int64_t first, cnt;
+    full_range(e, first, cnt);
+    int64_t i = ((int64_t)blockIdx.x - base) % active;
+    if (i < 0) i += active;
+    for (; i < cnt; i += active) {
+      const int64_t tile = e.tlist[first + i];
+      float2 yc[16];
+      const TileCtx c = tile_begin(e.yp, e.n, e.nb, e.tmap, tile, yc, sm);
+      full_tile_body(c, yc, e.P, e.part, e.nb, e.zpart, tile, tile, sm);
+    }
+    base += cnt;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gather_batched(const BatchHdr *__restrict__ bh,
@@ -1282,8 +1359,9 @@ hipError_t launch_batch_step(const void *batch_ws, int count, int64_t total_tile
     hipError_t e = side_stream(ss);
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ss->fork, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_force_full_batched, dim3((unsigned)total_tiles), dim3(256), 0, st, bh,
-                       count, total_tiles, total_blocks);
+    const unsigned full_grid = (unsigned)(total_tiles < kFullGrid ? total_tiles : kFullGrid);
+    hipLaunchKernelGGL(k_force_full_batched, dim3(full_grid), dim3(256), 0, st, bh, count,
+                       total_tiles, total_blocks);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_force_zero_batched, dim3((unsigned)total_tiles), dim3(256), 0, ss->s, bh,
