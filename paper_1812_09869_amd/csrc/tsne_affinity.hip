@@ -1123,56 +1123,79 @@ __device__ __forceinline__ void pack_tile(float4 *__restrict__ P, const float *_
                                           uint8_t *__restrict__ nzflag, int2 *__restrict__ tmap,
                                           int64_t tile, int64_t pslot) {
   __shared__ double red[2][4];
+  __shared__ float srow[3][T];  // a, m, r of the tile's rows (0 past n)
   int I, J;
   tile_coords(tile, nb, I, J);
   if (threadIdx.x == 0) tmap[tile] = make_int2(I, J);
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int tc = l & 15, tr = (l >> 4) + 4 * w;
   const bool diag = (I == J);
-  float ar[16], mr[16], rr[16], ac[16], mc[16], rc[16];
+  {
+    const int64_t i = (int64_t)I * T + t;
+    const bool ok = i < n;
+    srow[0][t] = ok ? a[i] : 0.f;
+    srow[1][t] = ok ? m[i] : 0.f;
+    srow[2][t] = ok ? r[i] : 0.f;
+  }
+  float ac[16], mc[16], rc[16];
   uint32_t rvalid = 0, cvalid = 0;  // bit k: row tr+16k (column tc+16k) is a real point
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    int64_t i = (int64_t)I * T + tr + 16 * k;
-    bool ok = i < n;
-    rvalid |= ok ? (1u << k) : 0u;
-    ar[k] = ok ? a[i] : 0.f;
-    mr[k] = ok ? m[i] : 0.f;
-    rr[k] = ok ? r[i] : 0.f;
-    int64_t j = (int64_t)J * T + tc + 16 * k;
-    ok = j < n;
+    rvalid |= ((int64_t)I * T + tr + 16 * k < n) ? (1u << k) : 0u;
+    const int64_t j = (int64_t)J * T + tc + 16 * k;
+    const bool ok = j < n;
     cvalid |= ok ? (1u << k) : 0u;
     ac[k] = ok ? a[j] : 0.f;
     mc[k] = ok ? m[j] : 0.f;
     rc[k] = ok ? r[j] : 0.f;
   }
+  __syncthreads();
   float4 *tp = P + (size_t)pslot * TT4;
   float psum = 0.f, plp = 0.f;
   bool any = false;
-#pragma unroll 2
-  for (int s = 0; s < 64; ++s) {
-    const int k = s >> 2, mq = s & 3;
-    float4 dv = tp[s * 256 + t];
-    float dd[4] = {dv.x, dv.y, dv.z, dv.w};
-    float pv[4];
+  // row k of the thread's block is four float4 (one per column quarter mq);
+  // rows alternate between two register buffers, so the next row's four
+  // loads are in flight while a row is converted
+  auto convert_row = [&](int k, const float4 (&dv)[4]) {
+    const int row = tr + 16 * k;
+    const float ark = srow[0][row], mrk = srow[1][row], rrk = srow[2][row];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int mm = 4 * mq + e;
-      float p = pair_p(dd[e], ar[k], mr[k], rr[k], ac[mm], mc[mm], rc[mm]);
-      if (diag && tr == tc && k == mm) p = 0.f;
-      if (!((rvalid >> k) & (cvalid >> mm) & 1u)) p = 0.f;
-      // values below the normal FP32 range are stored as 0 (they change no
-      // sum by more than 1e-38); a tile whose entries are all 0 is skipped
-      // by the attractive part of the force pass
-      if (p < FLT_MIN) p = 0.f;
-      any |= p > 0.f;
-      pv[e] = p;
-      psum += p;
-      // denormal p (< FLT_MIN) contribute below 1e-36 and are skipped: the
-      // hardware log flushes them to zero
-      plp += (p >= FLT_MIN) ? p * __builtin_amdgcn_logf(p) : 0.f;
+    for (int mq = 0; mq < 4; ++mq) {
+      const float dd[4] = {dv[mq].x, dv[mq].y, dv[mq].z, dv[mq].w};
+      float pv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int mm = 4 * mq + e;
+        float p = pair_p(dd[e], ark, mrk, rrk, ac[mm], mc[mm], rc[mm]);
+        if (diag && tr == tc && k == mm) p = 0.f;
+        if (!((rvalid >> k) & (cvalid >> mm) & 1u)) p = 0.f;
+        // values below the normal FP32 range are stored as 0 (they change no
+        // sum by more than 1e-38); a tile whose entries are all 0 is skipped
+        // by the attractive part of the force pass
+        if (p < FLT_MIN) p = 0.f;
+        any |= p > 0.f;
+        pv[e] = p;
+        psum += p;
+        // denormal p (< FLT_MIN) contribute below 1e-36 and are skipped: the
+        // hardware log flushes them to zero
+        plp += (p >= FLT_MIN) ? p * __builtin_amdgcn_logf(p) : 0.f;
+      }
+      tp[(k * 4 + mq) * 256 + t] = make_float4(pv[0], pv[1], pv[2], pv[3]);
     }
-    tp[s * 256 + t] = make_float4(pv[0], pv[1], pv[2], pv[3]);
+  };
+  float4 ba[4], bb[4];
+#pragma unroll
+  for (int mq = 0; mq < 4; ++mq) ba[mq] = tp[mq * 256 + t];
+#pragma unroll 1
+  for (int k = 0; k < 16; k += 2) {
+#pragma unroll
+    for (int mq = 0; mq < 4; ++mq) bb[mq] = tp[((k + 1) * 4 + mq) * 256 + t];
+    convert_row(k, ba);
+    if (k + 2 < 16) {
+#pragma unroll
+      for (int mq = 0; mq < 4; ++mq) ba[mq] = tp[((k + 2) * 4 + mq) * 256 + t];
+    }
+    convert_row(k + 1, bb);
   }
   double ds = wave_sum_d((double)psum), dl = wave_sum_d((double)plp);
   if (l == 0) {
