@@ -154,16 +154,23 @@ __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT
       for (int c = 0; c < kDistCT; ++c)
         acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
   }
+  // every norm is loaded before the first store, so no store waits on a load
+  double ni[4][4], nj[kDistCT];
+#pragma unroll
+  for (int c = 0; c < kDistCT; ++c) nj[c] = norms[col0 + c * 16 + li];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ni[a][r] = norms[(int64_t)b * T + row0_loc + a * 16 + lk + 4 * r];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int il = row0_loc + a * 16 + lk + 4 * r;
-      const double ni = norms[(int64_t)b * T + il];
 #pragma unroll
       for (int c = 0; c < kDistCT; ++c) {
         const int64_t j = col0 + c * 16 + li;
-        double dd = ni + norms[j] - 2.0 * acc[a][c][r];
+        double dd = ni[a][r] + nj[c] - 2.0 * acc[a][c][r];
         dblock[(int64_t)il * npad + j] = (float)fmax(dd, 0.0);
       }
     }
@@ -261,16 +268,23 @@ __global__ __launch_bounds__(256) void k_dist_f32(const float *__restrict__ xfT,
       for (int c = 0; c < 4; ++c)
         acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[c], acc[a][c], 0, 0, 0);
   }
+  // every norm is loaded before the first store, so no store waits on a load
+  float ni[4][4], nj[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) nj[c] = norms[col0 + c * 16 + li];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ni[a][r] = norms[(int64_t)b * T + row0_loc + a * 16 + 4 * lk + r];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int il = row0_loc + a * 16 + 4 * lk + r;
-      const float ni = norms[(int64_t)b * T + il];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t j = col0 + c * 16 + li;
-        const float dd = (ni + norms[j]) - 2.f * acc[a][c][r];
+        const float dd = (ni[a][r] + nj[c]) - 2.f * acc[a][c][r];
         dblock[(int64_t)il * npad + j] = fmaxf(dd, 0.f);
       }
     }
@@ -315,16 +329,23 @@ __global__ __launch_bounds__(256) void k_dist_lp(const H *__restrict__ xa,
           acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av[a], bv[c], acc[a][c], 0, 0, 0);
       }
   }
+  // every norm is loaded before the first store, so no store waits on a load
+  float ni[4][4], nj[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) nj[c] = norms[col0 + c * 16 + li];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ni[a][r] = norms[(int64_t)b * T + row0_loc + a * 16 + 4 * lk + r];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int il = row0_loc + a * 16 + 4 * lk + r;
-      const float ni = norms[(int64_t)b * T + il];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t j = col0 + c * 16 + li;
-        const float dd = (ni + norms[j]) - 2.f * (acc[a][c][r] * inv_s2);
+        const float dd = (ni[a][r] + nj[c]) - 2.f * (acc[a][c][r] * inv_s2);
         dblock[(int64_t)il * npad + j] = fmaxf(dd, 0.f);
       }
     }
@@ -505,19 +526,24 @@ __global__ __launch_bounds__(256, 2) void k_dist_x3(const H *__restrict__ xs,
   v4f A0[4][4], R[4][4];
   x3_contract<H, V8>(xs, k32, row0, col0, li, lk, A0, R);
   const X3Scale sc = x3_scale(h, bits);
-  float2 nj[4];
+  // every norm is loaded before the first store, so no store waits on a load
+  float2 nj[4], ni[4][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) nj[c] = nhl[col0 + c * 16 + li];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ni[t][r] = nhl[(int64_t)b * T + row0_loc + t * 16 + 4 * lk + r];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int il = row0_loc + t * 16 + 4 * lk + r;
-      const float2 ni = nhl[(int64_t)b * T + il];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t j = col0 + c * 16 + li;
-        dblock[(int64_t)il * npad + j] = x3_combine(ni, nj[c], A0[t][c][r], R[t][c][r], sc);
+        dblock[(int64_t)il * npad + j] =
+            x3_combine(ni[t][r], nj[c], A0[t][c][r], R[t][c][r], sc);
       }
     }
   }
