@@ -729,14 +729,26 @@ __device__ __forceinline__ void update_wg(const float4 *__restrict__ part,
   const int t = threadIdx.x, q = t / kUpdRows;
   const int r = (wg % kUpdPerBlock) * kUpdRows + t % kUpdRows;  // row within the block
   const int64_t ir = (int64_t)b * T + r;                         // internal position
-  const double Z = z_total(zpart, nt, sm);  // its barriers also publish sm.eta
+  // odd workgroups sum their rows before Z, even ones after, so that the
+  // HBM-bound row sums of one half overlap the cached Z reads of the other
+  // (both results are the same in either order); the barriers of either
+  // also publish sm.eta
+  double Z;
+  double4 rs;
+  if (wg & 1) {
+    rs = row_sums(part, slots, nslots, nb, b, r, q, sm);
+    Z = z_total(zpart, nt, sm);
+  } else {
+    Z = z_total(zpart, nt, sm);
+    rs = row_sums(part, slots, nslots, nb, b, r, q, sm);
+  }
   if (lr_rule) eta = sm.eta;
   if (wg == 0 && t == 0) {
     h->z = Z;
     if (z_out) *z_out = Z;
     if (!isfinite(Z) || !(Z > 0.0)) flag_error(h, kErrNonFinite);
   }
-  const float2 g = gradient_of(row_sums(part, slots, nslots, nb, b, r, q, sm), (double)alpha, Z);
+  const float2 g = gradient_of(rs, (double)alpha, Z);
   double sx = 0.0, sy = 0.0;
   bool bad = false;
   if (q == 0 && ir < n) {
