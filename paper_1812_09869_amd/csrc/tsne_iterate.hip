@@ -904,12 +904,85 @@ __device__ inline void full_range(const BatchEntry &e, int64_t &first, int64_t &
   cnt = min(max((int64_t)e.tcount[1], (int64_t)0), e.nt - first);
 }
 
+// Problems whose list offsets a workgroup of the nonzero-tile kernel keeps in
+// LDS (larger batches walk the table serially).
+constexpr int kBatchLds = 1024;
+
 __global__ __launch_bounds__(256, 2) void k_force_full_batched(const BatchHdr *__restrict__ bh,
                                                                int count, int64_t tiles,
                                                                int64_t blocks) {
   __shared__ ForceSmem sm;
+  __shared__ int64_t pre[kBatchLds + 1];  // list position of problem p's first nonzero tile
+  __shared__ int64_t nzero_s;
   if (!batch_ok(bh, count, tiles, blocks)) return;
   const BatchEntry *tab = batch_table(bh);
+  const int t = threadIdx.x;
+  if (count <= kBatchLds) {
+    // one wave: lane l sums the nonzero and all-zero counts of problems
+    // 16 l .. 16 l + 15 (loads in flight together), then an inclusive scan
+    // over the lanes gives every problem's offset
+    if (t < 64) {
+      constexpr int kPer = kBatchLds / 64;
+      int64_t c[kPer], zs = 0, run = 0;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int p = kPer * t + u;
+        c[u] = 0;
+        if (p < count) {
+          const BatchEntry &e = tab[p];
+          if (ready_is(e.h, e.n, 1)) {
+            int64_t first, cnt;
+            full_range(e, first, cnt);
+            c[u] = cnt;
+            zs += first;
+          }
+        }
+        run += c[u];
+      }
+      int64_t inc = run;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int64_t v = __shfl_up(inc, o, 64);
+        if (t >= o) inc += v;
+      }
+      int64_t off = inc - run;  // exclusive prefix of this lane's problems
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int p = kPer * t + u;
+        if (p < count) pre[p] = off;
+        off += c[u];
+      }
+      if (t == 63) pre[count] = inc;
+      for (int o = 32; o > 0; o >>= 1) zs += __shfl_xor(zs, o, 64);
+      if (t == 0) nzero_s = zs;
+    }
+    __syncthreads();
+    const int64_t nfull = pre[count], nzero = nzero_s;
+    // one workgroup per CU beside the all-zero kernel; two when most tiles
+    // hold P
+    const int64_t active = min((int64_t)gridDim.x, nfull > nzero ? kFullGrid : kFullGrid / 2);
+    if ((int64_t)blockIdx.x >= active) return;
+    for (int64_t g = blockIdx.x; g < nfull; g += active) {
+      int lo = 0, hi = count - 1;  // last problem with pre[p] <= g
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const BatchEntry &e = tab[lo];
+      int64_t first, cnt;
+      full_range(e, first, cnt);
+      const int64_t i = g - pre[lo];
+      if (i >= cnt) continue;  // not reached: pre counts exactly cnt positions
+      const int64_t tile = e.tlist[first + i];
+      float2 yc[16];
+      const TileCtx c = tile_begin(e.yp, e.n, e.nb, e.tmap, tile, yc, sm);
+      full_tile_body(c, yc, e.P, e.part, e.nb, e.zpart, tile, tile, sm);
+    }
+    return;
+  }
   int64_t nfull = 0, nzero = 0;
   for (int p = 0; p < count; ++p) {
     const BatchEntry &e = tab[p];
@@ -919,8 +992,6 @@ __global__ __launch_bounds__(256, 2) void k_force_full_batched(const BatchHdr *_
     nzero += first;
     nfull += cnt;
   }
-  // one workgroup per CU beside the all-zero kernel; two when most tiles
-  // hold P
   const int64_t active = min((int64_t)gridDim.x, nfull > nzero ? kFullGrid : kFullGrid / 2);
   if ((int64_t)blockIdx.x >= active) return;
   int64_t base = 0;  // list position of the problem's first nonzero tile
