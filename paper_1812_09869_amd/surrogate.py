@@ -4,7 +4,8 @@ A 50 -> 256 -> 256 -> 2 ReLU network is trained on the (x, y) pairs that the
 exact path produced, then maps new points straight to the embedding. Every
 forward pass, gradient and Adam step runs in libtsne355 (BF16 MFMA with FP32
 accumulation for the wide layers). Exact t-SNE remains the fallback (a short
-refinement seeded from the network's map) and the judge of its error.
+refinement seeded from the network's map) and the reference its error is
+measured against.
 
 Host-side bookkeeping only: input standardisation statistics and target
 scaling are computed once on the training set (numpy, FP64); after training
