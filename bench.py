@@ -570,13 +570,15 @@ def dissim_leg(x, perp=50.0, n=16384, reps=3):
     return res
 
 
-def implicit_leg(x, perp=50.0, iters=10, modes=("fp64", "fp32", "bf16")):
+def implicit_leg(x, perp=50.0, iters=10, modes=("fp64", "fp32", "bf16x3", "bf16")):
     """Implicit P on the benchmark workload (N = 65,536, D = 50, perplexity
     50) in each distance mode: workspace size against the stored-P one, and
-    the time of one iteration (every pass recomputes P block row by block
-    row: MFMA distances of the mode against the block row's own columns,
-    stage, pack, force), mean of `iters` after one untimed. Here the mode
-    sets the iteration rate, unlike the stored path."""
+    the time of one iteration (every pass recomputes the nonzero tiles of P,
+    buffer by buffer: the mode's MFMA distances with Eq. 3 in their epilogue,
+    then the force body; the all-zero tiles take the repulsion-only body),
+    mean of `iters` after one untimed. Here the mode sets the iteration rate,
+    unlike the stored path; bf16x3 is the mode that keeps the per-step
+    parity gates."""
     import torch
 
     from paper_1812_09869_amd import _lib, synth
@@ -712,7 +714,7 @@ def main():
 
         from paper_1812_09869_amd import synth
         xl, _ = synth.subspace(262144, d=128)
-        res = implicit_leg(torch.from_numpy(xl).cuda(), 50.0, iters=5, modes=("fp64", "bf16"))
+        res = implicit_leg(torch.from_numpy(xl).cuda(), 50.0, iters=5, modes=("fp64", "bf16x3", "bf16"))
         res["workload"] = "10-D subspace mixture, N=262144, D=128, perplexity 50"
         print(json.dumps(res), flush=True)
         return
