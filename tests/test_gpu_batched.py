@@ -51,6 +51,33 @@ def test_batched_bitwise_equals_single(rule):
         assert torch.equal(out[k], m.cost(batched.states[k][0])), k
 
 
+def test_more_problems_than_the_lds_table():
+    """1,030 small problems: more than the nonzero-tile kernel keeps in its LDS
+    table (1,024), so it walks the problem table instead. Every problem's status
+    is clean and sampled problems on both sides of the 1,024 boundary are
+    bitwise the state of separate runs."""
+    count = 1030
+    rng = np.random.Generator(np.random.PCG64(31))
+    ns = rng.integers(40, 300, count)
+    ds = rng.integers(2, 6, count)
+    probs = [((rng.standard_normal((int(n), int(d))) * 3).astype(np.float32), 8.0)
+             for n, d in zip(ns, ds)]
+    y0s = [synth.embedding_init(int(n), seed=500 + k) for k, n in enumerate(ns)]
+    print(f"\n[batched] {count} problems, {int(ns.sum())} points", flush=True)
+    batched = BatchedTSNE([(_t(x), p) for x, p in probs])
+    batched.init_states([_t(y) for y in y0s])
+    sched = Schedule(switch=2)
+    batched.run(3, sched=sched)
+    assert max(m.status() for m in batched.models) == 0
+    for k in (0, 511, 1023, 1024, count - 1):
+        x, p = probs[k]
+        single = ExactTSNE(_t(x), p)
+        st = single.init_state(_t(y0s[k]))
+        single.run(st, 3, sched=sched)
+        for a, b in zip(batched.states[k], st):
+            assert torch.equal(a, b), k
+
+
 def test_full_workload_bitwise_on_sampled_problems():
     """The benchmark's 64-problem workload (636,092 points) in the launch the benchmark
     times: after six batched sweeps of the benchmark schedule (the exaggeration phase),
