@@ -76,3 +76,30 @@ def test_mode_errors(ref, mode, p_bound, g_bound, max_bound):
     if max_bound is not None:
         assert mx <= max_bound
     assert klrel <= max(p_bound, 1e-5)
+
+
+# Sizes and widths at the edges of the x3 kernels: a 3-point problem, ragged
+# last row blocks (255, 257, 300 points), one coordinate, and widths one past
+# a 32-wide slice block (33, 65: a second, almost empty K step).
+EDGES = [(3, 2, 1.5), (255, 1, 10.0), (257, 33, 20.0), (300, 65, 30.0), (600, 64, 30.0)]
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("n,d,perp", EDGES, ids=[f"n{n}-d{d}" for n, d, _ in EDGES])
+def test_x3_edges_against_oracle(n, d, perp, mode):
+    rng = np.random.Generator(np.random.PCG64(1000 + n + d))
+    x = (rng.standard_normal((n, d)) * 4.0 + 20.0).astype(np.float32)  # offset: cancellation
+    st = oracle.calibrate(x, perp)
+    P = oracle.joint_p(x, st)
+    y = synth.embedding_init(n, seed=3) * 100.0
+    g_ref, _ = oracle.gradient(P, y.astype(np.float64), 1.0)
+    model = ExactTSNE(torch.from_numpy(x).cuda(), perp, dist_mode=mode)
+    assert model.status() == 0
+    pg = model.p_rows(0, n).cpu().numpy().astype(np.float64)
+    assert np.array_equal(pg, pg.T) and np.all(np.diag(pg) == 0)
+    fro = np.linalg.norm(pg - P) / np.linalg.norm(P)
+    mx = np.abs(pg - P).max() / P.max()
+    g, _ = model.gradient(torch.from_numpy(y).cuda(), 1.0)
+    grel = np.linalg.norm(g.cpu().numpy() - g_ref) / np.linalg.norm(g_ref)
+    print(f"\n  n={n} d={d} {mode}: P fro {fro:.2e} max {mx:.2e} | grad {grel:.2e}")
+    assert fro <= 1e-5 and mx <= 1e-5 and grel <= 1e-4
