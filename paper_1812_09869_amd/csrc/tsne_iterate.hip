@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256, 2) void k_force_range(const float4 *__restrict
 // separate launch; workgroup 0 stores it.
 // ----------------------------------------------------------------------------
 constexpr int kUpd = 1024;
-constexpr int kUpdRows = 128;                 // rows per workgroup
+constexpr int kUpdRows = 64;                  // rows per workgroup
 constexpr int kUpdPerBlock = T / kUpdRows;    // workgroups per row block
 static_assert(kUpdPerBlock == kMeanPartsPerBlock, "one re-centring partial per update workgroup");
 constexpr int kUpdSplit = kUpd / kUpdRows;    // threads per row
@@ -810,16 +810,23 @@ __global__ __launch_bounds__(kUpd) void k_update(
 __device__ __forceinline__ void recentre_wg(const double2 *__restrict__ meanpart, int64_t n,
                                             int32_t nb, float2 *__restrict__ Y, Hdr *h, int blk,
                                             float2 &smean) {
+  __shared__ double2 wred[4];
   if (!state_ok(h, n)) return;
-  if (threadIdx.x < 64) {  // one wave: strided partial sums, then a fixed-order wave sum
-    double mx = 0.0, my = 0.0;
-    for (int b = threadIdx.x; b < nb * kUpdPerBlock; b += 64) {
-      mx += meanpart[b].x;
-      my += meanpart[b].y;
-    }
-    mx = wave_sum_d(mx);
-    my = wave_sum_d(my);
-    if (threadIdx.x == 0) smean = make_float2((float)(mx / (double)n), (float)(my / (double)n));
+  // strided partial sums over the 256 threads, the wave sums, then the four
+  // wave results in order (a fixed order)
+  double mx = 0.0, my = 0.0;
+  for (int b = threadIdx.x; b < nb * kUpdPerBlock; b += 256) {
+    mx += meanpart[b].x;
+    my += meanpart[b].y;
+  }
+  mx = wave_sum_d(mx);
+  my = wave_sum_d(my);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = make_double2(mx, my);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double sx = (wred[0].x + wred[1].x) + (wred[2].x + wred[3].x);
+    const double sy = (wred[0].y + wred[1].y) + (wred[2].y + wred[3].y);
+    smean = make_float2((float)(sx / (double)n), (float)(sy / (double)n));
   }
   __syncthreads();
   const int64_t i = (int64_t)blk * 256 + threadIdx.x;
