@@ -22,7 +22,7 @@ namespace tsne {
 // tile holds the pairs (row tr + 16 (s / 4), column tc + 16 (4 (s % 4) + e)),
 // e = 0..3, so every wave-wide float4 load is one contiguous 1 KiB segment.
 // ---------------------------------------------------------------------------
-constexpr int kMeanPartsPerBlock = 4;  // re-centring partial sums per row block
+constexpr int kMeanPartsPerBlock = 2;  // re-centring partial sums per row block
 constexpr int64_t kImplicitTiles = 2048;  // implicit P: tiles recomputed per force launch (at least)
 constexpr int T = 256;             // tile edge
 constexpr int TT4 = T * T / 4;     // float4 per tile

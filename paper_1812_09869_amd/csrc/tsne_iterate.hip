@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256, 2) void k_force_range(const float4 *__restrict
 // separate launch; workgroup 0 stores it.
 // ----------------------------------------------------------------------------
 constexpr int kUpd = 1024;
-constexpr int kUpdRows = 64;                  // rows per workgroup
+constexpr int kUpdRows = 128;                 // rows per workgroup
 constexpr int kUpdPerBlock = T / kUpdRows;    // workgroups per row block
 static_assert(kUpdPerBlock == kMeanPartsPerBlock, "one re-centring partial per update workgroup");
 constexpr int kUpdSplit = kUpd / kUpdRows;    // threads per row
