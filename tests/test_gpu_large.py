@@ -1,20 +1,22 @@
 """Above 65,536 points: the streaming search and the precision path against the oracle.
 
-Workload: 98,304 points of the 64-component mixture on a random 10-D subspace of
-R^128 plus noise of std 0.05, perplexity 50. A row has 98,304 distances, more
-than the search keeps in registers (64 per thread of its 1,024), so every row
-takes the streaming branch that re-reads the distance block on each pass.
-The oracle's statistics of all rows are stored by
-tests/golden/make_large_reference.py, which lets the test form whole rows of
-P (Eq. 3) and gradient rows (Eq. 6) with Z over all ordered pairs.
+Workloads: the 64-component mixture on a random 10-D subspace of R^128 plus
+noise of std 0.05, perplexity 50, at N = 98,304 and at N = 262,144 (the
+precision configuration itself). A row has N distances, more than the search
+keeps in registers (64 per thread of its 1,024), so every row takes the
+streaming branch that re-reads the distance block on each pass. The oracle's
+statistics of all rows are stored by tests/golden/make_large_reference.py,
+which lets the test form whole rows of P (Eq. 3) and gradient rows (Eq. 6)
+with Z over all pairs.
 
 For every distance mode (all of them, so the printed lines are the precision
-report of this configuration): beta of every row, 48 sampled rows of P, Z and
-the gradient rows (alpha = 1 and 12) at a clustered map, and each sampled
-row's share of the KL (Eq. 5) implied by the mode's P. The FP64 and the
-compensated x3 modes are gated at the per-step tolerances (beta 1e-4; P 1e-5
-relative Frobenius and largest-entry error over the largest entry; gradient
-1e-4; Z 1e-6; KL shares 1e-5); the plain reduced modes are reported only.
+report of these configurations): beta of every row, 48 sampled rows of P, Z
+and the gradient rows (alpha = 1 and 12) at a clustered map, and each
+sampled row's share of the KL (Eq. 5) implied by the mode's P. The FP64 and
+the compensated x3 modes are gated at the per-step tolerances (beta 1e-4; P
+1e-5 relative Frobenius and largest-entry error over the largest entry;
+gradient 1e-4; Z 1e-6; KL shares 1e-5); the plain reduced modes are reported
+only.
 """
 import math
 import os
@@ -30,15 +32,17 @@ from paper_1812_09869_amd.tsne import ExactTSNE
 
 pytestmark = pytest.mark.gpu
 
-N, D, PERP = 98304, 128, 50.0
+D, PERP = 128, 50.0
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 GATED = {"fp64", "fp16x3", "bf16x3"}
+STATS = {98304: "large_rowstats.npz", 262144: "c3_rowstats.npz"}
 
 
-@pytest.fixture(scope="module")
-def ref():
+@pytest.fixture(scope="module", params=sorted(STATS))
+def ref(request):
+    N = request.param
     x, lab = synth.subspace(N, d=D)
-    z = np.load(os.path.join(GOLD, "large_rowstats.npz"))
+    z = np.load(os.path.join(GOLD, STATS[N]))
     st = oracle.RowStats(z["beta"], z["m"], z["S"], z["H"], z["iters"])
     check = np.array([0, 4321, N - 1])
     fresh = oracle.calibrate(x, PERP, rows=check)
@@ -54,7 +58,7 @@ def ref():
     kl_ref = oracle.kl_rows(prow, y64, rows, zr)
     print(f"\n[large] n={N} d={D}: oracle rows, Z and gradient rows in {time.time() - t0:.1f} s",
           flush=True)
-    return dict(x=x, st=st, rows=rows, prow=prow, y=y, z=zr, g=g_ref, kl=kl_ref)
+    return dict(N=N, x=x, st=st, rows=rows, prow=prow, y=y, z=zr, g=g_ref, kl=kl_ref)
 
 
 def _kl_shares(prow, y, rows, z):
@@ -72,7 +76,7 @@ def _kl_shares(prow, y, rows, z):
 
 @pytest.mark.parametrize("mode", ["fp64", "fp16x3", "bf16x3", "fp32", "fp16", "bf16"])
 def test_large_against_oracle(ref, mode):
-    x, st, rows, prow = ref["x"], ref["st"], ref["rows"], ref["prow"]
+    N, x, st, rows, prow = ref["N"], ref["x"], ref["st"], ref["rows"], ref["prow"]
     print(f"\n[case] n={N} d={D} mode={mode}", flush=True)
     t0 = time.time()
     model = ExactTSNE(torch.from_numpy(x).cuda(), PERP, dist_mode=mode)
