@@ -128,6 +128,37 @@ __device__ __forceinline__ float4 force_row(const float4 (&pv4)[4], float2 yi, c
   return make_float4(ax, ay, rx, ry);
 }
 
+// Totals of four rows' per-lane sums r0 .. r3 over the 16 lanes of a DPP
+// row, one kept per lane: lane tc ends with the total of r(2 b3 + b2), b3 and
+// b2 being bits 3 and 2 of tc.
+// The additions are row16_sum's, in the same order: pairs of lanes at
+// distance 8, then 4, 2 and 1 (after the first level every lane of a row
+// holds a function of tc mod 8, so row16_sum's rotations by 4, 2 and 1 add
+// the same operands as the exchanges used here), hence each total is bitwise
+// row16_sum's. Choosing the kept quantity after the first two levels drops
+// the additions every lane would repeat for totals it does not keep: 11
+// instructions for four totals instead of 16.
+__device__ __forceinline__ float row16_sum4(float r0, float r1, float r2, float r3, bool b3,
+                                            bool b2) {
+  // distance 8: a rotation by 8 inside the row exchanges its halves
+  const float x0 = r0 + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(r0), 0x128, 0xf, 0xf, true));
+  const float x1 = r1 + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(r1), 0x128, 0xf, 0xf, true));
+  const float x2 = r2 + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(r2), 0x128, 0xf, 0xf, true));
+  const float x3 = r3 + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(r3), 0x128, 0xf, 0xf, true));
+  const float sa = b3 ? x2 : x0;  // r0 or r2
+  const float sb = b3 ? x3 : x1;  // r1 or r3
+  // distance 4: a lane with bit 2 clear reads lane + 4 (row shift left),
+  // one with bit 2 set reads lane - 4 (row shift right); the lanes whose
+  // shifted read leaves the row take the other operand
+  const float ya = sa + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sa), 0x104, 0xf, 0xf, true));
+  const float yb = sb + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sb), 0x114, 0xf, 0xf, true));
+  float s = b2 ? yb : ya;
+  // distances 2 and 1 inside each group of four lanes (quad permutations)
+  s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0x4E, 0xf, 0xf, true));
+  s += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s), 0xB1, 0xf, 0xf, true));
+  return s;
+}
+
 // ---------------------------------------------------------------------------
 // P streaming through LDS. Each wave owns a ring of kStages row slots in LDS;
 // a slot holds the four float4 per lane that one row (k) of the thread's
@@ -220,39 +251,53 @@ __device__ __forceinline__ void tile_rows(const float4 *__restrict__ tp, float4 
   }
 }
 
+// Row of the thread's 16 x 16 block whose total the all-zero tile body keeps
+// in lane tc: rows are summed four at a time (4 j .. 4 j + 3) and lane tc
+// keeps row 4 j + (tc >> 2) of group j = tc & 3.
+__device__ __forceinline__ int zero_row_of_lane(int tc) { return 4 * (tc & 3) + (tc >> 2); }
+
 // A tile whose stored P is all zero: only the repulsive sums and Z, no P
-// traffic. Row positions come from LDS (no ring is in use here).
+// traffic. Row positions come from LDS (no ring is in use here). Rows are
+// taken in order (so Z and the column sums accumulate as row by row), four
+// per pass of the loop, and reduced over the lanes together.
 template <bool DIAG, bool EDGE>
 __device__ __forceinline__ void tile_rows_zero(const float2 *yrow, const float2 yc[16],
                                                uint32_t rvalid, uint32_t cvalid, int tr, int tc,
                                                float2 &myrow, float2 colrep[16], float &z) {
+  const bool b3 = (tc & 8) != 0, b2 = (tc & 4) != 0;
 #pragma unroll 1
-  for (int k = 0; k < 16; ++k) {
-    const float2 yi = yrow[tr + 16 * k];
-    float rx = 0.f, ry = 0.f;
+  for (int j = 0; j < 4; ++j) {
+    float rx[4], ry[4];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
-      const float q = fmaf(dx, dx, fmaf(dy, dy, 1.0f));
-      float w = __builtin_amdgcn_rcpf(q);
-      if (DIAG) {
-        if (tr == tc && k == m) w = 0.f;
-      }
-      if (EDGE) {
-        if (!((rvalid >> k) & (cvalid >> m) & 1u)) w = 0.f;
-      }
-      z += w;
-      const float w2 = w * w;
-      rx = fmaf(w2, dx, rx);
-      ry = fmaf(w2, dy, ry);
-      if (!DIAG) {
-        colrep[m].x = fmaf(-w2, dx, colrep[m].x);
-        colrep[m].y = fmaf(-w2, dy, colrep[m].y);
+    for (int g = 0; g < 4; ++g) {
+      const int k = 4 * j + g;
+      const float2 yi = yrow[tr + 16 * k];
+      rx[g] = 0.f;
+      ry[g] = 0.f;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const float dx = yi.x - yc[m].x, dy = yi.y - yc[m].y;
+        const float q = fmaf(dx, dx, fmaf(dy, dy, 1.0f));
+        float w = __builtin_amdgcn_rcpf(q);
+        if (DIAG) {
+          if (tr == tc && k == m) w = 0.f;
+        }
+        if (EDGE) {
+          if (!((rvalid >> k) & (cvalid >> m) & 1u)) w = 0.f;
+        }
+        z += w;
+        const float w2 = w * w;
+        rx[g] = fmaf(w2, dx, rx[g]);
+        ry[g] = fmaf(w2, dy, ry[g]);
+        if (!DIAG) {
+          colrep[m].x = fmaf(-w2, dx, colrep[m].x);
+          colrep[m].y = fmaf(-w2, dy, colrep[m].y);
+        }
       }
     }
-    rx = row16_sum(rx);
-    ry = row16_sum(ry);
-    if (tc == k) myrow = make_float2(rx, ry);
+    const float sx = row16_sum4(rx[0], rx[1], rx[2], rx[3], b3, b2);
+    const float sy = row16_sum4(ry[0], ry[1], ry[2], ry[3], b3, b2);
+    if ((tc & 3) == j) myrow = make_float2(sx, sy);
   }
 }
 
@@ -371,7 +416,9 @@ __device__ __forceinline__ void zero_tile_body(const TileCtx &c, const float2 (&
       tile_rows_zero<false, false>(sm.yrow, yc, c.rvalid, c.cvalid, c.tr, c.tc, myrow, colrep,
                                    z);
   }
-  prep[c.rslot] = myrow;
+  // this lane holds the total of row tr + 16 zero_row_of_lane(tc), not of
+  // row tr + 16 tc as in c.rslot
+  prep[(int64_t)c.rslot + 16 * (zero_row_of_lane(c.tc) - c.tc)] = myrow;
   // column side: the 16 row groups' sums meet in LDS
   if (c.I != c.J) {
 #pragma unroll
