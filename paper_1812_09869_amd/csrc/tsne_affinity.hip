@@ -512,14 +512,22 @@ __device__ __forceinline__ float x3_combine(float2 ni, float2 nj, float a0, floa
 }
 
 // Distance block of the x3 modes: a workgroup covers 64 rows x 256 columns,
-// as k_dist_lp.
+// as k_dist_lp. With P given, the block row's tiles (J >= b) also go
+// straight to their place in the packed buffer, in the layout k_stage
+// writes, so that no staging pass follows: lane (li, lk) of wave w holds,
+// for each of its rows tr + 16 k of a tile, columns li + 16 (4 w + c),
+// c = 0 .. 3, which is the float4 4 k + w of thread 16 tr + li there.
 template <typename H, typename V8>
 __global__ __launch_bounds__(256, 2) void k_dist_x3(const H *__restrict__ xs,
                                                  const float2 *__restrict__ nhl, int64_t npad,
                                                  int32_t k32, int32_t bits, int32_t b,
-                                                 float *__restrict__ dblock, const Hdr *h) {
+                                                 float *__restrict__ dblock, const Hdr *h,
+                                                 float4 *__restrict__ P, int32_t nb) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = (int64_t)blockIdx.x * 256 + w * 64;
+  // column tile, rotated so that the diagonal one (the workgroups with the
+  // most stores) is dispatched first
+  const int J = (int)((blockIdx.x + (unsigned)b) % gridDim.x);
+  const int64_t col0 = (int64_t)J * 256 + w * 64;
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -534,16 +542,39 @@ __global__ __launch_bounds__(256, 2) void k_dist_x3(const H *__restrict__ xs,
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) ni[t][r] = nhl[(int64_t)b * T + row0_loc + t * 16 + 4 * lk + r];
+  float4 *pt = (P != nullptr && J > b) ? P + (size_t)(tile_start(b, nb) + (J - b)) * TT4 : nullptr;
+  // the diagonal tile is symmetrised as k_stage does it: each value of the
+  // upper triangle (diagonal included) goes to its own place and to the
+  // mirrored one, one float at a time
+  float *pd = (P != nullptr && J == b) ? reinterpret_cast<float *>(P + (size_t)tile_start(b, nb) * TT4)
+                                       : nullptr;
+  // float of (row i, column j) of a tile in that layout
+  auto packed = [](int i, int j) {
+    return 4 * ((4 * (i >> 4) + (j >> 6)) * 256 + 16 * (i & 15) + (j & 15)) + ((j >> 4) & 3);
+  };
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int il = row0_loc + t * 16 + 4 * lk + r;
+      float v[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t j = col0 + c * 16 + li;
-        dblock[(int64_t)il * npad + j] =
-            x3_combine(ni[t][r], nj[c], A0[t][c][r], R[t][c][r], sc);
+        v[c] = x3_combine(ni[t][r], nj[c], A0[t][c][r], R[t][c][r], sc);
+        dblock[(int64_t)il * npad + j] = v[c];
+      }
+      if (pt) {
+        pt[((il >> 4) * 4 + w) * 256 + 16 * (il & 15) + li] = make_float4(v[0], v[1], v[2], v[3]);
+      } else if (pd) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int jl = 64 * w + 16 * c + li;  // column within the tile
+          if (jl >= il) {
+            pd[packed(il, jl)] = v[c];
+            if (jl > il) pd[packed(jl, il)] = v[c];
+          }
+        }
       }
     }
   }
@@ -2060,8 +2091,10 @@ __global__ void k_set_ready(Hdr *h, int32_t ready) {
 // Distances of row block b against all columns into dblock (its slot of the
 // group scratch), in the workspace's distance mode. xc, nrm: the centred X and its norms for the
 // FP64 mode (the reduced modes read their prepared operands).
-static void launch_dist(const Layout &L, void *ws, int b, const double *xc, const double *nrm,
-                        float *dblock, hipStream_t st) {
+// P: the packed buffer, for the modes whose distance kernel stages the block
+// row's tiles itself (the x3 modes), else nullptr. Returns whether it did.
+static bool launch_dist(const Layout &L, void *ws, int b, const double *xc, const double *nrm,
+                        float *dblock, float4 *P, hipStream_t st) {
   const Hdr *h = at<const Hdr>(ws, L.hdr);
   const float *norms32 = at<const float>(ws, L.norms32);
   const dim3 dgrid((unsigned)(L.npad / 256), T / 64);
@@ -2083,17 +2116,18 @@ static void launch_dist(const Layout &L, void *ws, int b, const double *xc, cons
     case TSNE_DIST_BF16X3:
       hipLaunchKernelGGL((k_dist_x3<__bf16, v8bf>), dgrid, dim3(256), 0, st,
                          at<const __bf16>(ws, L.xa), at<const float2>(ws, L.norms32), L.npad,
-                         L.kk / 4, x3_bits(L.kk / 4, true), b, dblock, h);
-      break;
+                         L.kk / 4, x3_bits(L.kk / 4, true), b, dblock, h, P, L.nb);
+      return P != nullptr;
     case TSNE_DIST_FP16X3:
       hipLaunchKernelGGL((k_dist_x3<_Float16, v8h>), dgrid, dim3(256), 0, st,
                          at<const _Float16>(ws, L.xa), at<const float2>(ws, L.norms32), L.npad,
-                         L.kk / 4, x3_bits(L.kk / 4, false), b, dblock, h);
-      break;
+                         L.kk / 4, x3_bits(L.kk / 4, false), b, dblock, h, P, L.nb);
+      return P != nullptr;
     default:
       hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64), dim3(256),
                          0, st, xc, nrm, L.npad, L.dpad, b, dblock);
   }
+  return false;
 }
 
 hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, double perplexity,
@@ -2161,8 +2195,10 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   auto slot = [&](int b) { return dblock + (size_t)(b % L.cal_group) * T * L.npad; };
   auto group_end = [&](int b0) { return b0 + L.cal_group < L.nb ? b0 + L.cal_group : L.nb; };
   // Distances of row block b (into its slot), all columns.
+  // Whether the distance kernel staged the block row's tiles itself.
+  bool staged = false;
   auto dist = [&](int b, const double *xc, const double *nrm) {
-    launch_dist(L, ws, b, xc, nrm, slot(b), st);
+    staged = launch_dist(L, ws, b, xc, nrm, slot(b), (stats_only || implicit) ? nullptr : P, st);
   };
   // The search over every row of the group starting at block b.
   auto calibrate = [&](int b) {
@@ -2278,7 +2314,7 @@ hipError_t launch_affinities(const Layout &L, const float *x, const float *dis, 
   for (int b0 = 0; b0 < L.nb; b0 += L.cal_group) {
     for (int b = b0; b < group_end(b0); ++b) dist(b, xc, nrm);
     calibrate(b0);
-    if (!stats_only && !implicit)
+    if (!stats_only && !implicit && !staged)
       for (int b = b0; b < group_end(b0); ++b)
         hipLaunchKernelGGL(k_stage, dim3(L.nb - b, kStageSplit), dim3(256), 0, st, slot(b),
                            L.npad, L.nb, b, P);
