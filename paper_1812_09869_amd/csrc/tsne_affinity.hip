@@ -127,12 +127,23 @@ constexpr int kDistCT = 2;  // 16-column MFMA tiles per wave (a wave covers 64 x
 // lane's two columns are neighbours in the tile layout
 constexpr int kTileCT = 2;
 
+// With P given, the block row's tiles (J >= b) also go straight to their
+// place in the packed buffer, in the layout k_stage writes, as in k_dist_x3:
+// for each of its rows a lane holds columns cl + li and cl + 16 + li of the
+// tile (cl = 128 h + 32 w, h the half of the tile this workgroup covers),
+// the two consecutive elements 2 (w mod 2) and 2 (w mod 2) + 1 of one float4
+// there. The column strips are rotated so that the diagonal tile's are
+// dispatched first.
+static_assert(kDistCT == 2, "the packed stores assume 32 columns per wave");
 __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT,
                                                   const double *__restrict__ norms, int64_t npad,
                                                   int32_t dpad, int32_t b,
-                                                  float *__restrict__ dblock) {
+                                                  float *__restrict__ dblock,
+                                                  float4 *__restrict__ P, int32_t nb) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t col0 = (int64_t)blockIdx.x * (64 * kDistCT) + w * (16 * kDistCT);
+  const int xs = (int)((blockIdx.x + 2u * (unsigned)b) % gridDim.x);  // column strip
+  const int J = xs >> 1, cl = 128 * (xs & 1) + 32 * w;
+  const int64_t col0 = (int64_t)xs * (64 * kDistCT) + w * (16 * kDistCT);
   const int row0_loc = blockIdx.y * 64;
   const int64_t row0 = (int64_t)b * T + row0_loc;
   const int li = l & 15, lk = l >> 4;
@@ -162,16 +173,38 @@ __global__ __launch_bounds__(256) void k_dist_f64(const double *__restrict__ xcT
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) ni[a][r] = norms[(int64_t)b * T + row0_loc + a * 16 + lk + 4 * r];
+  float *pt = (P != nullptr && J > b)
+                  ? reinterpret_cast<float *>(P + (size_t)(tile_start(b, nb) + (J - b)) * TT4)
+                  : nullptr;
+  float *pd = (P != nullptr && J == b) ? reinterpret_cast<float *>(P + (size_t)tile_start(b, nb) * TT4)
+                                       : nullptr;
+  auto packed = [](int i, int j) {  // float of (row i, column j) of a tile
+    return 4 * ((4 * (i >> 4) + (j >> 6)) * 256 + 16 * (i & 15) + (j & 15)) + ((j >> 4) & 3);
+  };
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int il = row0_loc + a * 16 + lk + 4 * r;
+      float v[kDistCT];
 #pragma unroll
       for (int c = 0; c < kDistCT; ++c) {
         const int64_t j = col0 + c * 16 + li;
         double dd = ni[a][r] + nj[c] - 2.0 * acc[a][c][r];
-        dblock[(int64_t)il * npad + j] = (float)fmax(dd, 0.0);
+        v[c] = (float)fmax(dd, 0.0);
+        dblock[(int64_t)il * npad + j] = v[c];
+      }
+      if (pt) {
+        *reinterpret_cast<float2 *>(pt + packed(il, cl + li)) = make_float2(v[0], v[1]);
+      } else if (pd) {
+#pragma unroll
+        for (int c = 0; c < kDistCT; ++c) {
+          const int jl = cl + 16 * c + li;  // column within the tile
+          if (jl >= il) {
+            pd[packed(il, jl)] = v[c];
+            if (jl > il) pd[packed(jl, il)] = v[c];
+          }
+        }
       }
     }
   }
@@ -2092,7 +2125,8 @@ __global__ void k_set_ready(Hdr *h, int32_t ready) {
 // group scratch), in the workspace's distance mode. xc, nrm: the centred X and its norms for the
 // FP64 mode (the reduced modes read their prepared operands).
 // P: the packed buffer, for the modes whose distance kernel stages the block
-// row's tiles itself (the x3 modes), else nullptr. Returns whether it did.
+// row's tiles itself (FP64 and the x3 modes), else nullptr. Returns whether
+// it did.
 static bool launch_dist(const Layout &L, void *ws, int b, const double *xc, const double *nrm,
                         float *dblock, float4 *P, hipStream_t st) {
   const Hdr *h = at<const Hdr>(ws, L.hdr);
@@ -2125,7 +2159,8 @@ static bool launch_dist(const Layout &L, void *ws, int b, const double *xc, cons
       return P != nullptr;
     default:
       hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)(L.npad / (64 * kDistCT)), T / 64), dim3(256),
-                         0, st, xc, nrm, L.npad, L.dpad, b, dblock);
+                         0, st, xc, nrm, L.npad, L.dpad, b, dblock, P, L.nb);
+      return P != nullptr;
   }
   return false;
 }
